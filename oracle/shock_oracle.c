@@ -1,0 +1,220 @@
+/*
+ * CPU oracle for the ShockHash leaf seed search -- TEST INFRASTRUCTURE ONLY.
+ * Definitions, notation and citations are in shock_oracle.h.  Plain C, one
+ * thread, no blocking or fusion: every seed is hashed, optionally filtered,
+ * tested for the pseudoforest property by counting the nodes and edges of
+ * each connected component, and the first qualifying seed is returned.
+ */
+#include "shock_oracle.h"
+
+#include <stddef.h>
+#include <string.h>
+
+#define GOLDEN 0x9E3779B97F4A7C15ULL
+
+uint64_t shock_oracle_fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ULL;
+  k ^= k >> 33;
+  return k;
+}
+
+void shock_oracle_slots(uint64_t x, uint64_t s, uint32_t n, uint32_t *h0, uint32_t *h1) {
+  uint64_t a = shock_oracle_fmix64(x);
+  uint64_t t = shock_oracle_fmix64((s + 1) * GOLDEN);
+  uint64_t c = a ^ t;
+  uint64_t p = (uint64_t)(uint32_t)c * (uint64_t)(uint32_t)(c >> 32);
+  uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
+  uint32_t first = (uint32_t)(((uint64_t)(z & 0xFFFFu) * n) >> 16);
+  *h0 = first;
+  if (n < 2) {
+    *h1 = 0; /* a single cell: the only slot there is */
+    return;
+  }
+  uint32_t r = (uint32_t)(((uint64_t)(z >> 16) * (n - 1)) >> 16);
+  *h1 = r + (r >= first ? 1u : 0u);
+}
+
+/* Section 2 (pseudoforests) and Section 4: a graph is a pseudoforest iff no
+ * connected component holds more edges than nodes.  Components are found by
+ * an explicit-stack depth-first search over an edge scan. */
+int shock_oracle_is_pseudoforest(uint32_t n, uint32_t n_edges, const uint32_t *h0, const uint32_t *h1) {
+  int comp[64];
+  uint32_t nodes_in[64], edges_in[64];
+  uint32_t stack[64];
+  uint32_t n_comp = 0;
+  for (uint32_t v = 0; v < n; ++v) comp[v] = -1;
+  for (uint32_t v = 0; v < n; ++v) {
+    if (comp[v] >= 0) continue;
+    uint32_t top = 0, count = 0;
+    comp[v] = (int)n_comp;
+    stack[top++] = v;
+    while (top > 0) {
+      uint32_t u = stack[--top];
+      ++count;
+      for (uint32_t e = 0; e < n_edges; ++e) {
+        uint32_t w;
+        if (h0[e] == u) w = h1[e];
+        else if (h1[e] == u) w = h0[e];
+        else continue;
+        if (comp[w] < 0) {
+          comp[w] = (int)n_comp;
+          stack[top++] = w;
+        }
+      }
+    }
+    nodes_in[n_comp] = count;
+    edges_in[n_comp] = 0;
+    ++n_comp;
+  }
+  for (uint32_t e = 0; e < n_edges; ++e) edges_in[comp[h0[e]]] += 1;
+  for (uint32_t c = 0; c < n_comp; ++c)
+    if (edges_in[c] > nodes_in[c]) return 0;
+  return 1;
+}
+
+/* Canonical (smallest-mask) orientation.  Keys forced by the structure come
+ * first: a free cell with exactly one unplaced incident key must take that key
+ * (the peeling of Section 5's proof).  What is left is a set of disjoint
+ * cycles, each with two valid directions; the highest-index unplaced key takes
+ * its h0 slot, which fixes its cycle's direction, and peeling resumes. */
+int shock_oracle_orientation(uint32_t n, const uint32_t *h0, const uint32_t *h1, uint64_t *f_out) {
+  int deg[64], used[64], placed[64];
+  uint32_t queue[64 * 4];
+  uint32_t head = 0, tail = 0, n_placed = 0;
+  uint64_t f = 0;
+  if (n > 64) return SHOCK_ORACLE_EINVAL;
+  for (uint32_t c = 0; c < n; ++c) {
+    deg[c] = 0;
+    used[c] = 0;
+  }
+  for (uint32_t k = 0; k < n; ++k) {
+    placed[k] = 0;
+    deg[h0[k]] += 1;
+    if (h1[k] != h0[k]) deg[h1[k]] += 1;
+  }
+  for (uint32_t c = 0; c < n; ++c)
+    if (deg[c] == 1) queue[tail++] = c;
+
+  for (;;) {
+    while (head < tail) {
+      uint32_t c = queue[head++];
+      if (used[c] || deg[c] != 1) continue;
+      uint32_t k = n;
+      for (uint32_t e = 0; e < n; ++e)
+        if (!placed[e] && (h0[e] == c || h1[e] == c)) {
+          k = e;
+          break;
+        }
+      if (k == n) return SHOCK_ORACLE_EINVAL;
+      if (h0[k] != c) f |= 1ULL << k;
+      used[c] = 1;
+      placed[k] = 1;
+      ++n_placed;
+      deg[h0[k]] -= 1;
+      if (h1[k] != h0[k]) deg[h1[k]] -= 1;
+      uint32_t other = (h0[k] == c) ? h1[k] : h0[k];
+      if (!used[other] && deg[other] == 1) {
+        if (tail >= sizeof(queue) / sizeof(queue[0])) return SHOCK_ORACLE_EINVAL;
+        queue[tail++] = other;
+      }
+    }
+    if (n_placed == n) break;
+    /* Only cycles remain: the highest-index unplaced key takes h0. */
+    uint32_t m = n;
+    for (uint32_t e = n; e-- > 0;)
+      if (!placed[e]) {
+        m = e;
+        break;
+      }
+    uint32_t c = h0[m];
+    if (used[c]) return SHOCK_ORACLE_EINVAL;
+    used[c] = 1;
+    placed[m] = 1;
+    ++n_placed;
+    deg[h0[m]] -= 1;
+    if (h1[m] != h0[m]) deg[h1[m]] -= 1;
+    if (!used[h1[m]] && deg[h1[m]] == 1) {
+      if (tail >= sizeof(queue) / sizeof(queue[0])) return SHOCK_ORACLE_EINVAL;
+      queue[tail++] = h1[m];
+    }
+  }
+  /* The choice must be a bijection onto [0, n). */
+  {
+    uint64_t hit = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+      uint32_t slot = ((f >> k) & 1) ? h1[k] : h0[k];
+      if ((hit >> slot) & 1) return SHOCK_ORACLE_EINVAL;
+      hit |= 1ULL << slot;
+    }
+  }
+  *f_out = f;
+  return SHOCK_ORACLE_OK;
+}
+
+static uint64_t full_mask(uint32_t n) { return n >= 64 ? ~0ULL : ((1ULL << n) - 1); }
+
+int shock_oracle_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                             uint64_t *out_seeds, uint64_t *out_orient,
+                             uint64_t start_seed, uint64_t max_seed, int use_filter) {
+  if (n_leaves == 0) return SHOCK_ORACLE_OK;
+  if (offsets == NULL || out_seeds == NULL || out_orient == NULL) return SHOCK_ORACLE_EINVAL;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    if (offsets[j + 1] < offsets[j]) return SHOCK_ORACLE_EINVAL;
+    if (offsets[j + 1] - offsets[j] > 64) return SHOCK_ORACLE_EINVAL;
+  }
+  if (keys == NULL && offsets[n_leaves] != offsets[0]) return SHOCK_ORACLE_EINVAL;
+
+  int status = SHOCK_ORACLE_OK;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    uint32_t n = (uint32_t)(offsets[j + 1] - offsets[j]);
+    const uint64_t *x = keys + offsets[j];
+    uint32_t h0[64], h1[64];
+    int found = 0;
+    for (uint64_t s = start_seed; s < max_seed; ++s) {
+      for (uint32_t i = 0; i < n; ++i) shock_oracle_slots(x[i], s, n, &h0[i], &h1[i]);
+      if (use_filter) {
+        uint64_t cover = 0;
+        for (uint32_t i = 0; i < n; ++i) cover |= (1ULL << h0[i]) | (1ULL << h1[i]);
+        if (cover != full_mask(n)) continue;
+      }
+      if (shock_oracle_is_pseudoforest(n, n, h0, h1)) {
+        uint64_t f = 0;
+        if (shock_oracle_orientation(n, h0, h1, &f) != SHOCK_ORACLE_OK) return SHOCK_ORACLE_EINVAL;
+        out_seeds[j] = s;
+        out_orient[j] = f;
+        found = 1;
+        break;
+      }
+    }
+    if (!found) {
+      out_seeds[j] = UINT64_MAX;
+      out_orient[j] = 0;
+      status = SHOCK_ORACLE_ENOTFOUND;
+    }
+  }
+  return status;
+}
+
+void shock_oracle_seed_stats(const uint64_t *keys, uint32_t n, uint64_t s0, uint64_t count,
+                             uint64_t *n_cover, uint64_t *n_pseudoforest, uint64_t *n_h0_bijective) {
+  uint64_t cover_count = 0, pf_count = 0, bij_count = 0;
+  uint32_t h0[64], h1[64];
+  for (uint64_t s = s0; s < s0 + count; ++s) {
+    uint64_t cover = 0, first = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      shock_oracle_slots(keys[i], s, n, &h0[i], &h1[i]);
+      cover |= (1ULL << h0[i]) | (1ULL << h1[i]);
+      first |= 1ULL << h0[i];
+    }
+    if (first == full_mask(n)) ++bij_count;
+    if (cover != full_mask(n)) continue;
+    ++cover_count;
+    if (shock_oracle_is_pseudoforest(n, n, h0, h1)) ++pf_count;
+  }
+  *n_cover = cover_count;
+  *n_pseudoforest = pf_count;
+  *n_h0_bijective = bij_count;
+}

@@ -1,0 +1,95 @@
+/*
+ * CPU oracle for the ShockHash leaf seed search -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, single-threaded, slow and deliberately unoptimised C.  It exists to
+ * check the GPU library, never to serve it: only the tests, the smoke check
+ * and the benchmark's CPU-baseline leg load it.  It shares no code, header or
+ * table with the HIP path.
+ *
+ * What it computes (ShockHash, Section 4, the equation defining the seed):
+ * for a leaf S of n keys, the smallest seed s in N such that some choice
+ * f : S -> {0,1} makes x -> h_{f(x)}(x, s) a bijection onto [0, n), plus one
+ * such f.  By the equivalence of Section 5 (equation "pseudoforests-orientable")
+ * and the pseudoforest remark of Section 2, a seed qualifies exactly when the
+ * graph G_s = ([n], {{h0(x,s), h1(x,s)} : x in S}) is a pseudoforest, i.e. no
+ * connected component has more edges than nodes.  The oracle decides this by
+ * counting nodes and edges per component (a depth-first search), which is a
+ * different algorithm from the union-find test of Appendix A.1 used on the GPU.
+ *
+ * Hash functions (the paper assumes fully random h0, h1 evaluated on a 64-bit
+ * master hash code, Section 8 and the footnote on uniform hashing in Section 5;
+ * the concrete family below is this library's frozen choice):
+ *   fmix64(k)   : MurmurHash3's 64-bit finaliser (Appleby), a bijection on u64
+ *                 k ^= k>>33; k *= 0xff51afd7ed558ccd; k ^= k>>33;
+ *                 k *= 0xc4ceb9fe1a85ec53; k ^= k>>33
+ *   a(x)        = fmix64(x)                              (per key)
+ *   t(s)        = fmix64((s + 1) * 0x9E3779B97F4A7C15)   (per seed, mod 2^64)
+ *   c           = a(x) XOR t(s)
+ *   P           = lo32(c) * hi32(c)                      (exact 64-bit product)
+ *   z           = lo32(P) XOR hi32(P)
+ *   h0          = ((z mod 2^16) * n) >> 16
+ *   r           = ((z >> 16) * (n - 1)) >> 16            (r in [0, n-2])
+ *   h1          = r + (r >= h0 ? 1 : 0)  for n >= 2;  h1 = 0 for n = 1
+ * so h1 != h0 whenever n >= 2: the graph has no self-loops, which is the
+ * variant the paper's implementation uses (footnote in Section 5).
+ *
+ * Orientation returned with a seed: the numerically smallest n-bit mask f
+ * (bit i <-> i-th key of the leaf) for which i -> h_{f_i} is a bijection.
+ * Section 5 (equation "orientations-cycles") shows a pseudoforest with c
+ * components has exactly 2^c such f, differing only in the direction of each
+ * component's cycle; the smallest mask directs every cycle so that its
+ * highest-index key takes its h0 slot.
+ */
+#ifndef SHOCK_ORACLE_H
+#define SHOCK_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHOCK_ORACLE_OK 0
+#define SHOCK_ORACLE_EINVAL (-1)
+#define SHOCK_ORACLE_ENOTFOUND (-2)
+
+/* MurmurHash3 fmix64. */
+uint64_t shock_oracle_fmix64(uint64_t k);
+
+/* The two candidate slots of key x under seed s in a leaf of n keys (1 <= n <= 64). */
+void shock_oracle_slots(uint64_t x, uint64_t s, uint32_t n, uint32_t *h0, uint32_t *h1);
+
+/* 1 if the multigraph on [n] with edges {h0[i], h1[i]} (i < n_edges) has no
+ * component with more edges than nodes, else 0.  Self-loops and parallel
+ * edges are allowed.  n <= 64, n_edges <= 64. */
+int shock_oracle_is_pseudoforest(uint32_t n, uint32_t n_edges, const uint32_t *h0, const uint32_t *h1);
+
+/* Canonical orientation (smallest valid mask) of n edges on n nodes.  Returns
+ * SHOCK_ORACLE_OK and writes *f, or SHOCK_ORACLE_EINVAL if no bijective
+ * choice exists (the graph is not a pseudoforest). */
+int shock_oracle_orientation(uint32_t n, const uint32_t *h0, const uint32_t *h1, uint64_t *f);
+
+/* Leaf seed search over a CSR batch (HOST pointers).
+ *   keys[offsets[j] .. offsets[j+1]) are leaf j's keys, offsets has n_leaves+1
+ *   nondecreasing entries, every leaf has at most 64 keys.
+ *   Seeds start_seed, start_seed+1, ..., max_seed-1 are tried in order.
+ *   use_filter = 1 first rejects seeds whose slots do not cover all n cells
+ *   (Section 4, the bit-mask filter; a necessary condition, so results are
+ *   identical with use_filter = 0).
+ * Outputs: out_seeds[j] = smallest qualifying seed, out_orient[j] = its
+ * canonical orientation; a leaf with no qualifying seed below max_seed gets
+ * UINT64_MAX and 0.  Returns SHOCK_ORACLE_EINVAL (outputs untouched) on a
+ * malformed batch, SHOCK_ORACLE_ENOTFOUND if any leaf hit the cap, else OK. */
+int shock_oracle_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                             uint64_t *out_seeds, uint64_t *out_orient,
+                             uint64_t start_seed, uint64_t max_seed, int use_filter);
+
+/* Statistics helper: over seeds s0 .. s0+count-1 of one leaf of n keys, count
+ * the seeds whose slots cover all n cells and, among them, the pseudoforests.
+ * Also counts seeds where h0 alone is a bijection. */
+void shock_oracle_seed_stats(const uint64_t *keys, uint32_t n, uint64_t s0, uint64_t count,
+                             uint64_t *n_cover, uint64_t *n_pseudoforest, uint64_t *n_h0_bijective);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
