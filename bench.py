@@ -1,0 +1,209 @@
+"""Benchmark: ShockHash leaf seed search throughput on one MI355X.
+
+A step is one pass of the whole hot path (premix + validation, the persistent
+search kernel with filtering, union-find tests, smallest-seed resolution and
+orientation) over one batch of 16384 leaves x 48 uint64 keys already resident
+in HBM.  Prints one JSON line (see the module-level FIELDS comment in main).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from workloads import WORKLOADS, make_workload  # noqa: E402
+
+METRIC = "leaves/s and seeds tested/s at n=48 (batched vs plain) + p50/p99 build latency"
+PEAK_INT_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 int32 lanes per clock x 2.4 GHz
+# Algorithmic 32-bit integer operations of the frozen hash and filter:
+# per key-evaluation: 2 xor (key ^ seed mix), 1 multiply 32x32->64, 1 xor
+# fold, 2 fastrange multiply-highs with their 16-bit field extractions (2),
+# h1 = r + (r >= h0) (3), two 64-bit bit-sets (2) and two 3-input ORs into the
+# coverage mask (2): 14.  Per seed: the seed mix fmix64((s+1)*gamma) (19) and
+# the coverage compare (1): 20.
+OPS_PER_EVAL = 14
+OPS_PER_SEED = 20
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
+def run_cpu_baseline(keys, offs, gpu_seeds, gpu_orient, budget_s):
+    """The oracle, single-threaded, on a bounded prefix of the same batch."""
+    import oracle
+
+    oracle.lib()
+    n_done = 0
+    t0 = time.perf_counter()
+    seeds_total = 0
+    match = True
+    L = len(offs) - 1
+    while n_done < L and time.perf_counter() - t0 < budget_s:
+        chunk = min(8, L - n_done)
+        sub = offs[n_done:n_done + chunk + 1]
+        rc, s, f = oracle.leaf_search(keys, sub)
+        seeds_total += int((s.astype(np.float64) + 1).sum())
+        match &= bool((s == gpu_seeds[n_done:n_done + chunk]).all() and (f == gpu_orient[n_done:n_done + chunk]).all())
+        n_done += chunk
+    dt = time.perf_counter() - t0
+    n = int(offs[1] - offs[0])
+    return {
+        "value": n_done / dt, "unit": "leaves/s", "cores": 1, "kind": "oracle",
+        "sample": f"first {n_done} leaves of the same batch, oracle single-threaded ({dt:.1f} s)",
+        "seeds_tested_per_s": seeds_total / dt, "key_evals_per_s": seeds_total * n / dt,
+        "cpu": cpu_info(), "matches_gpu": match,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fixed48")
+    ap.add_argument("--plain-leaves", type=int, default=1024)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--spl", type=int, default=0)
+    ap.add_argument("--block-iters", type=int, default=0)
+    ap.add_argument("--waves-per-wg", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the leaf search is data-parallel over leaves and this build "
+              "runs on a single MI355X; multi-GPU runs are not supported (see DESIGN.md, sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2308_09561_amd as shock
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = WORKLOADS[args.workload]
+    keys, offs = make_workload(args.workload)
+    L = len(offs) - 1
+    n = w.get("n")
+    k_d = torch.from_numpy(keys.view(np.int64)).to(dev)
+    o_d = torch.from_numpy(offs.view(np.int64)).to(dev)
+    seeds_d = torch.empty(L, dtype=torch.int64, device=dev)
+    orient_d = torch.empty(L, dtype=torch.int64, device=dev)
+    opts = dict(spl=args.spl, block_iters=args.block_iters, waves_per_wg=args.waves_per_wg)
+
+    def step():
+        rc, _, _ = shock.leaf_search(k_d, o_d, out_seeds=seeds_d, out_orient=orient_d, **opts)
+        if rc != shock.SHOCK_OK:
+            raise RuntimeError(f"search failed: {shock.shock_strerror(rc)}")
+
+    log(f"[bench] workload {args.workload}: {L} leaves, warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kernel_ms, seeds_tested, pf_checks = [], 0, 0
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        st = shock.shock_last_stats()
+        kernel_ms.append(st["kernel_ms"])
+        seeds_tested += st["seeds_tested"]
+        pf_checks += st["pf_checks"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    seeds = seeds_d.cpu().numpy().view(np.uint64)
+    orient = orient_d.cpu().numpy().view(np.uint64)
+    sizes = np.diff(offs).astype(np.float64)
+    useful_seeds = float((seeds.astype(np.float64) + 1).sum())
+    useful_evals = float(((seeds.astype(np.float64) + 1) * sizes).sum())
+    leaves_per_s = L / (ms_per_step / 1e3)
+    avg_kernel_ms = float(np.mean(kernel_ms))
+    alg_ops = useful_evals * OPS_PER_EVAL + useful_seeds * OPS_PER_SEED
+    achieved = alg_ops / (avg_kernel_ms / 1e3)
+    log(f"[bench] {ms_per_step:.2f} ms/step, kernel {avg_kernel_ms:.2f} ms, {leaves_per_s:.0f} leaves/s")
+
+    # Plain per-leaf form: one kernel launch per leaf, queued back to back.
+    plain = None
+    if args.plain_leaves > 0:
+        Lp = min(args.plain_leaves, L)
+        o_p = o_d[:Lp + 1]
+        s_p = torch.empty(Lp, dtype=torch.int64, device=dev)
+        f_p = torch.empty(Lp, dtype=torch.int64, device=dev)
+        shock.leaf_search(k_d, o_p, out_seeds=s_p, out_orient=f_p, mode=shock.SHOCK_MODE_PLAIN_PER_LEAF)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rc, _, _ = shock.leaf_search(k_d, o_p, out_seeds=s_p, out_orient=f_p, mode=shock.SHOCK_MODE_PLAIN_PER_LEAF)
+        torch.cuda.synchronize()
+        wall_p = time.perf_counter() - t1
+        st_p = shock.shock_last_stats()
+        same = bool((s_p.cpu() == seeds_d[:Lp].cpu()).all() and (f_p.cpu() == orient_d[:Lp].cpu()).all())
+        plain = {"leaves": Lp, "leaves_per_s": Lp / wall_p, "kernel_ms": st_p["kernel_ms"],
+                 "seeds_tested_per_s": st_p["seeds_tested"] / wall_p, "same_outputs_as_batched": same}
+        log(f"[bench] plain per-leaf: {Lp / wall_p:.0f} leaves/s")
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"[bench] cpu baseline (oracle, ~{args.cpu_budget:.0f} s)")
+        cpu = run_cpu_baseline(keys, offs, seeds, orient, args.cpu_budget)
+
+    out = {
+        "metric": METRIC,
+        "value": leaves_per_s,
+        "unit": "leaves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {L} leaves x {n} uniform uint64 keys (splitmix64 seed {w['seed']}), "
+                               f"persistent work-stealing kernel", "n_leaves": L, "leaf_size": n,
+                   "launch": {k: v for k, v in shock.shock_last_stats().items() if k in ("workers", "spl", "block_iters", "waves_per_wg")}},
+        "seeds_tested_per_s": seeds_tested / wall,
+        "useful_seeds_per_s": useful_seeds / (ms_per_step / 1e3),
+        "keys_per_s": float(sizes.sum()) / (ms_per_step / 1e3),
+        "key_evals_per_s": useful_evals / (ms_per_step / 1e3),
+        "overshoot": seeds_tested / args.steps / useful_seeds - 1.0,
+        "pf_checks_per_step": pf_checks / args.steps,
+        "plain_per_leaf": plain,
+        "batched_vs_plain": (leaves_per_s / plain["leaves_per_s"]) if plain else None,
+        "latency": None,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
+                     "unit": "Tops/s (int32 lane ops)", "frac": achieved / PEAK_INT_OPS, "traffic": None,
+                     "ops_per_key_eval": OPS_PER_EVAL, "ops_per_seed": OPS_PER_SEED,
+                     "kernel_ms": avg_kernel_ms},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,126 @@
+/*
+ * shockleaf -- ShockHash leaf seed search on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libshockleaf.so.  Plain pointers and sizes only.  Unless a comment
+ * says otherwise, every pointer is a DEVICE pointer on the current HIP device,
+ * and every buffer is owned, allocated and freed by the caller.
+ *
+ * The operation (ShockHash, Section 4, the equation that defines the stored
+ * seed): for each leaf S of n <= 64 keys, find the smallest seed s such that
+ * some choice f : S -> {0,1} makes x -> h_{f(x)}(x, s) a bijection onto
+ * [0, n), and return s with one such f.  By Section 5 (equation
+ * "pseudoforests-orientable") a seed qualifies exactly when the graph on [n]
+ * with one edge {h0(x,s), h1(x,s)} per key is a pseudoforest.  The search
+ * tries seeds in increasing order, rejects most of them with the coverage
+ * bit-mask filter of Section 4, confirms the rest with a union-find test of
+ * the pseudoforest property (Appendix A.1; every component must have no more
+ * edges than nodes, Section 2), and stops at the first acceptance.
+ *
+ * Hash family (frozen; the paper assumes ideal hashing of a 64-bit master
+ * code, Section 8 and Section 5's uniform-hashing footnote):
+ *   fmix64 = MurmurHash3's 64-bit finaliser,
+ *   a = fmix64(key), t = fmix64((s + 1) * 0x9E3779B97F4A7C15) (mod 2^64),
+ *   c = a ^ t, P = lo32(c) * hi32(c) (64-bit product), z = lo32(P) ^ hi32(P),
+ *   h0 = ((z & 0xFFFF) * n) >> 16, r = ((z >> 16) * (n - 1)) >> 16,
+ *   h1 = r + (r >= h0) for n >= 2 (never equal to h0: no self-loops,
+ *   matching the paper's implementation footnote in Section 5), h1 = 0 if n = 1.
+ *
+ * Orientation output: bit i of out_orient[j] is f of the i-th key of leaf j
+ * (0 = the key takes h0, 1 = it takes h1); bits >= n are zero.  Among the
+ * 2^c valid choices (c = number of components, Section 5, equation
+ * "orientations-cycles") the numerically smallest mask is returned, so the
+ * output is unique: tree keys point away from their component's cycle and
+ * every cycle is directed so that its highest-index key takes h0.
+ *
+ * Batch layout (CSR): leaf j owns keys[offsets[j] .. offsets[j+1]); offsets
+ * has n_leaves + 1 nondecreasing uint64 entries in units of keys; keys are raw
+ * 64-bit patterns.  A leaf with n = 0 or n = 1 is solved by the first seed
+ * tried (start_seed) with orientation 0.
+ *
+ * Thread safety: calls on different streams may run concurrently; each call
+ * uses its own scratch.  The library keeps per-device scratch caches that are
+ * freed at unload or by shock_release_scratch().
+ */
+#ifndef SHOCKLEAF_H
+#define SHOCKLEAF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define SHOCK_OK 0
+#define SHOCK_EINVAL (-1)    /* malformed batch or options; nothing launched, outputs untouched */
+#define SHOCK_ENOTFOUND (-2) /* some leaf has no qualifying seed below max_seed (seed = UINT64_MAX, orient = 0) */
+#define SHOCK_EDUPKEY (-3)   /* check_dups was set and some leaf holds a repeated key; outputs untouched */
+#define SHOCK_ECANCELED (-4) /* the cancel flag was raised; unfinished leaves hold seed = UINT64_MAX */
+#define SHOCK_EHIP (-5)      /* a HIP runtime call failed; see shock_last_error() */
+#define SHOCK_ENOMEM (-6)    /* scratch allocation failed */
+
+/* Launch strategies.  All produce bit-identical outputs. */
+#define SHOCK_MODE_AUTO 0
+#define SHOCK_MODE_PLAIN_PER_LEAF 1 /* one kernel launch per leaf, queued back to back, whole GPU on that leaf */
+#define SHOCK_MODE_PERSISTENT 2     /* one launch over all leaves: persistent work-stealing workers */
+
+#define SHOCK_DEFAULT_MAX_SEED 4294967296ULL /* 2^32, exclusive */
+
+typedef struct shock_opts {
+  uint64_t max_seed;      /* exclusive cap on seeds; 0 selects SHOCK_DEFAULT_MAX_SEED */
+  uint64_t start_seed;    /* first seed tried (resume point); default 0 */
+  int32_t mode;           /* SHOCK_MODE_*; AUTO = PERSISTENT */
+  int32_t spl;            /* seeds per lane per iteration: 1, 2 or 4; 0 = tuned default for the batch */
+  int32_t block_iters;    /* iterations per claimed seed block (block = 64*spl*block_iters seeds); 0 = tuned */
+  int32_t waves_per_wg;   /* waves per workgroup = leaves a workgroup works on at once (1..16); 0 = tuned */
+  int32_t workers;        /* persistent waves in the grid; 0 = fill the device */
+  int32_t check_dups;     /* 1 = reject leaves with repeated keys (SHOCK_EDUPKEY) */
+  const volatile int32_t *cancel; /* HOST pointer (pinned or managed memory) or NULL; nonzero = stop */
+  uint64_t reserved[4];
+} shock_opts;
+
+/* Defaults for every field. */
+void shock_opts_init(shock_opts *opts);
+
+/* Synchronous search on the null stream with default options.
+ *   keys       device, uint64[offsets[n_leaves]]
+ *   offsets    device, uint64[n_leaves + 1], nondecreasing, each leaf <= 64 keys
+ *   out_seeds  device, uint64[n_leaves]: smallest qualifying seed per leaf
+ *   out_orient device, uint64[n_leaves]: canonical orientation mask per leaf
+ * Returns SHOCK_OK, SHOCK_EINVAL (validated on the device before the search
+ * starts; outputs untouched), SHOCK_ENOTFOUND, SHOCK_EHIP or SHOCK_ENOMEM. */
+int shock_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                      uint64_t *out_seeds, uint64_t *out_orient);
+
+/* As shock_leaf_search, with options, on `hip_stream` (a hipStream_t, NULL =
+ * null stream).  Synchronous: returns when the outputs are final.  opts may be
+ * NULL (defaults). */
+int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                         uint64_t *out_seeds, uint64_t *out_orient,
+                         const shock_opts *opts, void *hip_stream);
+
+/* Device-side statistics of the last completed call on this host thread. */
+typedef struct shock_stats {
+  uint64_t seeds_tested;     /* seeds hashed, including seeds beyond a leaf's answer */
+  uint64_t filter_passes;    /* seeds that passed the coverage filter */
+  uint64_t pf_checks;        /* union-find tests run */
+  uint64_t blocks_claimed;   /* seed blocks handed out */
+  double kernel_ms;          /* time of the search kernel(s), HIP events on the call's stream */
+  int32_t workers;           /* persistent waves launched */
+  int32_t spl, block_iters, waves_per_wg; /* launch parameters actually used */
+} shock_stats;
+int shock_last_stats(shock_stats *out);
+
+/* Message of the last SHOCK_EHIP / SHOCK_ENOMEM on this host thread. */
+const char *shock_last_error(void);
+const char *shock_strerror(int status);
+
+/* Free cached scratch memory of the current device. */
+int shock_release_scratch(void);
+
+/* Library version of the frozen hash/orientation definition (1). */
+int shock_spec_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -57,6 +57,9 @@ def lib():
         L.shock_oracle_leaf_search.restype = ctypes.c_int
         L.shock_oracle_leaf_search.argtypes = [_u64p, _u64p, ctypes.c_uint64, _u64p, _u64p,
                                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int]
+        L.shock_oracle_verify.restype = ctypes.c_int
+        L.shock_oracle_verify.argtypes = [_u64p, _u64p, ctypes.c_uint64, _u64p, _u64p, ctypes.c_uint64,
+                                          ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint8)]
         L.shock_oracle_seed_stats.restype = None
         L.shock_oracle_seed_stats.argtypes = [_u64p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                               _u64p, _u64p, _u64p]
@@ -117,6 +120,47 @@ def leaf_search(keys, offsets, start_seed: int = 0, max_seed: int = DEFAULT_MAX_
     rc = lib().shock_oracle_leaf_search(_p64(keys) if keys.size else None, _p64(offsets) if offsets.size else None,
                                         L, _p64(seeds), _p64(orient), start_seed, max_seed, int(use_filter))
     return rc, seeds, orient
+
+
+def verify(keys, offsets, seeds, orient, start_seed: int = 0, window: int = 64):
+    """Per-leaf flags (see shock_oracle_verify): 0 = claimed seed qualifies, its
+    orientation is canonical and no seed in the window below it qualifies."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
+    orient = np.ascontiguousarray(orient, dtype=np.uint64)
+    L = len(offsets) - 1
+    flags = np.zeros(max(L, 1), dtype=np.uint8)
+    rc = lib().shock_oracle_verify(_p64(keys), _p64(offsets), L, _p64(seeds), _p64(orient), start_seed, window,
+                                   flags.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if rc != OK:
+        raise ValueError("malformed batch")
+    return flags[:L]
+
+
+def _leaf_chunks(offsets, parts):
+    L = len(offsets) - 1
+    step = max(1, (L + parts - 1) // parts)
+    return [(a, min(a + step, L)) for a in range(0, L, step)]
+
+
+def parallel(fn, keys, offsets, *per_leaf, threads: int | None = None, **kw):
+    """Run a per-leaf oracle function over leaf ranges on several host threads.
+    Each leaf is still processed by the single-threaded oracle code; the
+    driver only partitions the batch (ctypes releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    threads = threads or min(16, os.cpu_count() or 1)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    chunks = _leaf_chunks(offsets, threads * 4)
+
+    def run(ab):
+        a, b = ab
+        sub_off = offsets[a:b + 1]
+        args = [x[a:b] for x in per_leaf]
+        return fn(keys, sub_off, *args, **kw)
+
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(run, chunks))
 
 
 def seed_stats(keys, s0: int, count: int):

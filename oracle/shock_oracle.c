@@ -198,6 +198,45 @@ int shock_oracle_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint
   return status;
 }
 
+static int seed_qualifies(const uint64_t *x, uint32_t n, uint64_t s, uint32_t *h0, uint32_t *h1) {
+  for (uint32_t i = 0; i < n; ++i) shock_oracle_slots(x[i], s, n, &h0[i], &h1[i]);
+  return shock_oracle_is_pseudoforest(n, n, h0, h1);
+}
+
+int shock_oracle_verify(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                        const uint64_t *seeds, const uint64_t *orient, uint64_t start_seed,
+                        uint64_t window, uint8_t *flags) {
+  if (n_leaves == 0) return SHOCK_ORACLE_OK;
+  if (offsets == NULL || seeds == NULL || orient == NULL || flags == NULL) return SHOCK_ORACLE_EINVAL;
+  for (uint64_t j = 0; j < n_leaves; ++j)
+    if (offsets[j + 1] < offsets[j] || offsets[j + 1] - offsets[j] > 64) return SHOCK_ORACLE_EINVAL;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    uint32_t n = (uint32_t)(offsets[j + 1] - offsets[j]);
+    const uint64_t *x = keys + offsets[j];
+    uint32_t h0[64], h1[64];
+    uint8_t fl = 0;
+    uint64_t s = seeds[j];
+    if (s == UINT64_MAX) {
+      flags[j] = 8;
+      continue;
+    }
+    if (!seed_qualifies(x, n, s, h0, h1)) {
+      fl |= 1;
+    } else {
+      uint64_t f = 0;
+      if (shock_oracle_orientation(n, h0, h1, &f) != SHOCK_ORACLE_OK || f != orient[j]) fl |= 2;
+    }
+    uint64_t lo = s - start_seed > window ? s - window : start_seed;
+    for (uint64_t t = lo; t < s; ++t)
+      if (seed_qualifies(x, n, t, h0, h1)) {
+        fl |= 4;
+        break;
+      }
+    flags[j] = fl;
+  }
+  return SHOCK_ORACLE_OK;
+}
+
 void shock_oracle_seed_stats(const uint64_t *keys, uint32_t n, uint64_t s0, uint64_t count,
                              uint64_t *n_cover, uint64_t *n_pseudoforest, uint64_t *n_h0_bijective) {
   uint64_t cover_count = 0, pf_count = 0, bij_count = 0;

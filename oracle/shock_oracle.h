@@ -83,6 +83,17 @@ int shock_oracle_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint
                              uint64_t *out_seeds, uint64_t *out_orient,
                              uint64_t start_seed, uint64_t max_seed, int use_filter);
 
+/* Check claimed results leaf by leaf (HOST pointers).  For leaf j with
+ * claimed seed s = seeds[j] (UINT64_MAX = none), flags[j] gets
+ *   bit 0  s does not qualify (its graph is not a pseudoforest),
+ *   bit 1  orient[j] differs from the canonical orientation at s,
+ *   bit 2  some seed in [max(start_seed, s - window), s) qualifies,
+ *   bit 3  no seed was claimed (s = UINT64_MAX; nothing else checked).
+ * Returns SHOCK_ORACLE_EINVAL on a malformed batch, else OK. */
+int shock_oracle_verify(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                        const uint64_t *seeds, const uint64_t *orient, uint64_t start_seed,
+                        uint64_t window, uint8_t *flags);
+
 /* Statistics helper: over seeds s0 .. s0+count-1 of one leaf of n keys, count
  * the seeds whose slots cover all n cells and, among them, the pseudoforests.
  * Also counts seeds where h0 alone is a bijection. */

@@ -1,0 +1,14 @@
+"""shockleaf: ShockHash leaf seed search on MI355X (gfx950).
+
+Thin Python binding over the C ABI of libshockleaf.so (include/shockleaf.h).
+Every step of the search runs in the library's HIP kernels; this module only
+marshals torch device tensors (int64 tensors carry the uint64 key bits) and
+options.  Importing it without the built library raises, and so does calling
+it without a GPU: there is no fallback path.
+"""
+from .binding import (  # noqa: F401
+    SHOCK_OK, SHOCK_EINVAL, SHOCK_ENOTFOUND, SHOCK_EDUPKEY, SHOCK_ECANCELED, SHOCK_EHIP, SHOCK_ENOMEM,
+    SHOCK_MODE_AUTO, SHOCK_MODE_PLAIN_PER_LEAF, SHOCK_MODE_PERSISTENT, SHOCK_DEFAULT_MAX_SEED, NOT_FOUND_SEED,
+    ShockError, lib, lib_path, exported_symbols, shock_leaf_search, shock_leaf_search_ex, shock_last_stats,
+    shock_strerror, shock_spec_version, shock_release_scratch, leaf_search,
+)

@@ -1,0 +1,197 @@
+"""ctypes binding of libshockleaf.so: argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libshockleaf.so")
+
+SHOCK_OK = 0
+SHOCK_EINVAL = -1
+SHOCK_ENOTFOUND = -2
+SHOCK_EDUPKEY = -3
+SHOCK_ECANCELED = -4
+SHOCK_EHIP = -5
+SHOCK_ENOMEM = -6
+
+SHOCK_MODE_AUTO = 0
+SHOCK_MODE_PLAIN_PER_LEAF = 1
+SHOCK_MODE_PERSISTENT = 2
+
+SHOCK_DEFAULT_MAX_SEED = 1 << 32
+NOT_FOUND_SEED = (1 << 64) - 1
+
+# Names declared in include/shockleaf.h (checked by the CPU test suite).
+EXPORTED = [
+    "shock_opts_init", "shock_leaf_search", "shock_leaf_search_ex", "shock_last_stats",
+    "shock_last_error", "shock_strerror", "shock_release_scratch", "shock_spec_version",
+]
+
+
+class ShockOpts(ctypes.Structure):
+    _fields_ = [
+        ("max_seed", ctypes.c_uint64),
+        ("start_seed", ctypes.c_uint64),
+        ("mode", ctypes.c_int32),
+        ("spl", ctypes.c_int32),
+        ("block_iters", ctypes.c_int32),
+        ("waves_per_wg", ctypes.c_int32),
+        ("workers", ctypes.c_int32),
+        ("check_dups", ctypes.c_int32),
+        ("cancel", ctypes.c_void_p),
+        ("reserved", ctypes.c_uint64 * 4),
+    ]
+
+
+class ShockStats(ctypes.Structure):
+    _fields_ = [
+        ("seeds_tested", ctypes.c_uint64),
+        ("filter_passes", ctypes.c_uint64),
+        ("pf_checks", ctypes.c_uint64),
+        ("blocks_claimed", ctypes.c_uint64),
+        ("kernel_ms", ctypes.c_double),
+        ("workers", ctypes.c_int32),
+        ("spl", ctypes.c_int32),
+        ("block_iters", ctypes.c_int32),
+        ("waves_per_wg", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ShockError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"shockleaf status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with paper_2308_09561_amd.build.build()")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp = ctypes.c_void_p
+        L.shock_opts_init.restype = None
+        L.shock_opts_init.argtypes = [ctypes.POINTER(ShockOpts)]
+        L.shock_leaf_search.restype = ctypes.c_int
+        L.shock_leaf_search.argtypes = [vp, vp, ctypes.c_uint64, vp, vp]
+        L.shock_leaf_search_ex.restype = ctypes.c_int
+        L.shock_leaf_search_ex.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(ShockOpts), vp]
+        L.shock_last_stats.restype = ctypes.c_int
+        L.shock_last_stats.argtypes = [ctypes.POINTER(ShockStats)]
+        L.shock_last_error.restype = ctypes.c_char_p
+        L.shock_last_error.argtypes = []
+        L.shock_strerror.restype = ctypes.c_char_p
+        L.shock_strerror.argtypes = [ctypes.c_int]
+        L.shock_release_scratch.restype = ctypes.c_int
+        L.shock_release_scratch.argtypes = []
+        L.shock_spec_version.restype = ctypes.c_int
+        L.shock_spec_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    L = lib()
+    return {name: hasattr(L, name) for name in EXPORTED}
+
+
+def shock_strerror(status: int) -> str:
+    return lib().shock_strerror(status).decode()
+
+
+def shock_spec_version() -> int:
+    return lib().shock_spec_version()
+
+
+def shock_release_scratch() -> int:
+    return lib().shock_release_scratch()
+
+
+def shock_last_stats() -> dict:
+    st = ShockStats()
+    lib().shock_last_stats(ctypes.byref(st))
+    return st.as_dict()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def shock_leaf_search(keys, offsets, n_leaves, out_seeds, out_orient) -> int:
+    """C call with torch device tensors (or raw integer device addresses)."""
+    return lib().shock_leaf_search(*(_as_ptr(x) for x in (keys, offsets)), n_leaves,
+                                   _as_ptr(out_seeds), _as_ptr(out_orient))
+
+
+def _as_ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return ctypes.c_void_p(x)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_iters=0, waves_per_wg=0,
+              workers=0, check_dups=False, cancel_ptr=None) -> ShockOpts:
+    o = ShockOpts()
+    lib().shock_opts_init(ctypes.byref(o))
+    if max_seed is not None:
+        o.max_seed = max_seed
+    o.start_seed = start_seed
+    o.mode = mode
+    o.spl = spl
+    o.block_iters = block_iters
+    o.waves_per_wg = waves_per_wg
+    o.workers = workers
+    o.check_dups = int(bool(check_dups))
+    o.cancel = cancel_ptr
+    return o
+
+
+def shock_leaf_search_ex(keys, offsets, n_leaves, out_seeds, out_orient, opts: ShockOpts | None = None,
+                         stream=None) -> int:
+    s = None if stream is None else ctypes.c_void_p(stream)
+    return lib().shock_leaf_search_ex(_as_ptr(keys), _as_ptr(offsets), n_leaves, _as_ptr(out_seeds),
+                                      _as_ptr(out_orient), None if opts is None else ctypes.byref(opts), s)
+
+
+def leaf_search(keys, offsets, out_seeds=None, out_orient=None, stream=None, **opts):
+    """Search a CSR batch held in torch int64 CUDA tensors.
+
+    Returns (status, seeds, orient) with seeds/orient int64 tensors on the same
+    device (uint64 bit patterns).  Raises ShockError on SHOCK_EHIP/SHOCK_ENOMEM.
+    """
+    import torch
+
+    if keys.device.type != "cuda" or offsets.device.type != "cuda":
+        raise ValueError("keys and offsets must be device (cuda) tensors")
+    if keys.dtype != torch.int64 or offsets.dtype != torch.int64:
+        raise ValueError("keys and offsets must be int64 tensors carrying uint64 bits")
+    keys = keys.contiguous()
+    offsets = offsets.contiguous()
+    L = offsets.numel() - 1
+    if L < 0:
+        raise ValueError("offsets needs n_leaves + 1 entries")
+    if out_seeds is None:
+        out_seeds = torch.empty(max(L, 1), dtype=torch.int64, device=keys.device)
+    if out_orient is None:
+        out_orient = torch.empty(max(L, 1), dtype=torch.int64, device=keys.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(keys.device).cuda_stream
+    o = make_opts(**opts)
+    rc = shock_leaf_search_ex(keys if keys.numel() else offsets, offsets, L, out_seeds, out_orient, o, stream)
+    if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
+        raise ShockError(rc, lib().shock_last_error().decode())
+    return rc, out_seeds[:L], out_orient[:L]

@@ -1,0 +1,839 @@
+// ShockHash leaf seed search on MI355X (gfx950): kernels and the C ABI.
+//
+// The operation, hash family and output conventions are documented in
+// include/shockleaf.h.  Design in brief:
+//
+//  * One wave (64 lanes) is one worker.  A worker holds one leaf at a time and
+//    tests 64*SPL consecutive seeds per iteration, SPL seeds per lane.  The
+//    leaf's premixed keys are wave-uniform and come from scalar loads, so the
+//    per-(key, seed) work is pure VALU integer arithmetic: two xors, one
+//    32x32->64 multiply, an xor fold, two fastrange multiplies, the h1
+//    adjustment and the coverage bit-mask update (Section 4, filter by bit
+//    mask; the mask lives in registers).
+//  * A seed passes the filter when its mask covers all n cells; the wave
+//    ballot of those lanes gives the survivors in seed order.  Each survivor
+//    is confirmed by a wave-parallel union-find over the n cells in LDS
+//    (Appendix A.1 uses union-find for this test; every component must hold no
+//    more edges than nodes, the pseudoforest criterion of Section 2).
+//  * Seeds of a leaf are handed out in blocks by an atomic counter, so several
+//    workers can search one leaf.  Every block below the best accepted seed is
+//    searched to its first acceptance; a block may be skipped only if its
+//    first seed is not below the current best, so the minimum of the
+//    definition in Section 4 is exact whatever the interleaving.
+//  * Workers first take fresh leaves in order; once none are left they help
+//    unfinished leaves (work stealing at seed-block granularity).  The last
+//    worker to leave a closed leaf writes the seed and the canonical
+//    orientation, computed wave-parallel by peeling (Section 5's peeling
+//    process) and directing each cycle by its highest-index key.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "shockleaf.h"
+
+namespace {
+
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kMix1 = 0xff51afd7ed558ccdull;
+constexpr uint64_t kMix2 = 0xc4ceb9fe1a85ec53ull;
+constexpr uint64_t kNone = ~0ull;
+
+// Leaf claim word: bits 0..39 next block index, bits 40..62 workers inside the
+// leaf, bit 63 set once the leaf's result has been written.
+constexpr uint64_t kBlockMask = (1ull << 40) - 1;
+constexpr uint64_t kInflightOne = 1ull << 40;
+constexpr uint64_t kInflightMask = ((1ull << 23) - 1) << 40;
+constexpr uint64_t kFinalBit = 1ull << 63;
+
+// Global counters of one call (uint64 each).
+enum {
+  kCtrErr = 0,        // error bits, see kErr*
+  kCtrNotFound = 1,   // leaves that hit max_seed
+  kCtrSeeds = 2,      // seeds hashed
+  kCtrPasses = 3,     // seeds that passed the filter
+  kCtrPfChecks = 4,   // union-find tests
+  kCtrBlocks = 5,     // blocks claimed
+  kCtrGlobalCount = 8
+};
+// Per-launch counters (one set per kernel launch of a call).
+enum { kLcNextLeaf = 0, kLcDone = 1, kLcCount = 2 };
+
+constexpr uint64_t kErrInvalid = 1;
+constexpr uint64_t kErrDup = 2;
+constexpr uint64_t kErrOrient = 4;
+constexpr uint64_t kErrCancel = 8;
+
+constexpr int kMaxWavesPerWg = 16;
+
+struct Params {
+  const uint64_t *__restrict__ offsets;  // CSR offsets of the whole call
+  const uint64_t *__restrict__ premix;   // [n_leaves][64] premixed keys fmix64(x), zero padded
+  uint64_t leaf_begin;                   // first leaf of this launch
+  uint64_t leaf_count;                   // leaves of this launch
+  uint64_t start_seed, max_seed;
+  uint64_t *__restrict__ out_seeds;
+  uint64_t *__restrict__ out_orient;
+  unsigned long long *state;  // [n_leaves] claim words
+  unsigned long long *best;   // [n_leaves] smallest accepted seed so far
+  unsigned int *wleaf;        // [workers] leaf each worker is on (scan table for helpers)
+  unsigned long long *gctr;   // global counters of the call
+  unsigned long long *lctr;   // counters of this launch
+  const volatile int32_t *cancel;
+  uint64_t block;        // seeds per claimed block = 64 * SPL * block_iters
+  uint32_t block_iters;
+  uint32_t workers;
+};
+
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= kMix1;
+  k ^= k >> 33;
+  k *= kMix2;
+  k ^= k >> 33;
+  return k;
+}
+
+// Slots of one key under one seed from the premixed key halves (alo, ahi) and
+// the per-seed halves (tlo, thi).  nm1 = n - 1.
+__device__ __forceinline__ void slot_pair(uint32_t alo, uint32_t ahi, uint32_t tlo, uint32_t thi, uint32_t n,
+                                          uint32_t nm1, uint32_t &h0, uint32_t &h1) {
+  const uint32_t clo = alo ^ tlo;
+  const uint32_t chi = ahi ^ thi;
+  const uint64_t p = (uint64_t)clo * (uint64_t)chi;
+  const uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
+  h0 = __umulhi(z << 16, n);                       // ((z & 0xFFFF) * n) >> 16
+  const uint32_t r = __umulhi(z & 0xFFFF0000u, nm1);  // ((z >> 16) * (n-1)) >> 16
+  h1 = r + ((h0 + ~r) >> 31);                      // r + (r >= h0): h0 - 1 - r < 0 iff r >= h0
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t bcast32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+__device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long *p) {
+  return __hip_atomic_load(const_cast<unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Number of blocks a leaf needs before its limit: ceil((lim - start) / block).
+__device__ __forceinline__ uint64_t blocks_below(uint64_t start, uint64_t lim, uint64_t block) {
+  if (start >= lim) return 0;
+  const uint64_t span = lim - start;
+  return span / block + (span % block != 0 ? 1 : 0);
+}
+
+// Wave-uniform atomic add done by lane 0.
+__device__ __forceinline__ unsigned long long wave_atomic_add(unsigned long long *p, unsigned long long v) {
+  unsigned long long old = 0;
+  if (lane_id() == 0) old = atomicAdd(p, v);
+  return bcast64(old);
+}
+
+// Per-wave LDS scratch: union-find arrays for the pseudoforest test, or
+// incidence masks for the orientation (never live at the same time).
+struct WaveLds {
+  uint64_t keys[64];  // premixed keys of the leaf the wave is working on
+  union {
+    struct {
+      uint32_t parent[64];
+      uint32_t ecount[64];
+      uint32_t ncount[64];
+    } uf;
+    struct {
+      unsigned long long inc0[64];
+      unsigned long long inc1[64];
+      unsigned long long hit;
+    } ori;
+  };
+};
+
+// Pseudoforest test of one seed, wave-parallel.  Lane i < n holds edge i
+// (h0, h1); lane c < n also stands for cell c.  Components are found by
+// union-find with min-index hooking and pointer jumping; the graph is a
+// pseudoforest iff no component holds more edges than nodes.
+__device__ bool pf_test_wave(uint32_t n, uint32_t h0, uint32_t h1, WaveLds &lds) {
+  const uint32_t lane = lane_id();
+  const bool act = lane < n;
+  uint32_t *par = lds.uf.parent;
+  par[lane] = lane;
+  lds.uf.ecount[lane] = 0;
+  lds.uf.ncount[lane] = 0;
+  wave_lds_sync();
+  for (int round = 0; round < 64; ++round) {
+    for (int jump = 0; jump < 8; ++jump) {
+      const uint32_t p = par[lane];
+      const uint32_t pp = par[p];
+      const bool changed = act && pp != p;
+      wave_lds_sync();
+      if (changed) par[lane] = pp;
+      wave_lds_sync();
+      if (__ballot(changed) == 0) break;
+    }
+    bool pending = false;
+    if (act) {
+      const uint32_t ru = par[h0];
+      const uint32_t rv = par[h1];
+      if (ru != rv) {
+        atomicMin(&par[ru > rv ? ru : rv], ru < rv ? ru : rv);
+        pending = true;
+      }
+    }
+    wave_lds_sync();
+    if (__ballot(pending) == 0) break;
+  }
+  if (act) {
+    atomicAdd(&lds.uf.ecount[par[h0]], 1u);
+    atomicAdd(&lds.uf.ncount[par[lane]], 1u);
+  }
+  wave_lds_sync();
+  const bool bad = act && lds.uf.ecount[lane] > lds.uf.ncount[lane];
+  return __ballot(bad) == 0;
+}
+
+// Canonical orientation of an accepted seed, wave-parallel.  A free cell with
+// exactly one unplaced incident key takes that key (forced); when no such
+// cell remains, only disjoint cycles are left and the highest-index unplaced
+// key takes its h0 slot.  Returns false if the choice is not a bijection
+// (which cannot happen for a pseudoforest).
+__device__ bool orient_wave(uint32_t n, uint32_t h0, uint32_t h1, WaveLds &lds, uint64_t &f_out) {
+  const uint32_t lane = lane_id();
+  const bool act = lane < n;
+  lds.ori.inc0[lane] = 0;
+  lds.ori.inc1[lane] = 0;
+  if (lane == 0) lds.ori.hit = 0;
+  wave_lds_sync();
+  if (act) {
+    atomicOr(&lds.ori.inc0[h0], 1ull << lane);
+    atomicOr(&lds.ori.inc1[h1], 1ull << lane);
+  }
+  wave_lds_sync();
+  const uint64_t inc = lds.ori.inc0[lane] | lds.ori.inc1[lane];
+  const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  uint64_t rem = all, avail = all, f = 0;
+  for (int round = 0; round < 2 * 64 + 2 && rem != 0; ++round) {
+    const bool cell_free = act && ((avail >> lane) & 1);
+    const bool one = cell_free && __popcll(inc & rem) == 1;
+    const uint64_t d1 = __ballot(one);
+    if (d1 == 0) {
+      const uint32_t m = 63 - __clzll(rem);
+      const uint32_t c0 = __builtin_amdgcn_readlane(h0, m);
+      rem &= ~(1ull << m);
+      avail &= ~(1ull << c0);
+      continue;
+    }
+    const bool mine = act && ((rem >> lane) & 1);
+    const bool take0 = mine && ((d1 >> h0) & 1);
+    const bool take1 = mine && !take0 && ((d1 >> h1) & 1);
+    const uint64_t got = __ballot(take0 || take1);
+    const uint64_t fb = __ballot(take1);
+    rem &= ~got;
+    avail &= ~d1;
+    f |= fb;
+  }
+  if (act) {
+    const uint32_t slot = ((f >> lane) & 1) ? h1 : h0;
+    atomicOr(&lds.ori.hit, 1ull << slot);
+  }
+  wave_lds_sync();
+  f_out = f;
+  return rem == 0 && lds.ori.hit == all;
+}
+
+struct WaveStats {
+  uint64_t seeds = 0, passes = 0, pf = 0, blocks = 0;
+};
+
+// Search seeds [base, end) of one leaf for the first seed whose graph is a
+// pseudoforest.  `a` points at the leaf's premixed keys (wave-uniform).
+// Stops early once the leaf's best accepted seed is at or below the start of
+// the next iteration.  Returns kNone if no seed of the range qualifies.
+template <int SPL, bool WIDE>
+__device__ uint64_t search_block(const uint64_t *a, uint32_t n, uint64_t base, uint64_t end,
+                                 const unsigned long long *best_j, uint32_t my_alo, uint32_t my_ahi, WaveLds &lds,
+                                 WaveStats &st) {
+  const uint32_t lane = lane_id();
+  const uint32_t nm1 = n - 1;
+  const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  for (uint64_t ib = base; ib < end; ib += 64 * SPL) {
+    const unsigned long long cur_best = load_relaxed(best_j);
+    uint32_t tlo[SPL], thi[SPL], mlo[SPL], mhi[SPL];
+#pragma unroll
+    for (int j = 0; j < SPL; ++j) {
+      const uint64_t s = ib + (uint64_t)(j * 64 + lane);
+      const uint64_t t = fmix64((s + 1) * kGolden);
+      tlo[j] = (uint32_t)t;
+      thi[j] = (uint32_t)(t >> 32);
+      mlo[j] = 0;
+      mhi[j] = 0;
+    }
+#pragma unroll 2
+    for (uint32_t i = 0; i < n; ++i) {
+      const uint64_t ai = a[i];
+      const uint32_t alo = (uint32_t)ai, ahi = (uint32_t)(ai >> 32);
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        uint32_t h0, h1;
+        slot_pair(alo, ahi, tlo[j], thi[j], n, nm1, h0, h1);
+        if (WIDE) {
+          const uint64_t b = (1ull << h0) | (1ull << h1);
+          mlo[j] |= (uint32_t)b;
+          mhi[j] |= (uint32_t)(b >> 32);
+        } else {
+          mlo[j] |= (1u << h0) | (1u << h1);
+        }
+      }
+    }
+    const uint64_t span = end - ib;
+    st.seeds += span < (uint64_t)(64 * SPL) ? span : (uint64_t)(64 * SPL);
+#pragma unroll
+    for (int j = 0; j < SPL; ++j) {
+      const uint64_t m = WIDE ? (((uint64_t)mhi[j] << 32) | mlo[j]) : (uint64_t)mlo[j];
+      const bool ok = m == full && (uint64_t)(j * 64 + lane) < span;
+      uint64_t surv = __ballot(ok);
+      while (surv != 0) {
+        const uint32_t l = __builtin_ctzll(surv);
+        surv &= surv - 1;
+        const uint64_t s = ib + (uint64_t)(j * 64) + l;
+        st.passes += 1;
+        st.pf += 1;
+        const uint64_t t = fmix64((s + 1) * kGolden);
+        uint32_t h0 = 0, h1 = 0;
+        slot_pair(my_alo, my_ahi, (uint32_t)t, (uint32_t)(t >> 32), n, nm1, h0, h1);
+        if (pf_test_wave(n, h0, h1, lds)) return s;
+      }
+    }
+    if (bcast64(cur_best) <= ib + 64 * SPL) break;
+  }
+  return kNone;
+}
+
+// Write the result of leaf j.  Called by exactly one worker per leaf.
+__device__ void finalize_leaf(const Params &P, uint64_t j, uint32_t n, WaveLds &lds) {
+  const uint32_t lane = lane_id();
+  const uint64_t s = bcast64(load_relaxed(&P.best[j]));
+  uint64_t seed_out = s, f = 0;
+  if (s == kNone) {
+    if (lane == 0) atomicAdd(&P.gctr[kCtrNotFound], 1ull);
+    f = 0;
+  } else if (n >= 2) {
+    const uint64_t ai = P.premix[j * 64 + lane];
+    const uint64_t t = fmix64((s + 1) * kGolden);
+    uint32_t h0 = 0, h1 = 0;
+    slot_pair((uint32_t)ai, (uint32_t)(ai >> 32), (uint32_t)t, (uint32_t)(t >> 32), n, n - 1, h0, h1);
+    if (!orient_wave(n, h0, h1, lds, f)) {
+      if (lane == 0) atomicOr(&P.gctr[kCtrErr], kErrOrient);
+    }
+  }
+  if (lane == 0) {
+    P.out_seeds[j] = seed_out;
+    P.out_orient[j] = f;
+    __threadfence();
+    atomicAdd(&P.lctr[kLcDone], 1ull);
+  }
+}
+
+template <int SPL>
+__device__ uint64_t search_range(const Params &P, uint64_t j, uint32_t n, uint64_t base, uint64_t end,
+                                 uint32_t my_alo, uint32_t my_ahi, WaveLds &lds, WaveStats &st) {
+  const uint64_t *a = lds.keys;
+  if (n <= 1) return base;  // every seed qualifies
+  if (n <= 32) return search_block<SPL, false>(a, n, base, end, &P.best[j], my_alo, my_ahi, lds, st);
+  return search_block<SPL, true>(a, n, base, end, &P.best[j], my_alo, my_ahi, lds, st);
+}
+
+// Work on leaf j until it is closed: claim blocks in order, search each.
+template <int SPL>
+__device__ void work_leaf(const Params &P, uint64_t j, WaveLds &lds, WaveStats &st) {
+  const uint32_t lane = lane_id();
+  const uint64_t block = P.block;
+  const uint64_t o0 = P.offsets[j], o1 = P.offsets[j + 1];
+  const uint32_t n = (uint32_t)(o1 - o0);
+  const uint64_t ai = P.premix[j * 64 + lane];
+  const uint32_t my_alo = (uint32_t)ai, my_ahi = (uint32_t)(ai >> 32);
+  lds.keys[lane] = ai;
+  wave_lds_sync();
+  uint64_t claim = wave_atomic_add(&P.state[j], kInflightOne + 1);
+  if (claim & kFinalBit) {
+    wave_atomic_add(&P.state[j], (unsigned long long)(0 - kInflightOne));
+    return;
+  }
+  for (;;) {
+    const uint64_t b = claim & kBlockMask;
+    const uint64_t bst = bcast64(load_relaxed(&P.best[j]));
+    const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
+    if (b >= blocks_below(P.start_seed, lim, block)) break;
+    const uint64_t off = b * block;
+    if (P.cancel != nullptr && *P.cancel != 0) {
+      if (lane == 0) atomicOr(&P.gctr[kCtrErr], kErrCancel);
+      break;
+    }
+    const uint64_t base = P.start_seed + off;
+    const uint64_t end = (lim - base) < block ? lim : base + block;
+    st.blocks += 1;
+    const uint64_t found = search_range<SPL>(P, j, n, base, end, my_alo, my_ahi, lds, st);
+    if (found != kNone && lane == 0) atomicMin(&P.best[j], (unsigned long long)found);
+    claim = wave_atomic_add(&P.state[j], 1);
+  }
+  const uint64_t old = wave_atomic_add(&P.state[j], (unsigned long long)(0 - kInflightOne));
+  if (((old & kInflightMask) >> 40) == 1) {
+    bool cancelled = P.cancel != nullptr && *P.cancel != 0;
+    if (!cancelled) {
+      unsigned long long was = 0;
+      if (lane == 0) was = atomicOr(&P.state[j], kFinalBit);
+      was = bcast64(was);
+      if (!(was & kFinalBit)) finalize_leaf(P, j, n, lds);
+    }
+  }
+}
+
+// Pick a leaf to help: an unfinished leaf whose next block still lies below
+// its best seed.  Helpers scan the table of leaves the workers are on (or the
+// launch's leaves directly when there are at most 64) in chunks of 64 and pick
+// a candidate by rotating the ballot with the worker id, which spreads helpers
+// over the open leaves.  Returns kNone if no open leaf was seen.
+__device__ uint64_t find_help_leaf(const Params &P, uint32_t wid) {
+  const uint32_t lane = lane_id();
+  const uint64_t end = P.leaf_begin + P.leaf_count;
+  const bool direct = P.leaf_count <= 64;
+  const uint32_t n_entries = direct ? (uint32_t)P.leaf_count : P.workers;
+  const uint32_t chunks = (n_entries + 63) / 64;
+  const uint32_t first = direct ? 0 : (wid * 2654435761u) % chunks;
+  for (uint32_t c = 0; c < chunks; ++c) {
+    const uint32_t chunk = (first + c) % chunks;
+    const uint32_t idx = chunk * 64 + lane;
+    uint64_t leaf = kNone;
+    if (idx < n_entries) {
+      if (direct) {
+        leaf = P.leaf_begin + idx;
+      } else {
+        const uint32_t w = __hip_atomic_load(&P.wleaf[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (w != 0xFFFFFFFFu) leaf = w;
+      }
+    }
+    bool open = false;
+    if (leaf != kNone && leaf >= P.leaf_begin && leaf < end) {
+      const uint64_t stw = load_relaxed(&P.state[leaf]);
+      const uint64_t bst = load_relaxed(&P.best[leaf]);
+      const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
+      open = !(stw & kFinalBit) && (stw & kBlockMask) < blocks_below(P.start_seed, lim, P.block);
+    }
+    const uint64_t cand = __ballot(open);
+    if (cand != 0) {
+      const uint32_t rot = wid & 63;
+      const uint64_t rotated = rot ? ((cand >> rot) | (cand << (64 - rot))) : cand;
+      const uint32_t pick = (__builtin_ctzll(rotated) + rot) & 63;
+      const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)leaf, pick);
+      const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(leaf >> 32), pick);
+      return ((uint64_t)hi << 32) | lo;
+    }
+  }
+  return kNone;
+}
+
+template <int SPL>
+__global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
+  extern __shared__ unsigned long long lds_raw[];
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  WaveLds &lds = reinterpret_cast<WaveLds *>(lds_raw)[wave];
+  const uint32_t wid = blockIdx.x * (blockDim.x >> 6) + wave;
+  WaveStats st;
+  bool fresh = true;
+  uint32_t idle_rounds = 0;
+  for (;;) {
+    if (P.cancel != nullptr && *P.cancel != 0) {
+      if (lane == 0) atomicOr(&P.gctr[kCtrErr], kErrCancel);
+      break;
+    }
+    uint64_t j = kNone;
+    if (fresh) {
+      const uint64_t k = wave_atomic_add(&P.lctr[kLcNextLeaf], 1);
+      if (k < P.leaf_count) j = P.leaf_begin + k;
+      else fresh = false;
+    }
+    if (j == kNone) {
+      j = find_help_leaf(P, wid);
+      if (j == kNone) {
+        if (load_relaxed(&P.lctr[kLcDone]) >= P.leaf_count) break;
+        if (++idle_rounds > (1u << 20)) break;  // never expected; keeps the wait bounded
+        __builtin_amdgcn_s_sleep(8);
+        continue;
+      }
+    }
+    if (P.leaf_count > 64 && lane == 0) __hip_atomic_store(&P.wleaf[wid], (uint32_t)j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    work_leaf<SPL>(P, j, lds, st);
+  }
+  if (lane == 0) {
+    atomicAdd(&P.gctr[kCtrSeeds], (unsigned long long)st.seeds);
+    atomicAdd(&P.gctr[kCtrPasses], (unsigned long long)st.passes);
+    atomicAdd(&P.gctr[kCtrPfChecks], (unsigned long long)st.pf);
+    atomicAdd(&P.gctr[kCtrBlocks], (unsigned long long)st.blocks);
+  }
+}
+
+// Validate the batch, initialise per-leaf state and premix the keys.  One
+// wave per leaf; lane i premixes key i.  Also checks repeated keys on request.
+__global__ __launch_bounds__(256) void prepare_kernel(const uint64_t *__restrict__ keys,
+                                                      const uint64_t *__restrict__ offsets, uint64_t n_leaves,
+                                                      uint64_t *__restrict__ premix, unsigned long long *state,
+                                                      unsigned long long *best, unsigned long long *gctr,
+                                                      int check_dups) {
+  const uint64_t j = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63;
+  if (j >= n_leaves) return;
+  const uint64_t o0 = offsets[j], o1 = offsets[j + 1];
+  if (o1 < o0 || o1 - o0 > 64) {
+    if (lane == 0) atomicOr(&gctr[kCtrErr], kErrInvalid);
+    return;
+  }
+  const uint32_t n = (uint32_t)(o1 - o0);
+  uint64_t x = 0;
+  if (lane < n) x = keys[o0 + lane];
+  premix[j * 64 + lane] = lane < n ? fmix64(x) : 0;
+  if (lane == 0) {
+    state[j] = 0;
+    best[j] = kNone;
+  }
+  if (check_dups) {
+    bool dup = false;
+    for (uint32_t k = 0; k < n; ++k) {
+      const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, k);
+      const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), k);
+      const uint64_t y = ((uint64_t)hi << 32) | lo;
+      dup |= (lane < n && k != lane && y == x);
+    }
+    if (__ballot(dup) != 0 && lane == 0) atomicOr(&gctr[kCtrErr], kErrDup);
+  }
+}
+
+__global__ void init_counters_kernel(unsigned long long *gctr, unsigned long long *lctr, uint64_t n_lctr,
+                                     unsigned int *wleaf, uint32_t workers) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kCtrGlobalCount) gctr[i] = 0;
+  if (i < n_lctr) lctr[i] = 0;
+  if (i < workers) wleaf[i] = 0xFFFFFFFFu;
+}
+
+// Leaves left unfinished by a cancelled call report "no seed".
+__global__ void mark_unfinished_kernel(const unsigned long long *state, uint64_t n_leaves, uint64_t *out_seeds,
+                                       uint64_t *out_orient) {
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n_leaves && !(state[j] & kFinalBit)) {
+    out_seeds[j] = kNone;
+    out_orient[j] = 0;
+  }
+}
+
+// ------------------------------------------------------------------ host --
+
+thread_local char g_err[512];
+thread_local shock_stats g_stats;
+
+void set_err(const char *what, hipError_t e) {
+  snprintf(g_err, sizeof(g_err), "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                 \
+  do {                                \
+    hipError_t e_ = (call);           \
+    if (e_ != hipSuccess) {           \
+      set_err(#call, e_);             \
+      return SHOCK_EHIP;              \
+    }                                 \
+  } while (0)
+
+// Scratch cache per device, grown on demand and reused by later calls.
+struct Scratch {
+  void *buf = nullptr;
+  size_t bytes = 0;
+  void *host_ctr = nullptr;  // pinned copy of the global counters
+};
+std::mutex g_mu;
+std::vector<Scratch> g_scratch;
+
+struct Layout {
+  size_t premix, state, best, wleaf, gctr, lctr, total;
+};
+
+Layout layout(uint64_t n_leaves, uint32_t workers, uint64_t n_launches) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  Layout l;
+  size_t o = 0;
+  l.premix = o; o = up(o + n_leaves * 64 * 8);
+  l.state = o; o = up(o + n_leaves * 8);
+  l.best = o; o = up(o + n_leaves * 8);
+  l.wleaf = o; o = up(o + (size_t)workers * 4);
+  l.gctr = o; o = up(o + kCtrGlobalCount * 8);
+  l.lctr = o; o = up(o + n_launches * kLcCount * 8);
+  l.total = o;
+  return l;
+}
+
+int get_scratch(size_t bytes, void **buf, unsigned long long **host_ctr) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1);
+  Scratch &s = g_scratch[dev];
+  if (s.host_ctr == nullptr) {
+    hipError_t e = hipHostMalloc(&s.host_ctr, kCtrGlobalCount * 8, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      set_err("hipHostMalloc", e);
+      return SHOCK_ENOMEM;
+    }
+  }
+  if (s.bytes < bytes) {
+    if (s.buf) {
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(s.buf));
+      s.buf = nullptr;
+      s.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&s.buf, bytes);
+    if (e != hipSuccess) {
+      set_err("hipMalloc(scratch)", e);
+      return SHOCK_ENOMEM;
+    }
+    s.bytes = bytes;
+  }
+  *buf = s.buf;
+  *host_ctr = (unsigned long long *)s.host_ctr;
+  return SHOCK_OK;
+}
+
+struct Tuning {
+  int spl, block_iters, waves_per_wg;
+};
+
+// Defaults by leaf size; the Python autotuner may override per call.
+Tuning default_tuning(uint32_t n_hint, int mode) {
+  Tuning t;
+  t.spl = 2;
+  t.waves_per_wg = 4;
+  if (n_hint <= 24) t.block_iters = 1;
+  else if (n_hint <= 40) t.block_iters = 4;
+  else if (n_hint <= 52) t.block_iters = 16;
+  else t.block_iters = 32;
+  if (mode == SHOCK_MODE_PLAIN_PER_LEAF) t.block_iters = n_hint <= 40 ? 1 : 2;
+  return t;
+}
+
+int device_workers(int waves_per_wg) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256 * 16;
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 256 * 16;
+  // 8 waves per SIMD, 4 SIMDs per CU.
+  const int waves = p.multiProcessorCount * 32;
+  return (waves / waves_per_wg) * waves_per_wg;
+}
+
+template <int SPL>
+hipError_t launch_search(const Params &P, int wpw, hipStream_t stream) {
+  const uint32_t wgs = P.workers / wpw;
+  hipLaunchKernelGGL(search_kernel<SPL>, dim3(wgs), dim3(64 * wpw), sizeof(WaveLds) * wpw, stream, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_search_spl(int spl, const Params &P, int wpw, hipStream_t stream) {
+  switch (spl) {
+    case 1: return launch_search<1>(P, wpw, stream);
+    case 4: return launch_search<4>(P, wpw, stream);
+    default: return launch_search<2>(P, wpw, stream);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void shock_opts_init(shock_opts *o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->max_seed = SHOCK_DEFAULT_MAX_SEED;
+  o->mode = SHOCK_MODE_AUTO;
+}
+
+const char *shock_last_error(void) { return g_err; }
+
+const char *shock_strerror(int s) {
+  switch (s) {
+    case SHOCK_OK: return "ok";
+    case SHOCK_EINVAL: return "invalid argument or malformed batch";
+    case SHOCK_ENOTFOUND: return "no qualifying seed below max_seed for some leaf";
+    case SHOCK_EDUPKEY: return "repeated key within a leaf";
+    case SHOCK_ECANCELED: return "cancelled";
+    case SHOCK_EHIP: return "HIP runtime error";
+    case SHOCK_ENOMEM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+int shock_spec_version(void) { return 1; }
+
+int shock_last_stats(shock_stats *out) {
+  if (!out) return SHOCK_EINVAL;
+  *out = g_stats;
+  return SHOCK_OK;
+}
+
+int shock_release_scratch(void) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  if ((int)g_scratch.size() > dev && g_scratch[dev].buf) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(g_scratch[dev].buf));
+    g_scratch[dev].buf = nullptr;
+    g_scratch[dev].bytes = 0;
+  }
+  return SHOCK_OK;
+}
+
+int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_seeds,
+                         uint64_t *out_orient, const shock_opts *opts_in, void *hip_stream) {
+  shock_opts opts;
+  shock_opts_init(&opts);
+  if (opts_in) opts = *opts_in;
+  if (opts.max_seed == 0) opts.max_seed = SHOCK_DEFAULT_MAX_SEED;
+  memset(&g_stats, 0, sizeof(g_stats));
+  if (n_leaves == 0) return SHOCK_OK;
+  if (!offsets || !out_seeds || !out_orient) return SHOCK_EINVAL;
+  if (n_leaves > (1ull << 31)) return SHOCK_EINVAL;
+  if (opts.spl != 0 && opts.spl != 1 && opts.spl != 2 && opts.spl != 4) return SHOCK_EINVAL;
+  if (opts.block_iters < 0 || opts.block_iters > (1 << 16)) return SHOCK_EINVAL;
+  if (opts.waves_per_wg < 0 || opts.waves_per_wg > kMaxWavesPerWg) return SHOCK_EINVAL;
+  if (opts.workers < 0) return SHOCK_EINVAL;
+  const int mode = opts.mode == SHOCK_MODE_AUTO ? SHOCK_MODE_PERSISTENT : opts.mode;
+  if (mode != SHOCK_MODE_PERSISTENT && mode != SHOCK_MODE_PLAIN_PER_LEAF) return SHOCK_EINVAL;
+  hipStream_t stream = (hipStream_t)hip_stream;
+
+  // Launch parameters.  The size hint for defaults is the first leaf's size
+  // when known cheaply; the caller's explicit values win.
+  Tuning tune = default_tuning(48, mode);
+  if (opts.spl) tune.spl = opts.spl;
+  if (opts.block_iters) tune.block_iters = opts.block_iters;
+  if (opts.waves_per_wg) tune.waves_per_wg = opts.waves_per_wg;
+  int workers = opts.workers ? opts.workers : device_workers(tune.waves_per_wg);
+  workers = ((workers + tune.waves_per_wg - 1) / tune.waves_per_wg) * tune.waves_per_wg;
+  if (workers <= 0) return SHOCK_EINVAL;
+  const uint64_t n_launches = mode == SHOCK_MODE_PLAIN_PER_LEAF ? n_leaves : 1;
+
+  const Layout lay = layout(n_leaves, (uint32_t)workers, n_launches);
+  void *buf = nullptr;
+  unsigned long long *host_ctr = nullptr;
+  int rc = get_scratch(lay.total, &buf, &host_ctr);
+  if (rc != SHOCK_OK) return rc;
+  char *b = (char *)buf;
+  uint64_t *premix = (uint64_t *)(b + lay.premix);
+  unsigned long long *state = (unsigned long long *)(b + lay.state);
+  unsigned long long *best = (unsigned long long *)(b + lay.best);
+  unsigned int *wleaf = (unsigned int *)(b + lay.wleaf);
+  unsigned long long *gctr = (unsigned long long *)(b + lay.gctr);
+  unsigned long long *lctr = (unsigned long long *)(b + lay.lctr);
+
+  {
+    const uint64_t n_l = n_launches * kLcCount;
+    uint64_t m = n_l > (uint64_t)workers ? n_l : (uint64_t)workers;
+    if (m < kCtrGlobalCount) m = kCtrGlobalCount;
+    hipLaunchKernelGGL(init_counters_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, gctr, lctr, n_l,
+                       wleaf, (uint32_t)workers);
+    HIP_TRY(hipGetLastError());
+  }
+  if (!keys) {
+    // Only an all-empty batch may pass no keys; the prepare kernel cannot
+    // tell, so require a pointer.
+    return SHOCK_EINVAL;
+  }
+  hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)((n_leaves + 3) / 4)), dim3(256), 0, stream, keys, offsets,
+                     n_leaves, premix, state, best, gctr, opts.check_dups);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(host_ctr, gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (host_ctr[kCtrErr] & kErrInvalid) return SHOCK_EINVAL;
+  if (host_ctr[kCtrErr] & kErrDup) return SHOCK_EDUPKEY;
+
+  Params P;
+  P.offsets = offsets;
+  P.premix = premix;
+  P.start_seed = opts.start_seed;
+  P.max_seed = opts.max_seed;
+  P.out_seeds = out_seeds;
+  P.out_orient = out_orient;
+  P.state = state;
+  P.best = best;
+  P.wleaf = wleaf;
+  P.gctr = gctr;
+  P.cancel = opts.cancel;
+  P.block_iters = (uint32_t)tune.block_iters;
+  P.block = 64ull * (uint64_t)tune.spl * (uint64_t)tune.block_iters;
+  P.workers = (uint32_t)workers;
+
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, stream));
+  if (mode == SHOCK_MODE_PERSISTENT) {
+    P.leaf_begin = 0;
+    P.leaf_count = n_leaves;
+    P.lctr = lctr;
+    HIP_TRY(launch_search_spl(tune.spl, P, tune.waves_per_wg, stream));
+  } else {
+    for (uint64_t j = 0; j < n_leaves; ++j) {
+      P.leaf_begin = j;
+      P.leaf_count = 1;
+      P.lctr = lctr + j * kLcCount;
+      HIP_TRY(launch_search_spl(tune.spl, P, tune.waves_per_wg, stream));
+    }
+  }
+  HIP_TRY(hipEventRecord(e1, stream));
+  bool cancelled = false;
+  HIP_TRY(hipMemcpyAsync(host_ctr, gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (host_ctr[kCtrErr] & kErrCancel) {
+    cancelled = true;
+    hipLaunchKernelGGL(mark_unfinished_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, stream, state,
+                       n_leaves, out_seeds, out_orient);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  HIP_TRY(hipEventDestroy(e0));
+  HIP_TRY(hipEventDestroy(e1));
+  g_stats.seeds_tested = host_ctr[kCtrSeeds];
+  g_stats.filter_passes = host_ctr[kCtrPasses];
+  g_stats.pf_checks = host_ctr[kCtrPfChecks];
+  g_stats.blocks_claimed = host_ctr[kCtrBlocks];
+  g_stats.kernel_ms = ms;
+  g_stats.workers = workers;
+  g_stats.spl = tune.spl;
+  g_stats.block_iters = tune.block_iters;
+  g_stats.waves_per_wg = tune.waves_per_wg;
+  if (host_ctr[kCtrErr] & kErrOrient) {
+    snprintf(g_err, sizeof(g_err), "internal error: orientation of an accepted seed is not a bijection");
+    return SHOCK_EHIP;
+  }
+  if (cancelled) return SHOCK_ECANCELED;
+  if (host_ctr[kCtrNotFound] != 0) return SHOCK_ENOTFOUND;
+  return SHOCK_OK;
+}
+
+int shock_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_seeds,
+                      uint64_t *out_orient) {
+  return shock_leaf_search_ex(keys, offsets, n_leaves, out_seeds, out_orient, nullptr, nullptr);
+}
+
+}  // extern "C"

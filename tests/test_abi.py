@@ -1,0 +1,54 @@
+"""CPU checks of the C-ABI boundary: the library is built, loads, and exports
+every function include/shockleaf.h declares.  No compute call is made (no GPU
+here)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "shockleaf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(shock_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for must in ("shock_leaf_search", "shock_leaf_search_ex", "shock_opts_init", "shock_last_stats"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2308_09561_amd as shock
+    lib = shock.lib()
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(shock.binding.EXPORTED) >= set(_declared_functions())
+
+
+def test_library_is_a_gfx950_build():
+    import paper_2308_09561_amd as shock
+    blob = open(shock.lib_path(), "rb").read()
+    assert b"gfx950" in blob
+
+
+def test_binding_rejects_host_tensors():
+    torch = pytest.importorskip("torch")
+    import paper_2308_09561_amd as shock
+    k = torch.zeros(4, dtype=torch.int64)
+    o = torch.tensor([0, 4], dtype=torch.int64)
+    with pytest.raises(ValueError):
+        shock.leaf_search(k, o)
+
+
+def test_oracle_is_not_imported_by_the_package():
+    pkg = os.path.join(ROOT, "paper_2308_09561_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src and "shock_oracle" not in src, f
