@@ -24,13 +24,14 @@ from workloads import WORKLOADS, make_workload  # noqa: E402
 
 METRIC = "leaves/s and seeds tested/s at n=48 (batched vs plain) + p50/p99 build latency"
 PEAK_INT_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 int32 lanes per clock x 2.4 GHz
-# Algorithmic 32-bit integer operations of the frozen hash and filter:
-# per key-evaluation: 2 xor (key ^ seed mix), 1 multiply 32x32->64, 1 xor
-# fold, 2 fastrange multiply-highs with their 16-bit field extractions (2),
-# h1 = r + (r >= h0) (3), two 64-bit bit-sets (2) and two 3-input ORs into the
-# coverage mask (2): 14.  Per seed: the seed mix fmix64((s+1)*gamma) (19) and
-# the coverage compare (1): 20.
-OPS_PER_EVAL = 14
+# Algorithmic 32-bit integer operations of the frozen hash and filter, counted
+# as the fewest gfx950 VALU instructions that compute them:
+# per key-evaluation: 2 xor (key ^ seed mix), 1 multiply 32x32->64, 2 fold +
+# 16-bit field extractions (xor with shift, xor with mask), 2 fastrange
+# multiply-highs, h1 = r + (r >= h0) (compare + add-with-carry), two 64-bit
+# bit-sets and two 3-input ORs into the coverage mask: 13.  Per seed: the seed
+# mix fmix64((s+1)*gamma) (19) and the coverage compare (1): 20.
+OPS_PER_EVAL = 13
 OPS_PER_SEED = 20
 
 
@@ -135,6 +136,7 @@ def main():
         pf_checks += st["pf_checks"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    launch = {k: v for k, v in st.items() if k in ("workers", "spl", "block_iters", "waves_per_wg")}
     ms_per_step = wall * 1e3 / args.steps
     seeds = seeds_d.cpu().numpy().view(np.uint64)
     orient = orient_d.cpu().numpy().view(np.uint64)
@@ -186,7 +188,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {L} leaves x {n} uniform uint64 keys (splitmix64 seed {w['seed']}), "
                                f"persistent work-stealing kernel", "n_leaves": L, "leaf_size": n,
-                   "launch": {k: v for k, v in shock.shock_last_stats().items() if k in ("workers", "spl", "block_iters", "waves_per_wg")}},
+                   "launch": launch},
         "seeds_tested_per_s": seeds_tested / wall,
         "useful_seeds_per_s": useful_seeds / (ms_per_step / 1e3),
         "keys_per_s": float(sizes.sum()) / (ms_per_step / 1e3),

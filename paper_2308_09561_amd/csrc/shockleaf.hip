@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -43,25 +44,30 @@ constexpr uint64_t kMix1 = 0xff51afd7ed558ccdull;
 constexpr uint64_t kMix2 = 0xc4ceb9fe1a85ec53ull;
 constexpr uint64_t kNone = ~0ull;
 
-// Leaf claim word: bits 0..39 next block index, bits 40..62 workers inside the
-// leaf, bit 63 set once the leaf's result has been written.
+// Leaf claim word: bits 0..39 next unclaimed unit (a unit is one iteration,
+// 64*SPL consecutive seeds), bits 40..62 workers inside the leaf, bit 63 set
+// once the leaf's result has been written.
 constexpr uint64_t kBlockMask = (1ull << 40) - 1;
 constexpr uint64_t kInflightOne = 1ull << 40;
 constexpr uint64_t kInflightMask = ((1ull << 23) - 1) << 40;
 constexpr uint64_t kFinalBit = 1ull << 63;
 
-// Global counters of one call (uint64 each).
+// Global counters of one call (uint64 each).  Atomics on one address
+// serialise (about 12 ns each on MI355X), so the statistics are spread over
+// kStatSlots slots that the host sums.
+constexpr int kStatSlots = 64;
 enum {
   kCtrErr = 0,        // error bits, see kErr*
   kCtrNotFound = 1,   // leaves that hit max_seed
-  kCtrSeeds = 2,      // seeds hashed
-  kCtrPasses = 3,     // seeds that passed the filter
-  kCtrPfChecks = 4,   // union-find tests
-  kCtrBlocks = 5,     // blocks claimed
-  kCtrGlobalCount = 8
+  kCtrStats = 8,      // kStatSlots x {seeds hashed, filter passes, union-find tests, blocks}
+  kCtrGlobalCount = 8 + kStatSlots * 4
 };
-// Per-launch counters (one set per kernel launch of a call).
-enum { kLcNextLeaf = 0, kLcDone = 1, kLcCount = 2 };
+enum { kStSeeds = 0, kStPasses = 1, kStPf = 2, kStBlocks = 3 };
+// Per-launch counters (one set per kernel launch of a call).  Single-leaf
+// launches count finished workgroups in kExitGroups group counters and one
+// top counter, so no address sees more than ~64 increments.
+constexpr int kExitGroups = 64;
+enum { kLcNextLeaf = 0, kLcDone = 1, kLcExitTop = 2, kLcExitGroups = 4, kLcCount = 4 + kExitGroups };
 
 constexpr uint64_t kErrInvalid = 1;
 constexpr uint64_t kErrDup = 2;
@@ -84,9 +90,11 @@ struct Params {
   unsigned long long *gctr;   // global counters of the call
   unsigned long long *lctr;   // counters of this launch
   const volatile int32_t *cancel;
-  uint64_t block;        // seeds per claimed block = 64 * SPL * block_iters
-  uint32_t block_iters;
+  uint64_t block;        // seeds per claimed block = 64 * SPL * block_iters (split launches)
+  uint64_t unit;         // seeds per claim unit = 64 * SPL
+  uint32_t block_iters;  // most units one claim takes
   uint32_t workers;
+  uint32_t split;  // 1: one leaf, static block striding over the workers (no claim atomics)
 };
 
 __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
@@ -106,12 +114,26 @@ __device__ __forceinline__ void slot_pair(uint32_t alo, uint32_t ahi, uint32_t t
   const uint32_t chi = ahi ^ thi;
   const uint64_t p = (uint64_t)clo * (uint64_t)chi;
   const uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
-  h0 = __umulhi(z << 16, n);                       // ((z & 0xFFFF) * n) >> 16
-  const uint32_t r = __umulhi(z & 0xFFFF0000u, nm1);  // ((z >> 16) * (n-1)) >> 16
-  h1 = r + ((h0 + ~r) >> 31);                      // r + (r >= h0): h0 - 1 - r < 0 iff r >= h0
+  uint32_t f0 = __umulhi(z << 16, n);            // ((z & 0xFFFF) * n) >> 16
+  uint32_t r = __umulhi(z & 0xFFFF0000u, nm1);    // ((z >> 16) * (n-1)) >> 16
+  // h1 = r + (r >= h0).  The empty asm statements hide the operands' origin
+  // so that the compare stays 32-bit (one v_cmp + one v_addc) instead of
+  // being widened to 64 bits for the later 64-bit shift.
+  asm("" : "+v"(f0));
+  asm("" : "+v"(r));
+  uint32_t f1 = r + (uint32_t)(r >= f0);
+  asm("" : "+v"(f1));
+  h0 = f0;
+  h1 = f1;
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// m |= a | b as one 3-input OR.  Written out because the compiler otherwise
+// reassociates the mask updates of unrolled keys into two-input ORs.
+__device__ __forceinline__ void or3_into(uint32_t &m, uint32_t a, uint32_t b) {
+  asm("v_or3_b32 %0, %0, %1, %2" : "+v"(m) : "v"(a), "v"(b));
+}
 
 __device__ __forceinline__ uint64_t bcast64(uint64_t v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -132,6 +154,22 @@ __device__ __forceinline__ uint64_t blocks_below(uint64_t start, uint64_t lim, u
   if (start >= lim) return 0;
   const uint64_t span = lim - start;
   return span / block + (span % block != 0 ? 1 : 0);
+}
+
+// Waves communicate only through device-scope atomics (claim words, best
+// seeds, counters); every other buffer a kernel reads was written by an
+// earlier kernel.  Ordering between a wave's atomics on different words comes
+// from waiting for each returning atomic before issuing the next: the
+// returned value is moved to scalar registers, which the hardware cannot do
+// before the atomic has been performed.  No cache write-back or invalidate
+// fences are needed.
+__device__ __forceinline__ void depend_on(uint64_t v) { asm volatile("" ::"s"(v) : "memory"); }
+
+// Lower *p to v if smaller; returns only after the update is performed.
+__device__ __forceinline__ void wave_atomic_min_wait(unsigned long long *p, uint64_t v) {
+  unsigned long long old = 0;
+  if (lane_id() == 0) old = atomicMin(p, (unsigned long long)v);
+  depend_on(bcast64(old));
 }
 
 // Wave-uniform atomic add done by lane 0.
@@ -278,23 +316,30 @@ __device__ uint64_t search_block(const uint64_t *a, uint32_t n, uint64_t base, u
       mlo[j] = 0;
       mhi[j] = 0;
     }
-#pragma unroll 2
-    for (uint32_t i = 0; i < n; ++i) {
-      const uint64_t ai = a[i];
+    auto eval_key = [&](uint64_t ai) {
       const uint32_t alo = (uint32_t)ai, ahi = (uint32_t)(ai >> 32);
 #pragma unroll
       for (int j = 0; j < SPL; ++j) {
         uint32_t h0, h1;
         slot_pair(alo, ahi, tlo[j], thi[j], n, nm1, h0, h1);
         if (WIDE) {
-          const uint64_t b = (1ull << h0) | (1ull << h1);
-          mlo[j] |= (uint32_t)b;
-          mhi[j] |= (uint32_t)(b >> 32);
+          const uint64_t b0 = 1ull << h0, b1 = 1ull << h1;
+          or3_into(mlo[j], (uint32_t)b0, (uint32_t)b1);
+          or3_into(mhi[j], (uint32_t)(b0 >> 32), (uint32_t)(b1 >> 32));
         } else {
-          mlo[j] |= (1u << h0) | (1u << h1);
+          or3_into(mlo[j], 1u << h0, 1u << h1);
         }
       }
+    };
+    uint32_t i = 0;
+    for (; i + 4 <= n; i += 4) {
+      const uint64_t a0 = a[i], a1 = a[i + 1], a2 = a[i + 2], a3 = a[i + 3];
+      eval_key(a0);
+      eval_key(a1);
+      eval_key(a2);
+      eval_key(a3);
     }
+    for (; i < n; ++i) eval_key(a[i]);
     const uint64_t span = end - ib;
     st.seeds += span < (uint64_t)(64 * SPL) ? span : (uint64_t)(64 * SPL);
 #pragma unroll
@@ -339,7 +384,6 @@ __device__ void finalize_leaf(const Params &P, uint64_t j, uint32_t n, WaveLds &
   if (lane == 0) {
     P.out_seeds[j] = seed_out;
     P.out_orient[j] = f;
-    __threadfence();
     atomicAdd(&P.lctr[kLcDone], 1ull);
   }
 }
@@ -353,38 +397,45 @@ __device__ uint64_t search_range(const Params &P, uint64_t j, uint32_t n, uint64
   return search_block<SPL, true>(a, n, base, end, &P.best[j], my_alo, my_ahi, lds, st);
 }
 
-// Work on leaf j until it is closed: claim blocks in order, search each.
+// Work on leaf j until it is closed: claim runs of units in order, search
+// each.  A worker alone on a leaf claims block_iters units at a time; with k
+// workers inside it claims about block_iters/k, so speculative work beyond
+// the answer stays small when many helpers share a leaf.
 template <int SPL>
-__device__ void work_leaf(const Params &P, uint64_t j, WaveLds &lds, WaveStats &st) {
+__device__ void work_leaf(const Params &P, uint64_t j, bool helper, WaveLds &lds, WaveStats &st) {
   const uint32_t lane = lane_id();
-  const uint64_t block = P.block;
+  const uint64_t unit = P.unit;
   const uint64_t o0 = P.offsets[j], o1 = P.offsets[j + 1];
   const uint32_t n = (uint32_t)(o1 - o0);
   const uint64_t ai = P.premix[j * 64 + lane];
   const uint32_t my_alo = (uint32_t)ai, my_ahi = (uint32_t)(ai >> 32);
   lds.keys[lane] = ai;
   wave_lds_sync();
-  uint64_t claim = wave_atomic_add(&P.state[j], kInflightOne + 1);
+  uint64_t take = helper ? 1 : P.block_iters;  // a helper does not know the crowd yet
+  uint64_t claim = wave_atomic_add(&P.state[j], kInflightOne + take);
   if (claim & kFinalBit) {
     wave_atomic_add(&P.state[j], (unsigned long long)(0 - kInflightOne));
     return;
   }
   for (;;) {
-    const uint64_t b = claim & kBlockMask;
+    const uint64_t u = claim & kBlockMask;
     const uint64_t bst = bcast64(load_relaxed(&P.best[j]));
     const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
-    if (b >= blocks_below(P.start_seed, lim, block)) break;
-    const uint64_t off = b * block;
+    if (u >= blocks_below(P.start_seed, lim, unit)) break;
     if (P.cancel != nullptr && *P.cancel != 0) {
       if (lane == 0) atomicOr(&P.gctr[kCtrErr], kErrCancel);
       break;
     }
-    const uint64_t base = P.start_seed + off;
-    const uint64_t end = (lim - base) < block ? lim : base + block;
+    const uint64_t base = P.start_seed + u * unit;
+    const uint64_t span = take * unit;
+    const uint64_t end = (lim - base) < span ? lim : base + span;
     st.blocks += 1;
     const uint64_t found = search_range<SPL>(P, j, n, base, end, my_alo, my_ahi, lds, st);
-    if (found != kNone && lane == 0) atomicMin(&P.best[j], (unsigned long long)found);
-    claim = wave_atomic_add(&P.state[j], 1);
+    if (found != kNone) wave_atomic_min_wait(&P.best[j], found);
+    const uint64_t inflight = (claim & kInflightMask) >> 40;
+    take = P.block_iters / (inflight ? inflight : 1);
+    if (take == 0) take = 1;
+    claim = wave_atomic_add(&P.state[j], take);
   }
   const uint64_t old = wave_atomic_add(&P.state[j], (unsigned long long)(0 - kInflightOne));
   if (((old & kInflightMask) >> 40) == 1) {
@@ -396,6 +447,54 @@ __device__ void work_leaf(const Params &P, uint64_t j, WaveLds &lds, WaveStats &
       if (!(was & kFinalBit)) finalize_leaf(P, j, n, lds);
     }
   }
+}
+
+// One leaf searched by all workers of the launch with a static split: worker
+// w takes blocks w, w + W, w + 2W, ...  A worker stops at its first block
+// that starts at or above the best seed found so far, so every block below
+// the final best is searched to its first acceptance.  The last worker to
+// finish (counted per workgroup in LDS, then per launch) writes the result.
+template <int SPL>
+__device__ void split_leaf(const Params &P, uint64_t j, uint32_t wid, WaveLds &lds, WaveStats &st,
+                           uint32_t *wg_exits) {
+  const uint32_t lane = lane_id();
+  const uint64_t block = P.block;
+  const uint32_t n = (uint32_t)(P.offsets[j + 1] - P.offsets[j]);
+  const uint64_t ai = P.premix[j * 64 + lane];
+  lds.keys[lane] = ai;
+  wave_lds_sync();
+  for (uint64_t b = wid;; b += P.workers) {
+    const uint64_t bst = bcast64(load_relaxed(&P.best[j]));
+    const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
+    if (b >= blocks_below(P.start_seed, lim, block)) break;
+    if (P.cancel != nullptr && *P.cancel != 0) {
+      if (lane == 0) atomicOr(&P.gctr[kCtrErr], kErrCancel);
+      break;
+    }
+    const uint64_t base = P.start_seed + b * block;
+    const uint64_t end = (lim - base) < block ? lim : base + block;
+    st.blocks += 1;
+    const uint64_t found = search_range<SPL>(P, j, n, base, end, (uint32_t)ai, (uint32_t)(ai >> 32), lds, st);
+    if (found != kNone) wave_atomic_min_wait(&P.best[j], found);
+  }
+  uint32_t c = 0;
+  if (lane == 0) c = atomicAdd(wg_exits, 1u);
+  c = bcast32(c);
+  const uint32_t wpw = blockDim.x >> 6;
+  if (c != wpw - 1) return;
+  // Workgroup done: count it in its group, then count finished groups.
+  const uint32_t groups = gridDim.x < (uint32_t)kExitGroups ? gridDim.x : (uint32_t)kExitGroups;
+  const uint32_t grp = blockIdx.x % groups;
+  const uint32_t members = gridDim.x / groups + (grp < gridDim.x % groups ? 1u : 0u);
+  const uint64_t gc = wave_atomic_add(&P.lctr[kLcExitGroups + grp], 1);
+  if (gc != members - 1) return;
+  const uint64_t g = wave_atomic_add(&P.lctr[kLcExitTop], 1);
+  if (g != groups - 1) return;
+  if (P.cancel != nullptr && *P.cancel != 0) return;
+  unsigned long long was = 0;
+  if (lane == 0) was = atomicOr(&P.state[j], kFinalBit);
+  was = bcast64(was);
+  if (!(was & kFinalBit)) finalize_leaf(P, j, n, lds);
 }
 
 // Pick a leaf to help: an unfinished leaf whose next block still lies below
@@ -427,7 +526,7 @@ __device__ uint64_t find_help_leaf(const Params &P, uint32_t wid) {
       const uint64_t stw = load_relaxed(&P.state[leaf]);
       const uint64_t bst = load_relaxed(&P.best[leaf]);
       const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
-      open = !(stw & kFinalBit) && (stw & kBlockMask) < blocks_below(P.start_seed, lim, P.block);
+      open = !(stw & kFinalBit) && (stw & kBlockMask) < blocks_below(P.start_seed, lim, P.unit);
     }
     const uint64_t cand = __ballot(open);
     if (cand != 0) {
@@ -442,14 +541,33 @@ __device__ uint64_t find_help_leaf(const Params &P, uint32_t wid) {
   return kNone;
 }
 
+__device__ __forceinline__ void flush_stats(const Params &P, const WaveStats &st, uint32_t wid) {
+  if (lane_id() == 0) {
+    unsigned long long *slot = P.gctr + kCtrStats + (wid % kStatSlots) * 4;
+    if (st.seeds) atomicAdd(slot + kStSeeds, (unsigned long long)st.seeds);
+    if (st.passes) atomicAdd(slot + kStPasses, (unsigned long long)st.passes);
+    if (st.pf) atomicAdd(slot + kStPf, (unsigned long long)st.pf);
+    if (st.blocks) atomicAdd(slot + kStBlocks, (unsigned long long)st.blocks);
+  }
+}
+
 template <int SPL>
 __global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
   extern __shared__ unsigned long long lds_raw[];
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
+  const uint32_t wpw = blockDim.x >> 6;
   WaveLds &lds = reinterpret_cast<WaveLds *>(lds_raw)[wave];
-  const uint32_t wid = blockIdx.x * (blockDim.x >> 6) + wave;
+  uint32_t *wg_exits = reinterpret_cast<uint32_t *>(reinterpret_cast<WaveLds *>(lds_raw) + wpw);
+  const uint32_t wid = blockIdx.x * wpw + wave;
   WaveStats st;
+  if (P.split) {
+    if (threadIdx.x == 0) *wg_exits = 0;
+    __syncthreads();
+    split_leaf<SPL>(P, P.leaf_begin, wid, lds, st, wg_exits);
+    flush_stats(P, st, wid);
+    return;
+  }
   bool fresh = true;
   uint32_t idle_rounds = 0;
   for (;;) {
@@ -458,12 +576,14 @@ __global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
       break;
     }
     uint64_t j = kNone;
+    bool helper = false;
     if (fresh) {
       const uint64_t k = wave_atomic_add(&P.lctr[kLcNextLeaf], 1);
       if (k < P.leaf_count) j = P.leaf_begin + k;
       else fresh = false;
     }
     if (j == kNone) {
+      helper = true;
       j = find_help_leaf(P, wid);
       if (j == kNone) {
         if (load_relaxed(&P.lctr[kLcDone]) >= P.leaf_count) break;
@@ -473,14 +593,9 @@ __global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
       }
     }
     if (P.leaf_count > 64 && lane == 0) __hip_atomic_store(&P.wleaf[wid], (uint32_t)j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    work_leaf<SPL>(P, j, lds, st);
+    work_leaf<SPL>(P, j, helper, lds, st);
   }
-  if (lane == 0) {
-    atomicAdd(&P.gctr[kCtrSeeds], (unsigned long long)st.seeds);
-    atomicAdd(&P.gctr[kCtrPasses], (unsigned long long)st.passes);
-    atomicAdd(&P.gctr[kCtrPfChecks], (unsigned long long)st.pf);
-    atomicAdd(&P.gctr[kCtrBlocks], (unsigned long long)st.blocks);
-  }
+  flush_stats(P, st, wid);
 }
 
 // Validate the batch, initialise per-leaf state and premix the keys.  One
@@ -617,6 +732,19 @@ struct Tuning {
   int spl, block_iters, waves_per_wg;
 };
 
+// Rough expected number of seeds per leaf of n keys: the bound of the
+// construction theorem, (e/2)^n * e / sqrt(pi) (Section 5), shrunk by
+// 1.5 sqrt(n), which tracks the exact loop-free expectation within ~20% for
+// 16 <= n <= 64.  Only used to size launches.
+double expected_seeds(uint32_t n) {
+  if (n < 2) return 1.0;
+  const double e = 2.718281828459045;
+  double v = 1.0;
+  for (uint32_t i = 0; i < n; ++i) v *= e / 2.0;
+  v *= e / 1.7724538509055159 / (1.5 * sqrt((double)n));
+  return v < 1.0 ? 1.0 : v;
+}
+
 // Defaults by leaf size; the Python autotuner may override per call.
 Tuning default_tuning(uint32_t n_hint, int mode) {
   Tuning t;
@@ -626,8 +754,18 @@ Tuning default_tuning(uint32_t n_hint, int mode) {
   else if (n_hint <= 40) t.block_iters = 4;
   else if (n_hint <= 52) t.block_iters = 16;
   else t.block_iters = 32;
-  if (mode == SHOCK_MODE_PLAIN_PER_LEAF) t.block_iters = n_hint <= 40 ? 1 : 2;
+  if (mode == SHOCK_MODE_PLAIN_PER_LEAF) t.block_iters = 1;
   return t;
+}
+
+// Workers for a single-leaf (split) launch: enough 64*spl-seed blocks to cover
+// about twice the expected seed count in one round, at least one workgroup.
+int plain_workers(uint32_t n, int spl, int block_iters, int wpw, int max_workers) {
+  const double per = 64.0 * spl * block_iters;
+  double w = 2.0 * expected_seeds(n) / per;
+  int wi = w > max_workers ? max_workers : (int)w;
+  if (wi < wpw) wi = wpw;
+  return (wi / wpw) * wpw;
 }
 
 int device_workers(int waves_per_wg) {
@@ -643,7 +781,7 @@ int device_workers(int waves_per_wg) {
 template <int SPL>
 hipError_t launch_search(const Params &P, int wpw, hipStream_t stream) {
   const uint32_t wgs = P.workers / wpw;
-  hipLaunchKernelGGL(search_kernel<SPL>, dim3(wgs), dim3(64 * wpw), sizeof(WaveLds) * wpw, stream, P);
+  hipLaunchKernelGGL(search_kernel<SPL>, dim3(wgs), dim3(64 * wpw), sizeof(WaveLds) * wpw + 16, stream, P);
   return hipGetLastError();
 }
 
@@ -720,18 +858,13 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
   if (mode != SHOCK_MODE_PERSISTENT && mode != SHOCK_MODE_PLAIN_PER_LEAF) return SHOCK_EINVAL;
   hipStream_t stream = (hipStream_t)hip_stream;
 
-  // Launch parameters.  The size hint for defaults is the first leaf's size
-  // when known cheaply; the caller's explicit values win.
-  Tuning tune = default_tuning(48, mode);
-  if (opts.spl) tune.spl = opts.spl;
-  if (opts.block_iters) tune.block_iters = opts.block_iters;
-  if (opts.waves_per_wg) tune.waves_per_wg = opts.waves_per_wg;
-  int workers = opts.workers ? opts.workers : device_workers(tune.waves_per_wg);
-  workers = ((workers + tune.waves_per_wg - 1) / tune.waves_per_wg) * tune.waves_per_wg;
-  if (workers <= 0) return SHOCK_EINVAL;
+  // Scratch is laid out for the largest worker count any launch may use.
+  const int wpw_max_workers = device_workers(1);
+  const int max_workers = opts.workers > wpw_max_workers ? opts.workers : wpw_max_workers;
+  const int workers_cap = max_workers + kMaxWavesPerWg;
   const uint64_t n_launches = mode == SHOCK_MODE_PLAIN_PER_LEAF ? n_leaves : 1;
 
-  const Layout lay = layout(n_leaves, (uint32_t)workers, n_launches);
+  const Layout lay = layout(n_leaves, (uint32_t)workers_cap, n_launches);
   void *buf = nullptr;
   unsigned long long *host_ctr = nullptr;
   int rc = get_scratch(lay.total, &buf, &host_ctr);
@@ -746,10 +879,10 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
 
   {
     const uint64_t n_l = n_launches * kLcCount;
-    uint64_t m = n_l > (uint64_t)workers ? n_l : (uint64_t)workers;
+    uint64_t m = n_l > (uint64_t)workers_cap ? n_l : (uint64_t)workers_cap;
     if (m < kCtrGlobalCount) m = kCtrGlobalCount;
     hipLaunchKernelGGL(init_counters_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, gctr, lctr, n_l,
-                       wleaf, (uint32_t)workers);
+                       wleaf, (uint32_t)workers_cap);
     HIP_TRY(hipGetLastError());
   }
   if (!keys) {
@@ -760,10 +893,29 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
   hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)((n_leaves + 3) / 4)), dim3(256), 0, stream, keys, offsets,
                      n_leaves, premix, state, best, gctr, opts.check_dups);
   HIP_TRY(hipGetLastError());
+  // Leaf sizes for launch sizing: all offsets for per-leaf launches, the
+  // first and last otherwise (mean leaf size).
+  std::vector<uint64_t> h_off(mode == SHOCK_MODE_PLAIN_PER_LEAF ? n_leaves + 1 : 2);
   HIP_TRY(hipMemcpyAsync(host_ctr, gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
+  if (mode == SHOCK_MODE_PLAIN_PER_LEAF) {
+    HIP_TRY(hipMemcpyAsync(h_off.data(), offsets, (n_leaves + 1) * 8, hipMemcpyDeviceToHost, stream));
+  } else {
+    HIP_TRY(hipMemcpyAsync(&h_off[0], offsets, 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(&h_off[1], offsets + n_leaves, 8, hipMemcpyDeviceToHost, stream));
+  }
   HIP_TRY(hipStreamSynchronize(stream));
   if (host_ctr[kCtrErr] & kErrInvalid) return SHOCK_EINVAL;
   if (host_ctr[kCtrErr] & kErrDup) return SHOCK_EDUPKEY;
+
+  // Launch parameters: defaults from the mean leaf size, explicit options win.
+  const uint32_t n_mean = (uint32_t)((h_off.back() - h_off.front() + n_leaves / 2) / n_leaves);
+  Tuning tune = default_tuning(n_mean, mode);
+  if (opts.spl) tune.spl = opts.spl;
+  if (opts.block_iters) tune.block_iters = opts.block_iters;
+  if (opts.waves_per_wg) tune.waves_per_wg = opts.waves_per_wg;
+  int workers = opts.workers ? opts.workers : device_workers(tune.waves_per_wg);
+  workers = ((workers + tune.waves_per_wg - 1) / tune.waves_per_wg) * tune.waves_per_wg;
+  if (workers <= 0 || workers > workers_cap) return SHOCK_EINVAL;
 
   Params P;
   P.offsets = offsets;
@@ -779,6 +931,8 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
   P.cancel = opts.cancel;
   P.block_iters = (uint32_t)tune.block_iters;
   P.block = 64ull * (uint64_t)tune.spl * (uint64_t)tune.block_iters;
+  P.unit = 64ull * (uint64_t)tune.spl;
+  P.split = 0;
   P.workers = (uint32_t)workers;
 
   hipEvent_t e0, e1;
@@ -791,10 +945,14 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
     P.lctr = lctr;
     HIP_TRY(launch_search_spl(tune.spl, P, tune.waves_per_wg, stream));
   } else {
+    P.split = 1;
     for (uint64_t j = 0; j < n_leaves; ++j) {
       P.leaf_begin = j;
       P.leaf_count = 1;
       P.lctr = lctr + j * kLcCount;
+      const uint32_t nj = (uint32_t)(h_off[j + 1] - h_off[j]);
+      P.workers = opts.workers ? (uint32_t)workers
+                               : (uint32_t)plain_workers(nj, tune.spl, tune.block_iters, tune.waves_per_wg, workers);
       HIP_TRY(launch_search_spl(tune.spl, P, tune.waves_per_wg, stream));
     }
   }
@@ -813,12 +971,15 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
   HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
   HIP_TRY(hipEventDestroy(e0));
   HIP_TRY(hipEventDestroy(e1));
-  g_stats.seeds_tested = host_ctr[kCtrSeeds];
-  g_stats.filter_passes = host_ctr[kCtrPasses];
-  g_stats.pf_checks = host_ctr[kCtrPfChecks];
-  g_stats.blocks_claimed = host_ctr[kCtrBlocks];
+  for (int i = 0; i < kStatSlots; ++i) {
+    const unsigned long long *slot = host_ctr + kCtrStats + i * 4;
+    g_stats.seeds_tested += slot[kStSeeds];
+    g_stats.filter_passes += slot[kStPasses];
+    g_stats.pf_checks += slot[kStPf];
+    g_stats.blocks_claimed += slot[kStBlocks];
+  }
   g_stats.kernel_ms = ms;
-  g_stats.workers = workers;
+  g_stats.workers = (int32_t)P.workers;
   g_stats.spl = tune.spl;
   g_stats.block_iters = tune.block_iters;
   g_stats.waves_per_wg = tune.waves_per_wg;
