@@ -91,7 +91,20 @@ def main():
     ap.add_argument("--spl", type=int, default=0)
     ap.add_argument("--block-iters", type=int, default=0)
     ap.add_argument("--waves-per-wg", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB: only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "dispatches": 3}))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the leaf search is data-parallel over leaves and this build "

@@ -66,16 +66,20 @@ extern "C" {
 #define SHOCK_DEFAULT_MAX_SEED 4294967296ULL /* 2^32, exclusive */
 
 typedef struct shock_opts {
-  uint64_t max_seed;      /* exclusive cap on seeds; 0 selects SHOCK_DEFAULT_MAX_SEED */
+  uint64_t max_seed;      /* exclusive cap on seeds (at most 2^63); 0 selects SHOCK_DEFAULT_MAX_SEED */
   uint64_t start_seed;    /* first seed tried (resume point); default 0 */
   int32_t mode;           /* SHOCK_MODE_*; AUTO = PERSISTENT */
   int32_t spl;            /* seeds per lane per iteration: 1, 2 or 4; 0 = tuned default for the batch */
-  int32_t block_iters;    /* iterations per claimed seed block (block = 64*spl*block_iters seeds); 0 = tuned */
+  int32_t block_iters;    /* units (64*spl seeds) a worker claims at once, for every leaf size; 0 = by leaf size */
   int32_t waves_per_wg;   /* waves per workgroup = leaves a workgroup works on at once (1..16); 0 = tuned */
   int32_t workers;        /* persistent waves in the grid; 0 = fill the device */
   int32_t check_dups;     /* 1 = reject leaves with repeated keys (SHOCK_EDUPKEY) */
   const volatile int32_t *cancel; /* HOST pointer (pinned or managed memory) or NULL; nonzero = stop */
-  uint64_t reserved[4];
+  int32_t leaf_size_hint; /* typical leaf size, sizes launches where offsets are not read back (contexts); 0 = 48 */
+  int32_t reserved0;
+  const uint16_t *block_iters_by_n; /* HOST pointer to 65 claim sizes indexed by leaf size (0 = default), or NULL;
+                                       e.g. the autotuner's table; overridden by block_iters when that is set */
+  uint64_t reserved[2];
 } shock_opts;
 
 /* Defaults for every field. */
@@ -119,6 +123,52 @@ int shock_release_scratch(void);
 
 /* Library version of the frozen hash/orientation definition (1). */
 int shock_spec_version(void);
+
+/* ---- Contexts: asynchronous searches, several in flight, HIP graphs ------
+ *
+ * A context owns the scratch for batches of up to max_leaves leaves (about
+ * 600 bytes per leaf plus a fixed 130 KB) and pinned status counters.
+ * Searches on a context are enqueued on a stream without any host
+ * synchronisation, so a caller can keep several contexts in flight on
+ * different streams (continuous batching) or capture the enqueue sequence in
+ * a HIP graph and replay it.  Validation (nondecreasing offsets, n <= 64,
+ * repeated keys if check_dups) happens on the device: a failed batch is not
+ * searched, its outputs are left untouched, and the status is reported by
+ * shock_ctx_wait.  Launch sizes come from opts->leaf_size_hint (nothing is
+ * read back).  One search may be pending per context; a new enqueue on a
+ * pending context first waits for it.  Contexts are not thread-safe. */
+typedef struct shock_ctx shock_ctx;
+
+/* Create a context on the current device.  SHOCK_ENOMEM if its scratch does
+ * not fit. */
+int shock_ctx_create(uint64_t max_leaves, shock_ctx **out);
+int shock_ctx_destroy(shock_ctx *ctx);
+
+/* Enqueue a search of a CSR batch (n_leaves <= max_leaves; arguments as for
+ * shock_leaf_search_ex) on hip_stream.  Returns SHOCK_EINVAL for arguments
+ * checkable on the host, SHOCK_EHIP if a launch fails, else SHOCK_OK; the
+ * batch's own status comes from shock_ctx_wait. */
+int shock_ctx_search_async(shock_ctx *ctx, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                           uint64_t *out_seeds, uint64_t *out_orient, const shock_opts *opts, void *hip_stream);
+
+/* 1 if the context's last search has completed (or none is pending), 0 if it
+ * is still running, SHOCK_EHIP on error.  Never blocks. */
+int shock_ctx_query(shock_ctx *ctx);
+
+/* Block until the last search completes and return its status (as
+ * shock_leaf_search_ex).  Fills *stats (may be NULL); kernel_ms spans the
+ * search kernels, or the whole graph for graph launches. */
+int shock_ctx_wait(shock_ctx *ctx, shock_stats *stats);
+
+/* Capture the enqueue sequence of one search (same arguments as
+ * shock_ctx_search_async; no cancel flag) into a HIP graph held by the context,
+ * replacing any earlier one.  The graph records buffer addresses, not
+ * contents: each replay searches what those buffers hold at replay time. */
+int shock_ctx_graph_capture(shock_ctx *ctx, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                            uint64_t *out_seeds, uint64_t *out_orient, const shock_opts *opts, void *hip_stream);
+
+/* Replay the captured graph on hip_stream; complete it with shock_ctx_wait. */
+int shock_ctx_graph_launch(shock_ctx *ctx, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,8 @@ NOT_FOUND_SEED = (1 << 64) - 1
 EXPORTED = [
     "shock_opts_init", "shock_leaf_search", "shock_leaf_search_ex", "shock_last_stats",
     "shock_last_error", "shock_strerror", "shock_release_scratch", "shock_spec_version",
+    "shock_ctx_create", "shock_ctx_destroy", "shock_ctx_search_async", "shock_ctx_query", "shock_ctx_wait",
+    "shock_ctx_graph_capture", "shock_ctx_graph_launch",
 ]
 
 
@@ -40,7 +42,10 @@ class ShockOpts(ctypes.Structure):
         ("workers", ctypes.c_int32),
         ("check_dups", ctypes.c_int32),
         ("cancel", ctypes.c_void_p),
-        ("reserved", ctypes.c_uint64 * 4),
+        ("leaf_size_hint", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("block_iters_by_n", ctypes.c_void_p),
+        ("reserved", ctypes.c_uint64 * 2),
     ]
 
 
@@ -98,6 +103,20 @@ def lib():
         L.shock_release_scratch.argtypes = []
         L.shock_spec_version.restype = ctypes.c_int
         L.shock_spec_version.argtypes = []
+        L.shock_ctx_create.restype = ctypes.c_int
+        L.shock_ctx_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
+        L.shock_ctx_destroy.restype = ctypes.c_int
+        L.shock_ctx_destroy.argtypes = [vp]
+        L.shock_ctx_search_async.restype = ctypes.c_int
+        L.shock_ctx_search_async.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(ShockOpts), vp]
+        L.shock_ctx_graph_capture.restype = ctypes.c_int
+        L.shock_ctx_graph_capture.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(ShockOpts), vp]
+        L.shock_ctx_graph_launch.restype = ctypes.c_int
+        L.shock_ctx_graph_launch.argtypes = [vp, vp]
+        L.shock_ctx_query.restype = ctypes.c_int
+        L.shock_ctx_query.argtypes = [vp]
+        L.shock_ctx_wait.restype = ctypes.c_int
+        L.shock_ctx_wait.argtypes = [vp, ctypes.POINTER(ShockStats)]
         _lib = L
     return _lib
 
@@ -144,7 +163,8 @@ def _as_ptr(x):
 
 
 def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_iters=0, waves_per_wg=0,
-              workers=0, check_dups=False, cancel_ptr=None) -> ShockOpts:
+              workers=0, check_dups=False, cancel_ptr=None, leaf_size_hint=0, block_iters_by_n=None) -> ShockOpts:
+    """shock_opts with defaults; block_iters_by_n is a sequence of 65 ints or None."""
     o = ShockOpts()
     lib().shock_opts_init(ctypes.byref(o))
     if max_seed is not None:
@@ -157,6 +177,13 @@ def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_it
     o.workers = workers
     o.check_dups = int(bool(check_dups))
     o.cancel = cancel_ptr
+    o.leaf_size_hint = leaf_size_hint
+    if block_iters_by_n is not None:
+        if len(block_iters_by_n) != 65:
+            raise ValueError("block_iters_by_n needs 65 entries (leaf sizes 0..64)")
+        table = (ctypes.c_uint16 * 65)(*[int(v) for v in block_iters_by_n])
+        o._table = table  # keep alive with the options
+        o.block_iters_by_n = ctypes.cast(table, ctypes.c_void_p)
     return o
 
 
@@ -195,3 +222,73 @@ def leaf_search(keys, offsets, out_seeds=None, out_orient=None, stream=None, **o
     if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
         raise ShockError(rc, lib().shock_last_error().decode())
     return rc, out_seeds[:L], out_orient[:L]
+
+
+def _check_tensors(keys, offsets):
+    import torch
+
+    if keys.device.type != "cuda" or offsets.device.type != "cuda":
+        raise ValueError("keys and offsets must be device (cuda) tensors")
+    if keys.dtype != torch.int64 or offsets.dtype != torch.int64:
+        raise ValueError("keys and offsets must be int64 tensors carrying uint64 bits")
+
+
+class SearchContext:
+    """A shock_ctx: asynchronous searches on a stream, and captured graphs.
+
+    Buffers passed to search_async/capture must stay alive until wait()."""
+
+    def __init__(self, max_leaves: int):
+        self._h = ctypes.c_void_p()
+        rc = lib().shock_ctx_create(max_leaves, ctypes.byref(self._h))
+        if rc != SHOCK_OK:
+            raise ShockError(rc, lib().shock_last_error().decode())
+        self.max_leaves = max_leaves
+        self._keep = None
+
+    def close(self):
+        if self._h:
+            lib().shock_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _args(self, keys, offsets, out_seeds, out_orient, stream, opts):
+        import torch
+
+        _check_tensors(keys, offsets)
+        L = offsets.numel() - 1
+        if stream is None:
+            stream = torch.cuda.current_stream(keys.device).cuda_stream
+        o = make_opts(**opts)
+        self._keep = (keys, offsets, out_seeds, out_orient, o)
+        return (self._h, _as_ptr(keys), _as_ptr(offsets), L, _as_ptr(out_seeds), _as_ptr(out_orient),
+                ctypes.byref(o), ctypes.c_void_p(stream))
+
+    def search_async(self, keys, offsets, out_seeds, out_orient, stream=None, **opts) -> int:
+        return lib().shock_ctx_search_async(*self._args(keys, offsets, out_seeds, out_orient, stream, opts))
+
+    def capture(self, keys, offsets, out_seeds, out_orient, stream=None, **opts) -> int:
+        return lib().shock_ctx_graph_capture(*self._args(keys, offsets, out_seeds, out_orient, stream, opts))
+
+    def launch_graph(self, stream=None) -> int:
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        return lib().shock_ctx_graph_launch(self._h, ctypes.c_void_p(stream))
+
+    def query(self) -> int:
+        return lib().shock_ctx_query(self._h)
+
+    def wait(self):
+        """(status, stats dict) of the last search."""
+        st = ShockStats()
+        rc = lib().shock_ctx_wait(self._h, ctypes.byref(st))
+        if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
+            raise ShockError(rc, lib().shock_last_error().decode())
+        return rc, st.as_dict()

@@ -92,9 +92,10 @@ struct Params {
   const volatile int32_t *cancel;
   uint64_t block;        // seeds per claimed block = 64 * SPL * block_iters (split launches)
   uint64_t unit;         // seeds per claim unit = 64 * SPL
-  uint32_t block_iters;  // most units one claim takes
+  uint32_t block_iters;  // units per block of a single-leaf (split) launch
   uint32_t workers;
   uint32_t split;  // 1: one leaf, static block striding over the workers (no claim atomics)
+  uint16_t units_by_n[65];  // most units one claim takes, by leaf size (persistent launches)
 };
 
 __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
@@ -149,11 +150,11 @@ __device__ __forceinline__ unsigned long long load_relaxed(const unsigned long l
   return __hip_atomic_load(const_cast<unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Number of blocks a leaf needs before its limit: ceil((lim - start) / block).
-__device__ __forceinline__ uint64_t blocks_below(uint64_t start, uint64_t lim, uint64_t block) {
-  if (start >= lim) return 0;
-  const uint64_t span = lim - start;
-  return span / block + (span % block != 0 ? 1 : 0);
+// Whether chunk index u (of `size` seeds each, counted from start) begins
+// below lim.  u < 2^40 and size <= 2^24 by construction, so u * size cannot
+// overflow; the host caps max_seed at 2^63.
+__device__ __forceinline__ bool chunk_below(uint64_t u, uint64_t size, uint64_t start, uint64_t lim) {
+  return start < lim && u * size < lim - start;
 }
 
 // Waves communicate only through device-scope atomics (claim words, best
@@ -295,17 +296,19 @@ struct WaveStats {
 
 // Search seeds [base, end) of one leaf for the first seed whose graph is a
 // pseudoforest.  `a` points at the leaf's premixed keys (wave-uniform).
-// Stops early once the leaf's best accepted seed is at or below the start of
-// the next iteration.  Returns kNone if no seed of the range qualifies.
+// With `poll`, stops early once the leaf's best accepted seed is at or below
+// the start of the next iteration; polling only matters when other workers
+// hold lower parts of the leaf's seed range.  Returns kNone if no seed of the
+// range qualifies.
 template <int SPL, bool WIDE>
 __device__ uint64_t search_block(const uint64_t *a, uint32_t n, uint64_t base, uint64_t end,
-                                 const unsigned long long *best_j, uint32_t my_alo, uint32_t my_ahi, WaveLds &lds,
-                                 WaveStats &st) {
+                                 const unsigned long long *best_j, bool poll, uint32_t my_alo, uint32_t my_ahi,
+                                 WaveLds &lds, WaveStats &st) {
   const uint32_t lane = lane_id();
   const uint32_t nm1 = n - 1;
   const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
   for (uint64_t ib = base; ib < end; ib += 64 * SPL) {
-    const unsigned long long cur_best = load_relaxed(best_j);
+    const unsigned long long cur_best = poll ? load_relaxed(best_j) : kNone;
     uint32_t tlo[SPL], thi[SPL], mlo[SPL], mhi[SPL];
 #pragma unroll
     for (int j = 0; j < SPL; ++j) {
@@ -389,12 +392,12 @@ __device__ void finalize_leaf(const Params &P, uint64_t j, uint32_t n, WaveLds &
 }
 
 template <int SPL>
-__device__ uint64_t search_range(const Params &P, uint64_t j, uint32_t n, uint64_t base, uint64_t end,
+__device__ uint64_t search_range(const Params &P, uint64_t j, uint32_t n, uint64_t base, uint64_t end, bool poll,
                                  uint32_t my_alo, uint32_t my_ahi, WaveLds &lds, WaveStats &st) {
   const uint64_t *a = lds.keys;
   if (n <= 1) return base;  // every seed qualifies
-  if (n <= 32) return search_block<SPL, false>(a, n, base, end, &P.best[j], my_alo, my_ahi, lds, st);
-  return search_block<SPL, true>(a, n, base, end, &P.best[j], my_alo, my_ahi, lds, st);
+  if (n <= 32) return search_block<SPL, false>(a, n, base, end, &P.best[j], poll, my_alo, my_ahi, lds, st);
+  return search_block<SPL, true>(a, n, base, end, &P.best[j], poll, my_alo, my_ahi, lds, st);
 }
 
 // Work on leaf j until it is closed: claim runs of units in order, search
@@ -411,7 +414,8 @@ __device__ void work_leaf(const Params &P, uint64_t j, bool helper, WaveLds &lds
   const uint32_t my_alo = (uint32_t)ai, my_ahi = (uint32_t)(ai >> 32);
   lds.keys[lane] = ai;
   wave_lds_sync();
-  uint64_t take = helper ? 1 : P.block_iters;  // a helper does not know the crowd yet
+  const uint64_t most = P.units_by_n[n];
+  uint64_t take = helper ? 1 : most;  // a helper does not know the crowd yet
   uint64_t claim = wave_atomic_add(&P.state[j], kInflightOne + take);
   if (claim & kFinalBit) {
     wave_atomic_add(&P.state[j], (unsigned long long)(0 - kInflightOne));
@@ -421,7 +425,7 @@ __device__ void work_leaf(const Params &P, uint64_t j, bool helper, WaveLds &lds
     const uint64_t u = claim & kBlockMask;
     const uint64_t bst = bcast64(load_relaxed(&P.best[j]));
     const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
-    if (u >= blocks_below(P.start_seed, lim, unit)) break;
+    if (!chunk_below(u, unit, P.start_seed, lim)) break;
     if (P.cancel != nullptr && *P.cancel != 0) {
       if (lane == 0) atomicOr(&P.gctr[kCtrErr], kErrCancel);
       break;
@@ -430,12 +434,21 @@ __device__ void work_leaf(const Params &P, uint64_t j, bool helper, WaveLds &lds
     const uint64_t span = take * unit;
     const uint64_t end = (lim - base) < span ? lim : base + span;
     st.blocks += 1;
-    const uint64_t found = search_range<SPL>(P, j, n, base, end, my_alo, my_ahi, lds, st);
-    if (found != kNone) wave_atomic_min_wait(&P.best[j], found);
     const uint64_t inflight = (claim & kInflightMask) >> 40;
-    take = P.block_iters / (inflight ? inflight : 1);
-    if (take == 0) take = 1;
-    claim = wave_atomic_add(&P.state[j], take);
+    // Claim the next run now and read the answer after this run's search, so
+    // the atomic's round trip overlaps the hashing.  A claimed run is either
+    // searched or skipped because it starts at or above the best seed, so
+    // claiming ahead never loses a seed below the minimum.
+    uint64_t next_take = most / (inflight ? inflight : 1);
+    if (next_take == 0) next_take = 1;
+    unsigned long long next_claim = 0;
+    if (lane == 0) next_claim = atomicAdd(&P.state[j], (unsigned long long)next_take);
+    // Alone on the leaf at claim time: later joiners claim higher seeds, so no
+    // one can lower best below this range and polling is pointless.
+    const uint64_t found = search_range<SPL>(P, j, n, base, end, inflight > 1, my_alo, my_ahi, lds, st);
+    if (found != kNone) wave_atomic_min_wait(&P.best[j], found);
+    take = next_take;
+    claim = bcast64(next_claim);
   }
   const uint64_t old = wave_atomic_add(&P.state[j], (unsigned long long)(0 - kInflightOne));
   if (((old & kInflightMask) >> 40) == 1) {
@@ -466,7 +479,7 @@ __device__ void split_leaf(const Params &P, uint64_t j, uint32_t wid, WaveLds &l
   for (uint64_t b = wid;; b += P.workers) {
     const uint64_t bst = bcast64(load_relaxed(&P.best[j]));
     const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
-    if (b >= blocks_below(P.start_seed, lim, block)) break;
+    if (b >= (1ull << 40) || !chunk_below(b, block, P.start_seed, lim)) break;
     if (P.cancel != nullptr && *P.cancel != 0) {
       if (lane == 0) atomicOr(&P.gctr[kCtrErr], kErrCancel);
       break;
@@ -474,7 +487,7 @@ __device__ void split_leaf(const Params &P, uint64_t j, uint32_t wid, WaveLds &l
     const uint64_t base = P.start_seed + b * block;
     const uint64_t end = (lim - base) < block ? lim : base + block;
     st.blocks += 1;
-    const uint64_t found = search_range<SPL>(P, j, n, base, end, (uint32_t)ai, (uint32_t)(ai >> 32), lds, st);
+    const uint64_t found = search_range<SPL>(P, j, n, base, end, true, (uint32_t)ai, (uint32_t)(ai >> 32), lds, st);
     if (found != kNone) wave_atomic_min_wait(&P.best[j], found);
   }
   uint32_t c = 0;
@@ -526,7 +539,7 @@ __device__ uint64_t find_help_leaf(const Params &P, uint32_t wid) {
       const uint64_t stw = load_relaxed(&P.state[leaf]);
       const uint64_t bst = load_relaxed(&P.best[leaf]);
       const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
-      open = !(stw & kFinalBit) && (stw & kBlockMask) < blocks_below(P.start_seed, lim, P.unit);
+      open = !(stw & kFinalBit) && chunk_below(stw & kBlockMask, P.unit, P.start_seed, lim);
     }
     const uint64_t cand = __ballot(open);
     if (cand != 0) {
@@ -561,6 +574,8 @@ __global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
   uint32_t *wg_exits = reinterpret_cast<uint32_t *>(reinterpret_cast<WaveLds *>(lds_raw) + wpw);
   const uint32_t wid = blockIdx.x * wpw + wave;
   WaveStats st;
+  // A batch that failed validation (checked by prepare_kernel) is not searched.
+  if (__hip_atomic_load(&P.gctr[kCtrErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kErrInvalid | kErrDup)) return;
   if (P.split) {
     if (threadIdx.x == 0) *wg_exits = 0;
     __syncthreads();
@@ -586,11 +601,14 @@ __global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
       helper = true;
       j = find_help_leaf(P, wid);
       if (j == kNone) {
-        if (load_relaxed(&P.lctr[kLcDone]) >= P.leaf_count) break;
-        if (++idle_rounds > (1u << 20)) break;  // never expected; keeps the wait bounded
-        __builtin_amdgcn_s_sleep(8);
+        // Nothing open to help: leave, so that a kernel queued behind this
+        // one can use the slot.  A few retries cover owners that have not yet
+        // published their leaf.
+        if (load_relaxed(&P.lctr[kLcDone]) >= P.leaf_count || ++idle_rounds > 16) break;
+        __builtin_amdgcn_s_sleep(32);
         continue;
       }
+      idle_rounds = 0;
     }
     if (P.leaf_count > 64 && lane == 0) __hip_atomic_store(&P.wleaf[wid], (uint32_t)j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     work_leaf<SPL>(P, j, helper, lds, st);
@@ -641,15 +659,18 @@ __global__ void init_counters_kernel(unsigned long long *gctr, unsigned long lon
   if (i < workers) wleaf[i] = 0xFFFFFFFFu;
 }
 
-// Leaves left unfinished by a cancelled call report "no seed".
-__global__ void mark_unfinished_kernel(const unsigned long long *state, uint64_t n_leaves, uint64_t *out_seeds,
-                                       uint64_t *out_orient) {
+// Leaves left unfinished by a cancelled call report "no seed".  Does nothing
+// unless the call was cancelled.
+__global__ void mark_unfinished_kernel(const unsigned long long *gctr, const unsigned long long *state,
+                                       uint64_t n_leaves, uint64_t *out_seeds, uint64_t *out_orient) {
   const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (!(gctr[kCtrErr] & kErrCancel) || (gctr[kCtrErr] & (kErrInvalid | kErrDup))) return;
   if (j < n_leaves && !(state[j] & kFinalBit)) {
     out_seeds[j] = kNone;
     out_orient[j] = 0;
   }
 }
+
 
 // ------------------------------------------------------------------ host --
 
@@ -669,15 +690,8 @@ void set_err(const char *what, hipError_t e) {
     }                                 \
   } while (0)
 
-// Scratch cache per device, grown on demand and reused by later calls.
-struct Scratch {
-  void *buf = nullptr;
-  size_t bytes = 0;
-  void *host_ctr = nullptr;  // pinned copy of the global counters
-};
-std::mutex g_mu;
-std::vector<Scratch> g_scratch;
-
+// Scratch of one call: premixed keys, claim words, best seeds, the worker
+// table and counters.
 struct Layout {
   size_t premix, state, best, wleaf, gctr, lctr, total;
 };
@@ -695,6 +709,231 @@ Layout layout(uint64_t n_leaves, uint32_t workers, uint64_t n_launches) {
   l.total = o;
   return l;
 }
+
+// Rough expected number of seeds per leaf of n keys: the bound of the
+// construction theorem, (e/2)^n * e / sqrt(pi) (Section 5), shrunk by
+// 1.5 sqrt(n), which tracks the exact loop-free expectation within ~20% for
+// 16 <= n <= 64.  Only used to size launches.
+double expected_seeds(uint32_t n) {
+  if (n < 2) return 1.0;
+  const double e = 2.718281828459045;
+  double v = 1.0;
+  for (uint32_t i = 0; i < n; ++i) v *= e / 2.0;
+  v *= e / 1.7724538509055159 / (1.5 * sqrt((double)n));
+  return v < 1.0 ? 1.0 : v;
+}
+
+// Default claim size (units of 64*spl seeds) for a leaf of n keys: small
+// leaves finish in a few iterations, large ones amortise the claim atomic.
+int default_units(uint32_t n) {
+  if (n <= 24) return 1;
+  if (n <= 40) return 4;
+  if (n <= 52) return 16;
+  return 32;
+}
+
+// Workers for a single-leaf (split) launch: enough blocks to cover about
+// twice the expected seed count in one round, at least one workgroup.
+int plain_workers(uint32_t n, uint64_t block, int wpw, int max_workers) {
+  double w = 2.0 * expected_seeds(n) / (double)block;
+  int wi = w > max_workers ? max_workers : (int)w;
+  if (wi < wpw) wi = wpw;
+  return (wi / wpw) * wpw;
+}
+
+template <int SPL>
+hipError_t launch_search(const Params &P, int wpw, hipStream_t stream) {
+  const uint32_t wgs = P.workers / wpw;
+  hipLaunchKernelGGL(search_kernel<SPL>, dim3(wgs), dim3(64 * wpw), sizeof(WaveLds) * wpw + 16, stream, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_search_spl(int spl, const Params &P, int wpw, hipStream_t stream) {
+  switch (spl) {
+    case 1: return launch_search<1>(P, wpw, stream);
+    case 4: return launch_search<4>(P, wpw, stream);
+    default: return launch_search<2>(P, wpw, stream);
+  }
+}
+
+// Resident workers the device holds for a search kernel configuration
+// (cached per device, seeds per lane and waves per workgroup).
+int resident_workers(int spl, int wpw) {
+  static std::mutex mu;
+  static int cache[16][5][kMaxWavesPerWg + 1];
+  int dev = 0, cus = 256, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  const int si = spl == 1 ? 1 : spl == 4 ? 4 : 2;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev < 16 && cache[dev][si][wpw] > 0) return cache[dev][si][wpw];
+  }
+  {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+  }
+  const void *fn = spl == 1 ? (const void *)search_kernel<1> : spl == 4 ? (const void *)search_kernel<4>
+                                                                          : (const void *)search_kernel<2>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * wpw, sizeof(WaveLds) * wpw + 16) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 32 / wpw;
+  const int w = per_cu * cus * wpw;
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev < 16) cache[dev][si][wpw] = w;
+  return w;
+}
+
+// Everything needed to enqueue one call.
+struct Plan {
+  int mode;
+  int spl, units, wpw, workers;
+  uint64_t n_launches;
+  uint16_t units_by_n[65];
+};
+
+int make_plan(const shock_opts &opts, uint64_t n_leaves, uint32_t n_typical, Plan &pl) {
+  pl.mode = opts.mode == SHOCK_MODE_AUTO ? SHOCK_MODE_PERSISTENT : opts.mode;
+  if (pl.mode != SHOCK_MODE_PERSISTENT && pl.mode != SHOCK_MODE_PLAIN_PER_LEAF) return SHOCK_EINVAL;
+  pl.spl = opts.spl ? opts.spl : 2;
+  pl.wpw = opts.waves_per_wg ? opts.waves_per_wg : 4;
+  pl.units = opts.block_iters ? opts.block_iters
+                              : (pl.mode == SHOCK_MODE_PLAIN_PER_LEAF ? 1 : default_units(n_typical));
+  for (int n = 0; n <= 64; ++n) {
+    int u = opts.block_iters ? opts.block_iters : default_units((uint32_t)n);
+    if (opts.block_iters_by_n && opts.block_iters_by_n[n] > 0) u = opts.block_iters_by_n[n];
+    pl.units_by_n[n] = (uint16_t)(u > 65535 ? 65535 : u);
+  }
+  int w = opts.workers ? opts.workers : resident_workers(pl.spl, pl.wpw);
+  w = ((w + pl.wpw - 1) / pl.wpw) * pl.wpw;
+  if (w <= 0) return SHOCK_EINVAL;
+  pl.workers = w;
+  pl.n_launches = pl.mode == SHOCK_MODE_PLAIN_PER_LEAF ? n_leaves : 1;
+  return SHOCK_OK;
+}
+
+int check_opts(const shock_opts &opts, uint64_t n_leaves, const void *offsets, const void *out_seeds,
+               const void *out_orient) {
+  if (!offsets || !out_seeds || !out_orient) return SHOCK_EINVAL;
+  if (n_leaves > (1ull << 31)) return SHOCK_EINVAL;
+  if (opts.max_seed > (1ull << 63)) return SHOCK_EINVAL;
+  if (opts.spl != 0 && opts.spl != 1 && opts.spl != 2 && opts.spl != 4) return SHOCK_EINVAL;
+  if (opts.block_iters < 0 || opts.block_iters > (1 << 16)) return SHOCK_EINVAL;
+  if (opts.waves_per_wg < 0 || opts.waves_per_wg > kMaxWavesPerWg) return SHOCK_EINVAL;
+  if (opts.workers < 0 || opts.workers > (1 << 20)) return SHOCK_EINVAL;
+  if (opts.leaf_size_hint < 0 || opts.leaf_size_hint > 64) return SHOCK_EINVAL;
+  return SHOCK_OK;
+}
+
+// Device buffers and host mirrors of one call.
+struct CallBufs {
+  uint64_t *premix;
+  unsigned long long *state, *best, *gctr, *lctr;
+  unsigned int *wleaf;
+};
+
+CallBufs carve(void *buf, const Layout &lay) {
+  char *b = (char *)buf;
+  CallBufs c;
+  c.premix = (uint64_t *)(b + lay.premix);
+  c.state = (unsigned long long *)(b + lay.state);
+  c.best = (unsigned long long *)(b + lay.best);
+  c.wleaf = (unsigned int *)(b + lay.wleaf);
+  c.gctr = (unsigned long long *)(b + lay.gctr);
+  c.lctr = (unsigned long long *)(b + lay.lctr);
+  return c;
+}
+
+hipError_t enqueue_prologue(const CallBufs &cb, const Plan &pl, const uint64_t *keys, const uint64_t *offsets,
+                            uint64_t n_leaves, int check_dups, uint32_t workers_cap, hipStream_t stream) {
+  const uint64_t n_l = pl.n_launches * kLcCount;
+  uint64_t m = n_l > (uint64_t)workers_cap ? n_l : (uint64_t)workers_cap;
+  if (m < (uint64_t)kCtrGlobalCount) m = kCtrGlobalCount;
+  hipLaunchKernelGGL(init_counters_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, cb.gctr, cb.lctr,
+                     n_l, cb.wleaf, workers_cap);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)((n_leaves + 3) / 4)), dim3(256), 0, stream, keys, offsets,
+                     n_leaves, cb.premix, cb.state, cb.best, cb.gctr, check_dups);
+  return hipGetLastError();
+}
+
+Params base_params(const CallBufs &cb, const Plan &pl, const shock_opts &opts, const uint64_t *offsets,
+                   uint64_t *out_seeds, uint64_t *out_orient) {
+  Params P;
+  memset(&P, 0, sizeof(P));
+  P.offsets = offsets;
+  P.premix = cb.premix;
+  P.start_seed = opts.start_seed;
+  P.max_seed = opts.max_seed;
+  P.out_seeds = out_seeds;
+  P.out_orient = out_orient;
+  P.state = cb.state;
+  P.best = cb.best;
+  P.wleaf = cb.wleaf;
+  P.gctr = cb.gctr;
+  P.cancel = opts.cancel;
+  P.block_iters = (uint32_t)pl.units;
+  P.unit = 64ull * (uint64_t)pl.spl;
+  P.block = P.unit * (uint64_t)pl.units;
+  P.workers = (uint32_t)pl.workers;
+  memcpy(P.units_by_n, pl.units_by_n, sizeof(P.units_by_n));
+  return P;
+}
+
+// Enqueue the search kernel(s).  leaf_sizes (host, n_leaves + 1 offsets) sizes
+// per-leaf launches when known; otherwise n_typical is used for every leaf.
+hipError_t enqueue_search(Params P, const CallBufs &cb, const Plan &pl, uint64_t n_leaves, const uint64_t *h_off,
+                          uint32_t n_typical, bool workers_fixed, hipStream_t stream) {
+  if (pl.mode == SHOCK_MODE_PERSISTENT) {
+    P.leaf_begin = 0;
+    P.leaf_count = n_leaves;
+    P.lctr = cb.lctr;
+    P.split = 0;
+    return launch_search_spl(pl.spl, P, pl.wpw, stream);
+  }
+  P.split = 1;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    P.leaf_begin = j;
+    P.leaf_count = 1;
+    P.lctr = cb.lctr + j * kLcCount;
+    const uint32_t nj = h_off ? (uint32_t)(h_off[j + 1] - h_off[j]) : n_typical;
+    P.workers = workers_fixed ? (uint32_t)pl.workers : (uint32_t)plain_workers(nj, P.block, pl.wpw, pl.workers);
+    hipError_t e = launch_search_spl(pl.spl, P, pl.wpw, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int status_from(const unsigned long long *host_ctr, shock_stats *st) {
+  if (st) {
+    for (int i = 0; i < kStatSlots; ++i) {
+      const unsigned long long *slot = host_ctr + kCtrStats + i * 4;
+      st->seeds_tested += slot[kStSeeds];
+      st->filter_passes += slot[kStPasses];
+      st->pf_checks += slot[kStPf];
+      st->blocks_claimed += slot[kStBlocks];
+    }
+  }
+  const uint64_t err = host_ctr[kCtrErr];
+  if (err & kErrInvalid) return SHOCK_EINVAL;
+  if (err & kErrDup) return SHOCK_EDUPKEY;
+  if (err & kErrOrient) {
+    snprintf(g_err, sizeof(g_err), "internal error: orientation of an accepted seed is not a bijection");
+    return SHOCK_EHIP;
+  }
+  if (err & kErrCancel) return SHOCK_ECANCELED;
+  if (host_ctr[kCtrNotFound] != 0) return SHOCK_ENOTFOUND;
+  return SHOCK_OK;
+}
+
+// Per-device scratch cache of the synchronous entry points.
+struct Scratch {
+  void *buf = nullptr;
+  size_t bytes = 0;
+  void *host_ctr = nullptr;  // pinned copy of the global counters
+};
+std::mutex g_mu;
+std::vector<Scratch> g_scratch;
 
 int get_scratch(size_t bytes, void **buf, unsigned long long **host_ctr) {
   int dev = 0;
@@ -728,72 +967,23 @@ int get_scratch(size_t bytes, void **buf, unsigned long long **host_ctr) {
   return SHOCK_OK;
 }
 
-struct Tuning {
-  int spl, block_iters, waves_per_wg;
-};
-
-// Rough expected number of seeds per leaf of n keys: the bound of the
-// construction theorem, (e/2)^n * e / sqrt(pi) (Section 5), shrunk by
-// 1.5 sqrt(n), which tracks the exact loop-free expectation within ~20% for
-// 16 <= n <= 64.  Only used to size launches.
-double expected_seeds(uint32_t n) {
-  if (n < 2) return 1.0;
-  const double e = 2.718281828459045;
-  double v = 1.0;
-  for (uint32_t i = 0; i < n; ++i) v *= e / 2.0;
-  v *= e / 1.7724538509055159 / (1.5 * sqrt((double)n));
-  return v < 1.0 ? 1.0 : v;
-}
-
-// Defaults by leaf size; the Python autotuner may override per call.
-Tuning default_tuning(uint32_t n_hint, int mode) {
-  Tuning t;
-  t.spl = 2;
-  t.waves_per_wg = 4;
-  if (n_hint <= 24) t.block_iters = 1;
-  else if (n_hint <= 40) t.block_iters = 4;
-  else if (n_hint <= 52) t.block_iters = 16;
-  else t.block_iters = 32;
-  if (mode == SHOCK_MODE_PLAIN_PER_LEAF) t.block_iters = 1;
-  return t;
-}
-
-// Workers for a single-leaf (split) launch: enough 64*spl-seed blocks to cover
-// about twice the expected seed count in one round, at least one workgroup.
-int plain_workers(uint32_t n, int spl, int block_iters, int wpw, int max_workers) {
-  const double per = 64.0 * spl * block_iters;
-  double w = 2.0 * expected_seeds(n) / per;
-  int wi = w > max_workers ? max_workers : (int)w;
-  if (wi < wpw) wi = wpw;
-  return (wi / wpw) * wpw;
-}
-
-int device_workers(int waves_per_wg) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 256 * 16;
-  hipDeviceProp_t p;
-  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 256 * 16;
-  // 8 waves per SIMD, 4 SIMDs per CU.
-  const int waves = p.multiProcessorCount * 32;
-  return (waves / waves_per_wg) * waves_per_wg;
-}
-
-template <int SPL>
-hipError_t launch_search(const Params &P, int wpw, hipStream_t stream) {
-  const uint32_t wgs = P.workers / wpw;
-  hipLaunchKernelGGL(search_kernel<SPL>, dim3(wgs), dim3(64 * wpw), sizeof(WaveLds) * wpw + 16, stream, P);
-  return hipGetLastError();
-}
-
-hipError_t launch_search_spl(int spl, const Params &P, int wpw, hipStream_t stream) {
-  switch (spl) {
-    case 1: return launch_search<1>(P, wpw, stream);
-    case 4: return launch_search<4>(P, wpw, stream);
-    default: return launch_search<2>(P, wpw, stream);
-  }
-}
-
 }  // namespace
+
+// A search context: its own scratch for batches of up to max_leaves leaves,
+// pinned counters, events and an optional captured graph.
+struct shock_ctx {
+  int device = 0;
+  uint64_t max_leaves = 0;
+  uint32_t workers_cap = 0;
+  void *buf = nullptr;
+  size_t bytes = 0;
+  unsigned long long *host_ctr = nullptr;
+  hipEvent_t ev_begin = nullptr, ev_search = nullptr, ev_done = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  Plan last_plan{};
+  bool pending = false;
+};
 
 extern "C" {
 
@@ -848,55 +1038,31 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
   if (opts.max_seed == 0) opts.max_seed = SHOCK_DEFAULT_MAX_SEED;
   memset(&g_stats, 0, sizeof(g_stats));
   if (n_leaves == 0) return SHOCK_OK;
-  if (!offsets || !out_seeds || !out_orient) return SHOCK_EINVAL;
-  if (n_leaves > (1ull << 31)) return SHOCK_EINVAL;
-  if (opts.spl != 0 && opts.spl != 1 && opts.spl != 2 && opts.spl != 4) return SHOCK_EINVAL;
-  if (opts.block_iters < 0 || opts.block_iters > (1 << 16)) return SHOCK_EINVAL;
-  if (opts.waves_per_wg < 0 || opts.waves_per_wg > kMaxWavesPerWg) return SHOCK_EINVAL;
-  if (opts.workers < 0) return SHOCK_EINVAL;
+  int rc = check_opts(opts, n_leaves, offsets, out_seeds, out_orient);
+  if (rc != SHOCK_OK) return rc;
+  if (!keys) return SHOCK_EINVAL;
+  hipStream_t stream = (hipStream_t)hip_stream;
   const int mode = opts.mode == SHOCK_MODE_AUTO ? SHOCK_MODE_PERSISTENT : opts.mode;
   if (mode != SHOCK_MODE_PERSISTENT && mode != SHOCK_MODE_PLAIN_PER_LEAF) return SHOCK_EINVAL;
-  hipStream_t stream = (hipStream_t)hip_stream;
 
   // Scratch is laid out for the largest worker count any launch may use.
-  const int wpw_max_workers = device_workers(1);
-  const int max_workers = opts.workers > wpw_max_workers ? opts.workers : wpw_max_workers;
-  const int workers_cap = max_workers + kMaxWavesPerWg;
+  const int workers_cap = (opts.workers > 32 * 256 * 4 ? opts.workers : 32 * 256 * 4) + kMaxWavesPerWg;
   const uint64_t n_launches = mode == SHOCK_MODE_PLAIN_PER_LEAF ? n_leaves : 1;
-
   const Layout lay = layout(n_leaves, (uint32_t)workers_cap, n_launches);
   void *buf = nullptr;
   unsigned long long *host_ctr = nullptr;
-  int rc = get_scratch(lay.total, &buf, &host_ctr);
+  rc = get_scratch(lay.total, &buf, &host_ctr);
   if (rc != SHOCK_OK) return rc;
-  char *b = (char *)buf;
-  uint64_t *premix = (uint64_t *)(b + lay.premix);
-  unsigned long long *state = (unsigned long long *)(b + lay.state);
-  unsigned long long *best = (unsigned long long *)(b + lay.best);
-  unsigned int *wleaf = (unsigned int *)(b + lay.wleaf);
-  unsigned long long *gctr = (unsigned long long *)(b + lay.gctr);
-  unsigned long long *lctr = (unsigned long long *)(b + lay.lctr);
+  const CallBufs cb = carve(buf, lay);
 
-  {
-    const uint64_t n_l = n_launches * kLcCount;
-    uint64_t m = n_l > (uint64_t)workers_cap ? n_l : (uint64_t)workers_cap;
-    if (m < kCtrGlobalCount) m = kCtrGlobalCount;
-    hipLaunchKernelGGL(init_counters_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, gctr, lctr, n_l,
-                       wleaf, (uint32_t)workers_cap);
-    HIP_TRY(hipGetLastError());
-  }
-  if (!keys) {
-    // Only an all-empty batch may pass no keys; the prepare kernel cannot
-    // tell, so require a pointer.
-    return SHOCK_EINVAL;
-  }
-  hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)((n_leaves + 3) / 4)), dim3(256), 0, stream, keys, offsets,
-                     n_leaves, premix, state, best, gctr, opts.check_dups);
-  HIP_TRY(hipGetLastError());
-  // Leaf sizes for launch sizing: all offsets for per-leaf launches, the
-  // first and last otherwise (mean leaf size).
+  Plan pl;
+  rc = make_plan(opts, n_leaves, 48, pl);
+  if (rc != SHOCK_OK) return rc;
+  HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts.check_dups, (uint32_t)workers_cap, stream));
+  // Validation result and leaf sizes for launch sizing: all offsets for
+  // per-leaf launches, the first and last otherwise (mean leaf size).
   std::vector<uint64_t> h_off(mode == SHOCK_MODE_PLAIN_PER_LEAF ? n_leaves + 1 : 2);
-  HIP_TRY(hipMemcpyAsync(host_ctr, gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(host_ctr, cb.gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
   if (mode == SHOCK_MODE_PLAIN_PER_LEAF) {
     HIP_TRY(hipMemcpyAsync(h_off.data(), offsets, (n_leaves + 1) * 8, hipMemcpyDeviceToHost, stream));
   } else {
@@ -907,94 +1073,216 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
   if (host_ctr[kCtrErr] & kErrInvalid) return SHOCK_EINVAL;
   if (host_ctr[kCtrErr] & kErrDup) return SHOCK_EDUPKEY;
 
-  // Launch parameters: defaults from the mean leaf size, explicit options win.
   const uint32_t n_mean = (uint32_t)((h_off.back() - h_off.front() + n_leaves / 2) / n_leaves);
-  Tuning tune = default_tuning(n_mean, mode);
-  if (opts.spl) tune.spl = opts.spl;
-  if (opts.block_iters) tune.block_iters = opts.block_iters;
-  if (opts.waves_per_wg) tune.waves_per_wg = opts.waves_per_wg;
-  int workers = opts.workers ? opts.workers : device_workers(tune.waves_per_wg);
-  workers = ((workers + tune.waves_per_wg - 1) / tune.waves_per_wg) * tune.waves_per_wg;
-  if (workers <= 0 || workers > workers_cap) return SHOCK_EINVAL;
-
-  Params P;
-  P.offsets = offsets;
-  P.premix = premix;
-  P.start_seed = opts.start_seed;
-  P.max_seed = opts.max_seed;
-  P.out_seeds = out_seeds;
-  P.out_orient = out_orient;
-  P.state = state;
-  P.best = best;
-  P.wleaf = wleaf;
-  P.gctr = gctr;
-  P.cancel = opts.cancel;
-  P.block_iters = (uint32_t)tune.block_iters;
-  P.block = 64ull * (uint64_t)tune.spl * (uint64_t)tune.block_iters;
-  P.unit = 64ull * (uint64_t)tune.spl;
-  P.split = 0;
-  P.workers = (uint32_t)workers;
+  rc = make_plan(opts, n_leaves, n_mean, pl);
+  if (rc != SHOCK_OK) return rc;
+  if (pl.workers > workers_cap) return SHOCK_EINVAL;
+  Params P = base_params(cb, pl, opts, offsets, out_seeds, out_orient);
 
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, stream));
-  if (mode == SHOCK_MODE_PERSISTENT) {
-    P.leaf_begin = 0;
-    P.leaf_count = n_leaves;
-    P.lctr = lctr;
-    HIP_TRY(launch_search_spl(tune.spl, P, tune.waves_per_wg, stream));
-  } else {
-    P.split = 1;
-    for (uint64_t j = 0; j < n_leaves; ++j) {
-      P.leaf_begin = j;
-      P.leaf_count = 1;
-      P.lctr = lctr + j * kLcCount;
-      const uint32_t nj = (uint32_t)(h_off[j + 1] - h_off[j]);
-      P.workers = opts.workers ? (uint32_t)workers
-                               : (uint32_t)plain_workers(nj, tune.spl, tune.block_iters, tune.waves_per_wg, workers);
-      HIP_TRY(launch_search_spl(tune.spl, P, tune.waves_per_wg, stream));
-    }
-  }
+  HIP_TRY(enqueue_search(P, cb, pl, n_leaves, mode == SHOCK_MODE_PLAIN_PER_LEAF ? h_off.data() : nullptr, n_mean,
+                         opts.workers != 0, stream));
   HIP_TRY(hipEventRecord(e1, stream));
-  bool cancelled = false;
-  HIP_TRY(hipMemcpyAsync(host_ctr, gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
+  hipLaunchKernelGGL(mark_unfinished_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, stream, cb.gctr,
+                     cb.state, n_leaves, out_seeds, out_orient);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(host_ctr, cb.gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
-  if (host_ctr[kCtrErr] & kErrCancel) {
-    cancelled = true;
-    hipLaunchKernelGGL(mark_unfinished_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, stream, state,
-                       n_leaves, out_seeds, out_orient);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(stream));
-  }
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
   HIP_TRY(hipEventDestroy(e0));
   HIP_TRY(hipEventDestroy(e1));
-  for (int i = 0; i < kStatSlots; ++i) {
-    const unsigned long long *slot = host_ctr + kCtrStats + i * 4;
-    g_stats.seeds_tested += slot[kStSeeds];
-    g_stats.filter_passes += slot[kStPasses];
-    g_stats.pf_checks += slot[kStPf];
-    g_stats.blocks_claimed += slot[kStBlocks];
-  }
+  rc = status_from(host_ctr, &g_stats);
   g_stats.kernel_ms = ms;
   g_stats.workers = (int32_t)P.workers;
-  g_stats.spl = tune.spl;
-  g_stats.block_iters = tune.block_iters;
-  g_stats.waves_per_wg = tune.waves_per_wg;
-  if (host_ctr[kCtrErr] & kErrOrient) {
-    snprintf(g_err, sizeof(g_err), "internal error: orientation of an accepted seed is not a bijection");
-    return SHOCK_EHIP;
-  }
-  if (cancelled) return SHOCK_ECANCELED;
-  if (host_ctr[kCtrNotFound] != 0) return SHOCK_ENOTFOUND;
-  return SHOCK_OK;
+  g_stats.spl = pl.spl;
+  g_stats.block_iters = pl.units;
+  g_stats.waves_per_wg = pl.wpw;
+  return rc;
 }
 
 int shock_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_seeds,
                       uint64_t *out_orient) {
   return shock_leaf_search_ex(keys, offsets, n_leaves, out_seeds, out_orient, nullptr, nullptr);
+}
+
+int shock_ctx_create(uint64_t max_leaves, shock_ctx **out) {
+  if (!out || max_leaves == 0 || max_leaves > (1ull << 31)) return SHOCK_EINVAL;
+  *out = nullptr;
+  shock_ctx *c = new shock_ctx();
+  HIP_TRY(hipGetDevice(&c->device));
+  c->max_leaves = max_leaves;
+  c->workers_cap = 32 * 256 * 4 + kMaxWavesPerWg;
+  const Layout lay = layout(max_leaves, c->workers_cap, max_leaves);
+  c->bytes = lay.total;
+  hipError_t e = hipMalloc(&c->buf, c->bytes);
+  if (e != hipSuccess) {
+    set_err("hipMalloc(context scratch)", e);
+    delete c;
+    return SHOCK_ENOMEM;
+  }
+  e = hipHostMalloc((void **)&c->host_ctr, kCtrGlobalCount * 8, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    set_err("hipHostMalloc(context counters)", e);
+    (void)hipFree(c->buf);
+    delete c;
+    return SHOCK_ENOMEM;
+  }
+  memset(c->host_ctr, 0, kCtrGlobalCount * 8);
+  if (hipEventCreate(&c->ev_begin) != hipSuccess || hipEventCreate(&c->ev_search) != hipSuccess ||
+      hipEventCreate(&c->ev_done) != hipSuccess) {
+    set_err("hipEventCreate", hipErrorUnknown);
+    return SHOCK_EHIP;
+  }
+  *out = c;
+  return SHOCK_OK;
+}
+
+int shock_ctx_destroy(shock_ctx *c) {
+  if (!c) return SHOCK_EINVAL;
+  (void)hipSetDevice(c->device);
+  if (c->pending) (void)hipEventSynchronize(c->ev_done);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  (void)hipEventDestroy(c->ev_begin);
+  (void)hipEventDestroy(c->ev_search);
+  (void)hipEventDestroy(c->ev_done);
+  (void)hipHostFree(c->host_ctr);
+  (void)hipFree(c->buf);
+  delete c;
+  return SHOCK_OK;
+}
+
+// Enqueue the whole call on `stream` without any host synchronisation.
+static int ctx_enqueue(shock_ctx *c, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                       uint64_t *out_seeds, uint64_t *out_orient, const shock_opts &opts, hipStream_t stream,
+                       bool with_events) {
+  const CallBufs cb = carve(c->buf, layout(c->max_leaves, c->workers_cap, c->max_leaves));
+  Plan pl;
+  const uint32_t hint = opts.leaf_size_hint ? (uint32_t)opts.leaf_size_hint : 48;
+  int rc = make_plan(opts, n_leaves, hint, pl);
+  if (rc != SHOCK_OK) return rc;
+  if (pl.workers > (int)c->workers_cap) return SHOCK_EINVAL;
+  HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts.check_dups, c->workers_cap, stream));
+  Params P = base_params(cb, pl, opts, offsets, out_seeds, out_orient);
+  if (with_events) HIP_TRY(hipEventRecord(c->ev_begin, stream));
+  HIP_TRY(enqueue_search(P, cb, pl, n_leaves, nullptr, hint, opts.workers != 0, stream));
+  if (with_events) HIP_TRY(hipEventRecord(c->ev_search, stream));
+  hipLaunchKernelGGL(mark_unfinished_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, stream, cb.gctr,
+                     cb.state, n_leaves, out_seeds, out_orient);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->host_ctr, cb.gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
+  c->last_plan = pl;
+  return SHOCK_OK;
+}
+
+int shock_ctx_search_async(shock_ctx *c, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                           uint64_t *out_seeds, uint64_t *out_orient, const shock_opts *opts_in, void *hip_stream) {
+  if (!c) return SHOCK_EINVAL;
+  shock_opts opts;
+  shock_opts_init(&opts);
+  if (opts_in) opts = *opts_in;
+  if (opts.max_seed == 0) opts.max_seed = SHOCK_DEFAULT_MAX_SEED;
+  if (n_leaves == 0 || n_leaves > c->max_leaves || !keys) return SHOCK_EINVAL;
+  int rc = check_opts(opts, n_leaves, offsets, out_seeds, out_orient);
+  if (rc != SHOCK_OK) return rc;
+  if (c->pending) HIP_TRY(hipEventSynchronize(c->ev_done));  // the counters buffer is reused
+  hipStream_t stream = (hipStream_t)hip_stream;
+  rc = ctx_enqueue(c, keys, offsets, n_leaves, out_seeds, out_orient, opts, stream, true);
+  if (rc != SHOCK_OK) return rc;
+  HIP_TRY(hipEventRecord(c->ev_done, stream));
+  c->pending = true;
+  return SHOCK_OK;
+}
+
+int shock_ctx_query(shock_ctx *c) {
+  if (!c) return SHOCK_EINVAL;
+  if (!c->pending) return 1;
+  hipError_t e = hipEventQuery(c->ev_done);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  set_err("hipEventQuery", e);
+  return SHOCK_EHIP;
+}
+
+int shock_ctx_wait(shock_ctx *c, shock_stats *stats) {
+  if (!c) return SHOCK_EINVAL;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (!c->pending) return SHOCK_EINVAL;
+  HIP_TRY(hipEventSynchronize(c->ev_done));
+  c->pending = false;
+  int rc = status_from(c->host_ctr, stats);
+  if (stats) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev_begin, c->ev_search) == hipSuccess) stats->kernel_ms = ms;
+    stats->workers = c->last_plan.workers;
+    stats->spl = c->last_plan.spl;
+    stats->block_iters = c->last_plan.units;
+    stats->waves_per_wg = c->last_plan.wpw;
+  }
+  return rc;
+}
+
+int shock_ctx_graph_capture(shock_ctx *c, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                            uint64_t *out_seeds, uint64_t *out_orient, const shock_opts *opts_in, void *hip_stream) {
+  if (!c) return SHOCK_EINVAL;
+  shock_opts opts;
+  shock_opts_init(&opts);
+  if (opts_in) opts = *opts_in;
+  if (opts.max_seed == 0) opts.max_seed = SHOCK_DEFAULT_MAX_SEED;
+  if (n_leaves == 0 || n_leaves > c->max_leaves || !keys) return SHOCK_EINVAL;
+  int rc = check_opts(opts, n_leaves, offsets, out_seeds, out_orient);
+  if (rc != SHOCK_OK) return rc;
+  if (opts.cancel) return SHOCK_EINVAL;  // a captured graph cannot watch a host flag reliably across replays
+  if (c->pending) HIP_TRY(hipEventSynchronize(c->ev_done));
+  c->pending = false;
+  if (c->graph_exec) {
+    HIP_TRY(hipGraphExecDestroy(c->graph_exec));
+    c->graph_exec = nullptr;
+  }
+  if (c->graph) {
+    HIP_TRY(hipGraphDestroy(c->graph));
+    c->graph = nullptr;
+  }
+  {
+    Plan warm;  // resolves and caches occupancy queries before capture starts
+    rc = make_plan(opts, n_leaves, opts.leaf_size_hint ? (uint32_t)opts.leaf_size_hint : 48, warm);
+    if (rc != SHOCK_OK) return rc;
+  }
+  hipStream_t cap;
+  HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  rc = ctx_enqueue(c, keys, offsets, n_leaves, out_seeds, out_orient, opts, cap, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cap, &g);
+  (void)hipStreamDestroy(cap);
+  if (rc != SHOCK_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    set_err("hipStreamEndCapture", e);
+    return SHOCK_EHIP;
+  }
+  c->graph = g;
+  HIP_TRY(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+  (void)hip_stream;
+  return SHOCK_OK;
+}
+
+int shock_ctx_graph_launch(shock_ctx *c, void *hip_stream) {
+  if (!c || !c->graph_exec) return SHOCK_EINVAL;
+  if (c->pending) HIP_TRY(hipEventSynchronize(c->ev_done));
+  hipStream_t stream = (hipStream_t)hip_stream;
+  HIP_TRY(hipEventRecord(c->ev_begin, stream));
+  HIP_TRY(hipGraphLaunch(c->graph_exec, stream));
+  HIP_TRY(hipEventRecord(c->ev_search, stream));
+  HIP_TRY(hipEventRecord(c->ev_done, stream));
+  c->pending = true;
+  return SHOCK_OK;
 }
 
 }  // extern "C"

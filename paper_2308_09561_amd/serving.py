@@ -1,0 +1,261 @@
+"""Serving loop: continuous batching of MPHF-build requests on one GPU.
+
+A request carries N keys.  It is cut into leaves of `leaf_size` keys in input
+order, plus one remainder leaf, and its build is done when every leaf has its
+smallest seed and orientation.  The loop keeps up to `slots` batches in
+flight, each on its own search context and HIP stream:
+
+* Requests that arrive while others are on the GPU wait in a FIFO queue.
+* A free slot takes as many queued requests, in order, as the HBM budget and
+  the slot's capacity allow.
+* The slot uploads their keys, enqueues the search asynchronously and moves
+  on. Batches on different streams run concurrently: a persistent kernel's
+  idle workers leave once nothing is open in their batch, and a newer batch's
+  workgroups take their place.
+* When a slot's search completes, its results are copied back and its
+  requests are complete.
+
+Latency of a request = completion time - arrival time.  The device memory a
+request holds while admitted (its keys, offsets, outputs and its share of the
+search scratch) counts against the budget.  A request alone larger than the
+budget is rejected; a request still queued past its deadline times out.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .binding import SHOCK_OK, SearchContext
+
+SCRATCH_BYTES_PER_LEAF = 600  # premixed keys, claim word, best seed, counters
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the run
+    keys: np.ndarray        # uint64 keys (host)
+    deadline: float | None = None  # seconds after arrival; None = no deadline
+    # filled in by the server
+    offsets: np.ndarray | None = None
+    admitted: float | None = None
+    completed: float | None = None
+    status: str = "queued"
+    seeds: np.ndarray | None = None
+    orient: np.ndarray | None = None
+
+    @property
+    def n_leaves(self) -> int:
+        return len(self.offsets) - 1
+
+    def latency(self) -> float | None:
+        return None if self.completed is None else self.completed - self.arrival
+
+
+def leaf_offsets(n_keys: int, leaf_size: int) -> np.ndarray:
+    full = n_keys // leaf_size
+    offs = np.arange(full + 1, dtype=np.uint64) * np.uint64(leaf_size)
+    if n_keys % leaf_size:
+        offs = np.append(offs, np.uint64(n_keys))
+    return offs
+
+
+def footprint(n_keys: int, n_leaves: int) -> int:
+    """Device bytes a request holds while admitted."""
+    return 8 * n_keys + 8 * (n_leaves + 1) + 16 * n_leaves + SCRATCH_BYTES_PER_LEAF * n_leaves
+
+
+@dataclass
+class _Batch:
+    slot: int
+    reqs: list
+    leaf_base: list
+    bytes: int
+    keys_d: object = None
+    offs_d: object = None
+    seeds_d: object = None
+    orient_d: object = None
+    launched: float = 0.0
+
+
+@dataclass
+class ServeReport:
+    requests: list
+    makespan_s: float
+    max_bytes_in_flight: int
+    max_batches_in_flight: int
+    batches: int
+    extra: dict = field(default_factory=dict)
+
+    def summary(self) -> dict:
+        done = [r for r in self.requests if r.status == "done"]
+        lat = np.array([r.latency() for r in done], dtype=np.float64)
+        keys = float(sum(len(r.keys) for r in done))
+        leaves = float(sum(r.n_leaves for r in done))
+        return {
+            "requests": len(self.requests), "completed": len(done),
+            "timed_out": sum(r.status == "timeout" for r in self.requests),
+            "rejected": sum(r.status == "rejected" for r in self.requests),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+            "mean_ms": float(lat.mean() * 1e3) if lat.size else None,
+            "keys_per_s": keys / self.makespan_s if self.makespan_s > 0 else None,
+            "leaves_per_s": leaves / self.makespan_s if self.makespan_s > 0 else None,
+            "makespan_s": self.makespan_s, "batches": self.batches,
+            "max_bytes_in_flight": self.max_bytes_in_flight,
+            "max_batches_in_flight": self.max_batches_in_flight, **self.extra,
+        }
+
+
+class LeafServer:
+    def __init__(self, hbm_budget_bytes: int = 256 << 20, slots: int = 4, leaf_size: int = 48,
+                 max_batch_leaves: int = 1 << 16, search_opts: dict | None = None, device: str = "cuda:0"):
+        import torch
+
+        if leaf_size < 1 or leaf_size > 64:
+            raise ValueError("leaf_size must be in [1, 64]")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.budget = int(hbm_budget_bytes)
+        self.leaf_size = leaf_size
+        self.max_batch_leaves = max_batch_leaves
+        self.opts = dict(search_opts or {})
+        self.opts.setdefault("leaf_size_hint", leaf_size)
+        self.ctxs = [SearchContext(max_batch_leaves) for _ in range(slots)]
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+
+    def close(self):
+        for c in self.ctxs:
+            c.close()
+
+    # -- one batch -----------------------------------------------------------
+    def _launch(self, slot: int, reqs: list, now: float) -> _Batch:
+        torch = self.torch
+        keys = np.concatenate([r.keys for r in reqs]) if len(reqs) > 1 else reqs[0].keys
+        offs_parts, base, leaf_base = [], 0, []
+        lb = 0
+        for r in reqs:
+            offs_parts.append(r.offsets[:-1] + np.uint64(base))
+            leaf_base.append(lb)
+            base += len(r.keys)
+            lb += r.n_leaves
+        offs = np.append(np.concatenate(offs_parts), np.uint64(base))
+        L = len(offs) - 1
+        b = _Batch(slot=slot, reqs=reqs, leaf_base=leaf_base,
+                   bytes=sum(footprint(len(r.keys), r.n_leaves) for r in reqs), launched=now)
+        stream = self.streams[slot]
+        with torch.cuda.stream(stream):
+            kh = torch.from_numpy(np.ascontiguousarray(keys).view(np.int64)).pin_memory()
+            oh = torch.from_numpy(offs.view(np.int64)).pin_memory()
+            b.keys_d = kh.to(self.device, non_blocking=True)
+            b.offs_d = oh.to(self.device, non_blocking=True)
+            b.seeds_d = torch.empty(L, dtype=torch.int64, device=self.device)
+            b.orient_d = torch.empty(L, dtype=torch.int64, device=self.device)
+            rc = self.ctxs[slot].search_async(b.keys_d, b.offs_d, b.seeds_d, b.orient_d,
+                                              stream=stream.cuda_stream, **self.opts)
+        if rc != SHOCK_OK:
+            raise RuntimeError(f"search launch failed with status {rc}")
+        for r in reqs:
+            r.admitted = now
+            r.status = "running"
+        return b
+
+    def _finish(self, b: _Batch, now_fn):
+        rc, _ = self.ctxs[b.slot].wait()
+        seeds = b.seeds_d.cpu().numpy().view(np.uint64)
+        orient = b.orient_d.cpu().numpy().view(np.uint64)
+        t = now_fn()
+        for r, lb in zip(b.reqs, b.leaf_base):
+            r.seeds = seeds[lb:lb + r.n_leaves].copy()
+            r.orient = orient[lb:lb + r.n_leaves].copy()
+            r.completed = t
+            r.status = "done" if rc == SHOCK_OK else f"error {rc}"
+
+    # -- the loop ------------------------------------------------------------
+    def run(self, requests: list, realtime: bool = True) -> ServeReport:
+        """Serve requests (sorted by arrival).  With realtime=False every
+        request is treated as having arrived at time 0 (a backlog)."""
+        for r in requests:
+            r.offsets = leaf_offsets(len(r.keys), self.leaf_size)
+            r.status = "queued"
+            r.admitted = r.completed = None
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queue = collections.deque()
+        free_slots = list(range(len(self.ctxs)))
+        inflight = {}
+        bytes_in_flight = 0
+        max_bytes = 0
+        max_batches = 0
+        n_batches = 0
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0  # noqa: E731
+        while pending or queue or inflight:
+            t = now()
+            while pending and (not realtime or pending[0].arrival <= t):
+                queue.append(pending.popleft())
+            progressed = False
+            # completions
+            for slot, b in list(inflight.items()):
+                if self.ctxs[slot].query() == 1:
+                    self._finish(b, now)
+                    bytes_in_flight -= b.bytes
+                    del inflight[slot]
+                    free_slots.append(slot)
+                    progressed = True
+            # deadlines of queued requests
+            t = now()
+            kept = collections.deque()
+            for r in queue:
+                if r.deadline is not None and t - r.arrival > r.deadline:
+                    r.status = "timeout"
+                    r.completed = None
+                else:
+                    kept.append(r)
+            queue = kept
+            # admission
+            while free_slots and queue:
+                batch, add_bytes, leaves = [], 0, 0
+                while queue:
+                    r = queue[0]
+                    fb = footprint(len(r.keys), r.n_leaves)
+                    if fb > self.budget or r.n_leaves > self.max_batch_leaves:
+                        queue.popleft()
+                        r.status = "rejected"
+                        continue
+                    if bytes_in_flight + add_bytes + fb > self.budget or leaves + r.n_leaves > self.max_batch_leaves:
+                        break
+                    batch.append(queue.popleft())
+                    add_bytes += fb
+                    leaves += r.n_leaves
+                if not batch:
+                    break
+                slot = free_slots.pop()
+                inflight[slot] = self._launch(slot, batch, now())
+                bytes_in_flight += add_bytes
+                n_batches += 1
+                max_bytes = max(max_bytes, bytes_in_flight)
+                max_batches = max(max_batches, len(inflight))
+                progressed = True
+            if not progressed:
+                if inflight:
+                    time.sleep(0.0001)
+                elif pending:
+                    time.sleep(max(0.0, min(0.001, pending[0].arrival - now())))
+        makespan = now()
+        return ServeReport(requests=list(requests), makespan_s=makespan, max_bytes_in_flight=max_bytes,
+                           max_batches_in_flight=max_batches, batches=n_batches)
+
+
+def synthetic_stream(n_requests: int, rate_per_s: float, seed: int = 5, min_keys: int = 1000,
+                     max_keys: int = 1_000_000, deadline: float | None = None) -> list:
+    """Requests of the serving workload: Poisson arrivals, log-uniform key
+    counts, keys from splitmix64 per request (see workloads.serving_requests)."""
+    from workloads import serving_requests, splitmix64
+
+    out = []
+    for rid, (arr, n, kseed) in enumerate(serving_requests(n_requests, rate_per_s, seed, min_keys, max_keys)):
+        out.append(Request(rid=rid, arrival=arr, keys=splitmix64(kseed, n), deadline=deadline))
+    return out
