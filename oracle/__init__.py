@@ -60,6 +60,14 @@ def lib():
         L.shock_oracle_verify.restype = ctypes.c_int
         L.shock_oracle_verify.argtypes = [_u64p, _u64p, ctypes.c_uint64, _u64p, _u64p, ctypes.c_uint64,
                                           ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint8)]
+        L.shock_oracle_side.restype = ctypes.c_int
+        L.shock_oracle_side.argtypes = [ctypes.c_uint64]
+        L.shock_oracle_rf_slots.restype = None
+        L.shock_oracle_rf_slots.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_uint32, _u32p, _u32p]
+        L.shock_oracle_rf_leaf_search.restype = ctypes.c_int
+        L.shock_oracle_rf_leaf_search.argtypes = [_u64p, _u64p, ctypes.c_uint64, _u64p, _u32p, _u64p,
+                                                  ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
         L.shock_oracle_seed_stats.restype = None
         L.shock_oracle_seed_stats.argtypes = [_u64p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                               _u64p, _u64p, _u64p]
@@ -169,3 +177,30 @@ def seed_stats(keys, s0: int, count: int):
     a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
     lib().shock_oracle_seed_stats(_p64(keys), len(keys), s0, count, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
     return a.value, b.value, c.value
+
+
+def side(key: int) -> int:
+    return int(lib().shock_oracle_side(key & 0xFFFFFFFFFFFFFFFF))
+
+
+def rf_slots(key: int, seed: int, rot: int, k: int, n: int) -> tuple[int, int]:
+    a = ctypes.c_uint32()
+    b = ctypes.c_uint32()
+    lib().shock_oracle_rf_slots(key & 0xFFFFFFFFFFFFFFFF, seed & 0xFFFFFFFFFFFFFFFF, rot, k, n,
+                                ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def rf_leaf_search(keys, offsets, start_seed: int = 0, max_seed: int = DEFAULT_MAX_SEED, partial_k: int = 0,
+                   use_filter: bool = True):
+    """(status, seeds uint64[L], rot uint32[L], orient uint64[L]) of the rotation-fitting search."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    L = max(len(offsets) - 1, 0)
+    seeds = np.zeros(L, dtype=np.uint64)
+    rot = np.zeros(L, dtype=np.uint32)
+    orient = np.zeros(L, dtype=np.uint64)
+    rc = lib().shock_oracle_rf_leaf_search(_p64(keys) if keys.size else None, _p64(offsets) if offsets.size else None,
+                                           L, _p64(seeds), _p32(rot), _p64(orient), start_seed, max_seed,
+                                           partial_k, int(use_filter))
+    return rc, seeds, rot, orient

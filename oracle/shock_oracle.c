@@ -257,3 +257,66 @@ void shock_oracle_seed_stats(const uint64_t *keys, uint32_t n, uint64_t s0, uint
   *n_pseudoforest = pf_count;
   *n_h0_bijective = bij_count;
 }
+
+/* ---- Rotation fitting (definitions in shock_oracle.h) ---- */
+
+int shock_oracle_side(uint64_t x) { return (int)(shock_oracle_fmix64(x ^ 0xD1B54A32D192ED03ULL) >> 63); }
+
+void shock_oracle_rf_slots(uint64_t x, uint64_t s, uint32_t r, uint32_t k, uint32_t n, uint32_t *h0, uint32_t *h1) {
+  if (shock_oracle_side(x) == 0) {
+    shock_oracle_slots(x, s - (s % k), n, h0, h1);
+    return;
+  }
+  uint32_t g0, g1;
+  shock_oracle_slots(x, s, n, &g0, &g1);
+  *h0 = (g0 + r) % n;
+  *h1 = (g1 + r) % n;
+}
+
+int shock_oracle_rf_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                                uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient,
+                                uint64_t start_seed, uint64_t max_seed, uint32_t partial_k, int use_filter) {
+  if (n_leaves == 0) return SHOCK_ORACLE_OK;
+  if (offsets == NULL || out_seeds == NULL || out_rot == NULL || out_orient == NULL) return SHOCK_ORACLE_EINVAL;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    if (offsets[j + 1] < offsets[j]) return SHOCK_ORACLE_EINVAL;
+    if (offsets[j + 1] - offsets[j] > 64) return SHOCK_ORACLE_EINVAL;
+  }
+  if (keys == NULL && offsets[n_leaves] != offsets[0]) return SHOCK_ORACLE_EINVAL;
+
+  int status = SHOCK_ORACLE_OK;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    uint32_t n = (uint32_t)(offsets[j + 1] - offsets[j]);
+    const uint64_t *x = keys + offsets[j];
+    uint32_t k = partial_k ? partial_k : (n > 32 ? 8u : 1u);
+    uint32_t h0[64], h1[64];
+    int found = 0;
+    uint32_t rots = n > 0 ? n : 1;
+    for (uint64_t s = start_seed; s < max_seed && !found; ++s) {
+      for (uint32_t r = 0; r < rots; ++r) {
+        for (uint32_t i = 0; i < n; ++i) shock_oracle_rf_slots(x[i], s, r, k, n, &h0[i], &h1[i]);
+        if (use_filter) {
+          uint64_t cover = 0;
+          for (uint32_t i = 0; i < n; ++i) cover |= (1ULL << h0[i]) | (1ULL << h1[i]);
+          if (cover != full_mask(n)) continue;
+        }
+        if (shock_oracle_is_pseudoforest(n, n, h0, h1)) {
+          uint64_t f = 0;
+          if (shock_oracle_orientation(n, h0, h1, &f) != SHOCK_ORACLE_OK) return SHOCK_ORACLE_EINVAL;
+          out_seeds[j] = s;
+          out_rot[j] = r;
+          out_orient[j] = f;
+          found = 1;
+          break;
+        }
+      }
+    }
+    if (!found) {
+      out_seeds[j] = UINT64_MAX;
+      out_rot[j] = 0;
+      out_orient[j] = 0;
+      status = SHOCK_ORACLE_ENOTFOUND;
+    }
+  }
+  return status;
+}

@@ -94,6 +94,35 @@ int shock_oracle_verify(const uint64_t *keys, const uint64_t *offsets, uint64_t 
                         const uint64_t *seeds, const uint64_t *orient, uint64_t start_seed,
                         uint64_t window, uint8_t *flags);
 
+/* ---- Rotation fitting (Section 4, "Rotation Fitting"; Appendix A.2) ----
+ *
+ * Keys are split into two fixed sets by a 1-bit hash of the key alone:
+ *   side(x) = fmix64(x ^ 0xD1B54A32D192ED03) >> 63   (0 = first set, 1 = second).
+ * A candidate is a pair (s, r), s a seed and r in [0, n) a rotation.  Under it
+ *   a key x of the first set takes the slots  slots(x, s - (s mod k)),
+ *   a key x of the second set takes           (slots(x, s) + r) mod n (both slots),
+ * where k >= 1 is the partial-hash period of Appendix A.2 (k = 1: the first
+ * set is hashed with s itself).  Rotating the second set's slots is the
+ * cyclic rotation of its bit mask that the paper describes.  Candidates are
+ * tried in the order s = start, start+1, ... and, for each s, r = 0 .. n-1;
+ * the result is the first pair whose graph is a pseudoforest and the
+ * canonical orientation of that graph. */
+
+/* 1 if key x belongs to the second set. */
+int shock_oracle_side(uint64_t x);
+
+/* Slots of key x (leaf of n keys, index in the first or second set decided by
+ * side(x)) under candidate (s, r) with partial-hash period k. */
+void shock_oracle_rf_slots(uint64_t x, uint64_t s, uint32_t r, uint32_t k, uint32_t n, uint32_t *h0, uint32_t *h1);
+
+/* Rotation-fitting leaf search over a CSR batch (HOST pointers); as
+ * shock_oracle_leaf_search, plus the rotation of each result in out_rot
+ * (0 for leaves without a result).  partial_k = 0 selects the paper's rule:
+ * k = 8 for leaves of more than 32 keys, else 1. */
+int shock_oracle_rf_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                                uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient,
+                                uint64_t start_seed, uint64_t max_seed, uint32_t partial_k, int use_filter);
+
 /* Statistics helper: over seeds s0 .. s0+count-1 of one leaf of n keys, count
  * the seeds whose slots cover all n cells and, among them, the pseudoforests.
  * Also counts seeds where h0 alone is a bijection. */

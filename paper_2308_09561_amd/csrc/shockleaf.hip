@@ -723,13 +723,13 @@ double expected_seeds(uint32_t n) {
   return v < 1.0 ? 1.0 : v;
 }
 
-// Default claim size (units of 64*spl seeds) for a leaf of n keys: small
-// leaves finish in a few iterations, large ones amortise the claim atomic.
+// Default most units (of 64*spl seeds) one claim takes, by leaf size, as the
+// autotuner found on MI355X: claims shrink by themselves when several workers
+// share a leaf, so large leaves prefer large claims (fewer atomics).
 int default_units(uint32_t n) {
-  if (n <= 24) return 1;
-  if (n <= 40) return 4;
-  if (n <= 52) return 16;
-  return 32;
+  if (n <= 20) return 4;
+  if (n <= 28) return 32;
+  return 64;
 }
 
 // Workers for a single-leaf (split) launch: enough blocks to cover about
