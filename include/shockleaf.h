@@ -76,7 +76,7 @@ typedef struct shock_opts {
   int32_t check_dups;     /* 1 = reject leaves with repeated keys (SHOCK_EDUPKEY) */
   const volatile int32_t *cancel; /* HOST pointer (pinned or managed memory) or NULL; nonzero = stop */
   int32_t leaf_size_hint; /* typical leaf size, sizes launches where offsets are not read back (contexts); 0 = 48 */
-  int32_t reserved0;
+  int32_t partial_k;      /* rotation fitting only: partial-hash period 1 or 8; 0 = 8 above 32 keys, else 1 */
   const uint16_t *block_iters_by_n; /* HOST pointer to 65 claim sizes indexed by leaf size (0 = default), or NULL;
                                        e.g. the autotuner's table; overridden by block_iters when that is set */
   uint64_t reserved[2];
@@ -101,6 +101,24 @@ int shock_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_
 int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
                          uint64_t *out_seeds, uint64_t *out_orient,
                          const shock_opts *opts, void *hip_stream);
+
+/* ShockHash with rotation fitting (Section 4, "Rotation Fitting"; partial
+ * hash calculation, Appendix A.2).  Keys are split into two fixed sets by
+ * the top bit of fmix64(key ^ 0xD1B54A32D192ED03) (1 = second set).  A
+ * candidate is a pair (s, r), r in [0, n): keys of the first set take their
+ * slots under seed s - (s mod k), keys of the second set take their slots
+ * under seed s shifted by r mod n (the cyclic rotation of their bit mask).
+ * k is opts->partial_k (0 = 8 for leaves above 32 keys, else 1).
+ * Candidates are tried seed first, rotation second; the smallest pair whose
+ * graph is a pseudoforest is returned:
+ *   out_seeds  device, uint64[n_leaves]: s (UINT64_MAX if none below max_seed)
+ *   out_rot    device, uint32[n_leaves]: r
+ *   out_orient device, uint64[n_leaves]: canonical orientation of that graph
+ * max_seed may be at most 2^57.  Other arguments and statuses as
+ * shock_leaf_search_ex; synchronous. */
+int shock_rf_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                            uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient,
+                            const shock_opts *opts, void *hip_stream);
 
 /* Device-side statistics of the last completed call on this host thread. */
 typedef struct shock_stats {
@@ -150,6 +168,12 @@ int shock_ctx_destroy(shock_ctx *ctx);
  * batch's own status comes from shock_ctx_wait. */
 int shock_ctx_search_async(shock_ctx *ctx, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
                            uint64_t *out_seeds, uint64_t *out_orient, const shock_opts *opts, void *hip_stream);
+
+/* As shock_ctx_search_async, with rotation fitting (see
+ * shock_rf_leaf_search_ex); out_rot is a device uint32[n_leaves]. */
+int shock_ctx_rf_search_async(shock_ctx *ctx, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                              uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient,
+                              const shock_opts *opts, void *hip_stream);
 
 /* 1 if the context's last search has completed (or none is pending), 0 if it
  * is still running, SHOCK_EHIP on error.  Never blocks. */

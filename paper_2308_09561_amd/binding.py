@@ -27,7 +27,7 @@ EXPORTED = [
     "shock_opts_init", "shock_leaf_search", "shock_leaf_search_ex", "shock_last_stats",
     "shock_last_error", "shock_strerror", "shock_release_scratch", "shock_spec_version",
     "shock_ctx_create", "shock_ctx_destroy", "shock_ctx_search_async", "shock_ctx_query", "shock_ctx_wait",
-    "shock_ctx_graph_capture", "shock_ctx_graph_launch",
+    "shock_ctx_graph_capture", "shock_ctx_graph_launch", "shock_rf_leaf_search_ex", "shock_ctx_rf_search_async",
 ]
 
 
@@ -43,7 +43,7 @@ class ShockOpts(ctypes.Structure):
         ("check_dups", ctypes.c_int32),
         ("cancel", ctypes.c_void_p),
         ("leaf_size_hint", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("partial_k", ctypes.c_int32),
         ("block_iters_by_n", ctypes.c_void_p),
         ("reserved", ctypes.c_uint64 * 2),
     ]
@@ -113,6 +113,11 @@ def lib():
         L.shock_ctx_graph_capture.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(ShockOpts), vp]
         L.shock_ctx_graph_launch.restype = ctypes.c_int
         L.shock_ctx_graph_launch.argtypes = [vp, vp]
+        L.shock_rf_leaf_search_ex.restype = ctypes.c_int
+        L.shock_rf_leaf_search_ex.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, ctypes.POINTER(ShockOpts), vp]
+        L.shock_ctx_rf_search_async.restype = ctypes.c_int
+        L.shock_ctx_rf_search_async.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp, vp, ctypes.POINTER(ShockOpts),
+                                                vp]
         L.shock_ctx_query.restype = ctypes.c_int
         L.shock_ctx_query.argtypes = [vp]
         L.shock_ctx_wait.restype = ctypes.c_int
@@ -163,7 +168,8 @@ def _as_ptr(x):
 
 
 def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_iters=0, waves_per_wg=0,
-              workers=0, check_dups=False, cancel_ptr=None, leaf_size_hint=0, block_iters_by_n=None) -> ShockOpts:
+              workers=0, check_dups=False, cancel_ptr=None, leaf_size_hint=0, block_iters_by_n=None,
+              partial_k=0) -> ShockOpts:
     """shock_opts with defaults; block_iters_by_n is a sequence of 65 ints or None."""
     o = ShockOpts()
     lib().shock_opts_init(ctypes.byref(o))
@@ -178,6 +184,7 @@ def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_it
     o.check_dups = int(bool(check_dups))
     o.cancel = cancel_ptr
     o.leaf_size_hint = leaf_size_hint
+    o.partial_k = partial_k
     if block_iters_by_n is not None:
         if len(block_iters_by_n) != 65:
             raise ValueError("block_iters_by_n needs 65 entries (leaf sizes 0..64)")
@@ -192,6 +199,45 @@ def shock_leaf_search_ex(keys, offsets, n_leaves, out_seeds, out_orient, opts: S
     s = None if stream is None else ctypes.c_void_p(stream)
     return lib().shock_leaf_search_ex(_as_ptr(keys), _as_ptr(offsets), n_leaves, _as_ptr(out_seeds),
                                       _as_ptr(out_orient), None if opts is None else ctypes.byref(opts), s)
+
+
+def shock_rf_leaf_search_ex(keys, offsets, n_leaves, out_seeds, out_rot, out_orient, opts: ShockOpts | None = None,
+                            stream=None) -> int:
+    s = None if stream is None else ctypes.c_void_p(stream)
+    return lib().shock_rf_leaf_search_ex(_as_ptr(keys), _as_ptr(offsets), n_leaves, _as_ptr(out_seeds),
+                                         _as_ptr(out_rot), _as_ptr(out_orient),
+                                         None if opts is None else ctypes.byref(opts), s)
+
+
+def rf_leaf_search(keys, offsets, out_seeds=None, out_rot=None, out_orient=None, stream=None, **opts):
+    """Rotation-fitting search of a CSR batch in torch int64 CUDA tensors.
+
+    Returns (status, seeds, rotations, orient): seeds/orient int64 tensors
+    (uint64 bit patterns), rotations an int32 tensor, all on the keys' device.
+    """
+    import torch
+
+    _check_tensors(keys, offsets)
+    keys = keys.contiguous()
+    offsets = offsets.contiguous()
+    L = offsets.numel() - 1
+    if L < 0:
+        raise ValueError("offsets needs n_leaves + 1 entries")
+    dev = keys.device
+    if out_seeds is None:
+        out_seeds = torch.empty(max(L, 1), dtype=torch.int64, device=dev)
+    if out_rot is None:
+        out_rot = torch.empty(max(L, 1), dtype=torch.int32, device=dev)
+    if out_orient is None:
+        out_orient = torch.empty(max(L, 1), dtype=torch.int64, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    o = make_opts(**opts)
+    rc = shock_rf_leaf_search_ex(keys if keys.numel() else offsets, offsets, L, out_seeds, out_rot, out_orient, o,
+                                 stream)
+    if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
+        raise ShockError(rc, lib().shock_last_error().decode())
+    return rc, out_seeds[:L], out_rot[:L], out_orient[:L]
 
 
 def leaf_search(keys, offsets, out_seeds=None, out_orient=None, stream=None, **opts):
@@ -281,6 +327,12 @@ class SearchContext:
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         return lib().shock_ctx_graph_launch(self._h, ctypes.c_void_p(stream))
+
+    def rf_search_async(self, keys, offsets, out_seeds, out_rot, out_orient, stream=None, **opts) -> int:
+        """Rotation-fitting search; out_rot an int32 device tensor."""
+        a = self._args(keys, offsets, out_seeds, out_orient, stream, opts)
+        self._keep = self._keep + (out_rot,)
+        return lib().shock_ctx_rf_search_async(*a[:5], _as_ptr(out_rot), *a[5:])
 
     def query(self) -> int:
         return lib().shock_ctx_query(self._h)

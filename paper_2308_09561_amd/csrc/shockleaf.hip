@@ -43,6 +43,11 @@ constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kMix1 = 0xff51afd7ed558ccdull;
 constexpr uint64_t kMix2 = 0xc4ceb9fe1a85ec53ull;
 constexpr uint64_t kNone = ~0ull;
+// Rotation fitting: the 1-bit set hash of a key is the top bit of
+// fmix64(key ^ kSideKey); candidates (s, r) are encoded as s * 64 + r, which
+// orders them as the search does (seed first, then rotation).
+constexpr uint64_t kSideKey = 0xD1B54A32D192ED03ull;
+constexpr uint32_t kRfSeedsPerLane = 8;  // consecutive seeds per lane; the partial-hash period
 
 // Leaf claim word: bits 0..39 next unclaimed unit (a unit is one iteration,
 // 64*SPL consecutive seeds), bits 40..62 workers inside the leaf, bit 63 set
@@ -95,6 +100,9 @@ struct Params {
   uint32_t block_iters;  // units per block of a single-leaf (split) launch
   uint32_t workers;
   uint32_t split;  // 1: one leaf, static block striding over the workers (no claim atomics)
+  uint32_t partial_k;  // rotation fitting (best holds candidates s * 64 + r): 0 = 8 above 32 keys else 1; or 1 / 8
+  uint32_t *__restrict__ out_rot;              // rotation fitting: rotation per leaf
+  const unsigned long long *__restrict__ sides;  // [n_leaves] bit i = set of key i
   uint16_t units_by_n[65];  // most units one claim takes, by leaf size (persistent launches)
 };
 
@@ -184,6 +192,9 @@ __device__ __forceinline__ unsigned long long wave_atomic_add(unsigned long long
 // incidence masks for the orientation (never live at the same time).
 struct WaveLds {
   uint64_t keys[64];  // premixed keys of the leaf the wave is working on
+  uint64_t keys_a[64];  // rotation fitting: premixed keys of the first set, compacted
+  uint64_t keys_b[64];  // rotation fitting: premixed keys of the second set, compacted
+  unsigned long long rmask[2];  // rotation fitting: coverage masks of one seed (first, second set)
   union {
     struct {
       uint32_t parent[64];
@@ -367,19 +378,202 @@ __device__ uint64_t search_block(const uint64_t *a, uint32_t n, uint64_t base, u
   return kNone;
 }
 
+
+// ---- Rotation fitting (Section 4; partial hash calculation, Appendix A.2) --
+
+// Coverage mask of `cnt` premixed keys (wave-uniform, LDS) under one seed.
+template <bool WIDE>
+__device__ __forceinline__ uint64_t cover_mask(const uint64_t *a, uint32_t cnt, uint32_t tlo, uint32_t thi, uint32_t n,
+                                               uint32_t nm1) {
+  uint32_t mlo = 0, mhi = 0;
+  auto eval_key = [&](uint64_t ai) {
+    uint32_t h0, h1;
+    slot_pair((uint32_t)ai, (uint32_t)(ai >> 32), tlo, thi, n, nm1, h0, h1);
+    if (WIDE) {
+      const uint64_t b0 = 1ull << h0, b1 = 1ull << h1;
+      or3_into(mlo, (uint32_t)b0, (uint32_t)b1);
+      or3_into(mhi, (uint32_t)(b0 >> 32), (uint32_t)(b1 >> 32));
+    } else {
+      or3_into(mlo, 1u << h0, 1u << h1);
+    }
+  };
+  uint32_t i = 0;
+  for (; i + 4 <= cnt; i += 4) {
+    const uint64_t a0 = a[i], a1 = a[i + 1], a2 = a[i + 2], a3 = a[i + 3];
+    eval_key(a0);
+    eval_key(a1);
+    eval_key(a2);
+    eval_key(a3);
+  }
+  for (; i < cnt; ++i) eval_key(a[i]);
+  return WIDE ? (((uint64_t)mhi << 32) | mlo) : (uint64_t)mlo;
+}
+
+// Whether some rotation r in [0, n) makes rot_n(mb, r) | ma cover [0, n).
+// `pad` has every bit at or above n set.
+template <bool WIDE>
+__device__ __forceinline__ bool any_rotation_covers(uint64_t ma, uint64_t mb, uint32_t n, uint64_t pad) {
+  bool any = ((mb | ma | pad) == ~0ull);
+  if (WIDE) {
+    for (uint32_t r = 1; r < n; ++r) {
+      const uint64_t rot = (mb << r) | (mb >> (n - r));
+      any |= ((rot | ma | pad) == ~0ull);
+    }
+  } else {
+    const uint32_t ma32 = (uint32_t)ma, mb32 = (uint32_t)mb, pad32 = (uint32_t)pad;
+    for (uint32_t r = 1; r < n; ++r) {
+      const uint32_t rot = (mb32 << r) | (mb32 >> (n - r));
+      any |= ((rot | ma32 | pad32) == ~0u);
+    }
+  }
+  return any;
+}
+
+// Slots of this lane's key (lane < n) under candidate (s, r).
+__device__ __forceinline__ void rf_lane_slots(uint32_t my_alo, uint32_t my_ahi, uint32_t my_side, uint64_t s, uint32_t r,
+                                              bool partial, uint32_t n, uint32_t &h0, uint32_t &h1) {
+  const uint64_t sa = partial ? s - (s % kRfSeedsPerLane) : s;
+  const uint64_t t = fmix64(((my_side ? s : sa) + 1) * kGolden);
+  slot_pair(my_alo, my_ahi, (uint32_t)t, (uint32_t)(t >> 32), n, n - 1, h0, h1);
+  if (my_side) {
+    h0 += r;
+    h0 = h0 >= n ? h0 - n : h0;
+    h1 += r;
+    h1 = h1 >= n ? h1 - n : h1;
+  }
+}
+
+// Rotations of seed s whose graphs pass the coverage filter, one bit per
+// rotation, computed by the whole wave: every key ORs its slots into the
+// mask of its set in LDS, then lane r tests rotation r.
+__device__ uint64_t rf_rotations(uint32_t n, uint64_t s, bool partial, uint32_t my_alo, uint32_t my_ahi,
+                                 uint32_t my_side, WaveLds &lds) {
+  const uint32_t lane = lane_id();
+  if (lane < 2) lds.rmask[lane] = 0;
+  wave_lds_sync();
+  if (lane < n) {
+    uint32_t h0, h1;
+    rf_lane_slots(my_alo, my_ahi, my_side, s, 0, partial, n, h0, h1);
+    atomicOr(&lds.rmask[my_side], (1ull << h0) | (1ull << h1));
+  }
+  wave_lds_sync();
+  const uint64_t ma = lds.rmask[0], mb = lds.rmask[1];
+  const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  const uint64_t rot = lane == 0 ? mb : ((mb << lane) | (mb >> (n - lane))) & full;
+  return __ballot(lane < n && (rot | ma) == full);
+}
+
+// Search seeds [base, end) of one leaf for the first candidate (s, r), in the
+// order s ascending then r ascending, whose graph is a pseudoforest.  Lane l
+// of an iteration takes the kRfSeedsPerLane consecutive seeds starting at
+// ib + l * kRfSeedsPerLane, so with partial hashing the first set's mask
+// (seed s - s mod 8) is computed once per lane and iteration.  Returns the
+// encoded candidate s * 64 + r, or kNone.
+template <bool WIDE>
+__device__ uint64_t rf_search_block(uint32_t n, uint32_t na, uint32_t nb, bool partial, uint64_t base, uint64_t end,
+                                    const unsigned long long *best_j, bool poll, uint32_t my_alo, uint32_t my_ahi,
+                                    uint32_t my_side, WaveLds &lds, WaveStats &st) {
+  const uint32_t lane = lane_id();
+  const uint32_t nm1 = n - 1;
+  const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  const uint64_t pad = ~full;
+  constexpr uint32_t kSeeds = 64 * kRfSeedsPerLane;
+  for (uint64_t ib = base; ib < end; ib += kSeeds) {
+    const unsigned long long cur_best = poll ? load_relaxed(best_j) : kNone;
+    const uint64_t s0 = ib + (uint64_t)lane * kRfSeedsPerLane;
+    uint32_t flags = 0;
+    uint64_t ma = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kRfSeedsPerLane; ++i) {
+      const uint64_t s = s0 + i;
+      // s0 mod 8 is the same in every lane, so this choice is wave-uniform.
+      if (!partial || i == 0 || (s % kRfSeedsPerLane) == 0) {
+        const uint64_t sa = partial ? s - (s % kRfSeedsPerLane) : s;
+        const uint64_t ta = fmix64((sa + 1) * kGolden);
+        ma = cover_mask<WIDE>(lds.keys_a, na, (uint32_t)ta, (uint32_t)(ta >> 32), n, nm1);
+      }
+      const uint64_t t = fmix64((s + 1) * kGolden);
+      const uint64_t mb = cover_mask<WIDE>(lds.keys_b, nb, (uint32_t)t, (uint32_t)(t >> 32), n, nm1);
+      const bool any = any_rotation_covers<WIDE>(ma, mb, n, pad);
+      flags |= (any && s < end) ? (1u << i) : 0u;
+    }
+    const uint64_t span = end - ib;
+    st.seeds += span < (uint64_t)kSeeds ? span : (uint64_t)kSeeds;
+    uint64_t surv = __ballot(flags != 0);
+    while (surv != 0) {
+      const uint32_t l = __builtin_ctzll(surv);
+      surv &= surv - 1;
+      uint32_t fl = __builtin_amdgcn_readlane(flags, l);
+      while (fl != 0) {
+        const uint32_t i = __builtin_ctz(fl);
+        fl &= fl - 1;
+        const uint64_t s = ib + (uint64_t)l * kRfSeedsPerLane + i;
+        uint64_t rots = rf_rotations(n, s, partial, my_alo, my_ahi, my_side, lds);
+        while (rots != 0) {
+          const uint32_t r = __builtin_ctzll(rots);
+          rots &= rots - 1;
+          st.passes += 1;
+          st.pf += 1;
+          uint32_t h0 = 0, h1 = 0;
+          rf_lane_slots(my_alo, my_ahi, my_side, s, r, partial, n, h0, h1);
+          if (pf_test_wave(n, h0, h1, lds)) return s * 64 + r;
+        }
+      }
+    }
+    if (bcast64(cur_best) <= (ib + kSeeds) * 64) break;
+  }
+  return kNone;
+}
+
+// Split the leaf's keys into the two sets in LDS (compacted, input order).
+__device__ void rf_stage(const Params &P, uint64_t j, uint32_t n, uint64_t ai, uint32_t &na, uint32_t &nb,
+                         uint32_t &my_side, WaveLds &lds) {
+  const uint32_t lane = lane_id();
+  const uint64_t valid = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  const uint64_t sides = P.sides[j] & valid;
+  my_side = (uint32_t)((sides >> lane) & 1);
+  const uint64_t below = lane == 0 ? 0 : (~0ull >> (64 - lane));
+  const uint32_t rank_b = __popcll(sides & below);
+  const uint32_t rank_a = __popcll(~sides & valid & below);
+  if (lane < n) {
+    if (my_side) lds.keys_b[rank_b] = ai;
+    else lds.keys_a[rank_a] = ai;
+  }
+  nb = (uint32_t)__popcll(sides);
+  na = n - nb;
+  wave_lds_sync();
+}
+
+// Seed-space limit of a leaf from its best value (an encoded candidate under
+// rotation fitting): seeds at or above it cannot improve the result.
+template <bool RF>
+__device__ __forceinline__ uint64_t seed_limit(uint64_t best) {
+  if (best == kNone || !RF) return best;
+  return (best >> 6) + ((best & 63) != 0 ? 1 : 0);
+}
+
 // Write the result of leaf j.  Called by exactly one worker per leaf.
+template <bool RF>
 __device__ void finalize_leaf(const Params &P, uint64_t j, uint32_t n, WaveLds &lds) {
   const uint32_t lane = lane_id();
-  const uint64_t s = bcast64(load_relaxed(&P.best[j]));
+  const uint64_t b = bcast64(load_relaxed(&P.best[j]));
+  const uint64_t s = (b == kNone || !RF) ? b : (b >> 6);
+  const uint32_t r = (b == kNone || !RF) ? 0u : (uint32_t)(b & 63);
   uint64_t seed_out = s, f = 0;
   if (s == kNone) {
     if (lane == 0) atomicAdd(&P.gctr[kCtrNotFound], 1ull);
     f = 0;
   } else if (n >= 2) {
     const uint64_t ai = P.premix[j * 64 + lane];
-    const uint64_t t = fmix64((s + 1) * kGolden);
     uint32_t h0 = 0, h1 = 0;
-    slot_pair((uint32_t)ai, (uint32_t)(ai >> 32), (uint32_t)t, (uint32_t)(t >> 32), n, n - 1, h0, h1);
+    if (RF) {
+      const uint32_t my_side = (uint32_t)((P.sides[j] >> lane) & 1);
+      const bool partial = P.partial_k ? P.partial_k == kRfSeedsPerLane : n > 32;
+      rf_lane_slots((uint32_t)ai, (uint32_t)(ai >> 32), my_side, s, r, partial, n, h0, h1);
+    } else {
+      const uint64_t t = fmix64((s + 1) * kGolden);
+      slot_pair((uint32_t)ai, (uint32_t)(ai >> 32), (uint32_t)t, (uint32_t)(t >> 32), n, n - 1, h0, h1);
+    }
     if (!orient_wave(n, h0, h1, lds, f)) {
       if (lane == 0) atomicOr(&P.gctr[kCtrErr], kErrOrient);
     }
@@ -387,15 +581,25 @@ __device__ void finalize_leaf(const Params &P, uint64_t j, uint32_t n, WaveLds &
   if (lane == 0) {
     P.out_seeds[j] = seed_out;
     P.out_orient[j] = f;
+    if (RF) P.out_rot[j] = r;
     atomicAdd(&P.lctr[kLcDone], 1ull);
   }
 }
 
-template <int SPL>
+template <int SPL, bool RF>
 __device__ uint64_t search_range(const Params &P, uint64_t j, uint32_t n, uint64_t base, uint64_t end, bool poll,
                                  uint32_t my_alo, uint32_t my_ahi, WaveLds &lds, WaveStats &st) {
   const uint64_t *a = lds.keys;
-  if (n <= 1) return base;  // every seed qualifies
+  if (n <= 1) return RF ? base * 64 : base;  // every seed qualifies
+  if (RF) {
+    const uint64_t valid = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    const uint64_t sides = P.sides[j] & valid;
+    const uint32_t nb = (uint32_t)__popcll(sides), na = n - nb;
+    const uint32_t my_side = (uint32_t)((sides >> lane_id()) & 1);
+    const bool partial = P.partial_k ? P.partial_k == kRfSeedsPerLane : n > 32;
+    if (n <= 32) return rf_search_block<false>(n, na, nb, partial, base, end, &P.best[j], poll, my_alo, my_ahi, my_side, lds, st);
+    return rf_search_block<true>(n, na, nb, partial, base, end, &P.best[j], poll, my_alo, my_ahi, my_side, lds, st);
+  }
   if (n <= 32) return search_block<SPL, false>(a, n, base, end, &P.best[j], poll, my_alo, my_ahi, lds, st);
   return search_block<SPL, true>(a, n, base, end, &P.best[j], poll, my_alo, my_ahi, lds, st);
 }
@@ -404,7 +608,7 @@ __device__ uint64_t search_range(const Params &P, uint64_t j, uint32_t n, uint64
 // each.  A worker alone on a leaf claims block_iters units at a time; with k
 // workers inside it claims about block_iters/k, so speculative work beyond
 // the answer stays small when many helpers share a leaf.
-template <int SPL>
+template <int SPL, bool RF>
 __device__ void work_leaf(const Params &P, uint64_t j, bool helper, WaveLds &lds, WaveStats &st) {
   const uint32_t lane = lane_id();
   const uint64_t unit = P.unit;
@@ -413,6 +617,10 @@ __device__ void work_leaf(const Params &P, uint64_t j, bool helper, WaveLds &lds
   const uint64_t ai = P.premix[j * 64 + lane];
   const uint32_t my_alo = (uint32_t)ai, my_ahi = (uint32_t)(ai >> 32);
   lds.keys[lane] = ai;
+  if (RF) {
+    uint32_t na, nb, side;
+    rf_stage(P, j, n, ai, na, nb, side, lds);
+  }
   wave_lds_sync();
   const uint64_t most = P.units_by_n[n];
   uint64_t take = helper ? 1 : most;  // a helper does not know the crowd yet
@@ -423,7 +631,7 @@ __device__ void work_leaf(const Params &P, uint64_t j, bool helper, WaveLds &lds
   }
   for (;;) {
     const uint64_t u = claim & kBlockMask;
-    const uint64_t bst = bcast64(load_relaxed(&P.best[j]));
+    const uint64_t bst = seed_limit<RF>(bcast64(load_relaxed(&P.best[j])));
     const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
     if (!chunk_below(u, unit, P.start_seed, lim)) break;
     if (P.cancel != nullptr && *P.cancel != 0) {
@@ -445,7 +653,7 @@ __device__ void work_leaf(const Params &P, uint64_t j, bool helper, WaveLds &lds
     if (lane == 0) next_claim = atomicAdd(&P.state[j], (unsigned long long)next_take);
     // Alone on the leaf at claim time: later joiners claim higher seeds, so no
     // one can lower best below this range and polling is pointless.
-    const uint64_t found = search_range<SPL>(P, j, n, base, end, inflight > 1, my_alo, my_ahi, lds, st);
+    const uint64_t found = search_range<SPL, RF>(P, j, n, base, end, inflight > 1, my_alo, my_ahi, lds, st);
     if (found != kNone) wave_atomic_min_wait(&P.best[j], found);
     take = next_take;
     claim = bcast64(next_claim);
@@ -457,7 +665,7 @@ __device__ void work_leaf(const Params &P, uint64_t j, bool helper, WaveLds &lds
       unsigned long long was = 0;
       if (lane == 0) was = atomicOr(&P.state[j], kFinalBit);
       was = bcast64(was);
-      if (!(was & kFinalBit)) finalize_leaf(P, j, n, lds);
+      if (!(was & kFinalBit)) finalize_leaf<RF>(P, j, n, lds);
     }
   }
 }
@@ -467,7 +675,7 @@ __device__ void work_leaf(const Params &P, uint64_t j, bool helper, WaveLds &lds
 // that starts at or above the best seed found so far, so every block below
 // the final best is searched to its first acceptance.  The last worker to
 // finish (counted per workgroup in LDS, then per launch) writes the result.
-template <int SPL>
+template <int SPL, bool RF>
 __device__ void split_leaf(const Params &P, uint64_t j, uint32_t wid, WaveLds &lds, WaveStats &st,
                            uint32_t *wg_exits) {
   const uint32_t lane = lane_id();
@@ -475,9 +683,13 @@ __device__ void split_leaf(const Params &P, uint64_t j, uint32_t wid, WaveLds &l
   const uint32_t n = (uint32_t)(P.offsets[j + 1] - P.offsets[j]);
   const uint64_t ai = P.premix[j * 64 + lane];
   lds.keys[lane] = ai;
+  if (RF) {
+    uint32_t na, nb, side;
+    rf_stage(P, j, n, ai, na, nb, side, lds);
+  }
   wave_lds_sync();
   for (uint64_t b = wid;; b += P.workers) {
-    const uint64_t bst = bcast64(load_relaxed(&P.best[j]));
+    const uint64_t bst = seed_limit<RF>(bcast64(load_relaxed(&P.best[j])));
     const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
     if (b >= (1ull << 40) || !chunk_below(b, block, P.start_seed, lim)) break;
     if (P.cancel != nullptr && *P.cancel != 0) {
@@ -487,7 +699,7 @@ __device__ void split_leaf(const Params &P, uint64_t j, uint32_t wid, WaveLds &l
     const uint64_t base = P.start_seed + b * block;
     const uint64_t end = (lim - base) < block ? lim : base + block;
     st.blocks += 1;
-    const uint64_t found = search_range<SPL>(P, j, n, base, end, true, (uint32_t)ai, (uint32_t)(ai >> 32), lds, st);
+    const uint64_t found = search_range<SPL, RF>(P, j, n, base, end, true, (uint32_t)ai, (uint32_t)(ai >> 32), lds, st);
     if (found != kNone) wave_atomic_min_wait(&P.best[j], found);
   }
   uint32_t c = 0;
@@ -507,7 +719,7 @@ __device__ void split_leaf(const Params &P, uint64_t j, uint32_t wid, WaveLds &l
   unsigned long long was = 0;
   if (lane == 0) was = atomicOr(&P.state[j], kFinalBit);
   was = bcast64(was);
-  if (!(was & kFinalBit)) finalize_leaf(P, j, n, lds);
+  if (!(was & kFinalBit)) finalize_leaf<RF>(P, j, n, lds);
 }
 
 // Pick a leaf to help: an unfinished leaf whose next block still lies below
@@ -515,6 +727,7 @@ __device__ void split_leaf(const Params &P, uint64_t j, uint32_t wid, WaveLds &l
 // launch's leaves directly when there are at most 64) in chunks of 64 and pick
 // a candidate by rotating the ballot with the worker id, which spreads helpers
 // over the open leaves.  Returns kNone if no open leaf was seen.
+template <bool RF>
 __device__ uint64_t find_help_leaf(const Params &P, uint32_t wid) {
   const uint32_t lane = lane_id();
   const uint64_t end = P.leaf_begin + P.leaf_count;
@@ -537,7 +750,7 @@ __device__ uint64_t find_help_leaf(const Params &P, uint32_t wid) {
     bool open = false;
     if (leaf != kNone && leaf >= P.leaf_begin && leaf < end) {
       const uint64_t stw = load_relaxed(&P.state[leaf]);
-      const uint64_t bst = load_relaxed(&P.best[leaf]);
+      const uint64_t bst = seed_limit<RF>(load_relaxed(&P.best[leaf]));
       const uint64_t lim = bst < P.max_seed ? bst : P.max_seed;
       open = !(stw & kFinalBit) && chunk_below(stw & kBlockMask, P.unit, P.start_seed, lim);
     }
@@ -564,7 +777,9 @@ __device__ __forceinline__ void flush_stats(const Params &P, const WaveStats &st
   }
 }
 
-template <int SPL>
+// Plain search (RF false, SPL seeds per lane) or rotation fitting (RF true;
+// SPL unused): separate instances, so each gets its own register budget.
+template <int SPL, bool RF>
 __global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
   extern __shared__ unsigned long long lds_raw[];
   const uint32_t wave = threadIdx.x >> 6;
@@ -579,7 +794,7 @@ __global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
   if (P.split) {
     if (threadIdx.x == 0) *wg_exits = 0;
     __syncthreads();
-    split_leaf<SPL>(P, P.leaf_begin, wid, lds, st, wg_exits);
+    split_leaf<SPL, RF>(P, P.leaf_begin, wid, lds, st, wg_exits);
     flush_stats(P, st, wid);
     return;
   }
@@ -599,7 +814,7 @@ __global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
     }
     if (j == kNone) {
       helper = true;
-      j = find_help_leaf(P, wid);
+      j = find_help_leaf<RF>(P, wid);
       if (j == kNone) {
         // Nothing open to help: leave, so that a kernel queued behind this
         // one can use the slot.  A few retries cover owners that have not yet
@@ -611,7 +826,7 @@ __global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
       idle_rounds = 0;
     }
     if (P.leaf_count > 64 && lane == 0) __hip_atomic_store(&P.wleaf[wid], (uint32_t)j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    work_leaf<SPL>(P, j, helper, lds, st);
+    work_leaf<SPL, RF>(P, j, helper, lds, st);
   }
   flush_stats(P, st, wid);
 }
@@ -622,7 +837,7 @@ __global__ __launch_bounds__(256) void prepare_kernel(const uint64_t *__restrict
                                                       const uint64_t *__restrict__ offsets, uint64_t n_leaves,
                                                       uint64_t *__restrict__ premix, unsigned long long *state,
                                                       unsigned long long *best, unsigned long long *gctr,
-                                                      int check_dups) {
+                                                      unsigned long long *sides, int check_dups) {
   const uint64_t j = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint32_t lane = threadIdx.x & 63;
   if (j >= n_leaves) return;
@@ -635,9 +850,11 @@ __global__ __launch_bounds__(256) void prepare_kernel(const uint64_t *__restrict
   uint64_t x = 0;
   if (lane < n) x = keys[o0 + lane];
   premix[j * 64 + lane] = lane < n ? fmix64(x) : 0;
+  const uint64_t side_bits = __ballot(lane < n && (fmix64(x ^ kSideKey) >> 63) != 0);
   if (lane == 0) {
     state[j] = 0;
     best[j] = kNone;
+    sides[j] = side_bits;
   }
   if (check_dups) {
     bool dup = false;
@@ -662,12 +879,14 @@ __global__ void init_counters_kernel(unsigned long long *gctr, unsigned long lon
 // Leaves left unfinished by a cancelled call report "no seed".  Does nothing
 // unless the call was cancelled.
 __global__ void mark_unfinished_kernel(const unsigned long long *gctr, const unsigned long long *state,
-                                       uint64_t n_leaves, uint64_t *out_seeds, uint64_t *out_orient) {
+                                       uint64_t n_leaves, uint64_t *out_seeds, uint64_t *out_orient,
+                                       uint32_t *out_rot) {
   const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (!(gctr[kCtrErr] & kErrCancel) || (gctr[kCtrErr] & (kErrInvalid | kErrDup))) return;
   if (j < n_leaves && !(state[j] & kFinalBit)) {
     out_seeds[j] = kNone;
     out_orient[j] = 0;
+    if (out_rot) out_rot[j] = 0;
   }
 }
 
@@ -693,7 +912,7 @@ void set_err(const char *what, hipError_t e) {
 // Scratch of one call: premixed keys, claim words, best seeds, the worker
 // table and counters.
 struct Layout {
-  size_t premix, state, best, wleaf, gctr, lctr, total;
+  size_t premix, state, best, sides, wleaf, gctr, lctr, total;
 };
 
 Layout layout(uint64_t n_leaves, uint32_t workers, uint64_t n_launches) {
@@ -703,6 +922,7 @@ Layout layout(uint64_t n_leaves, uint32_t workers, uint64_t n_launches) {
   l.premix = o; o = up(o + n_leaves * 64 * 8);
   l.state = o; o = up(o + n_leaves * 8);
   l.best = o; o = up(o + n_leaves * 8);
+  l.sides = o; o = up(o + n_leaves * 8);
   l.wleaf = o; o = up(o + (size_t)workers * 4);
   l.gctr = o; o = up(o + kCtrGlobalCount * 8);
   l.lctr = o; o = up(o + n_launches * kLcCount * 8);
@@ -734,36 +954,37 @@ int default_units(uint32_t n) {
 
 // Workers for a single-leaf (split) launch: enough blocks to cover about
 // twice the expected seed count in one round, at least one workgroup.
-int plain_workers(uint32_t n, uint64_t block, int wpw, int max_workers) {
-  double w = 2.0 * expected_seeds(n) / (double)block;
+int plain_workers(uint32_t n, uint64_t block, int wpw, int max_workers, int rf) {
+  double w = 2.0 * expected_seeds(n) / (rf && n > 1 ? (double)n : 1.0) / (double)block;
   int wi = w > max_workers ? max_workers : (int)w;
   if (wi < wpw) wi = wpw;
   return (wi / wpw) * wpw;
 }
 
-template <int SPL>
+template <int SPL, bool RF>
 hipError_t launch_search(const Params &P, int wpw, hipStream_t stream) {
   const uint32_t wgs = P.workers / wpw;
-  hipLaunchKernelGGL(search_kernel<SPL>, dim3(wgs), dim3(64 * wpw), sizeof(WaveLds) * wpw + 16, stream, P);
+  hipLaunchKernelGGL((search_kernel<SPL, RF>), dim3(wgs), dim3(64 * wpw), sizeof(WaveLds) * wpw + 16, stream, P);
   return hipGetLastError();
 }
 
-hipError_t launch_search_spl(int spl, const Params &P, int wpw, hipStream_t stream) {
+hipError_t launch_search_spl(int spl, int rf, const Params &P, int wpw, hipStream_t stream) {
+  if (rf) return launch_search<1, true>(P, wpw, stream);
   switch (spl) {
-    case 1: return launch_search<1>(P, wpw, stream);
-    case 4: return launch_search<4>(P, wpw, stream);
-    default: return launch_search<2>(P, wpw, stream);
+    case 1: return launch_search<1, false>(P, wpw, stream);
+    case 4: return launch_search<4, false>(P, wpw, stream);
+    default: return launch_search<2, false>(P, wpw, stream);
   }
 }
 
 // Resident workers the device holds for a search kernel configuration
-// (cached per device, seeds per lane and waves per workgroup).
-int resident_workers(int spl, int wpw) {
+// (cached per device, kernel instance and waves per workgroup).
+int resident_workers(int spl, int rf, int wpw) {
   static std::mutex mu;
   static int cache[16][5][kMaxWavesPerWg + 1];
   int dev = 0, cus = 256, per_cu = 0;
   (void)hipGetDevice(&dev);
-  const int si = spl == 1 ? 1 : spl == 4 ? 4 : 2;
+  const int si = rf ? 0 : spl == 1 ? 1 : spl == 4 ? 4 : 2;
   {
     std::lock_guard<std::mutex> lk(mu);
     if (dev < 16 && cache[dev][si][wpw] > 0) return cache[dev][si][wpw];
@@ -772,8 +993,10 @@ int resident_workers(int spl, int wpw) {
     hipDeviceProp_t p;
     if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
   }
-  const void *fn = spl == 1 ? (const void *)search_kernel<1> : spl == 4 ? (const void *)search_kernel<4>
-                                                                          : (const void *)search_kernel<2>;
+  const void *fn = si == 0   ? (const void *)search_kernel<1, true>
+                   : si == 1 ? (const void *)search_kernel<1, false>
+                   : si == 4 ? (const void *)search_kernel<4, false>
+                             : (const void *)search_kernel<2, false>;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * wpw, sizeof(WaveLds) * wpw + 16) != hipSuccess ||
       per_cu <= 0)
     per_cu = 32 / wpw;
@@ -786,24 +1009,32 @@ int resident_workers(int spl, int wpw) {
 // Everything needed to enqueue one call.
 struct Plan {
   int mode;
+  int rf;
   int spl, units, wpw, workers;
   uint64_t n_launches;
   uint16_t units_by_n[65];
 };
 
-int make_plan(const shock_opts &opts, uint64_t n_leaves, uint32_t n_typical, Plan &pl) {
+// Rotation fitting: claim units are 64 lanes x 8 seeds and a leaf needs
+// about n times fewer seeds, so claims are small.
+int default_rf_units(uint32_t n) { return n >= 44 ? 2 : 1; }
+
+int make_plan(const shock_opts &opts, uint64_t n_leaves, uint32_t n_typical, int rf, Plan &pl) {
   pl.mode = opts.mode == SHOCK_MODE_AUTO ? SHOCK_MODE_PERSISTENT : opts.mode;
   if (pl.mode != SHOCK_MODE_PERSISTENT && pl.mode != SHOCK_MODE_PLAIN_PER_LEAF) return SHOCK_EINVAL;
+  pl.rf = rf;
   pl.spl = opts.spl ? opts.spl : 2;
   pl.wpw = opts.waves_per_wg ? opts.waves_per_wg : 4;
   pl.units = opts.block_iters ? opts.block_iters
-                              : (pl.mode == SHOCK_MODE_PLAIN_PER_LEAF ? 1 : default_units(n_typical));
+                              : (pl.mode == SHOCK_MODE_PLAIN_PER_LEAF ? 1
+                                                                      : (rf ? default_rf_units(n_typical)
+                                                                            : default_units(n_typical)));
   for (int n = 0; n <= 64; ++n) {
-    int u = opts.block_iters ? opts.block_iters : default_units((uint32_t)n);
+    int u = opts.block_iters ? opts.block_iters : (rf ? default_rf_units((uint32_t)n) : default_units((uint32_t)n));
     if (opts.block_iters_by_n && opts.block_iters_by_n[n] > 0) u = opts.block_iters_by_n[n];
     pl.units_by_n[n] = (uint16_t)(u > 65535 ? 65535 : u);
   }
-  int w = opts.workers ? opts.workers : resident_workers(pl.spl, pl.wpw);
+  int w = opts.workers ? opts.workers : resident_workers(pl.spl, rf, pl.wpw);
   w = ((w + pl.wpw - 1) / pl.wpw) * pl.wpw;
   if (w <= 0) return SHOCK_EINVAL;
   pl.workers = w;
@@ -821,13 +1052,14 @@ int check_opts(const shock_opts &opts, uint64_t n_leaves, const void *offsets, c
   if (opts.waves_per_wg < 0 || opts.waves_per_wg > kMaxWavesPerWg) return SHOCK_EINVAL;
   if (opts.workers < 0 || opts.workers > (1 << 20)) return SHOCK_EINVAL;
   if (opts.leaf_size_hint < 0 || opts.leaf_size_hint > 64) return SHOCK_EINVAL;
+  if (opts.partial_k != 0 && opts.partial_k != 1 && opts.partial_k != 8) return SHOCK_EINVAL;
   return SHOCK_OK;
 }
 
 // Device buffers and host mirrors of one call.
 struct CallBufs {
   uint64_t *premix;
-  unsigned long long *state, *best, *gctr, *lctr;
+  unsigned long long *state, *best, *sides, *gctr, *lctr;
   unsigned int *wleaf;
 };
 
@@ -837,6 +1069,7 @@ CallBufs carve(void *buf, const Layout &lay) {
   c.premix = (uint64_t *)(b + lay.premix);
   c.state = (unsigned long long *)(b + lay.state);
   c.best = (unsigned long long *)(b + lay.best);
+  c.sides = (unsigned long long *)(b + lay.sides);
   c.wleaf = (unsigned int *)(b + lay.wleaf);
   c.gctr = (unsigned long long *)(b + lay.gctr);
   c.lctr = (unsigned long long *)(b + lay.lctr);
@@ -853,12 +1086,12 @@ hipError_t enqueue_prologue(const CallBufs &cb, const Plan &pl, const uint64_t *
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)((n_leaves + 3) / 4)), dim3(256), 0, stream, keys, offsets,
-                     n_leaves, cb.premix, cb.state, cb.best, cb.gctr, check_dups);
+                     n_leaves, cb.premix, cb.state, cb.best, cb.gctr, cb.sides, check_dups);
   return hipGetLastError();
 }
 
 Params base_params(const CallBufs &cb, const Plan &pl, const shock_opts &opts, const uint64_t *offsets,
-                   uint64_t *out_seeds, uint64_t *out_orient) {
+                   uint64_t *out_seeds, uint64_t *out_orient, uint32_t *out_rot) {
   Params P;
   memset(&P, 0, sizeof(P));
   P.offsets = offsets;
@@ -867,14 +1100,17 @@ Params base_params(const CallBufs &cb, const Plan &pl, const shock_opts &opts, c
   P.max_seed = opts.max_seed;
   P.out_seeds = out_seeds;
   P.out_orient = out_orient;
+  P.out_rot = out_rot;
   P.state = cb.state;
   P.best = cb.best;
   P.wleaf = cb.wleaf;
   P.gctr = cb.gctr;
   P.cancel = opts.cancel;
   P.block_iters = (uint32_t)pl.units;
-  P.unit = 64ull * (uint64_t)pl.spl;
+  P.unit = pl.rf ? 64ull * kRfSeedsPerLane : 64ull * (uint64_t)pl.spl;
   P.block = P.unit * (uint64_t)pl.units;
+  P.partial_k = (uint32_t)opts.partial_k;
+  P.sides = cb.sides;
   P.workers = (uint32_t)pl.workers;
   memcpy(P.units_by_n, pl.units_by_n, sizeof(P.units_by_n));
   return P;
@@ -889,7 +1125,7 @@ hipError_t enqueue_search(Params P, const CallBufs &cb, const Plan &pl, uint64_t
     P.leaf_count = n_leaves;
     P.lctr = cb.lctr;
     P.split = 0;
-    return launch_search_spl(pl.spl, P, pl.wpw, stream);
+    return launch_search_spl(pl.spl, pl.rf, P, pl.wpw, stream);
   }
   P.split = 1;
   for (uint64_t j = 0; j < n_leaves; ++j) {
@@ -897,8 +1133,9 @@ hipError_t enqueue_search(Params P, const CallBufs &cb, const Plan &pl, uint64_t
     P.leaf_count = 1;
     P.lctr = cb.lctr + j * kLcCount;
     const uint32_t nj = h_off ? (uint32_t)(h_off[j + 1] - h_off[j]) : n_typical;
-    P.workers = workers_fixed ? (uint32_t)pl.workers : (uint32_t)plain_workers(nj, P.block, pl.wpw, pl.workers);
-    hipError_t e = launch_search_spl(pl.spl, P, pl.wpw, stream);
+    P.workers = workers_fixed ? (uint32_t)pl.workers
+                              : (uint32_t)plain_workers(nj, P.block, pl.wpw, pl.workers, pl.rf);
+    hipError_t e = launch_search_spl(pl.spl, pl.rf, P, pl.wpw, stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1030,8 +1267,10 @@ int shock_release_scratch(void) {
   return SHOCK_OK;
 }
 
-int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_seeds,
-                         uint64_t *out_orient, const shock_opts *opts_in, void *hip_stream) {
+}  // extern "C"
+
+static int search_sync(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_seeds,
+                       uint32_t *out_rot, uint64_t *out_orient, const shock_opts *opts_in, void *hip_stream, int rf) {
   shock_opts opts;
   shock_opts_init(&opts);
   if (opts_in) opts = *opts_in;
@@ -1041,6 +1280,7 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
   int rc = check_opts(opts, n_leaves, offsets, out_seeds, out_orient);
   if (rc != SHOCK_OK) return rc;
   if (!keys) return SHOCK_EINVAL;
+  if (rf && (!out_rot || opts.max_seed > (1ull << 57))) return SHOCK_EINVAL;
   hipStream_t stream = (hipStream_t)hip_stream;
   const int mode = opts.mode == SHOCK_MODE_AUTO ? SHOCK_MODE_PERSISTENT : opts.mode;
   if (mode != SHOCK_MODE_PERSISTENT && mode != SHOCK_MODE_PLAIN_PER_LEAF) return SHOCK_EINVAL;
@@ -1056,7 +1296,7 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
   const CallBufs cb = carve(buf, lay);
 
   Plan pl;
-  rc = make_plan(opts, n_leaves, 48, pl);
+  rc = make_plan(opts, n_leaves, 48, rf, pl);
   if (rc != SHOCK_OK) return rc;
   HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts.check_dups, (uint32_t)workers_cap, stream));
   // Validation result and leaf sizes for launch sizing: all offsets for
@@ -1074,10 +1314,10 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
   if (host_ctr[kCtrErr] & kErrDup) return SHOCK_EDUPKEY;
 
   const uint32_t n_mean = (uint32_t)((h_off.back() - h_off.front() + n_leaves / 2) / n_leaves);
-  rc = make_plan(opts, n_leaves, n_mean, pl);
+  rc = make_plan(opts, n_leaves, n_mean, rf, pl);
   if (rc != SHOCK_OK) return rc;
   if (pl.workers > workers_cap) return SHOCK_EINVAL;
-  Params P = base_params(cb, pl, opts, offsets, out_seeds, out_orient);
+  Params P = base_params(cb, pl, opts, offsets, out_seeds, out_orient, out_rot);
 
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -1087,7 +1327,7 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
                          opts.workers != 0, stream));
   HIP_TRY(hipEventRecord(e1, stream));
   hipLaunchKernelGGL(mark_unfinished_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, stream, cb.gctr,
-                     cb.state, n_leaves, out_seeds, out_orient);
+                     cb.state, n_leaves, out_seeds, out_orient, out_rot);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(host_ctr, cb.gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
@@ -1102,6 +1342,18 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
   g_stats.block_iters = pl.units;
   g_stats.waves_per_wg = pl.wpw;
   return rc;
+}
+
+extern "C" {
+
+int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_seeds,
+                         uint64_t *out_orient, const shock_opts *opts, void *hip_stream) {
+  return search_sync(keys, offsets, n_leaves, out_seeds, nullptr, out_orient, opts, hip_stream, 0);
+}
+
+int shock_rf_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_seeds,
+                            uint32_t *out_rot, uint64_t *out_orient, const shock_opts *opts, void *hip_stream) {
+  return search_sync(keys, offsets, n_leaves, out_seeds, out_rot, out_orient, opts, hip_stream, 1);
 }
 
 int shock_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_seeds,
@@ -1158,29 +1410,30 @@ int shock_ctx_destroy(shock_ctx *c) {
 
 // Enqueue the whole call on `stream` without any host synchronisation.
 static int ctx_enqueue(shock_ctx *c, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
-                       uint64_t *out_seeds, uint64_t *out_orient, const shock_opts &opts, hipStream_t stream,
-                       bool with_events) {
+                       uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient, const shock_opts &opts,
+                       hipStream_t stream, bool with_events) {
   const CallBufs cb = carve(c->buf, layout(c->max_leaves, c->workers_cap, c->max_leaves));
   Plan pl;
   const uint32_t hint = opts.leaf_size_hint ? (uint32_t)opts.leaf_size_hint : 48;
-  int rc = make_plan(opts, n_leaves, hint, pl);
+  int rc = make_plan(opts, n_leaves, hint, out_rot != nullptr, pl);
   if (rc != SHOCK_OK) return rc;
   if (pl.workers > (int)c->workers_cap) return SHOCK_EINVAL;
   HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts.check_dups, c->workers_cap, stream));
-  Params P = base_params(cb, pl, opts, offsets, out_seeds, out_orient);
+  Params P = base_params(cb, pl, opts, offsets, out_seeds, out_orient, out_rot);
   if (with_events) HIP_TRY(hipEventRecord(c->ev_begin, stream));
   HIP_TRY(enqueue_search(P, cb, pl, n_leaves, nullptr, hint, opts.workers != 0, stream));
   if (with_events) HIP_TRY(hipEventRecord(c->ev_search, stream));
   hipLaunchKernelGGL(mark_unfinished_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, stream, cb.gctr,
-                     cb.state, n_leaves, out_seeds, out_orient);
+                     cb.state, n_leaves, out_seeds, out_orient, out_rot);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(c->host_ctr, cb.gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
   c->last_plan = pl;
   return SHOCK_OK;
 }
 
-int shock_ctx_search_async(shock_ctx *c, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
-                           uint64_t *out_seeds, uint64_t *out_orient, const shock_opts *opts_in, void *hip_stream) {
+static int ctx_async(shock_ctx *c, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                     uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient, const shock_opts *opts_in,
+                     void *hip_stream) {
   if (!c) return SHOCK_EINVAL;
   shock_opts opts;
   shock_opts_init(&opts);
@@ -1191,11 +1444,24 @@ int shock_ctx_search_async(shock_ctx *c, const uint64_t *keys, const uint64_t *o
   if (rc != SHOCK_OK) return rc;
   if (c->pending) HIP_TRY(hipEventSynchronize(c->ev_done));  // the counters buffer is reused
   hipStream_t stream = (hipStream_t)hip_stream;
-  rc = ctx_enqueue(c, keys, offsets, n_leaves, out_seeds, out_orient, opts, stream, true);
+  if (out_rot && opts.max_seed > (1ull << 57)) return SHOCK_EINVAL;
+  rc = ctx_enqueue(c, keys, offsets, n_leaves, out_seeds, out_rot, out_orient, opts, stream, true);
   if (rc != SHOCK_OK) return rc;
   HIP_TRY(hipEventRecord(c->ev_done, stream));
   c->pending = true;
   return SHOCK_OK;
+}
+
+int shock_ctx_search_async(shock_ctx *c, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                           uint64_t *out_seeds, uint64_t *out_orient, const shock_opts *opts, void *hip_stream) {
+  return ctx_async(c, keys, offsets, n_leaves, out_seeds, nullptr, out_orient, opts, hip_stream);
+}
+
+int shock_ctx_rf_search_async(shock_ctx *c, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                              uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient, const shock_opts *opts,
+                              void *hip_stream) {
+  if (!out_rot) return SHOCK_EINVAL;
+  return ctx_async(c, keys, offsets, n_leaves, out_seeds, out_rot, out_orient, opts, hip_stream);
 }
 
 int shock_ctx_query(shock_ctx *c) {
@@ -1249,13 +1515,13 @@ int shock_ctx_graph_capture(shock_ctx *c, const uint64_t *keys, const uint64_t *
   }
   {
     Plan warm;  // resolves and caches occupancy queries before capture starts
-    rc = make_plan(opts, n_leaves, opts.leaf_size_hint ? (uint32_t)opts.leaf_size_hint : 48, warm);
+    rc = make_plan(opts, n_leaves, opts.leaf_size_hint ? (uint32_t)opts.leaf_size_hint : 48, 0, warm);
     if (rc != SHOCK_OK) return rc;
   }
   hipStream_t cap;
   HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  rc = ctx_enqueue(c, keys, offsets, n_leaves, out_seeds, out_orient, opts, cap, false);
+  rc = ctx_enqueue(c, keys, offsets, n_leaves, out_seeds, nullptr, out_orient, opts, cap, false);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(cap, &g);
   (void)hipStreamDestroy(cap);
