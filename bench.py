@@ -33,6 +33,21 @@ PEAK_INT_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 int32 lanes per clock x 2.4 GHz
 # mix fmix64((s+1)*gamma) (19) and the coverage compare (1): 20.
 OPS_PER_EVAL = 13
 OPS_PER_SEED = 20
+# Rotation fitting (Section 4; partial hashing, Appendix A.2), per seed of a
+# leaf with na keys in the first set, nb in the second and period k: nb key
+# evaluations, na / k amortised ones, the seed mixes (1 + 1/k) * 19, and the
+# n - 1 nonzero rotations: a funnel shift and an OR per 32-bit word of the
+# mask, an AND joining two words (leaves above 32 keys), and half of a
+# 3-input max accumulating the test: 2.5 ops up to 32 keys, 4.5 above; plus
+# the unrotated test (2).
+RF_OPS_PER_ROT_NARROW = 2.5
+RF_OPS_PER_ROT_WIDE = 4.5
+
+
+def rf_ops_per_seed(n: int, na: int, partial_k: int) -> float:
+    k = partial_k or (8 if n > 32 else 1)
+    rot = RF_OPS_PER_ROT_WIDE if n > 32 else RF_OPS_PER_ROT_NARROW
+    return OPS_PER_EVAL * ((n - na) + na / k) + 19 * (1 + 1 / k) + 2 + rot * max(n - 1, 0)
 
 
 def measured_traffic(workload: str):
@@ -48,6 +63,20 @@ def measured_traffic(workload: str):
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
         return None
     return rec["bytes_per_launch"]
+
+
+def first_set_bit(keys: np.ndarray) -> np.ndarray:
+    """Which of the two rotation-fitting key sets each key falls in (the top
+    bit of the MurmurHash3 64-bit finaliser of key ^ 0xD1B54A32D192ED03);
+    used only to count the operations a leaf's seeds cost."""
+    with np.errstate(over="ignore"):
+        x = keys.astype(np.uint64) ^ np.uint64(0xD1B54A32D192ED03)
+        x ^= x >> np.uint64(33)
+        x *= np.uint64(0xFF51AFD7ED558CCD)
+        x ^= x >> np.uint64(33)
+        x *= np.uint64(0xC4CEB9FE1A85EC53)
+        x ^= x >> np.uint64(33)
+    return (x >> np.uint64(63)).astype(np.int64)
 
 
 def log(msg):
@@ -109,6 +138,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=60,
                     help="requests per serving run (0 = skip the serving leg)")
     ap.add_argument("--untuned", action="store_true", help="ignore the autotuner's cached table for this device")
+    ap.add_argument("--rf-steps", type=int, default=3,
+                    help="timed steps of the rotation-fitting search on the same batch (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -205,6 +236,51 @@ def main():
                  "seeds_tested_per_s": st_p["seeds_tested"] / wall_p, "same_outputs_as_batched": same}
         log(f"[bench] plain per-leaf: {Lp / wall_p:.0f} leaves/s")
 
+    # Rotation fitting on the same batch: a different output (seed, rotation),
+    # reported beside the plain search.
+    rf = None
+    if args.rf_steps > 0:
+        rot_d = torch.empty(L, dtype=torch.int32, device=dev)
+        rs_d = torch.empty(L, dtype=torch.int64, device=dev)
+        rf_d = torch.empty(L, dtype=torch.int64, device=dev)
+        rf_opts = {k: v for k, v in opts.items() if k == "waves_per_wg" and v}
+
+        def rf_step():
+            rc, _, _, _ = shock.rf_leaf_search(k_d, o_d, out_seeds=rs_d, out_rot=rot_d, out_orient=rf_d, **rf_opts)
+            if rc != shock.SHOCK_OK:
+                raise RuntimeError(f"rotation-fitting search failed: {shock.shock_strerror(rc)}")
+
+        log(f"[bench] rotation fitting: {args.rf_steps} steps")
+        rf_step()
+        torch.cuda.synchronize()
+        rf_ms, rf_tested, rf_pf = [], 0, 0
+        t2 = time.perf_counter()
+        for _ in range(args.rf_steps):
+            rf_step()
+            st_r = shock.shock_last_stats()
+            rf_ms.append(st_r["kernel_ms"])
+            rf_tested += st_r["seeds_tested"]
+            rf_pf += st_r["pf_checks"]
+        torch.cuda.synchronize()
+        wall_r = (time.perf_counter() - t2) / args.rf_steps
+        rs = rs_d.cpu().numpy().view(np.uint64).astype(np.float64)
+        na = np.add.reduceat(1 - first_set_bit(keys), offs[:-1].astype(np.int64)) if len(keys) else np.zeros(L)
+        ops_seed = np.array([rf_ops_per_seed(int(sizes[j]), int(na[j]), 0) for j in range(L)])
+        rf_alg = float(((rs + 1) * ops_seed).sum())
+        rf_kernel = float(np.mean(rf_ms))
+        rf = {"leaves_per_s": L / wall_r, "ms_per_step": wall_r * 1e3, "kernel_ms": rf_kernel,
+              "mean_seed": float(rs.mean()), "mean_seed_plain": float(seeds.astype(np.float64).mean()),
+              "seeds_tested_per_s": rf_tested / args.rf_steps / wall_r,
+              "candidates_per_s": float(((rs + 1) * sizes).sum()) / wall_r,
+              "overshoot": rf_tested / args.rf_steps / float((rs + 1).sum()) - 1.0,
+              "pf_checks_per_step": rf_pf / args.rf_steps,
+              "vs_plain_search": (L / wall_r) / leaves_per_s,
+              "roofline": {"bound": "alu", "achieved": rf_alg / (rf_kernel / 1e3) / 1e12, "peak": PEAK_INT_OPS / 1e12,
+                           "unit": "Tops/s (int32 lane ops)", "frac": rf_alg / (rf_kernel / 1e3) / PEAK_INT_OPS,
+                           "ops_per_seed_mean": float(ops_seed.mean())}}
+        log(f"[bench] rotation fitting: {L / wall_r:.0f} leaves/s, kernel {rf_kernel:.2f} ms, "
+            f"frac {rf['roofline']['frac']:.3f}")
+
     # Serving: MPHF-build requests (log-uniform 1e3..1e6 keys, Poisson
     # arrivals) cut into 48-key leaves, continuous batching over 4 streams
     # within a 256 MiB HBM budget.  Two runs over the same first K requests:
@@ -262,6 +338,7 @@ def main():
         "plain_per_leaf": plain,
         "batched_vs_plain": (leaves_per_s / plain["leaves_per_s"]) if plain else None,
         "latency": latency,
+        "rotation_fitting": rf,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                      "unit": "Tops/s (int32 lane ops)", "frac": achieved / PEAK_INT_OPS,
                      "traffic": measured_traffic(args.workload),

@@ -409,24 +409,48 @@ __device__ __forceinline__ uint64_t cover_mask(const uint64_t *a, uint32_t cnt, 
   return WIDE ? (((uint64_t)mhi << 32) | mlo) : (uint64_t)mlo;
 }
 
-// Whether some rotation r in [0, n) makes rot_n(mb, r) | ma cover [0, n).
-// `pad` has every bit at or above n set.
+// Whether some rotation r in [0, n) makes rot_n(mb, r) | ma cover [0, n),
+// rot_n moving bit i to (i + r) mod n.  With D = mb | mb << n (mb repeated),
+// rot_n(mb, r) is bits [n - r, 2n - r) of D, so each rotation is one funnel
+// shift (v_alignbit) per 32-bit word and an OR with ma (plus the bits at or
+// above n).  A rotation covers iff that word (the AND of both words above 32
+// keys) is all ones, the largest 32-bit value, so the test keeps a running
+// maximum (v_max3, two rotations per instruction) in a vector register
+// instead of a lane mask per rotation.  `pad` has every bit at or above n set.
+__device__ __forceinline__ uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) {
+  const uint32_t m = a > b ? a : b;
+  return m > c ? m : c;
+}
+
 template <bool WIDE>
 __device__ __forceinline__ bool any_rotation_covers(uint64_t ma, uint64_t mb, uint32_t n, uint64_t pad) {
-  bool any = ((mb | ma | pad) == ~0ull);
-  if (WIDE) {
-    for (uint32_t r = 1; r < n; ++r) {
-      const uint64_t rot = (mb << r) | (mb >> (n - r));
-      any |= ((rot | ma | pad) == ~0ull);
-    }
+  const uint64_t z = ma | pad;
+  const uint64_t m0 = mb | z;  // r = 0
+  uint32_t acc = (uint32_t)m0 & (uint32_t)(m0 >> 32);
+  if (!WIDE) {
+    const uint32_t z32 = (uint32_t)z;
+    const uint64_t d = mb | (mb << n);  // n <= 32: 2n bits
+    const uint32_t d0 = (uint32_t)d, d1 = (uint32_t)(d >> 32);
+    uint32_t sh = 1;
+    for (; sh + 1 < n; sh += 2)
+      acc = umax3(acc, __builtin_amdgcn_alignbit(d1, d0, sh) | z32, __builtin_amdgcn_alignbit(d1, d0, sh + 1) | z32);
+    if (sh < n) acc = umax3(acc, acc, __builtin_amdgcn_alignbit(d1, d0, sh) | z32);
   } else {
-    const uint32_t ma32 = (uint32_t)ma, mb32 = (uint32_t)mb, pad32 = (uint32_t)pad;
-    for (uint32_t r = 1; r < n; ++r) {
-      const uint32_t rot = (mb32 << r) | (mb32 >> (n - r));
-      any |= ((rot | ma32 | pad32) == ~0u);
-    }
+    const uint32_t zlo = (uint32_t)z, zhi = (uint32_t)(z >> 32);
+    const unsigned __int128 d = (unsigned __int128)mb | ((unsigned __int128)mb << n);  // 33 <= n <= 64
+    const uint32_t w0 = (uint32_t)d, w1 = (uint32_t)(d >> 32), w2 = (uint32_t)(d >> 64), w3 = (uint32_t)(d >> 96);
+    auto word = [&](uint32_t a1, uint32_t a0, uint32_t b1, uint32_t b0, uint32_t sh) {
+      return (__builtin_amdgcn_alignbit(a1, a0, sh) | zlo) & (__builtin_amdgcn_alignbit(b1, b0, sh) | zhi);
+    };
+    for (uint32_t sh = 1; sh < 31; sh += 2)  // shifts 1..30, then 31 with the next range's first
+      acc = umax3(acc, word(w1, w0, w2, w1, sh), word(w1, w0, w2, w1, sh + 1));
+    uint32_t sh = 0;  // shifts 32 + sh
+    acc = umax3(acc, word(w1, w0, w2, w1, 31), word(w2, w1, w3, w2, 0));
+    for (sh = 1; sh + 33 < n; sh += 2)
+      acc = umax3(acc, word(w2, w1, w3, w2, sh), word(w2, w1, w3, w2, sh + 1));
+    if (sh + 32 < n) acc = umax3(acc, acc, word(w2, w1, w3, w2, sh));
   }
-  return any;
+  return acc == ~0u;
 }
 
 // Slots of this lane's key (lane < n) under candidate (s, r).
@@ -443,16 +467,51 @@ __device__ __forceinline__ void rf_lane_slots(uint32_t my_alo, uint32_t my_ahi, 
   }
 }
 
+// Pseudoforest test by peeling, wave-parallel: lane i < n holds edge i
+// (h0, h1), lane c stands for cell c.  Cells of degree one lose their edge,
+// all at once, until none is left; the graph is a pseudoforest iff what
+// remains (its 2-core) has no cell of degree above two, i.e. is a set of
+// disjoint cycles: a component with two or more cycles keeps a cell of degree
+// three or more in its 2-core.  Apart from building the incidence masks in
+// LDS, every round is a few register operations and two ballots, where the
+// union-find needs LDS round trips per step; rotation fitting tests many
+// more candidates per leaf, so it uses this form.  Needs n >= 2 (no loops).
+__device__ bool pf_peel_wave(uint32_t n, uint32_t h0, uint32_t h1, WaveLds &lds) {
+  const uint32_t lane = lane_id();
+  const bool act = lane < n;
+  unsigned long long *inc = lds.ori.inc0;
+  inc[lane] = 0;
+  wave_lds_sync();
+  if (act) {
+    atomicOr(&inc[h0], 1ull << lane);
+    atomicOr(&inc[h1], 1ull << lane);
+  }
+  wave_lds_sync();
+  const uint64_t mine = inc[lane];
+  uint64_t rem = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  // Every round that finds a cell of degree one removes an edge, so at most
+  // n + 1 rounds run.
+  for (uint32_t round = 0; round <= 64; ++round) {
+    const uint64_t d1 = __ballot(__popcll(mine & rem) == 1);
+    if (d1 == 0) break;
+    const bool gone = act && (((d1 >> h0) | (d1 >> h1)) & 1);
+    rem &= ~__ballot(gone);
+  }
+  return __ballot(__popcll(mine & rem) > 2) == 0;
+}
+
 // Rotations of seed s whose graphs pass the coverage filter, one bit per
 // rotation, computed by the whole wave: every key ORs its slots into the
-// mask of its set in LDS, then lane r tests rotation r.
+// mask of its set in LDS, then lane r tests rotation r.  h0, h1 return this
+// lane's slots under (s, 0).
 __device__ uint64_t rf_rotations(uint32_t n, uint64_t s, bool partial, uint32_t my_alo, uint32_t my_ahi,
-                                 uint32_t my_side, WaveLds &lds) {
+                                 uint32_t my_side, WaveLds &lds, uint32_t &h0, uint32_t &h1) {
   const uint32_t lane = lane_id();
   if (lane < 2) lds.rmask[lane] = 0;
   wave_lds_sync();
+  h0 = 0;
+  h1 = 0;
   if (lane < n) {
-    uint32_t h0, h1;
     rf_lane_slots(my_alo, my_ahi, my_side, s, 0, partial, n, h0, h1);
     atomicOr(&lds.rmask[my_side], (1ull << h0) | (1ull << h1));
   }
@@ -483,16 +542,17 @@ __device__ uint64_t rf_search_block(uint32_t n, uint32_t na, uint32_t nb, bool p
     const uint64_t s0 = ib + (uint64_t)lane * kRfSeedsPerLane;
     uint32_t flags = 0;
     uint64_t ma = 0;
-#pragma unroll
+#pragma unroll 1
     for (uint32_t i = 0; i < kRfSeedsPerLane; ++i) {
       const uint64_t s = s0 + i;
-      // s0 mod 8 is the same in every lane, so this choice is wave-uniform.
-      if (!partial || i == 0 || (s % kRfSeedsPerLane) == 0) {
-        const uint64_t sa = partial ? s - (s % kRfSeedsPerLane) : s;
-        const uint64_t ta = fmix64((sa + 1) * kGolden);
+      const uint64_t t = fmix64((s + 1) * kGolden);
+      // (ib + i) mod 8 = s mod 8 in every lane: a wave-uniform branch.
+      if (!partial) {
+        ma = cover_mask<WIDE>(lds.keys_a, na, (uint32_t)t, (uint32_t)(t >> 32), n, nm1);
+      } else if (i == 0 || ((ib + i) % kRfSeedsPerLane) == 0) {
+        const uint64_t ta = fmix64((s - (s % kRfSeedsPerLane) + 1) * kGolden);
         ma = cover_mask<WIDE>(lds.keys_a, na, (uint32_t)ta, (uint32_t)(ta >> 32), n, nm1);
       }
-      const uint64_t t = fmix64((s + 1) * kGolden);
       const uint64_t mb = cover_mask<WIDE>(lds.keys_b, nb, (uint32_t)t, (uint32_t)(t >> 32), n, nm1);
       const bool any = any_rotation_covers<WIDE>(ma, mb, n, pad);
       flags |= (any && s < end) ? (1u << i) : 0u;
@@ -508,15 +568,18 @@ __device__ uint64_t rf_search_block(uint32_t n, uint32_t na, uint32_t nb, bool p
         const uint32_t i = __builtin_ctz(fl);
         fl &= fl - 1;
         const uint64_t s = ib + (uint64_t)l * kRfSeedsPerLane + i;
-        uint64_t rots = rf_rotations(n, s, partial, my_alo, my_ahi, my_side, lds);
+        uint32_t g0, g1;
+        uint64_t rots = rf_rotations(n, s, partial, my_alo, my_ahi, my_side, lds, g0, g1);
         while (rots != 0) {
           const uint32_t r = __builtin_ctzll(rots);
           rots &= rots - 1;
           st.passes += 1;
           st.pf += 1;
-          uint32_t h0 = 0, h1 = 0;
-          rf_lane_slots(my_alo, my_ahi, my_side, s, r, partial, n, h0, h1);
-          if (pf_test_wave(n, h0, h1, lds)) return s * 64 + r;
+          // second-set slots move by r (mod n); both are below n
+          const uint32_t add = my_side ? r : 0u;
+          const uint32_t h0 = g0 + add >= n ? g0 + add - n : g0 + add;
+          const uint32_t h1 = g1 + add >= n ? g1 + add - n : g1 + add;
+          if (pf_peel_wave(n, h0, h1, lds)) return s * 64 + r;
         }
       }
     }
@@ -1017,7 +1080,7 @@ struct Plan {
 
 // Rotation fitting: claim units are 64 lanes x 8 seeds and a leaf needs
 // about n times fewer seeds, so claims are small.
-int default_rf_units(uint32_t n) { return n >= 44 ? 2 : 1; }
+int default_rf_units(uint32_t) { return 1; }
 
 int make_plan(const shock_opts &opts, uint64_t n_leaves, uint32_t n_typical, int rf, Plan &pl) {
   pl.mode = opts.mode == SHOCK_MODE_AUTO ? SHOCK_MODE_PERSISTENT : opts.mode;
