@@ -50,12 +50,13 @@ def rf_ops_per_seed(n: int, na: int, partial_k: int) -> float:
     return OPS_PER_EVAL * ((n - na) + na / k) + 19 * (1 + 1 / k) + 2 + rot * max(n - 1, 0)
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, kind: str = ""):
     """HBM bytes per search launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE passes (profiles/), or None if the kernel source changed since
-    they were taken or the workload differs."""
+    they were taken or the workload differs.  kind "rf_" is the rotation-fitting
+    kernel."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_search_kernel_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kind}search_kernel_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -277,7 +278,8 @@ def main():
               "vs_plain_search": (L / wall_r) / leaves_per_s,
               "roofline": {"bound": "alu", "achieved": rf_alg / (rf_kernel / 1e3) / 1e12, "peak": PEAK_INT_OPS / 1e12,
                            "unit": "Tops/s (int32 lane ops)", "frac": rf_alg / (rf_kernel / 1e3) / PEAK_INT_OPS,
-                           "ops_per_seed_mean": float(ops_seed.mean())}}
+                           "ops_per_seed_mean": float(ops_seed.mean()),
+                           "traffic": measured_traffic(args.workload, "rf_")}}
         log(f"[bench] rotation fitting: {L / wall_r:.0f} leaves/s, kernel {rf_kernel:.2f} ms, "
             f"frac {rf['roofline']['frac']:.3f}")
 
