@@ -25,6 +25,7 @@ DEFAULT_MAX_SEED = 1 << 32
 
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
 
 
 def build(force: bool = True) -> str:
@@ -68,6 +69,16 @@ def lib():
         L.shock_oracle_rf_leaf_search.restype = ctypes.c_int
         L.shock_oracle_rf_leaf_search.argtypes = [_u64p, _u64p, ctypes.c_uint64, _u64p, _u32p, _u64p,
                                                   ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
+        L.shock_oracle_leaf_query.restype = ctypes.c_int
+        L.shock_oracle_leaf_query.argtypes = [_u64p, _u64p, ctypes.c_uint64, _u64p, _u64p, _u64p]
+        L.shock_oracle_rf_leaf_query.restype = ctypes.c_int
+        L.shock_oracle_rf_leaf_query.argtypes = [_u64p, _u64p, ctypes.c_uint64, _u64p, _u32p, _u64p,
+                                                 ctypes.c_uint32, _u64p]
+        L.shock_oracle_rice_encode.restype = ctypes.c_int
+        L.shock_oracle_rice_encode.argtypes = [_u64p, _u64p, ctypes.c_uint64, _u8p, _u64p, ctypes.c_uint64, _u64p,
+                                               ctypes.c_uint64, _u64p, _u64p]
+        L.shock_oracle_rice_decode.restype = ctypes.c_int
+        L.shock_oracle_rice_decode.argtypes = [_u64p, _u64p, _u64p, ctypes.c_uint64, _u8p, _u64p]
         L.shock_oracle_seed_stats.restype = None
         L.shock_oracle_seed_stats.argtypes = [_u64p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                               _u64p, _u64p, _u64p]
@@ -204,3 +215,69 @@ def rf_leaf_search(keys, offsets, start_seed: int = 0, max_seed: int = DEFAULT_M
                                            L, _p64(seeds), _p32(rot), _p64(orient), start_seed, max_seed,
                                            partial_k, int(use_filter))
     return rc, seeds, rot, orient
+
+
+def leaf_query(keys, offsets, seeds, orient):
+    """(status, positions uint64[N]): the MPHF value of every key (Section 4's query)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
+    orient = np.ascontiguousarray(orient, dtype=np.uint64)
+    L = max(len(offsets) - 1, 0)
+    pos = np.zeros(max(int(offsets[-1]) if len(offsets) else 0, 1), dtype=np.uint64)
+    rc = lib().shock_oracle_leaf_query(_p64(keys) if keys.size else None, _p64(offsets), L, _p64(seeds),
+                                       _p64(orient), _p64(pos))
+    return rc, pos[:int(offsets[-1]) if len(offsets) else 0]
+
+
+def rf_leaf_query(keys, offsets, seeds, rot, orient, partial_k: int = 0):
+    """(status, positions uint64[N]) under rotation fitting."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
+    rot = np.ascontiguousarray(rot, dtype=np.uint32)
+    orient = np.ascontiguousarray(orient, dtype=np.uint64)
+    L = max(len(offsets) - 1, 0)
+    pos = np.zeros(max(int(offsets[-1]) if len(offsets) else 0, 1), dtype=np.uint64)
+    rc = lib().shock_oracle_rf_leaf_query(_p64(keys) if keys.size else None, _p64(offsets), L, _p64(seeds),
+                                          _p32(rot), _p64(orient), partial_k, _p64(pos))
+    return rc, pos[:int(offsets[-1]) if len(offsets) else 0]
+
+
+def rice_encode(values, offsets, k_by_n, fixed_words=None, unary_words=None):
+    """(status, fixed uint64[], unary uint64[], index uint64[], (fixed_bits, unary_bits)).
+
+    Without explicit capacities the streams are sized from a first call."""
+    values = np.ascontiguousarray(values, dtype=np.uint64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    k = np.ascontiguousarray(k_by_n, dtype=np.uint8)
+    assert k.size == 65
+    L = max(len(offsets) - 1, 0)
+    bits = np.zeros(2, dtype=np.uint64)
+    if fixed_words is None or unary_words is None:
+        rc = lib().shock_oracle_rice_encode(_p64(values) if values.size else None, _p64(offsets), L,
+                                            k.ctypes.data_as(_u8p), None, 0, None, 0, None, _p64(bits))
+        fixed_words = int((bits[0] + 63) // 64)
+        unary_words = int((bits[1] + 63) // 64)
+    fixed = np.zeros(max(fixed_words, 1), dtype=np.uint64)
+    unary = np.zeros(max(unary_words, 1), dtype=np.uint64)
+    index = np.zeros(2 * ((L + 63) // 64 + 1), dtype=np.uint64)
+    rc = lib().shock_oracle_rice_encode(_p64(values) if values.size else None, _p64(offsets), L,
+                                        k.ctypes.data_as(_u8p), _p64(fixed), fixed_words, _p64(unary), unary_words,
+                                        _p64(index), _p64(bits))
+    return rc, fixed[:fixed_words], unary[:unary_words], index, (int(bits[0]), int(bits[1]))
+
+
+def rice_decode(fixed, unary, offsets, k_by_n):
+    """(status, values uint64[L]) decoded from the two streams alone."""
+    fixed = np.ascontiguousarray(fixed, dtype=np.uint64)
+    unary = np.ascontiguousarray(unary, dtype=np.uint64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    k = np.ascontiguousarray(k_by_n, dtype=np.uint8)
+    L = max(len(offsets) - 1, 0)
+    values = np.zeros(max(L, 1), dtype=np.uint64)
+    f = fixed if fixed.size else np.zeros(1, dtype=np.uint64)
+    rc = lib().shock_oracle_rice_decode(_p64(f), _p64(unary) if unary.size else None, _p64(offsets), L,
+                                        k.ctypes.data_as(_u8p), _p64(values))
+    return rc, values[:L]
+

@@ -320,3 +320,126 @@ int shock_oracle_rf_leaf_search(const uint64_t *keys, const uint64_t *offsets, u
   }
   return status;
 }
+
+/* ---- Query ---------------------------------------------------------------- */
+
+static int check_csr(const uint64_t *offsets, uint64_t n_leaves) {
+  if (offsets == NULL) return 0;
+  for (uint64_t j = 0; j < n_leaves; ++j)
+    if (offsets[j + 1] < offsets[j] || offsets[j + 1] - offsets[j] > 64) return 0;
+  return 1;
+}
+
+int shock_oracle_leaf_query(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                            const uint64_t *seeds, const uint64_t *orient, uint64_t *out_pos) {
+  if (n_leaves == 0) return SHOCK_ORACLE_OK;
+  if (!check_csr(offsets, n_leaves) || seeds == NULL || orient == NULL || out_pos == NULL) return SHOCK_ORACLE_EINVAL;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    uint32_t n = (uint32_t)(offsets[j + 1] - offsets[j]);
+    for (uint32_t i = 0; i < n; ++i) {
+      uint64_t g = offsets[j] + i;
+      if (seeds[j] == UINT64_MAX) {
+        out_pos[g] = UINT64_MAX;
+        continue;
+      }
+      uint32_t h0, h1;
+      shock_oracle_slots(keys[g], seeds[j], n, &h0, &h1);
+      out_pos[g] = offsets[j] + (((orient[j] >> i) & 1) ? h1 : h0);
+    }
+  }
+  return SHOCK_ORACLE_OK;
+}
+
+int shock_oracle_rf_leaf_query(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                               const uint64_t *seeds, const uint32_t *rot, const uint64_t *orient,
+                               uint32_t partial_k, uint64_t *out_pos) {
+  if (n_leaves == 0) return SHOCK_ORACLE_OK;
+  if (!check_csr(offsets, n_leaves) || seeds == NULL || rot == NULL || orient == NULL || out_pos == NULL)
+    return SHOCK_ORACLE_EINVAL;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    uint32_t n = (uint32_t)(offsets[j + 1] - offsets[j]);
+    uint32_t k = partial_k ? partial_k : (n > 32 ? 8u : 1u);
+    for (uint32_t i = 0; i < n; ++i) {
+      uint64_t g = offsets[j] + i;
+      if (seeds[j] == UINT64_MAX) {
+        out_pos[g] = UINT64_MAX;
+        continue;
+      }
+      uint32_t h0, h1;
+      shock_oracle_rf_slots(keys[g], seeds[j], rot[j], k, n, &h0, &h1);
+      out_pos[g] = offsets[j] + (((orient[j] >> i) & 1) ? h1 : h0);
+    }
+  }
+  return SHOCK_ORACLE_OK;
+}
+
+/* ---- Golomb-Rice codes ----------------------------------------------------- */
+
+static void put_bit(uint64_t *stream, uint64_t p) { stream[p / 64] |= 1ULL << (p % 64); }
+static int get_bit(const uint64_t *stream, uint64_t p) { return (int)((stream[p / 64] >> (p % 64)) & 1); }
+
+int shock_oracle_rice_encode(const uint64_t *values, const uint64_t *offsets, uint64_t n_leaves,
+                             const uint8_t *k_by_n, uint64_t *fixed, uint64_t fixed_words, uint64_t *unary,
+                             uint64_t unary_words, uint64_t *index, uint64_t *bits) {
+  if (bits == NULL || k_by_n == NULL) return SHOCK_ORACLE_EINVAL;
+  if (n_leaves > 0 && (!check_csr(offsets, n_leaves) || values == NULL)) return SHOCK_ORACLE_EINVAL;
+  for (int n = 0; n <= 64; ++n)
+    if (k_by_n[n] > 56) return SHOCK_ORACLE_EINVAL;
+  /* first pass: lengths, and the quotient limit */
+  uint64_t fbits = 0, ubits = 0;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    uint32_t k = k_by_n[offsets[j + 1] - offsets[j]];
+    uint64_t q = values[j] >> k;
+    if (q >= (1ULL << 32)) return SHOCK_ORACLE_EINVAL;
+    fbits += k;
+    ubits += q + 1;
+  }
+  bits[0] = fbits;
+  bits[1] = ubits;
+  if ((fbits + 63) / 64 > fixed_words || (ubits + 63) / 64 > unary_words) return SHOCK_ORACLE_EINVAL;
+  if ((fixed_words > 0 && fixed == NULL) || (unary_words > 0 && unary == NULL) || index == NULL)
+    return SHOCK_ORACLE_EINVAL;
+  for (uint64_t w = 0; w < fixed_words; ++w) fixed[w] = 0;
+  for (uint64_t w = 0; w < unary_words; ++w) unary[w] = 0;
+  /* second pass: the codes, leaf by leaf */
+  uint64_t fp = 0, up = 0;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    if (j % 64 == 0) {
+      index[2 * (j / 64)] = fp;
+      index[2 * (j / 64) + 1] = up;
+    }
+    uint32_t k = k_by_n[offsets[j + 1] - offsets[j]];
+    for (uint32_t b = 0; b < k; ++b)
+      if ((values[j] >> b) & 1) put_bit(fixed, fp + b);
+    fp += k;
+    up += values[j] >> k; /* q zero bits */
+    put_bit(unary, up);   /* then the terminating one */
+    up += 1;
+  }
+  uint64_t m = (n_leaves + 63) / 64;
+  index[2 * m] = fp;
+  index[2 * m + 1] = up;
+  return SHOCK_ORACLE_OK;
+}
+
+int shock_oracle_rice_decode(const uint64_t *fixed, const uint64_t *unary, const uint64_t *offsets,
+                             uint64_t n_leaves, const uint8_t *k_by_n, uint64_t *values) {
+  if (n_leaves == 0) return SHOCK_ORACLE_OK;
+  if (!check_csr(offsets, n_leaves) || k_by_n == NULL || values == NULL || unary == NULL) return SHOCK_ORACLE_EINVAL;
+  uint64_t fp = 0, up = 0;
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    uint32_t k = k_by_n[offsets[j + 1] - offsets[j]];
+    uint64_t low = 0;
+    for (uint32_t b = 0; b < k; ++b) low |= (uint64_t)get_bit(fixed, fp + b) << b;
+    fp += k;
+    uint64_t q = 0;
+    while (!get_bit(unary, up)) {
+      ++q;
+      ++up;
+    }
+    ++up;
+    values[j] = (q << k) | low;
+  }
+  return SHOCK_ORACLE_OK;
+}
+

@@ -123,6 +123,43 @@ int shock_oracle_rf_leaf_search(const uint64_t *keys, const uint64_t *offsets, u
                                 uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient,
                                 uint64_t start_seed, uint64_t max_seed, uint32_t partial_k, int use_filter);
 
+/* ---- Query (Section 4: a key x is answered by h_{s, f(x)}(x)) ------------
+ * Key i of leaf j (global index offsets[j] + i) maps to
+ *   offsets[j] + (bit i of orient[j] ? h1 : h0)(x_i, seeds[j]),
+ * a global position in [0, offsets[n_leaves]).  Leaves whose seed is
+ * UINT64_MAX (none found) map their keys to UINT64_MAX.  The rotation-fitting
+ * form takes the slots of shock_oracle_rf_slots under (seeds[j], rot[j]) with
+ * period partial_k (0: 8 above 32 keys, else 1).  HOST pointers; out_pos has
+ * offsets[n_leaves] entries (indexed by the global key index). */
+int shock_oracle_leaf_query(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                            const uint64_t *seeds, const uint64_t *orient, uint64_t *out_pos);
+int shock_oracle_rf_leaf_query(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                               const uint64_t *seeds, const uint32_t *rot, const uint64_t *orient,
+                               uint32_t partial_k, uint64_t *out_pos);
+
+/* ---- Golomb-Rice codes of per-leaf values (the seed encoding of Section 4;
+ * Golomb 1966, Rice 1979) ----------------------------------------------------
+ * Leaf j (n_j = offsets[j+1] - offsets[j] keys) codes value v_j with the Rice
+ * parameter k = k_by_n[n_j] (k_by_n has 65 entries, each at most 56):
+ *   - its k low bits go to the FIXED stream, least significant first;
+ *   - its quotient q = v_j >> k goes to the UNARY stream as q zero bits
+ *     followed by one 1 bit.
+ * Each stream is the concatenation of the leaves' parts in leaf order.  Bit p
+ * of a stream is bit (p mod 64) of 64-bit word p / 64 (least significant bit
+ * first); unused bits are zero.
+ * The sampled index has 2 * (ceil(n_leaves / 64) + 1) words: for m = 0, 1,
+ * ..., entry (2m, 2m+1) is the (fixed, unary) bit position where leaf 64m's
+ * codes start (the last pair: the total lengths).
+ * encode: fixed / unary have fixed_words / unary_words words; bits[0], bits[1]
+ * receive the two stream lengths in bits.  Returns EINVAL if a quotient is
+ * 2^32 or more, or if a stream does not fit (bits[] still receive the lengths
+ * needed).  decode: the inverse, from the streams alone (no index). */
+int shock_oracle_rice_encode(const uint64_t *values, const uint64_t *offsets, uint64_t n_leaves,
+                             const uint8_t *k_by_n, uint64_t *fixed, uint64_t fixed_words, uint64_t *unary,
+                             uint64_t unary_words, uint64_t *index, uint64_t *bits);
+int shock_oracle_rice_decode(const uint64_t *fixed, const uint64_t *unary, const uint64_t *offsets,
+                             uint64_t n_leaves, const uint8_t *k_by_n, uint64_t *values);
+
 /* Statistics helper: over seeds s0 .. s0+count-1 of one leaf of n keys, count
  * the seeds whose slots cover all n cells and, among them, the pseudoforests.
  * Also counts seeds where h0 alone is a bijection. */
