@@ -28,6 +28,7 @@ EXPORTED = [
     "shock_last_error", "shock_strerror", "shock_release_scratch", "shock_spec_version",
     "shock_ctx_create", "shock_ctx_destroy", "shock_ctx_search_async", "shock_ctx_query", "shock_ctx_wait",
     "shock_ctx_graph_capture", "shock_ctx_graph_launch", "shock_rf_leaf_search_ex", "shock_ctx_rf_search_async",
+    "shock_leaf_query", "shock_rf_leaf_query", "shock_rice_encode", "shock_rice_decode",
 ]
 
 
@@ -118,6 +119,16 @@ def lib():
         L.shock_ctx_rf_search_async.restype = ctypes.c_int
         L.shock_ctx_rf_search_async.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp, vp, ctypes.POINTER(ShockOpts),
                                                 vp]
+        L.shock_leaf_query.restype = ctypes.c_int
+        L.shock_leaf_query.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, vp]
+        L.shock_rf_leaf_query.restype = ctypes.c_int
+        L.shock_rf_leaf_query.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, ctypes.c_int32, vp, vp]
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.shock_rice_encode.restype = ctypes.c_int
+        L.shock_rice_encode.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, ctypes.c_uint64, vp, ctypes.c_uint64, vp,
+                                        u64p, vp]
+        L.shock_rice_decode.restype = ctypes.c_int
+        L.shock_rice_decode.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint64, vp, vp, ctypes.c_uint64, vp, vp, vp]
         L.shock_ctx_query.restype = ctypes.c_int
         L.shock_ctx_query.argtypes = [vp]
         L.shock_ctx_wait.restype = ctypes.c_int
@@ -344,3 +355,83 @@ class SearchContext:
         if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
             raise ShockError(rc, lib().shock_last_error().decode())
         return rc, st.as_dict()
+
+
+# ---- queries and Golomb-Rice seed codes (include/shockcode.h) ---------------
+
+def _stream_of(t, stream):
+    import torch
+    return ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def leaf_query(keys, offsets, seeds, orient, out_pos=None, stream=None):
+    """(status, positions) for a CSR batch: int64 device tensors in, an int64
+    tensor of offsets[-1] global positions out (uint64 bit patterns)."""
+    import torch
+    _check_tensors(keys, offsets)
+    L = offsets.numel() - 1
+    N = int(offsets[-1].item()) if L >= 0 else 0
+    if out_pos is None:
+        out_pos = torch.empty(max(N, 1), dtype=torch.int64, device=keys.device)
+    rc = lib().shock_leaf_query(_as_ptr(keys if keys.numel() else offsets), _as_ptr(offsets), max(L, 0),
+                                _as_ptr(seeds), _as_ptr(orient), _as_ptr(out_pos), _stream_of(keys, stream))
+    return rc, out_pos[:N]
+
+
+def rf_leaf_query(keys, offsets, seeds, rot, orient, partial_k=0, out_pos=None, stream=None):
+    """leaf_query under rotation fitting; rot an int32 device tensor."""
+    import torch
+    _check_tensors(keys, offsets)
+    L = offsets.numel() - 1
+    N = int(offsets[-1].item()) if L >= 0 else 0
+    if out_pos is None:
+        out_pos = torch.empty(max(N, 1), dtype=torch.int64, device=keys.device)
+    rc = lib().shock_rf_leaf_query(_as_ptr(keys if keys.numel() else offsets), _as_ptr(offsets), max(L, 0),
+                                   _as_ptr(seeds), _as_ptr(rot), _as_ptr(orient), partial_k, _as_ptr(out_pos),
+                                   _stream_of(keys, stream))
+    return rc, out_pos[:N]
+
+
+def _table(k_by_n):
+    if len(k_by_n) != 65:
+        raise ValueError("k_by_n needs 65 entries (leaf sizes 0..64)")
+    return (ctypes.c_uint8 * 65)(*[int(v) for v in k_by_n])
+
+
+def rice_encode(values, offsets, k_by_n, stream=None):
+    """Golomb-Rice code one value per leaf.  Returns (status, fixed, unary,
+    index, (fixed_bits, unary_bits)) with int64 device tensors; a first call
+    with empty streams sizes them."""
+    import torch
+    dev = offsets.device
+    L = offsets.numel() - 1
+    table = _table(k_by_n)
+    bits = (ctypes.c_uint64 * 2)()
+    index = torch.zeros(2 * ((L + 63) // 64 + 1), dtype=torch.int64, device=dev)
+    st = _stream_of(offsets, stream)
+    vals = _as_ptr(values) if L > 0 else None
+    rc = lib().shock_rice_encode(vals, _as_ptr(offsets), L, table, None, 0, None, 0, _as_ptr(index), bits, st)
+    if rc not in (SHOCK_OK, SHOCK_EINVAL):
+        raise ShockError(rc, lib().shock_last_error().decode())
+    fw, uw = (int(bits[0]) + 63) // 64, (int(bits[1]) + 63) // 64
+    fixed = torch.empty(max(fw, 1), dtype=torch.int64, device=dev)
+    unary = torch.empty(max(uw, 1), dtype=torch.int64, device=dev)
+    rc = lib().shock_rice_encode(vals, _as_ptr(offsets), L, table, _as_ptr(fixed), fw, _as_ptr(unary), uw,
+                                 _as_ptr(index), bits, st)
+    if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
+        raise ShockError(rc, lib().shock_last_error().decode())
+    return rc, fixed[:fw], unary[:uw], index, (int(bits[0]), int(bits[1]))
+
+
+def rice_decode(fixed, unary, index, offsets, k_by_n, out_values=None, stream=None):
+    """(status, values) decoded on the device; values an int64 tensor."""
+    import torch
+    L = offsets.numel() - 1
+    if out_values is None:
+        out_values = torch.empty(max(L, 1), dtype=torch.int64, device=offsets.device)
+    rc = lib().shock_rice_decode(_as_ptr(fixed) if fixed.numel() else None, fixed.numel(),
+                                 _as_ptr(unary) if unary.numel() else None, unary.numel(), _as_ptr(index),
+                                 _as_ptr(offsets), max(L, 0), _table(k_by_n), _as_ptr(out_values),
+                                 _stream_of(offsets, stream))
+    return rc, out_values[:max(L, 0)]
+

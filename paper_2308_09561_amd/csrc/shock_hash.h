@@ -1,0 +1,58 @@
+// The library's frozen hash family (spec version 1), shared by the search and
+// query kernels.  The paper assumes fully random h0, h1 evaluated on a 64-bit
+// master hash code (Sections 5 and 8); this is the concrete choice:
+//   a = fmix64(x)                              MurmurHash3's 64-bit finaliser
+//   t = fmix64((s + 1) * 0x9E3779B97F4A7C15)   per seed, mod 2^64
+//   c = a ^ t;  P = lo32(c) * hi32(c);  z = lo32(P) ^ hi32(P)
+//   h0 = ((z mod 2^16) * n) >> 16;  r = ((z >> 16) * (n - 1)) >> 16
+//   h1 = r + (r >= h0)   (h1 != h0 for n >= 2; no self-loops)
+// Rotation fitting's 1-bit set hash: the top bit of fmix64(x ^ kSideKey).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shockhash {
+
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kMix1 = 0xff51afd7ed558ccdull;
+constexpr uint64_t kMix2 = 0xc4ceb9fe1a85ec53ull;
+constexpr uint64_t kSideKey = 0xD1B54A32D192ED03ull;
+
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= kMix1;
+  k ^= k >> 33;
+  k *= kMix2;
+  k ^= k >> 33;
+  return k;
+}
+
+// Per-seed mix t(s).
+__device__ __forceinline__ uint64_t seed_mix(uint64_t s) { return fmix64((s + 1) * kGolden); }
+
+// Slots of one key under one seed from the premixed key halves (alo, ahi) and
+// the per-seed halves (tlo, thi); nm1 = n - 1, n >= 2.
+__device__ __forceinline__ void slot_pair(uint32_t alo, uint32_t ahi, uint32_t tlo, uint32_t thi, uint32_t n,
+                                          uint32_t nm1, uint32_t &h0, uint32_t &h1) {
+  const uint32_t clo = alo ^ tlo;
+  const uint32_t chi = ahi ^ thi;
+  const uint64_t p = (uint64_t)clo * (uint64_t)chi;
+  const uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
+  uint32_t f0 = __umulhi(z << 16, n);            // ((z & 0xFFFF) * n) >> 16
+  uint32_t r = __umulhi(z & 0xFFFF0000u, nm1);    // ((z >> 16) * (n-1)) >> 16
+  // h1 = r + (r >= h0).  The empty asm statements hide the operands' origin
+  // so that the compare stays 32-bit (one v_cmp + one v_addc) instead of
+  // being widened to 64 bits for the later 64-bit shift.
+  asm("" : "+v"(f0));
+  asm("" : "+v"(r));
+  uint32_t f1 = r + (uint32_t)(r >= f0);
+  asm("" : "+v"(f1));
+  h0 = f0;
+  h1 = f1;
+}
+
+// 1 if key x belongs to rotation fitting's second set.
+__device__ __forceinline__ uint32_t key_side(uint64_t x) { return (uint32_t)(fmix64(x ^ kSideKey) >> 63); }
+
+}  // namespace shockhash

@@ -36,17 +36,19 @@
 #include <vector>
 
 #include "shockleaf.h"
+#include "shock_hash.h"
+#include "shock_internal.h"
 
 namespace {
 
-constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
-constexpr uint64_t kMix1 = 0xff51afd7ed558ccdull;
-constexpr uint64_t kMix2 = 0xc4ceb9fe1a85ec53ull;
+using shockhash::fmix64;
+using shockhash::kGolden;
+using shockhash::kSideKey;
+using shockhash::slot_pair;
+
 constexpr uint64_t kNone = ~0ull;
-// Rotation fitting: the 1-bit set hash of a key is the top bit of
-// fmix64(key ^ kSideKey); candidates (s, r) are encoded as s * 64 + r, which
-// orders them as the search does (seed first, then rotation).
-constexpr uint64_t kSideKey = 0xD1B54A32D192ED03ull;
+// Rotation fitting: candidates (s, r) are encoded as s * 64 + r, which orders
+// them as the search does (seed first, then rotation).
 constexpr uint32_t kRfSeedsPerLane = 8;  // consecutive seeds per lane; the partial-hash period
 
 // Leaf claim word: bits 0..39 next unclaimed unit (a unit is one iteration,
@@ -105,36 +107,6 @@ struct Params {
   const unsigned long long *__restrict__ sides;  // [n_leaves] bit i = set of key i
   uint16_t units_by_n[65];  // most units one claim takes, by leaf size (persistent launches)
 };
-
-__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
-  k ^= k >> 33;
-  k *= kMix1;
-  k ^= k >> 33;
-  k *= kMix2;
-  k ^= k >> 33;
-  return k;
-}
-
-// Slots of one key under one seed from the premixed key halves (alo, ahi) and
-// the per-seed halves (tlo, thi).  nm1 = n - 1.
-__device__ __forceinline__ void slot_pair(uint32_t alo, uint32_t ahi, uint32_t tlo, uint32_t thi, uint32_t n,
-                                          uint32_t nm1, uint32_t &h0, uint32_t &h1) {
-  const uint32_t clo = alo ^ tlo;
-  const uint32_t chi = ahi ^ thi;
-  const uint64_t p = (uint64_t)clo * (uint64_t)chi;
-  const uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
-  uint32_t f0 = __umulhi(z << 16, n);            // ((z & 0xFFFF) * n) >> 16
-  uint32_t r = __umulhi(z & 0xFFFF0000u, nm1);    // ((z >> 16) * (n-1)) >> 16
-  // h1 = r + (r >= h0).  The empty asm statements hide the operands' origin
-  // so that the compare stays 32-bit (one v_cmp + one v_addc) instead of
-  // being widened to 64 bits for the later 64-bit shift.
-  asm("" : "+v"(f0));
-  asm("" : "+v"(r));
-  uint32_t f1 = r + (uint32_t)(r >= f0);
-  asm("" : "+v"(f1));
-  h0 = f0;
-  h1 = f1;
-}
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -1268,6 +1240,8 @@ int get_scratch(size_t bytes, void **buf, unsigned long long **host_ctr) {
 }
 
 }  // namespace
+
+void shock_internal_set_error(const char *what, hipError_t e) { set_err(what, e); }
 
 // A search context: its own scratch for batches of up to max_leaves leaves,
 // pinned counters, events and an optional captured graph.
