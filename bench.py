@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--untuned", action="store_true", help="ignore the autotuner's cached table for this device")
     ap.add_argument("--rf-steps", type=int, default=3,
                     help="timed steps of the rotation-fitting search on the same batch (0 = skip)")
+    ap.add_argument("--code-leaves", type=int, default=1 << 21,
+                    help="leaves of 48 keys for the query and seed-code legs (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -283,6 +285,71 @@ def main():
         log(f"[bench] rotation fitting: {L / wall_r:.0f} leaves/s, kernel {rf_kernel:.2f} ms, "
             f"frac {rf['roofline']['frac']:.3f}")
 
+    # Leaf query and Golomb-Rice seed codes (HBM-bound) on a larger batch of
+    # 48-key leaves: uniform keys drawn on the device, the measured batch's
+    # seeds and orientations repeated.
+    code = None
+    if args.code_leaves > 0:
+        from paper_2308_09561_amd import rice
+        Lq = args.code_leaves
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(4848)
+        keys_q = torch.randint(-(1 << 63), (1 << 63) - 1, (Lq * 48,), generator=gen, device=dev, dtype=torch.int64)
+        offs_q = torch.arange(0, Lq + 1, device=dev, dtype=torch.int64) * 48
+        reps = (Lq + L - 1) // L
+        seeds_q = seeds_d.repeat(reps)[:Lq].contiguous()
+        orient_q = orient_d.repeat(reps)[:Lq].contiguous()
+        pos_q = torch.empty(Lq * 48, dtype=torch.int64, device=dev)
+        stream = torch.cuda.current_stream(dev)
+
+        def timed(fn, repeats=5):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(repeats):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / repeats
+
+        log(f"[bench] leaf query and seed codes: {Lq} leaves x 48 keys")
+        q_ms = timed(lambda: shock.leaf_query(keys_q, offs_q, seeds_q, orient_q, out_pos=pos_q))
+        q_bytes = Lq * 48 * 16 + Lq * 24  # keys in, positions out; offsets, seed, orientation per leaf
+        copy_ms = timed(lambda: pos_q.copy_(keys_q))  # a plain device copy of the same size, for reference
+        table = rice.plain_table()
+        rc, fx, un, idx, bits = shock.rice_encode(seeds_q, offs_q, table)
+        if rc != shock.SHOCK_OK:
+            raise RuntimeError(f"rice encode failed: {rc}")
+        t3 = time.perf_counter()
+        for _ in range(3):
+            shock.rice_encode(seeds_q, offs_q, table)
+        enc_ms = (time.perf_counter() - t3) / 3 * 1e3
+        vals_q = torch.empty(Lq, dtype=torch.int64, device=dev)
+        d_ms = timed(lambda: shock.rice_decode(fx, un, idx, offs_q, table, out_values=vals_q))
+        same = bool(torch.equal(vals_q, seeds_q))
+        stream_bytes = (bits[0] + bits[1]) / 8
+        d_bytes = stream_bytes + Lq * 16 + idx.numel() * 8  # streams, offsets, values out, index
+        p48 = rice.success_probability(48)
+        code = {
+            "leaves": Lq, "keys": Lq * 48,
+            "query": {"ms": q_ms, "keys_per_s": Lq * 48 / (q_ms / 1e3),
+                      "roofline": {"bound": "hbm", "achieved": q_bytes / (q_ms / 1e3) / 1e9, "peak": 8000.0,
+                                   "unit": "GB/s", "frac": q_bytes / (q_ms / 1e3) / 8e12, "traffic": None,
+                                   "bytes_per_launch": q_bytes,
+                                   "plain_copy_GBps": Lq * 48 * 16 / (copy_ms / 1e3) / 1e9}},
+            "rice": {"k_48": table[48], "bits_per_leaf": (bits[0] + bits[1]) / Lq,
+                     "expected_bits_per_leaf": rice.expected_length(table[48], p48),
+                     "bits_per_key": (bits[0] + bits[1]) / Lq / 48,
+                     "encode_ms_sync": enc_ms, "encode_leaves_per_s": Lq / (enc_ms / 1e3),
+                     "decode_ms": d_ms, "decode_leaves_per_s": Lq / (d_ms / 1e3), "decode_round_trip": same,
+                     "decode_roofline": {"bound": "hbm", "achieved": d_bytes / (d_ms / 1e3) / 1e9, "peak": 8000.0,
+                                         "unit": "GB/s", "frac": d_bytes / (d_ms / 1e3) / 8e12}},
+        }
+        log(f"[bench]   query {q_ms:.3f} ms ({code['query']['roofline']['achieved']:.0f} GB/s), "
+            f"encode {enc_ms:.2f} ms, decode {d_ms:.3f} ms, {code['rice']['bits_per_leaf']:.2f} bits/leaf")
+        del keys_q, pos_q
+
     # Serving: MPHF-build requests (log-uniform 1e3..1e6 keys, Poisson
     # arrivals) cut into 48-key leaves, continuous batching over 4 streams
     # within a 256 MiB HBM budget.  Two runs over the same first K requests:
@@ -341,6 +408,7 @@ def main():
         "batched_vs_plain": (leaves_per_s / plain["leaves_per_s"]) if plain else None,
         "latency": latency,
         "rotation_fitting": rf,
+        "leaf_query_and_codes": code,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                      "unit": "Tops/s (int32 lane ops)", "frac": achieved / PEAK_INT_OPS,
                      "traffic": measured_traffic(args.workload),

@@ -30,8 +30,9 @@ extern "C" {
  * keys u64[offsets[n_leaves]], offsets u64[n_leaves+1], seeds u64[n_leaves],
  * orient u64[n_leaves], out_pos u64[offsets[n_leaves]].  Asynchronous on
  * hip_stream (NULL: the null stream).  offsets must be a valid CSR (as the
- * search checks); a leaf of more than 64 keys is skipped and its keys' entries
- * left untouched.  Returns SHOCK_EINVAL for NULL pointers. */
+ * search checks); leaves are taken in groups of 64, and a group holding a leaf
+ * of more than 64 keys or decreasing offsets is skipped (its keys' entries
+ * left untouched).  Returns SHOCK_EINVAL for NULL pointers. */
 int shock_leaf_query(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, const uint64_t *seeds,
                      const uint64_t *orient, uint64_t *out_pos, void *hip_stream);
 

@@ -110,13 +110,20 @@ def save(rec: dict, path: str | None = None) -> str:
 
 
 def load(device: str | None = None) -> dict | None:
-    """The cached record for this device, or None."""
+    """The cached record for this device, or None.  Falls back to a record of
+    the same architecture when the marketing name differs (it can, between
+    driver stacks and under profilers)."""
     try:
-        path = cache_path(device)
+        device = device or _device_name()
     except Exception:
         return None
+    path = cache_path(device)
     if not os.path.exists(path):
-        return None
+        arch = device.split("-", 1)[0]
+        same = sorted(f for f in os.listdir(TUNING_DIR) if f.startswith(arch + "-")) if os.path.isdir(TUNING_DIR) else []
+        if not same:
+            return None
+        path = os.path.join(TUNING_DIR, same[0])
     with open(path) as fh:
         return json.load(fh)
 

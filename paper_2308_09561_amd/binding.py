@@ -364,32 +364,37 @@ def _stream_of(t, stream):
     return ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream(t.device).cuda_stream)
 
 
+def _query_out(keys, offsets, out_pos):
+    """The output tensor: the caller's (any length >= offsets[-1], returned
+    as given, no host sync) or a new one sized from offsets[-1]."""
+    import torch
+    if out_pos is not None:
+        return out_pos, out_pos
+    N = int(offsets[-1].item()) if offsets.numel() else 0
+    buf = torch.empty(max(N, 1), dtype=torch.int64, device=keys.device)
+    return buf, buf[:N]
+
+
 def leaf_query(keys, offsets, seeds, orient, out_pos=None, stream=None):
     """(status, positions) for a CSR batch: int64 device tensors in, an int64
     tensor of offsets[-1] global positions out (uint64 bit patterns)."""
-    import torch
     _check_tensors(keys, offsets)
     L = offsets.numel() - 1
-    N = int(offsets[-1].item()) if L >= 0 else 0
-    if out_pos is None:
-        out_pos = torch.empty(max(N, 1), dtype=torch.int64, device=keys.device)
+    buf, ret = _query_out(keys, offsets, out_pos)
     rc = lib().shock_leaf_query(_as_ptr(keys if keys.numel() else offsets), _as_ptr(offsets), max(L, 0),
-                                _as_ptr(seeds), _as_ptr(orient), _as_ptr(out_pos), _stream_of(keys, stream))
-    return rc, out_pos[:N]
+                                _as_ptr(seeds), _as_ptr(orient), _as_ptr(buf), _stream_of(keys, stream))
+    return rc, ret
 
 
 def rf_leaf_query(keys, offsets, seeds, rot, orient, partial_k=0, out_pos=None, stream=None):
     """leaf_query under rotation fitting; rot an int32 device tensor."""
-    import torch
     _check_tensors(keys, offsets)
     L = offsets.numel() - 1
-    N = int(offsets[-1].item()) if L >= 0 else 0
-    if out_pos is None:
-        out_pos = torch.empty(max(N, 1), dtype=torch.int64, device=keys.device)
+    buf, ret = _query_out(keys, offsets, out_pos)
     rc = lib().shock_rf_leaf_query(_as_ptr(keys if keys.numel() else offsets), _as_ptr(offsets), max(L, 0),
-                                   _as_ptr(seeds), _as_ptr(rot), _as_ptr(orient), partial_k, _as_ptr(out_pos),
+                                   _as_ptr(seeds), _as_ptr(rot), _as_ptr(orient), partial_k, _as_ptr(buf),
                                    _stream_of(keys, stream))
-    return rc, out_pos[:N]
+    return rc, ret
 
 
 def _table(k_by_n):

@@ -1,10 +1,10 @@
 // Leaf queries and Golomb-Rice seed codes on MI355X (gfx950).
 //
-// Query (Section 4: a key x is answered by h_{s, f(x)}(x)): one wave per
-// leaf, lane i evaluates key i of the leaf under the leaf's seed (and
-// rotation) and picks slot h0 or h1 by bit i of the orientation.  The work is
-// a few dozen integer operations per key against 16 bytes of traffic per key,
-// so the kernel is bound by HBM; loads and stores of a leaf are contiguous.
+// Query (Section 4: a key x is answered by h_{s, f(x)}(x)): every key is
+// evaluated under its leaf's seed (and rotation) and takes slot h0 or h1 by
+// its bit of the orientation.  The work is a few dozen integer operations per
+// key against 16 bytes of traffic per key, so the kernel is bound by HBM; a
+// workgroup stages 64 leaves' metadata in LDS and streams their keys.
 //
 // Golomb-Rice codes (the seed encoding of Section 4; Golomb 1966, Rice 1979):
 // a wave takes a block of 64 leaves.  Encoding runs three kernels: per-block
@@ -63,6 +63,13 @@ __device__ __forceinline__ uint64_t wave_excl_scan(uint64_t v) {
 
 // ---- query ------------------------------------------------------------------
 
+// A workgroup takes a group of 64 consecutive leaves.  Their offsets, seed
+// mixes and orientations are staged in LDS once, with a byte per key naming
+// its leaf (at most 64 x 64 keys); then the 256 threads stride over the
+// group's keys, which are contiguous in the CSR, so loads and stores are fully
+// coalesced whatever the leaf sizes.
+constexpr uint32_t kQueryGroup = 64;
+
 template <bool RF>
 __global__ __launch_bounds__(256) void query_kernel(const uint64_t *__restrict__ keys,
                                                     const uint64_t *__restrict__ offsets, uint64_t n_leaves,
@@ -70,37 +77,92 @@ __global__ __launch_bounds__(256) void query_kernel(const uint64_t *__restrict__
                                                     const uint32_t *__restrict__ rot,
                                                     const uint64_t *__restrict__ orient, uint32_t partial_k,
                                                     uint64_t *__restrict__ out_pos) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-  for (uint64_t j = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); j < n_leaves; j += waves) {
-    const uint64_t o0 = offsets[j], o1 = offsets[j + 1];
-    if (o1 < o0 || o1 - o0 > 64) continue;  // not a leaf: its keys are left untouched
-    const uint32_t n = (uint32_t)(o1 - o0);
-    if (lane >= n) continue;
-    const uint64_t s = seeds[j];
-    const uint64_t x = keys[o0 + lane];
-    uint64_t pos = kNone;
-    if (s != kNone) {
-      uint32_t h0 = 0, h1 = 0;
-      if (n >= 2) {
-        const uint64_t a = fmix64(x);
-        uint64_t sk = s;
-        uint32_t r = 0;
-        if (RF) {
-          const uint32_t k = partial_k ? partial_k : (n > 32 ? 8u : 1u);
-          if (key_side(x)) r = rot[j] % n;
-          else sk = s - s % k;
-        }
-        const uint64_t t = seed_mix(sk);
-        slot_pair((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)t, (uint32_t)(t >> 32), n, n - 1, h0, h1);
-        if (RF) {
-          h0 = h0 + r >= n ? h0 + r - n : h0 + r;
-          h1 = h1 + r >= n ? h1 + r - n : h1 + r;
+  __shared__ uint64_t s_off[kQueryGroup + 1];
+  __shared__ uint64_t s_t[kQueryGroup];   // seed mix of the leaf (second set under RF)
+  __shared__ uint64_t s_ta[kQueryGroup];  // RF: seed mix of the first set
+  __shared__ uint64_t s_f[kQueryGroup];   // orientation
+  __shared__ uint32_t s_r[kQueryGroup];   // RF: rotation mod n
+  __shared__ uint32_t s_miss[kQueryGroup];  // 1: the leaf has no seed
+  __shared__ uint32_t s_ok;
+  __shared__ uint8_t s_leaf[kQueryGroup * 64];  // key (relative to the group's first) -> leaf
+  const uint32_t tid = threadIdx.x;
+  const uint64_t n_groups = (n_leaves + kQueryGroup - 1) / kQueryGroup;
+  for (uint64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+    const uint64_t j0 = grp * kQueryGroup;
+    const uint32_t cnt = (uint32_t)(n_leaves - j0 < kQueryGroup ? n_leaves - j0 : kQueryGroup);
+    if (tid == 0) s_ok = 1;
+    if (tid <= cnt) s_off[tid] = offsets[j0 + tid];
+    __syncthreads();
+    if (tid < cnt) {
+      const uint64_t n64 = s_off[tid + 1] - s_off[tid];
+      if (s_off[tid + 1] < s_off[tid] || n64 > 64) s_ok = 0;
+      const uint32_t n = (uint32_t)n64;
+      const uint64_t sd = seeds[tid + j0];
+      s_f[tid] = orient[tid + j0];
+      s_miss[tid] = sd == kNone;
+      s_t[tid] = seed_mix(sd);
+      if (RF) {
+        const uint32_t k = partial_k ? partial_k : (n > 32 ? 8u : 1u);
+        s_ta[tid] = seed_mix(sd - sd % k);
+        s_r[tid] = n ? rot[tid + j0] % n : 0;
+      }
+    }
+    __syncthreads();
+    // A group holding a leaf that is not one (more than 64 keys, decreasing
+    // offsets) is skipped: its keys' entries are left untouched.
+    if (s_ok) {
+      const uint64_t k0 = s_off[0], k1 = s_off[cnt];
+      // key -> leaf table: thread t fills leaf t / 4's quarter t % 4
+      {
+        const uint32_t lf = tid >> 2, part = tid & 3;
+        if (lf < cnt) {
+          const uint32_t a = (uint32_t)(s_off[lf] - k0), e = (uint32_t)(s_off[lf + 1] - k0);
+          for (uint32_t i = a + part; i < e; i += 4) s_leaf[i] = (uint8_t)lf;
         }
       }
-      pos = o0 + (((orient[j] >> lane) & 1) ? h1 : h0);
+      __syncthreads();
+      // four keys per thread and step, their loads issued together
+      constexpr uint32_t kUnroll = 4;
+      const uint64_t step = (uint64_t)blockDim.x * kUnroll;
+      for (uint64_t g0 = k0 + tid; g0 < k1; g0 += step) {
+        uint64_t x[kUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+          const uint64_t g = g0 + (uint64_t)u * blockDim.x;
+          x[u] = g < k1 ? keys[g] : 0;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+          const uint64_t g = g0 + (uint64_t)u * blockDim.x;
+          if (g >= k1) break;
+          const uint32_t lo = s_leaf[g - k0];
+          const uint64_t base = s_off[lo];
+          const uint32_t n = (uint32_t)(s_off[lo + 1] - base);
+          const uint32_t i = (uint32_t)(g - base);
+          uint64_t pos = kNone;
+          if (!s_miss[lo]) {
+            uint32_t h0 = 0, h1 = 0;
+            if (n >= 2) {
+              const uint64_t a = fmix64(x[u]);
+              uint64_t t = s_t[lo];
+              uint32_t r = 0;
+              if (RF) {
+                if (key_side(x[u])) r = s_r[lo];
+                else t = s_ta[lo];
+              }
+              slot_pair((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)t, (uint32_t)(t >> 32), n, n - 1, h0, h1);
+              if (RF) {
+                h0 = h0 + r >= n ? h0 + r - n : h0 + r;
+                h1 = h1 + r >= n ? h1 + r - n : h1 + r;
+              }
+            }
+            pos = base + (((s_f[lo] >> i) & 1) ? h1 : h0);
+          }
+          out_pos[g] = pos;
+        }
+      }
     }
-    out_pos[o0 + lane] = pos;
+    __syncthreads();
   }
 }
 
@@ -152,32 +214,54 @@ __global__ __launch_bounds__(256) void rice_len_kernel(const uint64_t *__restric
 }
 
 // Phase 2: in-place exclusive scan of the block lengths (pairs), totals in the
-// last pair and in totals[0..1].  One workgroup of 1024 threads, chunk by chunk.
+// last pair and in totals[0..1].  One workgroup of 1024 threads; per chunk,
+// thread t sums kScanPer consecutive pairs, the workgroup scans the 1024
+// sums (wave shuffles, then the 16 wave totals), and each thread rewrites its
+// pairs as running sums.
+constexpr uint32_t kScanPer = 16;
+
 __global__ __launch_bounds__(1024) void rice_scan_kernel(uint64_t *index, uint64_t n_blocks, uint64_t *totals) {
-  __shared__ uint64_t sf[1024], su[1024];
-  const uint32_t t = threadIdx.x;
+  __shared__ uint64_t wf[16], wu[16];
+  const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
   uint64_t carry_f = 0, carry_u = 0;
-  for (uint64_t c = 0; c < n_blocks; c += 1024) {
-    const uint64_t b = c + t;
-    const uint64_t f = b < n_blocks ? index[2 * b] : 0;
-    const uint64_t u = b < n_blocks ? index[2 * b + 1] : 0;
-    sf[t] = f;
-    su[t] = u;
+  for (uint64_t c = 0; c < n_blocks; c += 1024ull * kScanPer) {
+    const uint64_t b0 = c + (uint64_t)t * kScanPer;
+    uint64_t sf = 0, su = 0;
+    for (uint32_t e = 0; e < kScanPer; ++e) {
+      const uint64_t b = b0 + e;
+      if (b < n_blocks) {
+        sf += index[2 * b];
+        su += index[2 * b + 1];
+      }
+    }
+    const uint64_t xf = wave_excl_scan(sf), xu = wave_excl_scan(su);
+    if (lane == 63) {
+      wf[wave] = xf + sf;
+      wu[wave] = xu + su;
+    }
     __syncthreads();
-    for (uint32_t d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
-      const uint64_t af = t >= d ? sf[t - d] : 0;
-      const uint64_t au = t >= d ? su[t - d] : 0;
-      __syncthreads();
-      sf[t] += af;
-      su[t] += au;
-      __syncthreads();
+    uint64_t pf = 0, pu = 0, tf = 0, tu = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+      if (w < wave) {
+        pf += wf[w];
+        pu += wu[w];
+      }
+      tf += wf[w];
+      tu += wu[w];
     }
-    if (b < n_blocks) {
-      index[2 * b] = carry_f + sf[t] - f;
-      index[2 * b + 1] = carry_u + su[t] - u;
+    uint64_t rf = carry_f + pf + xf, ru = carry_u + pu + xu;
+    for (uint32_t e = 0; e < kScanPer; ++e) {
+      const uint64_t b = b0 + e;
+      if (b < n_blocks) {
+        const uint64_t f = index[2 * b], u = index[2 * b + 1];
+        index[2 * b] = rf;
+        index[2 * b + 1] = ru;
+        rf += f;
+        ru += u;
+      }
     }
-    carry_f += sf[1023];
-    carry_u += su[1023];
+    carry_f += tf;
+    carry_u += tu;
     __syncthreads();
   }
   if (t == 0) {
@@ -193,14 +277,36 @@ __global__ void fill_zero_kernel(uint64_t *p, uint64_t words) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = 0;
 }
 
+// OR the bits of one stream segment: words [w0, w0 + span) assembled in the
+// wave's LDS buffer.  The first and last word may be shared with the
+// neighbouring blocks and are ORed atomically; the others belong to this
+// block alone and are stored.
+__device__ __forceinline__ void flush_words(const unsigned long long *buf, uint64_t w0, uint32_t span,
+                                            unsigned long long *stream) {
+  const uint32_t lane = lane_id();
+  if (lane < span) {
+    const unsigned long long v = buf[lane];
+    if (lane == 0 || lane == span - 1) {
+      if (v) atomicOr(&stream[w0 + lane], v);
+    } else {
+      stream[w0 + lane] = v;
+    }
+  }
+}
+
 // Phase 3: write the codes.  The streams were zeroed and are large enough
-// (checked on the host from the totals).
+// (checked on the host from the totals).  A block's fixed part spans at most
+// 57 words; its unary part is assembled in LDS when it spans at most 64 words
+// and ORed into the stream directly otherwise.
 __global__ __launch_bounds__(256) void rice_write_kernel(const uint64_t *__restrict__ values,
                                                          const uint64_t *__restrict__ offsets, uint64_t n_leaves,
                                                          RiceTable T, const uint64_t *__restrict__ index,
                                                          unsigned long long *fixed, unsigned long long *unary,
                                                          unsigned long long *err) {
+  __shared__ unsigned long long bufs[4][2][64];
   const uint32_t lane = threadIdx.x & 63;
+  unsigned long long *fbuf = bufs[threadIdx.x >> 6][0];
+  unsigned long long *ubuf = bufs[threadIdx.x >> 6][1];
   const uint64_t n_blocks = (n_leaves + 63) / 64;
   const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
   for (uint64_t b = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < n_blocks; b += waves) {
@@ -211,15 +317,30 @@ __global__ __launch_bounds__(256) void rice_write_kernel(const uint64_t *__restr
     if (have) leaf_code(offsets, values, j, T, k, q, low, err);
     const uint64_t F = index[2 * b] + wave_excl_scan(have ? k : 0);
     const uint64_t U = index[2 * b + 1] + wave_excl_scan(have ? q + 1 : 0);
-    if (!have) continue;
-    if (k != 0 && low != 0) {
-      const uint64_t w = F >> 6;
-      const uint32_t sh = (uint32_t)(F & 63);
-      atomicOr(&fixed[w], (unsigned long long)(low << sh));
-      if (sh + k > 64) atomicOr(&fixed[w + 1], (unsigned long long)(low >> (64 - sh)));
+    const uint64_t f0 = index[2 * b], f1 = index[2 * b + 2];
+    const uint64_t u0 = index[2 * b + 1], u1 = index[2 * b + 3];
+    const uint64_t fw0 = f0 >> 6, uw0 = u0 >> 6;
+    const uint32_t fspan = f1 > f0 ? (uint32_t)(((f1 - 1) >> 6) - fw0 + 1) : 0;
+    const uint64_t uspan64 = u1 > u0 ? ((u1 - 1) >> 6) - uw0 + 1 : 0;
+    const bool ulds = uspan64 <= 64;
+    fbuf[lane] = 0;
+    ubuf[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (have) {
+      if (k != 0 && low != 0) {
+        const uint32_t w = (uint32_t)((F >> 6) - fw0);
+        const uint32_t sh = (uint32_t)(F & 63);
+        atomicOr(&fbuf[w], (unsigned long long)(low << sh));
+        if (sh + k > 64) atomicOr(&fbuf[w + 1], (unsigned long long)(low >> (64 - sh)));
+      }
+      const uint64_t p = U + q;
+      if (ulds) atomicOr(&ubuf[(p >> 6) - uw0], 1ull << (p & 63));
+      else atomicOr(&unary[p >> 6], 1ull << (p & 63));
     }
-    const uint64_t p = U + q;
-    atomicOr(&unary[p >> 6], 1ull << (p & 63));
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    flush_words(fbuf, fw0, fspan, fixed);
+    if (ulds) flush_words(ubuf, uw0, (uint32_t)uspan64, unary);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
 }
 
@@ -296,6 +417,13 @@ int grid_for(uint64_t items, uint32_t per_block) {
   return g == 0 ? 1 : (int)g;
 }
 
+// One workgroup per group of 64 leaves, up to 2^20 workgroups (grid-stride beyond).
+int query_grid(uint64_t n_leaves) {
+  uint64_t g = (n_leaves + kQueryGroup - 1) / kQueryGroup;
+  if (g > (1u << 20)) g = 1u << 20;
+  return g == 0 ? 1 : (int)g;
+}
+
 bool load_table(const uint8_t *k_by_n, RiceTable &T) {
   if (!k_by_n) return false;
   for (int n = 0; n <= 64; ++n) {
@@ -322,7 +450,7 @@ int shock_leaf_query(const uint64_t *keys, const uint64_t *offsets, uint64_t n_l
                      const uint64_t *orient, uint64_t *out_pos, void *hip_stream) {
   if (n_leaves == 0) return SHOCK_OK;
   if (!keys || !offsets || !seeds || !orient || !out_pos || n_leaves > (1ull << 40)) return SHOCK_EINVAL;
-  hipLaunchKernelGGL(query_kernel<false>, dim3(grid_for(n_leaves, 4)), dim3(256), 0, (hipStream_t)hip_stream, keys,
+  hipLaunchKernelGGL(query_kernel<false>, dim3(query_grid(n_leaves)), dim3(256), 0, (hipStream_t)hip_stream, keys,
                      offsets, n_leaves, seeds, (const uint32_t *)nullptr, orient, 0u, out_pos);
   HIP_TRY(hipGetLastError());
   return SHOCK_OK;
@@ -334,7 +462,7 @@ int shock_rf_leaf_query(const uint64_t *keys, const uint64_t *offsets, uint64_t 
   if (n_leaves == 0) return SHOCK_OK;
   if (!keys || !offsets || !seeds || !rot || !orient || !out_pos || n_leaves > (1ull << 40)) return SHOCK_EINVAL;
   if (partial_k != 0 && partial_k != 1 && partial_k != 8) return SHOCK_EINVAL;
-  hipLaunchKernelGGL(query_kernel<true>, dim3(grid_for(n_leaves, 4)), dim3(256), 0, (hipStream_t)hip_stream, keys,
+  hipLaunchKernelGGL(query_kernel<true>, dim3(query_grid(n_leaves)), dim3(256), 0, (hipStream_t)hip_stream, keys,
                      offsets, n_leaves, seeds, rot, orient, (uint32_t)partial_k, out_pos);
   HIP_TRY(hipGetLastError());
   return SHOCK_OK;
