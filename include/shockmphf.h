@@ -1,0 +1,105 @@
+/*
+ * shockmphf: a flat ShockHash minimal perfect hash function built and queried
+ * on MI355X (gfx950).  Part of libshockleaf.so.
+ *
+ * The paper builds ShockHash-RS (ShockHash as the leaf search of RecSplit) and
+ * outlines a flat alternative (Section 8; Appendix A.4: buckets split once into
+ * leaves, prefix sums of bucket and leaf sizes).  This is that flat scheme,
+ * with the open choices made as follows:
+ *   - B = max(1, ceil(N / bucket_size)) buckets; bucket(x) =
+ *     hi64(fmix64(x ^ 0x5851F42D4C957F2D) * B);
+ *   - bucket i of m_i keys has L_i = ceil(m_i / leaf_target) leaves;
+ *     leaf(x, sigma, L) = (lo32(fmix64(x ^ fmix64((sigma + 1) *
+ *     0xD6E8FEB86659FD93))) * L) >> 32 with the bucket's splitting seed sigma_i,
+ *     the smallest sigma (< 2^16) whose leaves all hold at most leaf_max keys
+ *     (a per-bucket seed bounding leaf sizes, one of the measures Appendix A.4
+ *     lists);
+ *   - a leaf's keys, sorted ascending, get the smallest ShockHash seed and the
+ *     canonical orientation of shock_leaf_search (include/shockleaf.h);
+ *   - the leaf seeds are Golomb-Rice coded (include/shockcode.h) with the
+ *     caller's table of Rice parameters by leaf size;
+ *   - each key's choice f(x) is stored in a 1-bit retrieval structure: a
+ *     3-hypergraph XOR system over 3 * seg cells, seg = ceil(1.23 N / 3) + 8,
+ *     solved by peeling in synchronous rounds (a simpler stand-in for the
+ *     paper's BuRR ribbon retrieval; about 1.23 bits per key instead of
+ *     about 1.01);
+ *   - the value of key x: (key offset of its leaf) + h_{f(x)}(x, seed).
+ * For the N distinct keys it was built from, the function is a bijection onto
+ * [0, N).  For other keys it returns some value in [0, N) (or UINT64_MAX if
+ * the key falls in an empty bucket).
+ *
+ * Keys and positions are DEVICE arrays unless marked host.  The structure
+ * owns its device memory until shock_mphf_destroy.
+ */
+#ifndef SHOCKMPHF_H
+#define SHOCKMPHF_H
+
+#include <stdint.h>
+
+#include "shockleaf.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  uint32_t bucket_size; /* expected keys per bucket; default 2000 */
+  uint32_t leaf_target; /* keys per leaf on average (L_i = ceil(m_i / leaf_target)); default 40 */
+  uint32_t leaf_max;    /* largest leaf, at most 64; default 56 */
+  uint32_t max_rho_tries; /* retrieval seeds tried; default 64 */
+  const uint8_t *rice_k_by_n; /* HOST u8[65]: Rice parameter by leaf size (each at most 56); copied at build */
+  uint64_t reserved[4];
+} shock_mphf_params;
+
+typedef struct shock_mphf shock_mphf;
+
+typedef struct {
+  uint64_t n_keys, n_buckets, n_leaves;
+  uint64_t rho;          /* retrieval seed */
+  uint64_t seg;          /* cells per third of the retrieval table */
+  uint32_t max_sigma;    /* largest splitting seed */
+  uint32_t peel_rounds;  /* rounds of the successful retrieval peeling */
+  uint64_t seed_fixed_bits, seed_unary_bits;
+  /* stored bits by part: bucket offsets, leaf bases and splitting seeds;
+   * leaf sizes; coded seeds with their index; retrieval cells */
+  uint64_t bits_buckets, bits_leaf_sizes, bits_seeds, bits_retrieval, bits_total;
+  double build_ms;       /* wall time of the build call */
+  double search_ms;      /* of which the leaf search (kernel time) */
+} shock_mphf_stats;
+
+/* Defaults as documented above; rice_k_by_n = NULL. */
+void shock_mphf_params_init(shock_mphf_params *p);
+
+/* Build the function of n_keys distinct keys (device u64[n_keys]).  The Rice
+ * table is required.  Synchronous on hip_stream.  Returns SHOCK_EINVAL for
+ * bad parameters (leaf_max > 64, leaf_target 0 or above leaf_max, a bucket
+ * needing more than 1024 leaves), SHOCK_EDUPKEY if keys repeat within a leaf,
+ * SHOCK_ENOTFOUND if a leaf or the retrieval found no seed, SHOCK_ENOMEM /
+ * SHOCK_EHIP on allocation or HIP failures.  On success *out owns the
+ * structure. */
+int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_params *params, shock_mphf **out,
+                     void *hip_stream);
+
+/* positions[i] = the function's value of queries[i] (device arrays).
+ * Asynchronous on hip_stream. */
+int shock_mphf_query(const shock_mphf *m, const uint64_t *queries, uint64_t n_queries, uint64_t *positions,
+                     void *hip_stream);
+
+/* Sizes and build figures. */
+int shock_mphf_info(const shock_mphf *m, shock_mphf_stats *info);
+
+/* Copy the stored parts to HOST arrays (any pointer may be NULL): bucket
+ * offsets u64[B+1], leaf bases u64[B+1], splitting seeds u32[B], leaf sizes
+ * u8[n_leaves], leaf seeds u64[n_leaves] (decoded), retrieval cells u8[3 * seg]
+ * (one per byte). */
+int shock_mphf_export(const shock_mphf *m, uint64_t *bucket_offset, uint64_t *leaf_base, uint32_t *sigma,
+                      uint8_t *leaf_sizes, uint64_t *leaf_seeds, uint8_t *cells);
+
+/* Free the structure (NULL is allowed). */
+int shock_mphf_destroy(shock_mphf *m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHOCKMPHF_H */

@@ -14,7 +14,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "shock_oracle.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("shock_oracle.c", "shock_oracle_mphf.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK = 0
@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-                               "-o", tmp, _SRC])
+                               "-o", tmp, *_SRCS])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -79,6 +79,21 @@ def lib():
                                                ctypes.c_uint64, _u64p, _u64p]
         L.shock_oracle_rice_decode.restype = ctypes.c_int
         L.shock_oracle_rice_decode.argtypes = [_u64p, _u64p, _u64p, ctypes.c_uint64, _u8p, _u64p]
+        L.shock_oracle_mphf_split.restype = ctypes.c_int
+        L.shock_oracle_mphf_split.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                              ctypes.c_uint32, ctypes.c_uint64, _u64p, _u64p, _u32p, _u8p,
+                                              ctypes.c_uint64, _u64p, _u64p, _u64p]
+        L.shock_oracle_xor_segment.restype = ctypes.c_uint64
+        L.shock_oracle_xor_segment.argtypes = [ctypes.c_uint64]
+        L.shock_oracle_xor_build.restype = ctypes.c_int
+        L.shock_oracle_xor_build.argtypes = [_u64p, _u8p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, _u64p,
+                                             _u8p]
+        L.shock_oracle_xor_get.restype = ctypes.c_int
+        L.shock_oracle_xor_get.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, _u8p, _u8p]
+        L.shock_oracle_mphf_query.restype = ctypes.c_int
+        L.shock_oracle_mphf_query.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                              ctypes.c_uint64, _u64p, _u64p, _u32p, _u8p, _u64p, ctypes.c_uint64,
+                                              _u8p, _u64p]
         L.shock_oracle_seed_stats.restype = None
         L.shock_oracle_seed_stats.argtypes = [_u64p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                               _u64p, _u64p, _u64p]
@@ -280,4 +295,101 @@ def rice_decode(fixed, unary, offsets, k_by_n):
     rc = lib().shock_oracle_rice_decode(_p64(f), _p64(unary) if unary.size else None, _p64(offsets), L,
                                         k.ctypes.data_as(_u8p), _p64(values))
     return rc, values[:L]
+
+
+# ---- flat ShockHash MPHF ------------------------------------------------------
+
+def _p8(a: np.ndarray):
+    return a.ctypes.data_as(_u8p)
+
+
+def mphf_buckets(n_keys: int, bucket_size: int) -> int:
+    return 1 if n_keys == 0 or bucket_size == 0 else -(-n_keys // bucket_size)
+
+
+def mphf_split(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: int = 56):
+    """(status, dict) of the bucket/leaf layout: bucket_offset, leaf_base,
+    sigma, leaf_sizes, leaf_keys, key_index, leaf_offsets (global key offsets)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    N = keys.size
+    B = mphf_buckets(N, bucket_size)
+    cap = B + N // max(leaf_target, 1) + 1
+    bo = np.zeros(B + 1, np.uint64)
+    lb = np.zeros(B + 1, np.uint64)
+    sg = np.zeros(B, np.uint32)
+    sz = np.zeros(max(cap, 1), np.uint8)
+    lk = np.zeros(max(N, 1), np.uint64)
+    ki = np.zeros(max(N, 1), np.uint64)
+    nl = ctypes.c_uint64()
+    rc = lib().shock_oracle_mphf_split(_p64(keys) if N else None, N, bucket_size, leaf_target, leaf_max, B,
+                                       _p64(bo), _p64(lb), _p32(sg), _p8(sz), cap, _p64(lk), _p64(ki),
+                                       ctypes.byref(nl))
+    L = int(nl.value)
+    sizes = sz[:L]
+    offs = np.zeros(L + 1, np.uint64)
+    np.cumsum(sizes.astype(np.uint64), out=offs[1:])
+    return rc, {"n_buckets": B, "bucket_offset": bo, "leaf_base": lb, "sigma": sg, "leaf_sizes": sizes,
+                "leaf_keys": lk[:N], "key_index": ki[:N], "leaf_offsets": offs, "n_leaves": L}
+
+
+def xor_segment(n_keys: int) -> int:
+    return int(lib().shock_oracle_xor_segment(n_keys))
+
+
+def xor_build(keys, values, rho_start: int = 0, max_tries: int = 64):
+    """(status, rho, z uint8[3 * seg])."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    values = np.ascontiguousarray(values, dtype=np.uint8)
+    N = keys.size
+    z = np.zeros(3 * xor_segment(N), np.uint8)
+    rho = ctypes.c_uint64()
+    rc = lib().shock_oracle_xor_build(_p64(keys) if N else None, _p8(values) if N else None, N, rho_start,
+                                      max_tries, ctypes.byref(rho), _p8(z))
+    return rc, int(rho.value), z
+
+
+def xor_get(keys, rho: int, z):
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.zeros(max(keys.size, 1), np.uint8)
+    lib().shock_oracle_xor_get(_p64(keys), keys.size, rho, _p8(np.ascontiguousarray(z, np.uint8)), _p8(out))
+    return out[:keys.size]
+
+
+def mphf_build(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: int = 56):
+    """The whole flat MPHF: layout, leaf seeds and orientations (the leaf
+    search), the retrieval of each key's choice, and every key's position
+    (index i of the input keys -> positions[i])."""
+    rc, lay = mphf_split(keys, bucket_size, leaf_target, leaf_max)
+    if rc != OK:
+        return rc, None
+    lk, offs = lay["leaf_keys"], lay["leaf_offsets"]
+    rc, seeds, orient = leaf_search(lk, offs)
+    if rc != OK:
+        return rc, None
+    sizes = lay["leaf_sizes"].astype(np.int64)
+    leaf_of_key = np.repeat(np.arange(lay["n_leaves"]), sizes)
+    idx_in_leaf = np.arange(lk.size) - offs[:-1].astype(np.int64)[leaf_of_key] if lk.size else np.zeros(0, np.int64)
+    f = ((orient[leaf_of_key] >> idx_in_leaf.astype(np.uint64)) & np.uint64(1)).astype(np.uint8) if lk.size \
+        else np.zeros(0, np.uint8)
+    rc, rho, z = xor_build(lk, f)
+    if rc != OK:
+        return rc, None
+    _, pos_leaf_order = leaf_query(lk, offs, seeds, orient)
+    positions = np.zeros(lk.size, np.uint64)
+    positions[lay["key_index"].astype(np.int64)] = pos_leaf_order
+    lay.update({"seeds": seeds, "orient": orient, "choice": f, "rho": rho, "z": z, "positions": positions,
+                "leaf_target": leaf_target, "leaf_max": leaf_max, "bucket_size": bucket_size})
+    return OK, lay
+
+
+def mphf_query(lay, queries):
+    """(status, positions) of query keys through the stored structure."""
+    q = np.ascontiguousarray(queries, dtype=np.uint64)
+    out = np.zeros(max(q.size, 1), np.uint64)
+    N = lay["leaf_keys"].size
+    rc = lib().shock_oracle_mphf_query(_p64(q), q.size, N, lay["leaf_target"], lay["n_buckets"],
+                                       _p64(lay["bucket_offset"]), _p64(lay["leaf_base"]), _p32(lay["sigma"]),
+                                       _p8(np.ascontiguousarray(lay["leaf_sizes"])), _p64(lay["seeds"]),
+                                       lay["rho"], _p8(lay["z"]), _p64(out))
+    return rc, out[:q.size]
 

@@ -160,6 +160,57 @@ int shock_oracle_rice_encode(const uint64_t *values, const uint64_t *offsets, ui
 int shock_oracle_rice_decode(const uint64_t *fixed, const uint64_t *unary, const uint64_t *offsets,
                              uint64_t n_leaves, const uint8_t *k_by_n, uint64_t *values);
 
+/* ---- A flat ShockHash MPHF (Section 8's flat decomposition; the two-level
+ * scheme of Appendix A.4 with per-bucket splitting seeds) ------------------
+ * Definitions (this library's choices; the paper leaves the scheme open):
+ *   B = max(1, ceil(N / bucket_size)) buckets;
+ *   bucket(x) = hi64(fmix64(x ^ 0x5851F42D4C957F2D) * B);
+ *   bucket i of m_i keys gets L_i = ceil(m_i / leaf_target) leaves;
+ *   leaf(x, sigma, L) = (lo32(fmix64(x ^ fmix64((sigma + 1) * 0xD6E8FEB86659FD93))) * L) >> 32;
+ *   sigma_i = the smallest sigma whose leaves all hold at most leaf_max keys;
+ *   leaves are numbered globally bucket by bucket, and a leaf's keys are
+ *   sorted ascending (so the leaf search and its canonical orientation are
+ *   defined by the key set alone).
+ * split: HOST arrays.  keys u64[N] (distinct); out: bucket_offset u64[B+1]
+ * (key offsets), leaf_base u64[B+1] (leaf offsets), sigma u32[B],
+ * leaf_sizes u8[leaf_cap], leaf_keys u64[N] (the keys in leaf order),
+ * key_index u64[N] (original index of each of those keys), *n_leaves.
+ * Returns EINVAL for bad parameters (leaf_max > 64, leaf_target 0 or above
+ * leaf_max, bucket_size 0), leaf_cap too small, or a bucket whose splitting
+ * seed would exceed 2^16. */
+int shock_oracle_mphf_split(const uint64_t *keys, uint64_t n_keys, uint32_t bucket_size, uint32_t leaf_target,
+                            uint32_t leaf_max, uint64_t n_buckets, uint64_t *bucket_offset, uint64_t *leaf_base,
+                            uint32_t *sigma, uint8_t *leaf_sizes, uint64_t leaf_cap, uint64_t *leaf_keys,
+                            uint64_t *key_index, uint64_t *n_leaves);
+
+/* 1-bit retrieval by a 3-hypergraph XOR system (a simpler stand-in for the
+ * ribbon retrieval of Section 2): M = 3 * seg cells, seg = ceil(1.23 N / 3) + 8,
+ * each key x hashes under retrieval seed rho to one cell in each third:
+ *   u = fmix64(x ^ fmix64((rho + 1) * 0xA0761D6478BD642F)), v = fmix64(u)
+ *   c0 = (lo32(u) * seg) >> 32, c1 = seg + ((hi32(u) * seg) >> 32),
+ *   c2 = 2 * seg + ((lo32(v) * seg) >> 32)
+ * and the value of x is Z[c0] ^ Z[c1] ^ Z[c2].  Z is found by peeling in
+ * synchronous rounds: in each round every remaining key with a cell of
+ * exactly one remaining key is peeled at the first such cell (c0, c1, c2
+ * order), all of them at once; then, rounds in reverse, each peeled key sets
+ * its peel cell to its value XOR its other two cells.  rho is the smallest
+ * seed from rho_start on (at most max_tries) for which every key peels.
+ * build: HOST arrays; values u8[N] (0/1); Z u8[3 * seg] (one cell per byte).
+ * Returns ENOTFOUND if no seed of the range peels. */
+uint64_t shock_oracle_xor_segment(uint64_t n_keys);
+int shock_oracle_xor_build(const uint64_t *keys, const uint8_t *values, uint64_t n_keys, uint64_t rho_start,
+                           uint32_t max_tries, uint64_t *rho, uint8_t *z);
+int shock_oracle_xor_get(const uint64_t *keys, uint64_t n_keys, uint64_t rho, const uint8_t *z, uint8_t *values);
+
+/* The MPHF's value of each query key (which must be one of the built keys):
+ * bucket, splitting seed, leaf and its key offset, then the leaf query
+ * offset + h_{f(x)}(x, seed) with f(x) read from the retrieval structure.
+ * leaf_seeds u64[n_leaves]: the leaf search's seeds. */
+int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_t n_keys, uint32_t leaf_target,
+                            uint64_t n_buckets, const uint64_t *bucket_offset, const uint64_t *leaf_base,
+                            const uint32_t *sigma, const uint8_t *leaf_sizes, const uint64_t *leaf_seeds,
+                            uint64_t rho, const uint8_t *z, uint64_t *out_pos);
+
 /* Statistics helper: over seeds s0 .. s0+count-1 of one leaf of n keys, count
  * the seeds whose slots cover all n cells and, among them, the pseudoforests.
  * Also counts seeds where h0 alone is a bijection. */

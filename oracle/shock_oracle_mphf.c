@@ -1,0 +1,231 @@
+/*
+ * CPU oracle, flat ShockHash MPHF part -- TEST INFRASTRUCTURE ONLY.
+ * Plain single-threaded C; definitions in shock_oracle.h.
+ */
+#include "shock_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+static uint64_t bucket_of(uint64_t x, uint64_t n_buckets) {
+  uint64_t h = shock_oracle_fmix64(x ^ 0x5851F42D4C957F2DULL);
+  return (uint64_t)(((unsigned __int128)h * n_buckets) >> 64);
+}
+
+static uint32_t leaf_of(uint64_t x, uint32_t sigma, uint32_t n_leaves) {
+  uint64_t t = shock_oracle_fmix64(((uint64_t)sigma + 1) * 0xD6E8FEB86659FD93ULL);
+  uint64_t h = shock_oracle_fmix64(x ^ t);
+  return (uint32_t)(((uint64_t)(uint32_t)h * n_leaves) >> 32);
+}
+
+static int cmp_u64(const void *a, const void *b) {
+  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return x < y ? -1 : x > y ? 1 : 0;
+}
+
+int shock_oracle_mphf_split(const uint64_t *keys, uint64_t n_keys, uint32_t bucket_size, uint32_t leaf_target,
+                            uint32_t leaf_max, uint64_t n_buckets, uint64_t *bucket_offset, uint64_t *leaf_base,
+                            uint32_t *sigma, uint8_t *leaf_sizes, uint64_t leaf_cap, uint64_t *leaf_keys,
+                            uint64_t *key_index, uint64_t *n_leaves) {
+  if (bucket_size == 0 || leaf_target == 0 || leaf_max > 64 || leaf_target > leaf_max) return SHOCK_ORACLE_EINVAL;
+  uint64_t want_b = n_keys == 0 ? 1 : (n_keys + bucket_size - 1) / bucket_size;
+  if (n_buckets != want_b) return SHOCK_ORACLE_EINVAL;
+  /* buckets: sizes, offsets, keys grouped by bucket (input order within) */
+  for (uint64_t b = 0; b <= n_buckets; ++b) bucket_offset[b] = 0;
+  for (uint64_t i = 0; i < n_keys; ++i) bucket_offset[bucket_of(keys[i], n_buckets) + 1] += 1;
+  for (uint64_t b = 0; b < n_buckets; ++b) bucket_offset[b + 1] += bucket_offset[b];
+  uint64_t *fill = (uint64_t *)malloc(sizeof(uint64_t) * (n_buckets + 1));
+  uint64_t *grouped = (uint64_t *)malloc(sizeof(uint64_t) * (n_keys + 1));
+  uint64_t *grouped_idx = (uint64_t *)malloc(sizeof(uint64_t) * (n_keys + 1));
+  if (!fill || !grouped || !grouped_idx) return SHOCK_ORACLE_EINVAL;
+  memcpy(fill, bucket_offset, sizeof(uint64_t) * (n_buckets + 1));
+  for (uint64_t i = 0; i < n_keys; ++i) {
+    uint64_t b = bucket_of(keys[i], n_buckets);
+    grouped[fill[b]] = keys[i];
+    grouped_idx[fill[b]] = i;
+    fill[b] += 1;
+  }
+  /* leaves per bucket and their global numbering */
+  leaf_base[0] = 0;
+  for (uint64_t b = 0; b < n_buckets; ++b) {
+    uint64_t m = bucket_offset[b + 1] - bucket_offset[b];
+    leaf_base[b + 1] = leaf_base[b] + (m + leaf_target - 1) / leaf_target;
+  }
+  int rc = SHOCK_ORACLE_OK;
+  if (leaf_base[n_buckets] > leaf_cap) rc = SHOCK_ORACLE_EINVAL;
+  *n_leaves = leaf_base[n_buckets];
+  uint64_t count[1 << 12];
+  for (uint64_t b = 0; b < n_buckets && rc == SHOCK_ORACLE_OK; ++b) {
+    uint64_t o = bucket_offset[b], m = bucket_offset[b + 1] - o;
+    uint32_t L = (uint32_t)(leaf_base[b + 1] - leaf_base[b]);
+    if (L > (1u << 12)) {
+      rc = SHOCK_ORACLE_EINVAL;
+      break;
+    }
+    /* smallest splitting seed whose leaves all fit */
+    uint32_t s = 0;
+    for (;; ++s) {
+      if (s >= (1u << 16)) {
+        rc = SHOCK_ORACLE_EINVAL;
+        break;
+      }
+      for (uint32_t j = 0; j < L; ++j) count[j] = 0;
+      int fits = 1;
+      for (uint64_t i = 0; i < m; ++i) {
+        uint32_t j = leaf_of(grouped[o + i], s, L);
+        if (++count[j] > leaf_max) fits = 0;
+      }
+      if (fits) break;
+    }
+    if (rc != SHOCK_ORACLE_OK) break;
+    sigma[b] = s;
+    /* leaves: sizes, then keys leaf by leaf in ascending order */
+    uint64_t start = o;
+    for (uint32_t j = 0; j < L; ++j) {
+      uint64_t k = 0;
+      for (uint64_t i = 0; i < m; ++i)
+        if (leaf_of(grouped[o + i], s, L) == j) {
+          leaf_keys[start + k] = grouped[o + i];
+          ++k;
+        }
+      leaf_sizes[leaf_base[b] + j] = (uint8_t)k;
+      qsort(leaf_keys + start, k, sizeof(uint64_t), cmp_u64);
+      start += k;
+    }
+  }
+  /* original index of every key in leaf order (keys are distinct) */
+  if (rc == SHOCK_ORACLE_OK) {
+    for (uint64_t b = 0; b < n_buckets; ++b) {
+      for (uint64_t i = bucket_offset[b]; i < bucket_offset[b + 1]; ++i) {
+        for (uint64_t g = bucket_offset[b]; g < bucket_offset[b + 1]; ++g)
+          if (grouped[g] == leaf_keys[i]) {
+            key_index[i] = grouped_idx[g];
+            break;
+          }
+      }
+    }
+  }
+  free(fill);
+  free(grouped);
+  free(grouped_idx);
+  return rc;
+}
+
+/* ---- XOR retrieval ---------------------------------------------------------- */
+
+uint64_t shock_oracle_xor_segment(uint64_t n_keys) { return (123 * n_keys + 299) / 300 + 8; }
+
+static void xor_cells(uint64_t x, uint64_t rho, uint64_t seg, uint64_t c[3]) {
+  uint64_t u = shock_oracle_fmix64(x ^ shock_oracle_fmix64((rho + 1) * 0xA0761D6478BD642FULL));
+  uint64_t v = shock_oracle_fmix64(u);
+  c[0] = ((uint64_t)(uint32_t)u * seg) >> 32;
+  c[1] = seg + (((u >> 32) * seg) >> 32);
+  c[2] = 2 * seg + (((uint64_t)(uint32_t)v * seg) >> 32);
+}
+
+int shock_oracle_xor_build(const uint64_t *keys, const uint8_t *values, uint64_t n_keys, uint64_t rho_start,
+                           uint32_t max_tries, uint64_t *rho, uint8_t *z) {
+  uint64_t seg = shock_oracle_xor_segment(n_keys), m = 3 * seg;
+  uint32_t *cnt = (uint32_t *)malloc(sizeof(uint32_t) * m);
+  uint32_t *round = (uint32_t *)malloc(sizeof(uint32_t) * (n_keys + 1));
+  uint8_t *peel = (uint8_t *)malloc(n_keys + 1);
+  if (!cnt || !round || !peel) return SHOCK_ORACLE_EINVAL;
+  int rc = SHOCK_ORACLE_ENOTFOUND;
+  for (uint32_t t = 0; t < max_tries; ++t) {
+    uint64_t r0 = rho_start + t;
+    memset(cnt, 0, sizeof(uint32_t) * m);
+    for (uint64_t i = 0; i < n_keys; ++i) {
+      uint64_t c[3];
+      xor_cells(keys[i], r0, seg, c);
+      for (int q = 0; q < 3; ++q) cnt[c[q]] += 1;
+      round[i] = 0; /* 0: not peeled; r >= 1: peeled in round r */
+    }
+    uint64_t left = n_keys;
+    uint32_t r = 0;
+    while (left > 0) {
+      ++r;
+      uint64_t peeled = 0;
+      /* detect on the counts at the start of the round */
+      for (uint64_t i = 0; i < n_keys; ++i) {
+        if (round[i]) continue;
+        uint64_t c[3];
+        xor_cells(keys[i], r0, seg, c);
+        for (int q = 0; q < 3; ++q)
+          if (cnt[c[q]] == 1) {
+            round[i] = r;
+            peel[i] = (uint8_t)q;
+            ++peeled;
+            break;
+          }
+      }
+      if (peeled == 0) break;
+      /* then remove them */
+      for (uint64_t i = 0; i < n_keys; ++i) {
+        if (round[i] != r) continue;
+        uint64_t c[3];
+        xor_cells(keys[i], r0, seg, c);
+        for (int q = 0; q < 3; ++q) cnt[c[q]] -= 1;
+      }
+      left -= peeled;
+    }
+    if (left > 0) continue;
+    /* assignment, rounds in reverse */
+    memset(z, 0, m);
+    for (uint32_t rr = r; rr >= 1; --rr) {
+      for (uint64_t i = 0; i < n_keys; ++i) {
+        if (round[i] != rr) continue;
+        uint64_t c[3];
+        xor_cells(keys[i], r0, seg, c);
+        uint8_t acc = values[i] & 1;
+        for (int q = 0; q < 3; ++q)
+          if (q != peel[i]) acc ^= z[c[q]];
+        z[c[peel[i]]] = acc;
+      }
+    }
+    *rho = r0;
+    rc = SHOCK_ORACLE_OK;
+    break;
+  }
+  free(cnt);
+  free(round);
+  free(peel);
+  return rc;
+}
+
+int shock_oracle_xor_get(const uint64_t *keys, uint64_t n_keys, uint64_t rho, const uint8_t *z, uint8_t *values) {
+  uint64_t seg = shock_oracle_xor_segment(n_keys);
+  for (uint64_t i = 0; i < n_keys; ++i) {
+    uint64_t c[3];
+    xor_cells(keys[i], rho, seg, c);
+    values[i] = z[c[0]] ^ z[c[1]] ^ z[c[2]];
+  }
+  return SHOCK_ORACLE_OK;
+}
+
+int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_t n_keys, uint32_t leaf_target,
+                            uint64_t n_buckets, const uint64_t *bucket_offset, const uint64_t *leaf_base,
+                            const uint32_t *sigma, const uint8_t *leaf_sizes, const uint64_t *leaf_seeds,
+                            uint64_t rho, const uint8_t *z, uint64_t *out_pos) {
+  uint64_t seg = shock_oracle_xor_segment(n_keys);
+  for (uint64_t q = 0; q < n_queries; ++q) {
+    uint64_t x = queries[q];
+    uint64_t b = bucket_of(x, n_buckets);
+    uint64_t m = bucket_offset[b + 1] - bucket_offset[b];
+    uint32_t L = (uint32_t)((m + leaf_target - 1) / leaf_target);
+    if (L == 0) {
+      out_pos[q] = UINT64_MAX;
+      continue;
+    }
+    uint32_t j = leaf_of(x, sigma[b], L);
+    uint64_t start = bucket_offset[b];
+    for (uint32_t jj = 0; jj < j; ++jj) start += leaf_sizes[leaf_base[b] + jj];
+    uint32_t n = leaf_sizes[leaf_base[b] + j];
+    uint64_t c[3];
+    xor_cells(x, rho, seg, c);
+    int f = z[c[0]] ^ z[c[1]] ^ z[c[2]];
+    uint32_t h0 = 0, h1 = 0;
+    if (n >= 1) shock_oracle_slots(x, leaf_seeds[leaf_base[b] + j], n, &h0, &h1);
+    out_pos[q] = start + (f ? h1 : h0);
+  }
+  return SHOCK_ORACLE_OK;
+}

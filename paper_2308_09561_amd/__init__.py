@@ -11,5 +11,5 @@ from .binding import (  # noqa: F401
     SHOCK_MODE_AUTO, SHOCK_MODE_PLAIN_PER_LEAF, SHOCK_MODE_PERSISTENT, SHOCK_DEFAULT_MAX_SEED, NOT_FOUND_SEED,
     ShockError, lib, lib_path, exported_symbols, shock_leaf_search, shock_leaf_search_ex, shock_last_stats,
     shock_strerror, shock_spec_version, shock_release_scratch, leaf_search, SearchContext, make_opts,
-    shock_rf_leaf_search_ex, rf_leaf_search, leaf_query, rf_leaf_query, rice_encode, rice_decode,
+    shock_rf_leaf_search_ex, rf_leaf_search, leaf_query, rf_leaf_query, rice_encode, rice_decode, MPHF,
 )

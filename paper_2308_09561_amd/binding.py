@@ -29,6 +29,8 @@ EXPORTED = [
     "shock_ctx_create", "shock_ctx_destroy", "shock_ctx_search_async", "shock_ctx_query", "shock_ctx_wait",
     "shock_ctx_graph_capture", "shock_ctx_graph_launch", "shock_rf_leaf_search_ex", "shock_ctx_rf_search_async",
     "shock_leaf_query", "shock_rf_leaf_query", "shock_rice_encode", "shock_rice_decode",
+    "shock_mphf_params_init", "shock_mphf_build", "shock_mphf_query", "shock_mphf_info", "shock_mphf_export",
+    "shock_mphf_destroy",
 ]
 
 
@@ -61,6 +63,32 @@ class ShockStats(ctypes.Structure):
         ("spl", ctypes.c_int32),
         ("block_iters", ctypes.c_int32),
         ("waves_per_wg", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class MphfParams(ctypes.Structure):
+    _fields_ = [
+        ("bucket_size", ctypes.c_uint32),
+        ("leaf_target", ctypes.c_uint32),
+        ("leaf_max", ctypes.c_uint32),
+        ("max_rho_tries", ctypes.c_uint32),
+        ("rice_k_by_n", ctypes.c_void_p),
+        ("reserved", ctypes.c_uint64 * 4),
+    ]
+
+
+class MphfStats(ctypes.Structure):
+    _fields_ = [
+        ("n_keys", ctypes.c_uint64), ("n_buckets", ctypes.c_uint64), ("n_leaves", ctypes.c_uint64),
+        ("rho", ctypes.c_uint64), ("seg", ctypes.c_uint64),
+        ("max_sigma", ctypes.c_uint32), ("peel_rounds", ctypes.c_uint32),
+        ("seed_fixed_bits", ctypes.c_uint64), ("seed_unary_bits", ctypes.c_uint64),
+        ("bits_buckets", ctypes.c_uint64), ("bits_leaf_sizes", ctypes.c_uint64), ("bits_seeds", ctypes.c_uint64),
+        ("bits_retrieval", ctypes.c_uint64), ("bits_total", ctypes.c_uint64),
+        ("build_ms", ctypes.c_double), ("search_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -129,6 +157,18 @@ def lib():
                                         u64p, vp]
         L.shock_rice_decode.restype = ctypes.c_int
         L.shock_rice_decode.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint64, vp, vp, ctypes.c_uint64, vp, vp, vp]
+        L.shock_mphf_params_init.restype = None
+        L.shock_mphf_params_init.argtypes = [ctypes.POINTER(MphfParams)]
+        L.shock_mphf_build.restype = ctypes.c_int
+        L.shock_mphf_build.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(MphfParams), ctypes.POINTER(vp), vp]
+        L.shock_mphf_query.restype = ctypes.c_int
+        L.shock_mphf_query.argtypes = [vp, vp, ctypes.c_uint64, vp, vp]
+        L.shock_mphf_info.restype = ctypes.c_int
+        L.shock_mphf_info.argtypes = [vp, ctypes.POINTER(MphfStats)]
+        L.shock_mphf_export.restype = ctypes.c_int
+        L.shock_mphf_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.shock_mphf_destroy.restype = ctypes.c_int
+        L.shock_mphf_destroy.argtypes = [vp]
         L.shock_ctx_query.restype = ctypes.c_int
         L.shock_ctx_query.argtypes = [vp]
         L.shock_ctx_wait.restype = ctypes.c_int
@@ -439,4 +479,81 @@ def rice_decode(fixed, unary, index, offsets, k_by_n, out_values=None, stream=No
                                  _as_ptr(offsets), max(L, 0), _table(k_by_n), _as_ptr(out_values),
                                  _stream_of(offsets, stream))
     return rc, out_values[:max(L, 0)]
+
+
+# ---- flat ShockHash MPHF (include/shockmphf.h) ---------------------------------
+
+class MPHF:
+    """A minimal perfect hash function of distinct uint64 keys, built and
+    queried on the GPU.  Raises ShockError if the build fails."""
+
+    def __init__(self, keys, bucket_size=2000, leaf_target=40, leaf_max=56, rice_table=None, stream=None):
+        import numpy as np
+        if keys.device.type != "cuda" or keys.dtype.itemsize != 8:
+            raise ValueError("keys must be a 64-bit device tensor")
+        if rice_table is None:
+            from .rice import plain_table
+            rice_table = plain_table()
+        keys = keys.contiguous()
+        p = MphfParams()
+        lib().shock_mphf_params_init(ctypes.byref(p))
+        p.bucket_size, p.leaf_target, p.leaf_max = bucket_size, leaf_target, leaf_max
+        table = _table(rice_table)
+        p.rice_k_by_n = ctypes.cast(table, ctypes.c_void_p)
+        self._h = ctypes.c_void_p()
+        self.rice_table = [int(v) for v in rice_table]
+        rc = lib().shock_mphf_build(_as_ptr(keys) if keys.numel() else None, keys.numel(), ctypes.byref(p),
+                                    ctypes.byref(self._h), _stream_of(keys, stream))
+        self.status = rc
+        if rc != SHOCK_OK:
+            raise ShockError(rc, shock_strerror(rc) + " / " + lib().shock_last_error().decode())
+        self.n_keys = keys.numel()
+        self._np = np
+
+    def query(self, queries, out=None, stream=None):
+        """Positions (an int64 device tensor) of the query keys."""
+        import torch
+        if out is None:
+            out = torch.empty(max(queries.numel(), 1), dtype=torch.int64, device=queries.device)
+        rc = lib().shock_mphf_query(self._h, _as_ptr(queries) if queries.numel() else None, queries.numel(),
+                                    _as_ptr(out), _stream_of(queries, stream))
+        if rc != SHOCK_OK:
+            raise ShockError(rc, shock_strerror(rc))
+        return out[:queries.numel()]
+
+    def info(self) -> dict:
+        st = MphfStats()
+        lib().shock_mphf_info(self._h, ctypes.byref(st))
+        d = st.as_dict()
+        d["bits_per_key"] = d["bits_total"] / max(d["n_keys"], 1)
+        return d
+
+    def export(self) -> dict:
+        """The stored parts as numpy arrays (leaf seeds decoded)."""
+        np = self._np
+        st = self.info()
+        B, L = st["n_buckets"], st["n_leaves"]
+        bo = np.zeros(B + 1, np.uint64)
+        lb = np.zeros(B + 1, np.uint64)
+        sg = np.zeros(max(B, 1), np.uint32)
+        sz = np.zeros(max(L, 1), np.uint8)
+        sd = np.zeros(max(L, 1), np.uint64)
+        z = np.zeros(3 * st["seg"], np.uint8)
+        rc = lib().shock_mphf_export(self._h, bo.ctypes.data, lb.ctypes.data, sg.ctypes.data, sz.ctypes.data,
+                                     sd.ctypes.data, z.ctypes.data)
+        if rc != SHOCK_OK:
+            raise ShockError(rc, shock_strerror(rc))
+        return {"bucket_offset": bo, "leaf_base": lb, "sigma": sg[:B], "leaf_sizes": sz[:L], "seeds": sd[:L],
+                "z": z, "rho": st["rho"], "seg": st["seg"]}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().shock_mphf_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 

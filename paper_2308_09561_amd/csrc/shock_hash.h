@@ -19,7 +19,7 @@ constexpr uint64_t kMix1 = 0xff51afd7ed558ccdull;
 constexpr uint64_t kMix2 = 0xc4ceb9fe1a85ec53ull;
 constexpr uint64_t kSideKey = 0xD1B54A32D192ED03ull;
 
-__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+__host__ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
   k ^= k >> 33;
   k *= kMix1;
   k ^= k >> 33;

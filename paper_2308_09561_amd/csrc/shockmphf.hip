@@ -1,0 +1,790 @@
+// Flat ShockHash MPHF on MI355X (gfx950): build and query.  Definitions in
+// include/shockmphf.h.
+//
+// Build, all on the device (the host only sizes buffers and steps the rounds):
+//   bucket counts (atomics)  ->  one-workgroup scan of bucket sizes and leaf
+//   counts  ->  scatter keys by bucket  ->  per bucket (a wave): the smallest
+//   splitting seed whose leaves fit (leaf histogram in LDS), then leaf sizes,
+//   offsets and a scatter into leaf order  ->  per leaf (a wave): bitonic sort
+//   of its keys in registers  ->  the persistent leaf search of
+//   shock_leaf_search_ex  ->  Golomb-Rice codes of the seeds  ->  the
+//   retrieval of each key's choice: a 3-hypergraph XOR system peeled in
+//   synchronous rounds (per round one detect pass and one removal pass over
+//   the keys; the host reads one counter per round), then solved rounds in
+//   reverse (keys of one round write distinct cells and read none written in
+//   that round), packed to bits.
+// Query: a thread per key: bucket, splitting seed, leaf, the leaf's key offset
+// from the byte sizes, its seed decoded from the Rice streams (the block
+// index, the widths of the leaves before it in its block of 64, and a select
+// in the unary stream), three retrieval bits, then the leaf's slot.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <chrono>
+
+#include "shockcode.h"
+#include "shockmphf.h"
+#include "shock_hash.h"
+#include "shock_internal.h"
+
+namespace {
+
+using shockhash::fmix64;
+using shockhash::seed_mix;
+using shockhash::slot_pair;
+
+constexpr uint64_t kNone = ~0ull;
+constexpr uint64_t kBucketKey = 0x5851F42D4C957F2Dull;
+constexpr uint64_t kSplitMul = 0xD6E8FEB86659FD93ull;
+constexpr uint64_t kRetrievalMul = 0xA0761D6478BD642Full;
+constexpr uint32_t kMaxLeavesPerBucket = 1024;
+constexpr uint32_t kMaxSigma = 1u << 16;
+
+constexpr uint64_t kErrTooManyLeaves = 1;
+constexpr uint64_t kErrSigma = 2;
+
+struct KTable {
+  uint8_t k[65];
+};
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+__device__ __forceinline__ uint64_t bucket_of(uint64_t x, uint64_t n_buckets) {
+  return __umul64hi(fmix64(x ^ kBucketKey), n_buckets);
+}
+__device__ __forceinline__ uint64_t split_mix(uint32_t sigma) { return fmix64(((uint64_t)sigma + 1) * kSplitMul); }
+__device__ __forceinline__ uint32_t leaf_of(uint64_t x, uint64_t tmix, uint32_t n_leaves) {
+  return (uint32_t)(((uint64_t)(uint32_t)fmix64(x ^ tmix) * n_leaves) >> 32);
+}
+__device__ __forceinline__ void xor_cells(uint64_t x, uint64_t rmix, uint64_t seg, uint64_t c[3]) {
+  const uint64_t u = fmix64(x ^ rmix);
+  const uint64_t v = fmix64(u);
+  c[0] = ((u & 0xFFFFFFFFull) * seg) >> 32;
+  c[1] = seg + (((u >> 32) * seg) >> 32);
+  c[2] = 2 * seg + (((v & 0xFFFFFFFFull) * seg) >> 32);
+}
+
+__device__ __forceinline__ uint64_t wave_excl_scan(uint64_t v) {
+  const uint32_t lane = lane_id();
+  uint64_t x = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x - v;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+__global__ void fill_u8_kernel(uint8_t *p, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+// ---- layout -------------------------------------------------------------------
+
+__global__ void bucket_count_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t n_buckets,
+                                    uint32_t *counts) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_keys; i += stride)
+    atomicAdd(&counts[bucket_of(keys[i], n_buckets)], 1u);
+}
+
+// Exclusive scans of bucket sizes (-> bucket_offset) and leaf counts
+// ceil(m / leaf_target) (-> leaf_base), each with the total appended.  One
+// workgroup of 1024 threads, 16 buckets per thread and chunk.
+__global__ __launch_bounds__(1024) void layout_scan_kernel(const uint32_t *counts, uint64_t n_buckets,
+                                                           uint32_t leaf_target, uint64_t *bucket_offset,
+                                                           uint64_t *leaf_base, unsigned long long *err) {
+  constexpr uint32_t kPer = 16;
+  __shared__ uint64_t wm[16], wl[16];
+  const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  uint64_t carry_m = 0, carry_l = 0;
+  for (uint64_t c = 0; c < n_buckets; c += 1024ull * kPer) {
+    const uint64_t b0 = c + (uint64_t)t * kPer;
+    uint64_t sm = 0, sl = 0;
+    for (uint32_t e = 0; e < kPer; ++e) {
+      const uint64_t b = b0 + e;
+      if (b < n_buckets) {
+        const uint64_t m = counts[b], l = (m + leaf_target - 1) / leaf_target;
+        if (l > kMaxLeavesPerBucket) atomicOr(err, kErrTooManyLeaves);
+        sm += m;
+        sl += l;
+      }
+    }
+    const uint64_t xm = wave_excl_scan(sm), xl = wave_excl_scan(sl);
+    if (lane == 63) {
+      wm[wave] = xm + sm;
+      wl[wave] = xl + sl;
+    }
+    __syncthreads();
+    uint64_t pm = 0, pl = 0, tm = 0, tl = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+      if (w < wave) {
+        pm += wm[w];
+        pl += wl[w];
+      }
+      tm += wm[w];
+      tl += wl[w];
+    }
+    uint64_t rm = carry_m + pm + xm, rl = carry_l + pl + xl;
+    for (uint32_t e = 0; e < kPer; ++e) {
+      const uint64_t b = b0 + e;
+      if (b < n_buckets) {
+        const uint64_t m = counts[b];
+        bucket_offset[b] = rm;
+        leaf_base[b] = rl;
+        rm += m;
+        rl += (m + leaf_target - 1) / leaf_target;
+      }
+    }
+    carry_m += tm;
+    carry_l += tl;
+    __syncthreads();
+  }
+  if (t == 0) {
+    bucket_offset[n_buckets] = carry_m;
+    leaf_base[n_buckets] = carry_l;
+  }
+}
+
+__global__ void bucket_scatter_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t n_buckets,
+                                      const uint64_t *__restrict__ bucket_offset, uint32_t *cursor,
+                                      uint64_t *__restrict__ grouped) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_keys; i += stride) {
+    const uint64_t x = keys[i];
+    const uint64_t b = bucket_of(x, n_buckets);
+    grouped[bucket_offset[b] + atomicAdd(&cursor[b], 1u)] = x;
+  }
+}
+
+// One wave per bucket: the smallest splitting seed whose leaves all fit, then
+// leaf sizes, global leaf key offsets, and the keys scattered into leaf order
+// (unsorted within a leaf).
+__global__ __launch_bounds__(256) void split_kernel(const uint64_t *__restrict__ grouped,
+                                                    const uint64_t *__restrict__ bucket_offset,
+                                                    const uint64_t *__restrict__ leaf_base, uint64_t n_buckets,
+                                                    uint32_t leaf_max, uint32_t *sigma, uint8_t *leaf_sizes,
+                                                    uint64_t *leaf_off, uint64_t *__restrict__ leaf_keys,
+                                                    unsigned long long *err) {
+  __shared__ uint32_t bins_all[4][kMaxLeavesPerBucket];
+  const uint32_t lane = lane_id();
+  uint32_t *bins = bins_all[threadIdx.x >> 6];
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t b = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < n_buckets; b += waves) {
+    const uint64_t o = bucket_offset[b], m = bucket_offset[b + 1] - o;
+    const uint64_t lb = leaf_base[b];
+    const uint32_t L = (uint32_t)(leaf_base[b + 1] - lb);
+    if (L == 0) {
+      if (lane == 0) sigma[b] = 0;
+      continue;
+    }
+    if (L > kMaxLeavesPerBucket) continue;  // flagged by the scan
+    uint32_t s = 0;
+    bool found = false;
+    for (; s < kMaxSigma; ++s) {
+      const uint64_t tm = split_mix(s);
+      for (uint32_t j = lane; j < L; j += 64) bins[j] = 0;
+      wave_sync();
+      bool over = false;
+      for (uint64_t i = lane; i < m; i += 64) {
+        const uint32_t c = atomicAdd(&bins[leaf_of(grouped[o + i], tm, L)], 1u) + 1;
+        over |= c > leaf_max;
+      }
+      wave_sync();
+      if (__ballot(over) == 0) {
+        found = true;
+        break;
+      }
+    }
+    if (!found) {
+      if (lane == 0) atomicOr(err, kErrSigma);
+      continue;
+    }
+    if (lane == 0) sigma[b] = s;
+    // sizes -> exclusive starts (in place), chunk by chunk of 64 leaves
+    uint64_t carry = 0;
+    for (uint32_t j0 = 0; j0 < L; j0 += 64) {
+      const uint32_t j = j0 + lane;
+      const uint32_t sz = j < L ? bins[j] : 0;
+      const uint64_t start = carry + wave_excl_scan(sz);
+      if (j < L) {
+        leaf_sizes[lb + j] = (uint8_t)sz;
+        leaf_off[lb + j] = o + start;
+        bins[j] = (uint32_t)start;
+      }
+      carry = __shfl(start + sz, 63);  // start already includes the carry
+    }
+    wave_sync();
+    const uint64_t tm = split_mix(s);
+    for (uint64_t i = lane; i < m; i += 64) {
+      const uint64_t x = grouped[o + i];
+      leaf_keys[o + atomicAdd(&bins[leaf_of(x, tm, L)], 1u)] = x;
+    }
+    wave_sync();
+  }
+}
+
+// One wave per leaf: sort its keys ascending (bitonic network over the 64
+// lanes; lanes beyond the leaf hold the largest value and stay at the end).
+__global__ __launch_bounds__(256) void leaf_sort_kernel(uint64_t *keys, const uint64_t *__restrict__ leaf_off,
+                                                        const uint8_t *__restrict__ leaf_sizes, uint64_t n_leaves) {
+  const uint32_t lane = lane_id();
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t g = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < n_leaves; g += waves) {
+    const uint64_t o = leaf_off[g];
+    const uint32_t n = leaf_sizes[g];
+    uint64_t v = lane < n ? keys[o + lane] : kNone;
+    for (uint32_t k = 2; k <= 64; k <<= 1) {
+      for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+        const uint64_t w = __shfl_xor(v, j);
+        const bool up = (lane & k) == 0;
+        const bool lower = (lane & j) == 0;
+        const uint64_t lo = v < w ? v : w, hi = v < w ? w : v;
+        v = (lower == up) ? lo : hi;
+      }
+    }
+    if (lane < n) keys[o + lane] = v;
+  }
+}
+
+// ---- retrieval ------------------------------------------------------------------
+
+__global__ void choice_kernel(const uint64_t *__restrict__ leaf_off, const uint8_t *__restrict__ leaf_sizes,
+                              const uint64_t *__restrict__ orient, uint64_t n_leaves, uint8_t *choice) {
+  const uint32_t lane = lane_id();
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  for (uint64_t g = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < n_leaves; g += waves)
+    if (lane < leaf_sizes[g]) choice[leaf_off[g] + lane] = (uint8_t)((orient[g] >> lane) & 1);
+}
+
+__global__ void xor_count_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
+                                 uint32_t *cnt, uint32_t *round) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_keys; i += stride) {
+    uint64_t c[3];
+    xor_cells(keys[i], rmix, seg, c);
+    atomicAdd(&cnt[c[0]], 1u);
+    atomicAdd(&cnt[c[1]], 1u);
+    atomicAdd(&cnt[c[2]], 1u);
+    round[i] = 0;
+  }
+}
+
+// Round r, detect: every key not yet peeled with a cell of count one (at the
+// start of the round) is peeled in this round at its first such cell.
+__global__ void xor_detect_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
+                                  const uint32_t *__restrict__ cnt, uint32_t *round, uint8_t *peel, uint32_t r,
+                                  unsigned long long *peeled) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n_keys; i0 += stride) {
+    const uint64_t i = i0 + threadIdx.x;
+    bool got = false;
+    if (i < n_keys && round[i] == 0) {
+      uint64_t c[3];
+      xor_cells(keys[i], rmix, seg, c);
+      for (int q = 0; q < 3; ++q) {
+        if (cnt[c[q]] == 1) {
+          round[i] = r;
+          peel[i] = (uint8_t)q;
+          got = true;
+          break;
+        }
+      }
+    }
+    const uint64_t mask = __ballot(got);
+    if (lane_id() == 0 && mask) atomicAdd(peeled, (unsigned long long)__popcll(mask));
+  }
+}
+
+__global__ void xor_remove_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
+                                  uint32_t *cnt, const uint32_t *__restrict__ round, uint32_t r) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_keys; i += stride) {
+    if (round[i] != r) continue;
+    uint64_t c[3];
+    xor_cells(keys[i], rmix, seg, c);
+    atomicSub(&cnt[c[0]], 1u);
+    atomicSub(&cnt[c[1]], 1u);
+    atomicSub(&cnt[c[2]], 1u);
+  }
+}
+
+__global__ void xor_assign_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
+                                  const uint32_t *__restrict__ round, const uint8_t *__restrict__ peel,
+                                  const uint8_t *__restrict__ choice, uint8_t *z, uint32_t r) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_keys; i += stride) {
+    if (round[i] != r) continue;
+    uint64_t c[3];
+    xor_cells(keys[i], rmix, seg, c);
+    const uint32_t p = peel[i];
+    uint8_t acc = choice[i] & 1;
+    for (uint32_t q = 0; q < 3; ++q)
+      if (q != p) acc ^= z[c[q]];
+    z[c[p]] = acc;
+  }
+}
+
+__global__ void pack_bits_kernel(const uint8_t *__restrict__ z, uint64_t cells, uint64_t *bits) {
+  const uint64_t words = (cells + 63) / 64;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride) {
+    uint64_t v = 0;
+    for (uint32_t b = 0; b < 64; ++b) {
+      const uint64_t c = w * 64 + b;
+      if (c < cells && z[c]) v |= 1ull << b;
+    }
+    bits[w] = v;
+  }
+}
+
+// ---- query ------------------------------------------------------------------
+
+struct QueryArgs {
+  const uint64_t *bucket_offset, *leaf_base;
+  const uint32_t *sigma;
+  const uint8_t *leaf_sizes;
+  const uint64_t *fixed, *unary, *index, *zbits;
+  uint64_t fixed_words, unary_words;
+  uint64_t n_buckets, seg, rmix;
+  uint32_t leaf_target;
+  KTable K;
+};
+
+// Position of the r-th one bit (0-based) at or after bit p of the stream.
+__device__ __forceinline__ uint64_t select_one(const uint64_t *s, uint64_t words, uint64_t p, uint64_t r) {
+  uint64_t w = p >> 6;
+  uint64_t word = w < words ? s[w] & (~0ull << (p & 63)) : 0;
+  for (;;) {
+    const uint64_t c = (uint64_t)__popcll(word);
+    if (c > r || w + 1 >= words) break;
+    r -= c;
+    ++w;
+    word = s[w];
+  }
+  for (uint64_t i = 0; i < r && word; ++i) word &= word - 1;
+  return word ? w * 64 + (uint64_t)__builtin_ctzll(word) : kNone;
+}
+
+__global__ __launch_bounds__(256) void mphf_query_kernel(QueryArgs A, const uint64_t *__restrict__ queries,
+                                                         uint64_t n_queries, uint64_t *__restrict__ out) {
+  __shared__ uint8_t K[65];
+  if (threadIdx.x < 65) K[threadIdx.x] = A.K.k[threadIdx.x];
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_queries; t += stride) {
+    const uint64_t x = queries[t];
+    const uint64_t b = bucket_of(x, A.n_buckets);
+    const uint64_t o = A.bucket_offset[b], m = A.bucket_offset[b + 1] - o;
+    if (m == 0) {
+      out[t] = kNone;
+      continue;
+    }
+    const uint32_t L = (uint32_t)((m + A.leaf_target - 1) / A.leaf_target);
+    const uint64_t lb = A.leaf_base[b];
+    const uint32_t j = leaf_of(x, split_mix(A.sigma[b]), L);
+    const uint64_t g = lb + j;
+    uint64_t start = 0;
+    for (uint64_t jj = lb; jj < g; ++jj) start += A.leaf_sizes[jj];
+    const uint32_t n = A.leaf_sizes[g];
+    // the leaf's seed: fixed bits after the widths of the leaves before it in its block
+    const uint64_t blk = g >> 6;
+    uint64_t F = A.index[2 * blk];
+    for (uint64_t gg = blk * 64; gg < g; ++gg) F += K[A.leaf_sizes[gg]];
+    const uint32_t k = K[n];
+    uint64_t low = 0;
+    if (k) {
+      const uint64_t w = F >> 6;
+      const uint32_t sh = (uint32_t)(F & 63);
+      if (w < A.fixed_words) low = A.fixed[w] >> sh;
+      if (sh + k > 64 && w + 1 < A.fixed_words) low |= A.fixed[w + 1] << (64 - sh);
+      low &= ~0ull >> (64 - k);
+    }
+    const uint64_t U0 = A.index[2 * blk + 1];
+    const uint32_t i = (uint32_t)(g & 63);
+    const uint64_t end = select_one(A.unary, A.unary_words, U0, i);
+    const uint64_t begin = i == 0 ? U0 : select_one(A.unary, A.unary_words, U0, i - 1) + 1;
+    const uint64_t seed = end == kNone ? kNone : (((end - begin) << k) | low);
+    // the choice from the retrieval cells
+    uint64_t c[3];
+    xor_cells(x, A.rmix, A.seg, c);
+    const uint32_t f = (uint32_t)(((A.zbits[c[0] >> 6] >> (c[0] & 63)) ^ (A.zbits[c[1] >> 6] >> (c[1] & 63)) ^
+                                   (A.zbits[c[2] >> 6] >> (c[2] & 63))) & 1);
+    uint32_t h0 = 0, h1 = 0;
+    if (n >= 2) {
+      const uint64_t a = fmix64(x), ts = seed_mix(seed);
+      slot_pair((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)ts, (uint32_t)(ts >> 32), n, n - 1, h0, h1);
+    }
+    out[t] = o + start + (f ? h1 : h0);
+  }
+}
+
+int grid_for(uint64_t items, uint32_t per_block) {
+  uint64_t g = (items + per_block - 1) / per_block;
+  if (g > 65536) g = 65536;
+  return g == 0 ? 1 : (int)g;
+}
+
+}  // namespace
+
+struct shock_mphf {
+  uint64_t n_keys = 0, n_buckets = 0, n_leaves = 0;
+  uint32_t leaf_target = 0, leaf_max = 0, bucket_size = 0;
+  uint64_t rho = 0, seg = 0;
+  uint32_t max_sigma = 0, peel_rounds = 0;
+  KTable K{};
+  uint64_t *bucket_offset = nullptr, *leaf_base = nullptr;
+  uint32_t *sigma = nullptr;
+  uint8_t *leaf_sizes = nullptr;
+  uint64_t *fixed = nullptr, *unary = nullptr, *index = nullptr, *zbits = nullptr;
+  uint64_t fixed_words = 0, unary_words = 0, index_words = 0, zwords = 0;
+  uint64_t fixed_bits = 0, unary_bits = 0;
+  double build_ms = 0, search_ms = 0;
+};
+
+namespace {
+
+// Device allocations of one build, freed on every exit path.
+struct Scratch {
+  std::vector<void *> ptrs;
+  template <typename T>
+  hipError_t alloc(T **p, size_t count) {
+    *p = nullptr;
+    hipError_t e = hipMalloc((void **)p, (count ? count : 1) * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back((void *)*p);
+    return e;
+  }
+  void release(void *p) {
+    for (auto &q : ptrs)
+      if (q == p) q = nullptr;
+  }
+  ~Scratch() {
+    for (void *p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+void free_mphf(shock_mphf *m) {
+  if (!m) return;
+  void *ps[] = {m->bucket_offset, m->leaf_base, m->sigma, m->leaf_sizes, m->fixed, m->unary, m->index, m->zbits};
+  for (void *p : ps)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+}  // namespace
+
+#define HIP_TRY(call)                       \
+  do {                                      \
+    hipError_t e_ = (call);                 \
+    if (e_ != hipSuccess) {                 \
+      shock_internal_set_error(#call, e_);  \
+      return e_ == hipErrorOutOfMemory ? SHOCK_ENOMEM : SHOCK_EHIP; \
+    }                                       \
+  } while (0)
+
+static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params &P, shock_mphf *M,
+                      hipStream_t stream) {
+  Scratch S;
+  const uint64_t B = N == 0 ? 1 : (N + P.bucket_size - 1) / P.bucket_size;
+  M->n_keys = N;
+  M->n_buckets = B;
+  unsigned long long *err = nullptr;
+  uint64_t *host = nullptr;  // pinned: [0] error bits, [1] n_leaves, [2] peeled count
+  HIP_TRY(S.alloc(&err, 2));
+  HIP_TRY(hipHostMalloc((void **)&host, 4 * sizeof(uint64_t)));
+  struct HostFree {
+    uint64_t *p;
+    ~HostFree() { (void)hipHostFree(p); }
+  } host_guard{host};
+  uint32_t *counts = nullptr;
+  HIP_TRY(S.alloc(&counts, B));
+  HIP_TRY(hipMalloc((void **)&M->bucket_offset, (B + 1) * sizeof(uint64_t)));
+  HIP_TRY(hipMalloc((void **)&M->leaf_base, (B + 1) * sizeof(uint64_t)));
+  HIP_TRY(hipMalloc((void **)&M->sigma, B * sizeof(uint32_t)));
+  HIP_TRY(hipMemsetAsync(err, 0, 2 * sizeof(unsigned long long), stream));
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(B, 256)), dim3(256), 0, stream, counts, B, 0u);
+  if (N) hipLaunchKernelGGL(bucket_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, keys, N, B, counts);
+  hipLaunchKernelGGL(layout_scan_kernel, dim3(1), dim3(1024), 0, stream, counts, B, P.leaf_target, M->bucket_offset,
+                     M->leaf_base, err);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&host[1], M->leaf_base + B, 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (host[0] & kErrTooManyLeaves) return SHOCK_EINVAL;
+  const uint64_t L = host[1];
+  M->n_leaves = L;
+  HIP_TRY(hipMalloc((void **)&M->leaf_sizes, (L ? L : 1)));
+  uint64_t *grouped = nullptr, *leaf_keys = nullptr, *leaf_off = nullptr;
+  HIP_TRY(S.alloc(&grouped, N));
+  HIP_TRY(S.alloc(&leaf_keys, N));
+  HIP_TRY(S.alloc(&leaf_off, L + 1));
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(B, 256)), dim3(256), 0, stream, counts, B, 0u);
+  if (N)
+    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, keys, N, B,
+                       (const uint64_t *)M->bucket_offset, counts, grouped);
+  hipLaunchKernelGGL(split_kernel, dim3(grid_for(B, 4)), dim3(256), 0, stream, (const uint64_t *)grouped,
+                     (const uint64_t *)M->bucket_offset, (const uint64_t *)M->leaf_base, B, P.leaf_max, M->sigma,
+                     M->leaf_sizes, leaf_off, leaf_keys, err);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(leaf_off + L, &N, 8, hipMemcpyHostToDevice, stream));
+  if (L)
+    hipLaunchKernelGGL(leaf_sort_kernel, dim3(grid_for(L, 4)), dim3(256), 0, stream, leaf_keys,
+                       (const uint64_t *)leaf_off, (const uint8_t *)M->leaf_sizes, L);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (host[0] & kErrSigma) return SHOCK_ENOTFOUND;
+  S.release(grouped);
+  HIP_TRY(hipFree(grouped));
+
+  // leaf seeds and orientations
+  uint64_t *seeds = nullptr, *orient = nullptr;
+  HIP_TRY(S.alloc(&seeds, L));
+  HIP_TRY(S.alloc(&orient, L));
+  if (L) {
+    shock_opts o;
+    shock_opts_init(&o);
+    o.check_dups = 1;
+    const int rc = shock_leaf_search_ex(leaf_keys, leaf_off, L, seeds, orient, &o, stream);
+    if (rc != SHOCK_OK) return rc;
+    shock_stats st;
+    if (shock_last_stats(&st) == SHOCK_OK) M->search_ms = st.kernel_ms;
+  }
+  // Golomb-Rice codes of the seeds
+  uint64_t bits[2] = {0, 0};
+  const uint64_t n_blocks = (L + 63) / 64;
+  M->index_words = 2 * (n_blocks + 1);
+  HIP_TRY(hipMalloc((void **)&M->index, M->index_words * sizeof(uint64_t)));
+  int rc = shock_rice_encode(seeds, leaf_off, L, M->K.k, nullptr, 0, nullptr, 0, M->index, bits, stream);
+  if (rc != SHOCK_OK && rc != SHOCK_EINVAL) return rc;
+  M->fixed_bits = bits[0];
+  M->unary_bits = bits[1];
+  M->fixed_words = (bits[0] + 63) / 64;
+  M->unary_words = (bits[1] + 63) / 64;
+  HIP_TRY(hipMalloc((void **)&M->fixed, (M->fixed_words ? M->fixed_words : 1) * 8));
+  HIP_TRY(hipMalloc((void **)&M->unary, (M->unary_words ? M->unary_words : 1) * 8));
+  rc = shock_rice_encode(seeds, leaf_off, L, M->K.k, M->fixed, M->fixed_words, M->unary, M->unary_words, M->index,
+                         bits, stream);
+  if (rc != SHOCK_OK) return rc;
+
+  // retrieval of each key's choice
+  uint8_t *choice = nullptr, *peel = nullptr, *z = nullptr;
+  uint32_t *cnt = nullptr, *round = nullptr;
+  const uint64_t seg = (123 * N + 299) / 300 + 8, cells = 3 * seg;
+  M->seg = seg;
+  HIP_TRY(S.alloc(&choice, N));
+  HIP_TRY(S.alloc(&peel, N));
+  HIP_TRY(S.alloc(&round, N));
+  HIP_TRY(S.alloc(&cnt, cells));
+  HIP_TRY(S.alloc(&z, cells));
+  if (L)
+    hipLaunchKernelGGL(choice_kernel, dim3(grid_for(L, 4)), dim3(256), 0, stream, (const uint64_t *)leaf_off,
+                       (const uint8_t *)M->leaf_sizes, (const uint64_t *)orient, L, choice);
+  HIP_TRY(hipGetLastError());
+  bool solved = false;
+  uint32_t rounds = 0;
+  for (uint32_t t = 0; t < P.max_rho_tries && !solved; ++t) {
+    const uint64_t rho = t;
+    const uint64_t rmix = shockhash::fmix64((rho + 1) * kRetrievalMul);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, cnt, cells, 0u);
+    if (N) hipLaunchKernelGGL(xor_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg, cnt, round);
+    HIP_TRY(hipGetLastError());
+    uint64_t left = N;
+    uint32_t r = 0;
+    while (left > 0) {
+      ++r;
+      HIP_TRY(hipMemsetAsync(err + 1, 0, 8, stream));
+      hipLaunchKernelGGL(xor_detect_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg,
+                         (const uint32_t *)cnt, round, peel, r, err + 1);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(&host[2], err + 1, 8, hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      const uint64_t peeled = host[2];
+      if (peeled == 0) break;
+      hipLaunchKernelGGL(xor_remove_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg,
+                         cnt, (const uint32_t *)round, r);
+      HIP_TRY(hipGetLastError());
+      left -= peeled;
+    }
+    if (left > 0) continue;
+    rounds = r;  // every round of a successful peeling removed keys
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, z, cells);
+    for (uint32_t rr = rounds; rr >= 1; --rr)
+      hipLaunchKernelGGL(xor_assign_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg,
+                         (const uint32_t *)round, (const uint8_t *)peel, (const uint8_t *)choice, z, rr);
+    HIP_TRY(hipGetLastError());
+    M->rho = rho;
+    solved = true;
+  }
+  if (!solved) return SHOCK_ENOTFOUND;
+  M->peel_rounds = rounds;
+  M->zwords = (cells + 63) / 64;
+  HIP_TRY(hipMalloc((void **)&M->zbits, M->zwords * 8));
+  hipLaunchKernelGGL(pack_bits_kernel, dim3(grid_for(M->zwords, 256)), dim3(256), 0, stream, (const uint8_t *)z, cells,
+                     M->zbits);
+  HIP_TRY(hipGetLastError());
+  // the largest splitting seed (for the record)
+  if (B) {
+    uint32_t *hs = (uint32_t *)malloc(B * sizeof(uint32_t));
+    if (!hs) return SHOCK_ENOMEM;
+    hipError_t e = hipMemcpyAsync(hs, M->sigma, B * sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    for (uint64_t b = 0; b < B && e == hipSuccess; ++b) M->max_sigma = hs[b] > M->max_sigma ? hs[b] : M->max_sigma;
+    free(hs);
+    HIP_TRY(e);
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  return SHOCK_OK;
+}
+
+extern "C" {
+
+void shock_mphf_params_init(shock_mphf_params *p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->bucket_size = 2000;
+  p->leaf_target = 40;
+  p->leaf_max = 56;
+  p->max_rho_tries = 64;
+  p->rice_k_by_n = nullptr;
+}
+
+int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_params *params, shock_mphf **out,
+                     void *hip_stream) {
+  if (!params || !out || (n_keys && !keys)) return SHOCK_EINVAL;
+  const shock_mphf_params &P = *params;
+  if (P.bucket_size == 0 || P.leaf_target == 0 || P.leaf_max > 64 || P.leaf_target > P.leaf_max) return SHOCK_EINVAL;
+  if (P.max_rho_tries == 0 || !P.rice_k_by_n || n_keys >= (1ull << 32)) return SHOCK_EINVAL;
+  *out = nullptr;
+  shock_mphf *M = new shock_mphf;
+  M->leaf_target = P.leaf_target;
+  M->leaf_max = P.leaf_max;
+  M->bucket_size = P.bucket_size;
+  for (int n = 0; n <= 64; ++n) {
+    if (P.rice_k_by_n[n] > 56) {
+      delete M;
+      return SHOCK_EINVAL;
+    }
+    M->K.k[n] = P.rice_k_by_n[n];
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = build_impl(keys, n_keys, P, M, (hipStream_t)hip_stream);
+  if (rc != SHOCK_OK) {
+    free_mphf(M);
+    return rc;
+  }
+  M->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = M;
+  return SHOCK_OK;
+}
+
+int shock_mphf_query(const shock_mphf *m, const uint64_t *queries, uint64_t n_queries, uint64_t *positions,
+                     void *hip_stream) {
+  if (!m) return SHOCK_EINVAL;
+  if (n_queries == 0) return SHOCK_OK;
+  if (!queries || !positions) return SHOCK_EINVAL;
+  QueryArgs A;
+  A.bucket_offset = m->bucket_offset;
+  A.leaf_base = m->leaf_base;
+  A.sigma = m->sigma;
+  A.leaf_sizes = m->leaf_sizes;
+  A.fixed = m->fixed;
+  A.unary = m->unary;
+  A.index = m->index;
+  A.zbits = m->zbits;
+  A.fixed_words = m->fixed_words;
+  A.unary_words = m->unary_words;
+  A.n_buckets = m->n_buckets;
+  A.seg = m->seg;
+  A.rmix = shockhash::fmix64((m->rho + 1) * kRetrievalMul);
+  A.leaf_target = m->leaf_target;
+  A.K = m->K;
+  hipLaunchKernelGGL(mphf_query_kernel, dim3(grid_for(n_queries, 256)), dim3(256), 0, (hipStream_t)hip_stream, A,
+                     queries, n_queries, positions);
+  HIP_TRY(hipGetLastError());
+  return SHOCK_OK;
+}
+
+int shock_mphf_info(const shock_mphf *m, shock_mphf_stats *info) {
+  if (!m || !info) return SHOCK_EINVAL;
+  memset(info, 0, sizeof(*info));
+  info->n_keys = m->n_keys;
+  info->n_buckets = m->n_buckets;
+  info->n_leaves = m->n_leaves;
+  info->rho = m->rho;
+  info->seg = m->seg;
+  info->max_sigma = m->max_sigma;
+  info->peel_rounds = m->peel_rounds;
+  info->seed_fixed_bits = m->fixed_bits;
+  info->seed_unary_bits = m->unary_bits;
+  info->bits_buckets = (m->n_buckets + 1) * 64 * 2 + m->n_buckets * 32;
+  info->bits_leaf_sizes = m->n_leaves * 8;
+  info->bits_seeds = m->fixed_bits + m->unary_bits + m->index_words * 64 + 65 * 8;
+  info->bits_retrieval = 3 * m->seg;
+  info->bits_total = info->bits_buckets + info->bits_leaf_sizes + info->bits_seeds + info->bits_retrieval;
+  info->build_ms = m->build_ms;
+  info->search_ms = m->search_ms;
+  return SHOCK_OK;
+}
+
+int shock_mphf_export(const shock_mphf *m, uint64_t *bucket_offset, uint64_t *leaf_base, uint32_t *sigma,
+                      uint8_t *leaf_sizes, uint64_t *leaf_seeds, uint8_t *cells) {
+  if (!m) return SHOCK_EINVAL;
+  const uint64_t B = m->n_buckets, L = m->n_leaves;
+  if (bucket_offset) HIP_TRY(hipMemcpy(bucket_offset, m->bucket_offset, (B + 1) * 8, hipMemcpyDeviceToHost));
+  if (leaf_base) HIP_TRY(hipMemcpy(leaf_base, m->leaf_base, (B + 1) * 8, hipMemcpyDeviceToHost));
+  if (sigma) HIP_TRY(hipMemcpy(sigma, m->sigma, B * 4, hipMemcpyDeviceToHost));
+  if (leaf_sizes && L) HIP_TRY(hipMemcpy(leaf_sizes, m->leaf_sizes, L, hipMemcpyDeviceToHost));
+  if (leaf_seeds && L) {
+    uint64_t *off = nullptr, *vals = nullptr;
+    HIP_TRY(hipMalloc((void **)&off, (L + 1) * 8));
+    hipError_t e = hipMalloc((void **)&vals, L * 8);
+    // leaf offsets from the sizes (host prefix sums)
+    uint8_t *hs = (uint8_t *)malloc(L);
+    uint64_t *ho = (uint64_t *)malloc((L + 1) * 8);
+    if (e == hipSuccess && hs && ho) e = hipMemcpy(hs, m->leaf_sizes, L, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && hs && ho) {
+      ho[0] = 0;
+      for (uint64_t g = 0; g < L; ++g) ho[g + 1] = ho[g] + hs[g];
+      e = hipMemcpy(off, ho, (L + 1) * 8, hipMemcpyHostToDevice);
+    }
+    int rc = SHOCK_OK;
+    if (e == hipSuccess && hs && ho)
+      rc = shock_rice_decode(m->fixed, m->fixed_words, m->unary, m->unary_words, m->index, off, L, m->K.k, vals,
+                             nullptr);
+    if (e == hipSuccess && rc == SHOCK_OK && hs && ho) e = hipMemcpy(leaf_seeds, vals, L * 8, hipMemcpyDeviceToHost);
+    free(hs);
+    free(ho);
+    (void)hipFree(off);
+    if (vals) (void)hipFree(vals);
+    if (!hs || !ho) return SHOCK_ENOMEM;
+    HIP_TRY(e);
+    if (rc != SHOCK_OK) return rc;
+  }
+  if (cells) {
+    const uint64_t n = 3 * m->seg;
+    uint64_t *w = (uint64_t *)malloc(m->zwords * 8);
+    if (!w) return SHOCK_ENOMEM;
+    hipError_t e = hipMemcpy(w, m->zbits, m->zwords * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      for (uint64_t c = 0; c < n; ++c) cells[c] = (uint8_t)((w[c >> 6] >> (c & 63)) & 1);
+    free(w);
+    HIP_TRY(e);
+  }
+  return SHOCK_OK;
+}
+
+int shock_mphf_destroy(shock_mphf *m) {
+  free_mphf(m);
+  return SHOCK_OK;
+}
+
+}  // extern "C"

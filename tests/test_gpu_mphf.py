@@ -1,0 +1,123 @@
+"""GPU parity of the flat ShockHash MPHF (include/shockmphf.h) against the
+oracle: every stored part bit-exact (bucket offsets, leaf bases, splitting
+seeds, leaf sizes, leaf seeds, retrieval seed and cells), every key's
+position equal, and the bijection onto [0, N) at full size."""
+import numpy as np
+import pytest
+
+from workloads import splitmix64
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(bucket_size=300, leaf_target=12, leaf_max=18)
+
+
+@pytest.fixture(scope="module")
+def shock():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_09561_amd as shock
+    shock.lib()
+    return shock
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def _host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def _build(shock, keys, **params):
+    print(f"[gpu] mphf build N={len(keys)} {params}", flush=True)
+    k = _dev(keys) if len(keys) else torch.zeros(0, dtype=torch.int64, device="cuda")
+    m = shock.MPHF(k, **params)
+    torch.cuda.synchronize()
+    return m, k
+
+
+@pytest.mark.parametrize("N", [1, 2, 17, 1000, 6000])
+def test_mphf_matches_oracle(shock, oracle_mod, N):
+    keys = splitmix64(2100 + N, N)
+    m, k = _build(shock, keys, **SMALL)
+    try:
+        rc, lay = oracle_mod.mphf_build(keys, **SMALL)
+        assert rc == 0
+        ex = m.export()
+        assert (ex["bucket_offset"] == lay["bucket_offset"]).all()
+        assert (ex["leaf_base"] == lay["leaf_base"]).all()
+        assert (ex["sigma"] == lay["sigma"]).all()
+        assert (ex["leaf_sizes"] == lay["leaf_sizes"]).all()
+        assert (ex["seeds"] == lay["seeds"]).all()
+        assert ex["rho"] == lay["rho"] and (ex["z"] == lay["z"]).all()
+        pos = _host(m.query(k))
+        torch.cuda.synchronize()
+        assert (pos == lay["positions"]).all()
+        assert sorted(pos.tolist()) == list(range(N))
+    finally:
+        m.close()
+
+
+def test_mphf_default_parameters_full_size(shock, oracle_mod):
+    """200,000 keys with the default layout (buckets of 2000, leaves of 40 on
+    average, at most 56): the layout equals the oracle's split, a sample of
+    leaves has the oracle's seeds, the oracle's query over the exported
+    structure equals the GPU query for every key, and the positions are a
+    permutation of [0, N)."""
+    N = 200_000
+    keys = splitmix64(2200, N)
+    m, k = _build(shock, keys)
+    try:
+        info = m.info()
+        print(f"[gpu] mphf info {info}", flush=True)
+        assert info["n_keys"] == N and 1.5 < info["bits_per_key"] < 2.6
+        pos_t = m.query(k)
+        srt, _ = torch.sort(pos_t)
+        assert torch.equal(srt, torch.arange(N, device="cuda", dtype=torch.int64))
+        ex = m.export()
+        rc, lay = oracle_mod.mphf_split(keys, 2000, 40, 56)
+        assert rc == 0
+        for f in ("bucket_offset", "leaf_base", "sigma", "leaf_sizes"):
+            assert (ex[f] == lay[f]).all(), f
+        offs = lay["leaf_offsets"]
+        pick = np.random.default_rng(2201).choice(lay["n_leaves"], 24, replace=False)
+        for j in pick:
+            _, s, _ = oracle_mod.leaf_search(lay["leaf_keys"], offs[j:j + 2])
+            assert int(s[0]) == int(ex["seeds"][j]), j
+        struct = dict(lay, seeds=ex["seeds"], rho=ex["rho"], z=ex["z"], leaf_target=40)
+        rc, want = oracle_mod.mphf_query(struct, keys)
+        assert rc == 0 and (_host(pos_t) == want).all()
+    finally:
+        m.close()
+
+
+def test_mphf_queries_of_other_keys_stay_in_range(shock):
+    keys = splitmix64(2300, 5000)
+    m, k = _build(shock, keys, **SMALL)
+    try:
+        others = _dev(splitmix64(2301, 4000))
+        p = _host(m.query(others))
+        assert ((p < 5000) | (p == np.uint64(0xFFFFFFFFFFFFFFFF))).all()
+    finally:
+        m.close()
+
+
+def test_mphf_errors(shock):
+    keys = np.concatenate([splitmix64(2400, 500), splitmix64(2400, 3)])  # three keys repeat
+    with pytest.raises(shock.ShockError) as e:
+        _build(shock, keys, **SMALL)
+    assert e.value.status == shock.SHOCK_EDUPKEY
+    for bad in (dict(bucket_size=0), dict(leaf_target=60, leaf_max=56), dict(leaf_max=65)):
+        with pytest.raises(shock.ShockError) as e:
+            _build(shock, splitmix64(2401, 100), **bad)
+        assert e.value.status == shock.SHOCK_EINVAL
+    m, _ = _build(shock, np.zeros(0, np.uint64), **SMALL)
+    try:
+        assert m.info()["n_keys"] == 0
+        p = _host(m.query(_dev(splitmix64(2402, 10))))
+        assert (p == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
+    finally:
+        m.close()
