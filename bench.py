@@ -143,6 +143,8 @@ def main():
                     help="timed steps of the rotation-fitting search on the same batch (0 = skip)")
     ap.add_argument("--code-leaves", type=int, default=1 << 21,
                     help="leaves of 48 keys for the query and seed-code legs (0 = skip)")
+    ap.add_argument("--mphf-keys", type=int, default=1 << 22,
+                    help="keys of the flat MPHF build and query leg (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -350,6 +352,54 @@ def main():
             f"encode {enc_ms:.2f} ms, decode {d_ms:.3f} ms, {code['rice']['bits_per_leaf']:.2f} bits/leaf")
         del keys_q, pos_q
 
+    # A complete flat MPHF over uniform keys: build (layout, leaf searches,
+    # seed codes, retrieval) and query of every key, with plain and with
+    # rotation-fitting leaves.
+    mphf = None
+    if args.mphf_keys > 0:
+        Nm = args.mphf_keys
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(2222)
+        keys_m = torch.randint(-(1 << 63), (1 << 63) - 1, (Nm,), generator=gen, device=dev, dtype=torch.int64)
+        pos_m = torch.empty(Nm, dtype=torch.int64, device=dev)
+        stream = torch.cuda.current_stream(dev)
+        mphf = {"keys": Nm, "params": {"bucket_size": 2000, "leaf_target": 40, "leaf_max": 56}}
+        for mode, rf_leaves in (("plain", False), ("rotation_fitting", True)):
+            log(f"[bench] flat MPHF of {Nm} keys, {mode} leaves")
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            m = shock.MPHF(keys_m, rotation_fitting=rf_leaves)  # the first build also loads the kernels
+            cold_s = time.perf_counter() - t4
+            m.close()
+            t4 = time.perf_counter()
+            m = shock.MPHF(keys_m, rotation_fitting=rf_leaves)
+            build_s = time.perf_counter() - t4
+            info = m.info()
+            m.query(keys_m, out=pos_m)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(5):
+                m.query(keys_m, out=pos_m)
+            e1.record(stream)
+            e1.synchronize()
+            q_ms = e0.elapsed_time(e1) / 5
+            srt, _ = torch.sort(pos_m)
+            ok = bool(torch.equal(srt, torch.arange(Nm, device=dev, dtype=torch.int64)))
+            m.close()
+            mphf[mode] = {
+                "build_s": build_s, "build_keys_per_s": Nm / build_s, "first_build_s": cold_s,
+                "phases_ms": {k: info[k] for k in ("layout_ms", "search_call_ms", "codes_ms", "retrieval_ms")},
+                "leaf_search_kernel_ms": info["search_ms"], "bits_per_key": info["bits_per_key"],
+                "bits_per_key_parts": {k: info[k] / Nm for k in ("bits_buckets", "bits_leaf_sizes", "bits_seeds",
+                                                                 "bits_retrieval")},
+                "n_leaves": info["n_leaves"], "peel_rounds": info["peel_rounds"], "max_sigma": info["max_sigma"],
+                "query_ms": q_ms, "query_keys_per_s": Nm / (q_ms / 1e3), "bijection": ok}
+            log(f"[bench]   build {build_s * 1e3:.1f} ms ({Nm / build_s:.3g} keys/s, leaf search "
+                f"{info['search_ms']:.1f} ms), {info['bits_per_key']:.3f} bits/key, query {q_ms:.3f} ms, "
+                f"bijection {ok}")
+        del keys_m, pos_m
+
     # Serving: MPHF-build requests (log-uniform 1e3..1e6 keys, Poisson
     # arrivals) cut into 48-key leaves, continuous batching over 4 streams
     # within a 256 MiB HBM budget.  Two runs over the same first K requests:
@@ -376,6 +426,23 @@ def main():
             log(f"[bench]   p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, {summ['keys_per_s']:.3g} keys/s")
         latency["p50_ms"] = latency["rate_70pct_capacity"]["p50_ms"]
         latency["p99_ms"] = latency["rate_70pct_capacity"]["p99_ms"]
+        if mphf is not None:
+            # The same requests served as complete MPHF builds, at 70% of the
+            # measured build capacity in keys/s.
+            from paper_2308_09561_amd.serving import MphfServer
+            reqs = synthetic_stream(args.serve_requests, rate_per_s=1.0, seed=5)
+            mean_keys = float(np.mean([len(r.keys) for r in reqs]))
+            rate = 0.7 * mphf["rotation_fitting"]["build_keys_per_s"] / mean_keys
+            reqs = synthetic_stream(args.serve_requests, rate_per_s=rate, seed=5)
+            srv = MphfServer(hbm_budget_bytes=256 << 20, slots=4, rotation_fitting=True)
+            log(f"[bench] MPHF serving: {len(reqs)} requests at {rate:.1f}/s")
+            rep_m = srv.run(reqs, realtime=True)
+            srv.close()
+            summ = rep_m.summary()
+            summ["rate_per_s"] = rate
+            latency["mphf_builds_70pct_capacity"] = summ
+            log(f"[bench]   p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, {summ['keys_per_s']:.3g} keys/s, "
+                f"{summ.get('bits_per_key', 0):.3f} bits/key")
 
     cpu = None
     if not args.no_cpu:
@@ -409,6 +476,7 @@ def main():
         "latency": latency,
         "rotation_fitting": rf,
         "leaf_query_and_codes": code,
+        "flat_mphf": mphf,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                      "unit": "Tops/s (int32 lane ops)", "frac": achieved / PEAK_INT_OPS,
                      "traffic": measured_traffic(args.workload),

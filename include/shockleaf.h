@@ -37,9 +37,10 @@
  * 64-bit patterns.  A leaf with n = 0 or n = 1 is solved by the first seed
  * tried (start_seed) with orientation 0.
  *
- * Thread safety: calls on different streams may run concurrently; each call
- * uses its own scratch.  The library keeps per-device scratch caches that are
- * freed at unload or by shock_release_scratch().
+ * Thread safety: synchronous calls from different host threads (on
+ * different streams) may run concurrently: each host thread keeps its own
+ * per-device scratch cache, held until the process ends or until that thread
+ * calls shock_release_scratch().
  */
 #ifndef SHOCKLEAF_H
 #define SHOCKLEAF_H
@@ -136,7 +137,7 @@ int shock_last_stats(shock_stats *out);
 const char *shock_last_error(void);
 const char *shock_strerror(int status);
 
-/* Free cached scratch memory of the current device. */
+/* Free the calling thread's cached scratch memory of the current device. */
 int shock_release_scratch(void);
 
 /* Library version of the frozen hash/orientation definition (1). */

@@ -15,8 +15,10 @@
  *     (a per-bucket seed bounding leaf sizes, one of the measures Appendix A.4
  *     lists);
  *   - a leaf's keys, sorted ascending, get the smallest ShockHash seed and the
- *     canonical orientation of shock_leaf_search (include/shockleaf.h);
- *   - the leaf seeds are Golomb-Rice coded (include/shockcode.h) with the
+ *     canonical orientation of shock_leaf_search (include/shockleaf.h), or
+ *     with rotation_fitting the smallest candidate (s, r) of
+ *     shock_rf_leaf_search_ex, stored as the value v = s * n + r;
+ *   - the leaf values are Golomb-Rice coded (include/shockcode.h) with the
  *     caller's table of Rice parameters by leaf size;
  *   - each key's choice f(x) is stored in a 1-bit retrieval structure: a
  *     3-hypergraph XOR system over 3 * seg cells, seg = ceil(1.23 N / 3) + 8,
@@ -48,7 +50,9 @@ typedef struct {
   uint32_t leaf_max;    /* largest leaf, at most 64; default 56 */
   uint32_t max_rho_tries; /* retrieval seeds tried; default 64 */
   const uint8_t *rice_k_by_n; /* HOST u8[65]: Rice parameter by leaf size (each at most 56); copied at build */
-  uint64_t reserved[4];
+  uint32_t rotation_fitting; /* 1: leaves use rotation fitting (Section 4); default 0 */
+  int32_t partial_k;         /* rotation fitting's partial-hash period: 0 (8 above 32 keys, else 1), 1 or 8 */
+  uint64_t reserved[3];
 } shock_mphf_params;
 
 typedef struct shock_mphf shock_mphf;
@@ -65,6 +69,11 @@ typedef struct {
   uint64_t bits_buckets, bits_leaf_sizes, bits_seeds, bits_retrieval, bits_total;
   double build_ms;       /* wall time of the build call */
   double search_ms;      /* of which the leaf search (kernel time) */
+  /* wall time of the build's phases: bucket and leaf layout (with the leaf
+   * sorts), the leaf search call, the seed codes, the retrieval */
+  double layout_ms, search_call_ms, codes_ms, retrieval_ms;
+  uint32_t rho_tries;    /* retrieval seeds tried */
+  uint32_t reserved0;
 } shock_mphf_stats;
 
 /* Defaults as documented above; rice_k_by_n = NULL. */
@@ -90,8 +99,8 @@ int shock_mphf_info(const shock_mphf *m, shock_mphf_stats *info);
 
 /* Copy the stored parts to HOST arrays (any pointer may be NULL): bucket
  * offsets u64[B+1], leaf bases u64[B+1], splitting seeds u32[B], leaf sizes
- * u8[n_leaves], leaf seeds u64[n_leaves] (decoded), retrieval cells u8[3 * seg]
- * (one per byte). */
+ * u8[n_leaves], leaf values u64[n_leaves] (decoded: seeds, or s * n + r under
+ * rotation fitting), retrieval cells u8[3 * seg] (one per byte). */
 int shock_mphf_export(const shock_mphf *m, uint64_t *bucket_offset, uint64_t *leaf_base, uint32_t *sigma,
                       uint8_t *leaf_sizes, uint64_t *leaf_seeds, uint8_t *cells);
 

@@ -92,8 +92,8 @@ def lib():
         L.shock_oracle_xor_get.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, _u8p, _u8p]
         L.shock_oracle_mphf_query.restype = ctypes.c_int
         L.shock_oracle_mphf_query.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
-                                              ctypes.c_uint64, _u64p, _u64p, _u32p, _u8p, _u64p, ctypes.c_uint64,
-                                              _u8p, _u64p]
+                                              ctypes.c_uint64, _u64p, _u64p, _u32p, _u8p, _u64p, ctypes.c_int,
+                                              ctypes.c_uint32, ctypes.c_uint64, _u8p, _u64p]
         L.shock_oracle_seed_stats.restype = None
         L.shock_oracle_seed_stats.argtypes = [_u64p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                               _u64p, _u64p, _u64p]
@@ -355,15 +355,22 @@ def xor_get(keys, rho: int, z):
     return out[:keys.size]
 
 
-def mphf_build(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: int = 56):
+def mphf_build(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: int = 56, rf: bool = False,
+               partial_k: int = 0):
     """The whole flat MPHF: layout, leaf seeds and orientations (the leaf
-    search), the retrieval of each key's choice, and every key's position
-    (index i of the input keys -> positions[i])."""
+    search, or rotation fitting with values s * n + r), the retrieval of each
+    key's choice, and every key's position (index i of the input keys ->
+    positions[i])."""
     rc, lay = mphf_split(keys, bucket_size, leaf_target, leaf_max)
     if rc != OK:
         return rc, None
     lk, offs = lay["leaf_keys"], lay["leaf_offsets"]
-    rc, seeds, orient = leaf_search(lk, offs)
+    if rf:
+        rc, s_rf, rot, orient = rf_leaf_search(lk, offs, partial_k=partial_k)
+        sizes_u = lay["leaf_sizes"].astype(np.uint64)
+        seeds = np.where(sizes_u >= 2, s_rf * sizes_u + rot.astype(np.uint64), s_rf)
+    else:
+        rc, seeds, orient = leaf_search(lk, offs)
     if rc != OK:
         return rc, None
     sizes = lay["leaf_sizes"].astype(np.int64)
@@ -374,11 +381,15 @@ def mphf_build(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: i
     rc, rho, z = xor_build(lk, f)
     if rc != OK:
         return rc, None
-    _, pos_leaf_order = leaf_query(lk, offs, seeds, orient)
+    if rf:
+        _, pos_leaf_order = rf_leaf_query(lk, offs, s_rf, rot, orient, partial_k=partial_k)
+    else:
+        _, pos_leaf_order = leaf_query(lk, offs, seeds, orient)
     positions = np.zeros(lk.size, np.uint64)
     positions[lay["key_index"].astype(np.int64)] = pos_leaf_order
     lay.update({"seeds": seeds, "orient": orient, "choice": f, "rho": rho, "z": z, "positions": positions,
-                "leaf_target": leaf_target, "leaf_max": leaf_max, "bucket_size": bucket_size})
+                "leaf_target": leaf_target, "leaf_max": leaf_max, "bucket_size": bucket_size, "rf": bool(rf),
+                "partial_k": partial_k})
     return OK, lay
 
 
@@ -389,7 +400,9 @@ def mphf_query(lay, queries):
     N = lay["leaf_keys"].size
     rc = lib().shock_oracle_mphf_query(_p64(q), q.size, N, lay["leaf_target"], lay["n_buckets"],
                                        _p64(lay["bucket_offset"]), _p64(lay["leaf_base"]), _p32(lay["sigma"]),
-                                       _p8(np.ascontiguousarray(lay["leaf_sizes"])), _p64(lay["seeds"]),
-                                       lay["rho"], _p8(lay["z"]), _p64(out))
+                                       _p8(np.ascontiguousarray(lay["leaf_sizes"])),
+                                       _p64(np.ascontiguousarray(lay["seeds"], dtype=np.uint64)),
+                                       int(lay.get("rf", False)), lay.get("partial_k", 0), lay["rho"], _p8(lay["z"]),
+                                       _p64(out))
     return rc, out[:q.size]
 

@@ -205,11 +205,13 @@ int shock_oracle_xor_get(const uint64_t *keys, uint64_t n_keys, uint64_t rho, co
 /* The MPHF's value of each query key (which must be one of the built keys):
  * bucket, splitting seed, leaf and its key offset, then the leaf query
  * offset + h_{f(x)}(x, seed) with f(x) read from the retrieval structure.
- * leaf_seeds u64[n_leaves]: the leaf search's seeds. */
+ * leaf_values u64[n_leaves]: the leaf search's seeds, or with rf = 1 the
+ * rotation-fitting candidates stored as s * n + r (slots of
+ * shock_oracle_rf_slots with period partial_k; 0 = 8 above 32 keys, else 1). */
 int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_t n_keys, uint32_t leaf_target,
                             uint64_t n_buckets, const uint64_t *bucket_offset, const uint64_t *leaf_base,
-                            const uint32_t *sigma, const uint8_t *leaf_sizes, const uint64_t *leaf_seeds,
-                            uint64_t rho, const uint8_t *z, uint64_t *out_pos);
+                            const uint32_t *sigma, const uint8_t *leaf_sizes, const uint64_t *leaf_values,
+                            int rf, uint32_t partial_k, uint64_t rho, const uint8_t *z, uint64_t *out_pos);
 
 /* Statistics helper: over seeds s0 .. s0+count-1 of one leaf of n keys, count
  * the seeds whose slots cover all n cells and, among them, the pseudoforests.

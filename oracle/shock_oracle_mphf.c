@@ -204,8 +204,8 @@ int shock_oracle_xor_get(const uint64_t *keys, uint64_t n_keys, uint64_t rho, co
 
 int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_t n_keys, uint32_t leaf_target,
                             uint64_t n_buckets, const uint64_t *bucket_offset, const uint64_t *leaf_base,
-                            const uint32_t *sigma, const uint8_t *leaf_sizes, const uint64_t *leaf_seeds,
-                            uint64_t rho, const uint8_t *z, uint64_t *out_pos) {
+                            const uint32_t *sigma, const uint8_t *leaf_sizes, const uint64_t *leaf_values,
+                            int rf, uint32_t partial_k, uint64_t rho, const uint8_t *z, uint64_t *out_pos) {
   uint64_t seg = shock_oracle_xor_segment(n_keys);
   for (uint64_t q = 0; q < n_queries; ++q) {
     uint64_t x = queries[q];
@@ -224,7 +224,13 @@ int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_
     xor_cells(x, rho, seg, c);
     int f = z[c[0]] ^ z[c[1]] ^ z[c[2]];
     uint32_t h0 = 0, h1 = 0;
-    if (n >= 1) shock_oracle_slots(x, leaf_seeds[leaf_base[b] + j], n, &h0, &h1);
+    uint64_t v = leaf_values[leaf_base[b] + j];
+    if (rf && n >= 2) {
+      uint32_t k = partial_k ? partial_k : (n > 32 ? 8u : 1u);
+      shock_oracle_rf_slots(x, v / n, (uint32_t)(v % n), k, n, &h0, &h1);
+    } else if (n >= 1) {
+      shock_oracle_slots(x, v, n, &h0, &h1);
+    }
     out_pos[q] = start + (f ? h1 : h0);
   }
   return SHOCK_ORACLE_OK;

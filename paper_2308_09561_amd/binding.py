@@ -76,7 +76,9 @@ class MphfParams(ctypes.Structure):
         ("leaf_max", ctypes.c_uint32),
         ("max_rho_tries", ctypes.c_uint32),
         ("rice_k_by_n", ctypes.c_void_p),
-        ("reserved", ctypes.c_uint64 * 4),
+        ("rotation_fitting", ctypes.c_uint32),
+        ("partial_k", ctypes.c_int32),
+        ("reserved", ctypes.c_uint64 * 3),
     ]
 
 
@@ -89,6 +91,8 @@ class MphfStats(ctypes.Structure):
         ("bits_buckets", ctypes.c_uint64), ("bits_leaf_sizes", ctypes.c_uint64), ("bits_seeds", ctypes.c_uint64),
         ("bits_retrieval", ctypes.c_uint64), ("bits_total", ctypes.c_uint64),
         ("build_ms", ctypes.c_double), ("search_ms", ctypes.c_double),
+        ("layout_ms", ctypes.c_double), ("search_call_ms", ctypes.c_double), ("codes_ms", ctypes.c_double),
+        ("retrieval_ms", ctypes.c_double), ("rho_tries", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
     ]
 
     def as_dict(self):
@@ -487,7 +491,8 @@ class MPHF:
     """A minimal perfect hash function of distinct uint64 keys, built and
     queried on the GPU.  Raises ShockError if the build fails."""
 
-    def __init__(self, keys, bucket_size=2000, leaf_target=40, leaf_max=56, rice_table=None, stream=None):
+    def __init__(self, keys, bucket_size=2000, leaf_target=40, leaf_max=56, rice_table=None, stream=None,
+                 rotation_fitting=False, partial_k=0):
         import numpy as np
         if keys.device.type != "cuda" or keys.dtype.itemsize != 8:
             raise ValueError("keys must be a 64-bit device tensor")
@@ -498,6 +503,7 @@ class MPHF:
         p = MphfParams()
         lib().shock_mphf_params_init(ctypes.byref(p))
         p.bucket_size, p.leaf_target, p.leaf_max = bucket_size, leaf_target, leaf_max
+        p.rotation_fitting, p.partial_k = int(bool(rotation_fitting)), partial_k
         table = _table(rice_table)
         p.rice_k_by_n = ctypes.cast(table, ctypes.c_void_p)
         self._h = ctypes.c_void_p()

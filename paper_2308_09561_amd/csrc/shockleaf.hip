@@ -1198,21 +1198,21 @@ int status_from(const unsigned long long *host_ctr, shock_stats *st) {
   return SHOCK_OK;
 }
 
-// Per-device scratch cache of the synchronous entry points.
+// Scratch cache of the synchronous entry points, per host thread and device:
+// a synchronous call holds its scratch until it returns, so calls from
+// different threads must not share it.
 struct Scratch {
   void *buf = nullptr;
   size_t bytes = 0;
   void *host_ctr = nullptr;  // pinned copy of the global counters
 };
-std::mutex g_mu;
-std::vector<Scratch> g_scratch;
+thread_local std::vector<Scratch> t_scratch;
 
 int get_scratch(size_t bytes, void **buf, unsigned long long **host_ctr) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(g_mu);
-  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1);
-  Scratch &s = g_scratch[dev];
+  if ((int)t_scratch.size() <= dev) t_scratch.resize(dev + 1);
+  Scratch &s = t_scratch[dev];
   if (s.host_ctr == nullptr) {
     hipError_t e = hipHostMalloc(&s.host_ctr, kCtrGlobalCount * 8, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -1294,12 +1294,11 @@ int shock_last_stats(shock_stats *out) {
 int shock_release_scratch(void) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(g_mu);
-  if ((int)g_scratch.size() > dev && g_scratch[dev].buf) {
+  if ((int)t_scratch.size() > dev && t_scratch[dev].buf) {
     HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipFree(g_scratch[dev].buf));
-    g_scratch[dev].buf = nullptr;
-    g_scratch[dev].bytes = 0;
+    HIP_TRY(hipFree(t_scratch[dev].buf));
+    t_scratch[dev].buf = nullptr;
+    t_scratch[dev].bytes = 0;
   }
   return SHOCK_OK;
 }

@@ -254,6 +254,16 @@ __global__ __launch_bounds__(256) void leaf_sort_kernel(uint64_t *keys, const ui
   }
 }
 
+// Rotation fitting: a leaf's stored value is its candidate index s * n + r.
+__global__ void rf_values_kernel(uint64_t *seeds, const uint32_t *__restrict__ rot,
+                                 const uint8_t *__restrict__ leaf_sizes, uint64_t n_leaves) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_leaves; g += stride) {
+    const uint32_t n = leaf_sizes[g];
+    if (n >= 2 && seeds[g] != kNone) seeds[g] = seeds[g] * n + rot[g];
+  }
+}
+
 // ---- retrieval ------------------------------------------------------------------
 
 __global__ void choice_kernel(const uint64_t *__restrict__ leaf_off, const uint8_t *__restrict__ leaf_sizes,
@@ -355,6 +365,7 @@ struct QueryArgs {
   uint64_t fixed_words, unary_words;
   uint64_t n_buckets, seg, rmix;
   uint32_t leaf_target;
+  uint32_t rf, partial_k;
   KTable K;
 };
 
@@ -411,7 +422,7 @@ __global__ __launch_bounds__(256) void mphf_query_kernel(QueryArgs A, const uint
     const uint32_t i = (uint32_t)(g & 63);
     const uint64_t end = select_one(A.unary, A.unary_words, U0, i);
     const uint64_t begin = i == 0 ? U0 : select_one(A.unary, A.unary_words, U0, i - 1) + 1;
-    const uint64_t seed = end == kNone ? kNone : (((end - begin) << k) | low);
+    const uint64_t value = end == kNone ? kNone : (((end - begin) << k) | low);
     // the choice from the retrieval cells
     uint64_t c[3];
     xor_cells(x, A.rmix, A.seg, c);
@@ -419,8 +430,18 @@ __global__ __launch_bounds__(256) void mphf_query_kernel(QueryArgs A, const uint
                                    (A.zbits[c[2] >> 6] >> (c[2] & 63))) & 1);
     uint32_t h0 = 0, h1 = 0;
     if (n >= 2) {
+      uint64_t seed = value;
+      uint32_t r = 0;
+      if (A.rf) {  // value = s * n + r; the first set hashes with s - s mod k
+        seed = value / n;
+        const uint32_t pk = A.partial_k ? A.partial_k : (n > 32 ? 8u : 1u);
+        if (shockhash::key_side(x)) r = (uint32_t)(value - seed * n);
+        else seed -= seed % pk;
+      }
       const uint64_t a = fmix64(x), ts = seed_mix(seed);
       slot_pair((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)ts, (uint32_t)(ts >> 32), n, n - 1, h0, h1);
+      h0 = h0 + r >= n ? h0 + r - n : h0 + r;
+      h1 = h1 + r >= n ? h1 + r - n : h1 + r;
     }
     out[t] = o + start + (f ? h1 : h0);
   }
@@ -437,6 +458,7 @@ int grid_for(uint64_t items, uint32_t per_block) {
 struct shock_mphf {
   uint64_t n_keys = 0, n_buckets = 0, n_leaves = 0;
   uint32_t leaf_target = 0, leaf_max = 0, bucket_size = 0;
+  uint32_t rf = 0, partial_k = 0;
   uint64_t rho = 0, seg = 0;
   uint32_t max_sigma = 0, peel_rounds = 0;
   KTable K{};
@@ -447,6 +469,8 @@ struct shock_mphf {
   uint64_t fixed_words = 0, unary_words = 0, index_words = 0, zwords = 0;
   uint64_t fixed_bits = 0, unary_bits = 0;
   double build_ms = 0, search_ms = 0;
+  double layout_ms = 0, search_call_ms = 0, codes_ms = 0, retrieval_ms = 0;
+  uint32_t rho_tries = 0;
 };
 
 namespace {
@@ -490,9 +514,14 @@ void free_mphf(shock_mphf *m) {
     }                                       \
   } while (0)
 
+static double ms_since(std::chrono::steady_clock::time_point t) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+}
+
 static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params &P, shock_mphf *M,
                       hipStream_t stream) {
   Scratch S;
+  auto tp = std::chrono::steady_clock::now();
   const uint64_t B = N == 0 ? 1 : (N + P.bucket_size - 1) / P.bucket_size;
   M->n_keys = N;
   M->n_buckets = B;
@@ -544,6 +573,8 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   if (host[0] & kErrSigma) return SHOCK_ENOTFOUND;
   S.release(grouped);
   HIP_TRY(hipFree(grouped));
+  M->layout_ms = ms_since(tp);
+  tp = std::chrono::steady_clock::now();
 
   // leaf seeds and orientations
   uint64_t *seeds = nullptr, *orient = nullptr;
@@ -553,11 +584,26 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
     shock_opts o;
     shock_opts_init(&o);
     o.check_dups = 1;
-    const int rc = shock_leaf_search_ex(leaf_keys, leaf_off, L, seeds, orient, &o, stream);
+    int rc;
+    if (M->rf) {
+      uint32_t *rot = nullptr;
+      HIP_TRY(S.alloc(&rot, L));
+      o.partial_k = (int32_t)M->partial_k;
+      rc = shock_rf_leaf_search_ex(leaf_keys, leaf_off, L, seeds, rot, orient, &o, stream);
+      if (rc == SHOCK_OK) {
+        hipLaunchKernelGGL(rf_values_kernel, dim3(grid_for(L, 256)), dim3(256), 0, stream, seeds,
+                           (const uint32_t *)rot, (const uint8_t *)M->leaf_sizes, L);
+        HIP_TRY(hipGetLastError());
+      }
+    } else {
+      rc = shock_leaf_search_ex(leaf_keys, leaf_off, L, seeds, orient, &o, stream);
+    }
     if (rc != SHOCK_OK) return rc;
     shock_stats st;
     if (shock_last_stats(&st) == SHOCK_OK) M->search_ms = st.kernel_ms;
   }
+  M->search_call_ms = ms_since(tp);
+  tp = std::chrono::steady_clock::now();
   // Golomb-Rice codes of the seeds
   uint64_t bits[2] = {0, 0};
   const uint64_t n_blocks = (L + 63) / 64;
@@ -575,6 +621,8 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
                          bits, stream);
   if (rc != SHOCK_OK) return rc;
 
+  M->codes_ms = ms_since(tp);
+  tp = std::chrono::steady_clock::now();
   // retrieval of each key's choice
   uint8_t *choice = nullptr, *peel = nullptr, *z = nullptr;
   uint32_t *cnt = nullptr, *round = nullptr;
@@ -593,6 +641,7 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   uint32_t rounds = 0;
   for (uint32_t t = 0; t < P.max_rho_tries && !solved; ++t) {
     const uint64_t rho = t;
+    M->rho_tries = t + 1;
     const uint64_t rmix = shockhash::fmix64((rho + 1) * kRetrievalMul);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, cnt, cells, 0u);
     if (N) hipLaunchKernelGGL(xor_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg, cnt, round);
@@ -642,6 +691,7 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
     HIP_TRY(e);
   }
   HIP_TRY(hipStreamSynchronize(stream));
+  M->retrieval_ms = ms_since(tp);
   return SHOCK_OK;
 }
 
@@ -663,11 +713,14 @@ int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_par
   const shock_mphf_params &P = *params;
   if (P.bucket_size == 0 || P.leaf_target == 0 || P.leaf_max > 64 || P.leaf_target > P.leaf_max) return SHOCK_EINVAL;
   if (P.max_rho_tries == 0 || !P.rice_k_by_n || n_keys >= (1ull << 32)) return SHOCK_EINVAL;
+  if (P.rotation_fitting > 1 || (P.partial_k != 0 && P.partial_k != 1 && P.partial_k != 8)) return SHOCK_EINVAL;
   *out = nullptr;
   shock_mphf *M = new shock_mphf;
   M->leaf_target = P.leaf_target;
   M->leaf_max = P.leaf_max;
   M->bucket_size = P.bucket_size;
+  M->rf = P.rotation_fitting;
+  M->partial_k = (uint32_t)P.partial_k;
   for (int n = 0; n <= 64; ++n) {
     if (P.rice_k_by_n[n] > 56) {
       delete M;
@@ -706,6 +759,8 @@ int shock_mphf_query(const shock_mphf *m, const uint64_t *queries, uint64_t n_qu
   A.seg = m->seg;
   A.rmix = shockhash::fmix64((m->rho + 1) * kRetrievalMul);
   A.leaf_target = m->leaf_target;
+  A.rf = m->rf;
+  A.partial_k = m->partial_k;
   A.K = m->K;
   hipLaunchKernelGGL(mphf_query_kernel, dim3(grid_for(n_queries, 256)), dim3(256), 0, (hipStream_t)hip_stream, A,
                      queries, n_queries, positions);
@@ -732,6 +787,11 @@ int shock_mphf_info(const shock_mphf *m, shock_mphf_stats *info) {
   info->bits_total = info->bits_buckets + info->bits_leaf_sizes + info->bits_seeds + info->bits_retrieval;
   info->build_ms = m->build_ms;
   info->search_ms = m->search_ms;
+  info->layout_ms = m->layout_ms;
+  info->search_call_ms = m->search_call_ms;
+  info->codes_ms = m->codes_ms;
+  info->retrieval_ms = m->retrieval_ms;
+  info->rho_tries = m->rho_tries;
   return SHOCK_OK;
 }
 

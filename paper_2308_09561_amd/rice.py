@@ -16,6 +16,7 @@ Configuration only: nothing here runs on the search path.
 """
 from __future__ import annotations
 
+import functools
 import math
 from fractions import Fraction
 
@@ -57,6 +58,18 @@ def _unicyclic_weight(k: int) -> Fraction:
     return (functional - Fraction(k) ** (k - 1)) * 2 ** (k - 1) / math.factorial(k)
 
 
+@functools.lru_cache(maxsize=1)
+def _pseudoforest_series(n_max: int = 64) -> tuple:
+    """Coefficients of exp(sum_k w_k z^k) up to z^n_max (the exponential
+    formula); they do not depend on the leaf size."""
+    w = [Fraction(0)] + [_unicyclic_weight(k) for k in range(1, n_max + 1)]
+    series = [Fraction(1)] + [Fraction(0)] * n_max
+    for m in range(1, n_max + 1):
+        series[m] = sum(k * w[k] * series[m - k] for k in range(1, m + 1)) / m
+    return tuple(series)
+
+
+@functools.lru_cache(maxsize=None)
 def success_probability(n: int) -> float:
     """Probability that one seed of an n-key leaf qualifies under ideal
     loop-free hashing: a graph of n keys on n cells is a pseudoforest iff every
@@ -64,16 +77,18 @@ def success_probability(n: int) -> float:
     exponential formula over such components."""
     if n <= 1:
         return 1.0
-    w = [Fraction(0)] + [_unicyclic_weight(k) for k in range(1, n + 1)]
-    series = [Fraction(1)] + [Fraction(0)] * n
-    for m in range(1, n + 1):
-        series[m] = sum(k * w[k] * series[m - k] for k in range(1, m + 1)) / m
+    series = _pseudoforest_series(max(64, n))
     return float(Fraction(math.factorial(n)) ** 2 * series[n] / Fraction(n * (n - 1)) ** n)
 
 
 def plain_table() -> list[int]:
     """k per leaf size 0..64 for the plain search's seeds (start seed 0)."""
-    return [0 if n <= 1 else optimal_k(success_probability(n)) for n in range(65)]
+    return list(_plain_table())
+
+
+@functools.lru_cache(maxsize=1)
+def _plain_table() -> tuple:
+    return tuple(0 if n <= 1 else optimal_k(success_probability(n)) for n in range(65))
 
 
 def table_from_means(mean_by_n) -> list[int]:

@@ -19,16 +19,24 @@ Latency of a request = completion time - arrival time.  The device memory a
 request holds while admitted (its keys, offsets, outputs and its share of the
 search scratch) counts against the budget.  A request alone larger than the
 budget is rejected; a request still queued past its deadline times out.
+
+MphfServer serves the same requests with complete minimal perfect hash
+functions (the flat ShockHash MPHF of include/shockmphf.h): each request is
+one build on one of `slots` worker threads, each with its own HIP stream, so
+builds overlap on the GPU; admission follows the same budget and queue rules
+with the build's device footprint.
 """
 from __future__ import annotations
 
 import collections
+import threading
 import time
+from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor, wait
 from dataclasses import dataclass, field
 
 import numpy as np
 
-from .binding import SHOCK_OK, SearchContext
+from .binding import MPHF, SHOCK_OK, SearchContext
 
 SCRATCH_BYTES_PER_LEAF = 600  # premixed keys, claim word, best seed, counters
 
@@ -46,9 +54,12 @@ class Request:
     status: str = "queued"
     seeds: np.ndarray | None = None
     orient: np.ndarray | None = None
+    info: dict | None = None  # MPHF build figures (MphfServer)
 
     @property
     def n_leaves(self) -> int:
+        if self.offsets is None:
+            return int(self.info["n_leaves"]) if self.info else 0
         return len(self.offsets) - 1
 
     def latency(self) -> float | None:
@@ -95,6 +106,10 @@ class ServeReport:
         lat = np.array([r.latency() for r in done], dtype=np.float64)
         keys = float(sum(len(r.keys) for r in done))
         leaves = float(sum(r.n_leaves for r in done))
+        infos = [r.info for r in done if r.info]
+        if infos:
+            self.extra.setdefault("bits_per_key", float(sum(i["bits_total"] for i in infos) /
+                                                        max(sum(i["n_keys"] for i in infos), 1)))
         return {
             "requests": len(self.requests), "completed": len(done),
             "timed_out": sum(r.status == "timeout" for r in self.requests),
@@ -259,3 +274,114 @@ def synthetic_stream(n_requests: int, rate_per_s: float, seed: int = 5, min_keys
     for rid, (arr, n, kseed) in enumerate(serving_requests(n_requests, rate_per_s, seed, min_keys, max_keys)):
         out.append(Request(rid=rid, arrival=arr, keys=splitmix64(kseed, n), deadline=deadline))
     return out
+
+
+def mphf_footprint(n_keys: int) -> int:
+    """Device bytes an MPHF build of n_keys holds at its peak: the keys, two
+    reordered copies, leaf search outputs and scratch, and the retrieval's
+    counters, rounds, choices and cells (about 36 bytes per key)."""
+    leaves = n_keys // 8 + 1
+    return 24 * n_keys + (16 + SCRATCH_BYTES_PER_LEAF) * leaves + 12 * n_keys + (1 << 20)
+
+
+class MphfServer:
+    """Requests served as complete MPHF builds (see the module docstring)."""
+
+    def __init__(self, hbm_budget_bytes: int = 1 << 30, slots: int = 2, bucket_size: int = 2000,
+                 leaf_target: int = 40, leaf_max: int = 56, rice_table=None, verify: bool = False,
+                 rotation_fitting: bool = False, device: str = "cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.budget = int(hbm_budget_bytes)
+        self.slots = slots
+        self.params = dict(bucket_size=bucket_size, leaf_target=leaf_target, leaf_max=leaf_max, rice_table=rice_table,
+                           rotation_fitting=rotation_fitting)
+        self.verify = verify
+        self._local = threading.local()
+        self.pool = ThreadPoolExecutor(max_workers=slots)
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+
+    def _stream(self):
+        st = getattr(self._local, "stream", None)
+        if st is None:
+            st = self._local.stream = self.torch.cuda.Stream(device=self.device)
+        return st
+
+    def _build(self, r: Request, now_fn):
+        torch = self.torch
+        stream = self._stream()
+        with torch.cuda.stream(stream):
+            kh = torch.from_numpy(np.ascontiguousarray(r.keys).view(np.int64)).pin_memory()
+            kd = kh.to(self.device, non_blocking=True)
+            m = MPHF(kd, stream=stream.cuda_stream, **self.params)
+            try:
+                r.info = m.info()
+                if self.verify:
+                    pos = m.query(kd, stream=stream.cuda_stream)
+                    srt, _ = torch.sort(pos)
+                    ok = bool(torch.equal(srt, torch.arange(len(r.keys), device=self.device, dtype=torch.int64)))
+                    r.info["bijection"] = ok
+            finally:
+                m.close()
+            stream.synchronize()
+        r.completed = now_fn()
+        r.status = "done" if (not self.verify or r.info.get("bijection")) else "error bijection"
+        return r
+
+    def run(self, requests: list, realtime: bool = True) -> ServeReport:
+        for r in requests:
+            r.offsets = None
+            r.status = "queued"
+            r.admitted = r.completed = None
+            r.info = None
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queue = collections.deque()
+        inflight = {}
+        bytes_in_flight = max_bytes = max_batches = n_batches = 0
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0  # noqa: E731
+        while pending or queue or inflight:
+            t = now()
+            while pending and (not realtime or pending[0].arrival <= t):
+                queue.append(pending.popleft())
+            for fut in [f for f in inflight if f.done()]:
+                fut.result()  # re-raise build errors
+                bytes_in_flight -= inflight.pop(fut)
+            t = now()
+            queue = collections.deque(r for r in queue if not self._expired(r, t))
+            while queue and len(inflight) < self.slots:
+                r = queue[0]
+                fb = mphf_footprint(len(r.keys))
+                if fb > self.budget:
+                    queue.popleft()
+                    r.status = "rejected"
+                    continue
+                if bytes_in_flight + fb > self.budget:
+                    break
+                queue.popleft()
+                r.admitted = now()
+                r.status = "running"
+                inflight[self.pool.submit(self._build, r, now)] = fb
+                bytes_in_flight += fb
+                n_batches += 1
+                max_bytes = max(max_bytes, bytes_in_flight)
+                max_batches = max(max_batches, len(inflight))
+            if inflight:
+                wait(list(inflight), timeout=0.0005, return_when=FIRST_COMPLETED)
+            elif pending:
+                time.sleep(max(0.0, min(0.001, pending[0].arrival - now())))
+        return ServeReport(requests=list(requests), makespan_s=now(), max_bytes_in_flight=max_bytes,
+                           max_batches_in_flight=max_batches, batches=n_batches)
+
+    @staticmethod
+    def _expired(r: Request, t: float) -> bool:
+        if r.deadline is not None and t - r.arrival > r.deadline:
+            r.status = "timeout"
+            r.completed = None
+            return True
+        return False
+

@@ -39,12 +39,13 @@ def _build(shock, keys, **params):
     return m, k
 
 
+@pytest.mark.parametrize("rf", [False, True], ids=["plain", "rf"])
 @pytest.mark.parametrize("N", [1, 2, 17, 1000, 6000])
-def test_mphf_matches_oracle(shock, oracle_mod, N):
+def test_mphf_matches_oracle(shock, oracle_mod, N, rf):
     keys = splitmix64(2100 + N, N)
-    m, k = _build(shock, keys, **SMALL)
+    m, k = _build(shock, keys, rotation_fitting=rf, **SMALL)
     try:
-        rc, lay = oracle_mod.mphf_build(keys, **SMALL)
+        rc, lay = oracle_mod.mphf_build(keys, rf=rf, **SMALL)
         assert rc == 0
         ex = m.export()
         assert (ex["bucket_offset"] == lay["bucket_offset"]).all()
@@ -119,5 +120,79 @@ def test_mphf_errors(shock):
         assert m.info()["n_keys"] == 0
         p = _host(m.query(_dev(splitmix64(2402, 10))))
         assert (p == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
+    finally:
+        m.close()
+
+
+def test_concurrent_builds_and_searches_from_threads(shock):
+    """Synchronous calls from several host threads on their own streams run
+    concurrently; each thread keeps its own scratch, so results equal the
+    serial ones."""
+    from concurrent.futures import ThreadPoolExecutor
+    from workloads import fixed_leaves
+
+    batches = [fixed_leaves(256, 30 + i, 2500 + i) for i in range(4)]
+
+    def search(i):
+        keys, offs = batches[i]
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            rc, s, f = shock.leaf_search(_dev(keys), _dev(offs), stream=stream.cuda_stream)
+            stream.synchronize()
+        return rc, _host(s), _host(f)
+
+    print("[gpu] serial searches", flush=True)
+    serial = [search(i) for i in range(4)]
+    print("[gpu] threaded searches", flush=True)
+    with ThreadPoolExecutor(4) as ex:
+        threaded = list(ex.map(search, range(4)))
+    for a, b in zip(serial, threaded):
+        assert a[0] == b[0] == 0 and (a[1] == b[1]).all() and (a[2] == b[2]).all()
+
+    def build(i):
+        keys = splitmix64(2600 + i, 3000 + 500 * i)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            k = _dev(keys)
+            m = shock.MPHF(k, stream=stream.cuda_stream, **SMALL)
+            p = _host(m.query(k, stream=stream.cuda_stream))
+            stream.synchronize()
+            m.close()
+        return p
+
+    print("[gpu] threaded builds", flush=True)
+    with ThreadPoolExecutor(3) as ex:
+        outs = list(ex.map(build, range(3)))
+    for i, p in enumerate(outs):
+        assert sorted(p.tolist()) == list(range(3000 + 500 * i))
+        assert (p == build(i)).all()
+
+
+def test_mphf_rotation_fitting_full_size(shock, oracle_mod):
+    """200,000 keys, default layout, rotation-fitting leaves: the oracle's
+    query over the exported structure equals the GPU query for every key, a
+    sample of leaves has the oracle's candidates, and the positions are a
+    permutation of [0, N)."""
+    N = 200_000
+    keys = splitmix64(2700, N)
+    m, k = _build(shock, keys, rotation_fitting=True)
+    try:
+        pos_t = m.query(k)
+        srt, _ = torch.sort(pos_t)
+        assert torch.equal(srt, torch.arange(N, device="cuda", dtype=torch.int64))
+        ex = m.export()
+        rc, lay = oracle_mod.mphf_split(keys, 2000, 40, 56)
+        assert rc == 0
+        for f in ("bucket_offset", "leaf_base", "sigma", "leaf_sizes"):
+            assert (ex[f] == lay[f]).all(), f
+        offs = lay["leaf_offsets"]
+        for j in np.random.default_rng(2701).choice(lay["n_leaves"], 24, replace=False):
+            _, s, r, _ = oracle_mod.rf_leaf_search(lay["leaf_keys"], offs[j:j + 2])
+            n = int(offs[j + 1] - offs[j])
+            want = int(s[0]) * n + int(r[0]) if n >= 2 else int(s[0])
+            assert want == int(ex["seeds"][j]), j
+        struct = dict(lay, seeds=ex["seeds"], rho=ex["rho"], z=ex["z"], leaf_target=40, rf=True, partial_k=0)
+        rc, want = oracle_mod.mphf_query(struct, keys)
+        assert rc == 0 and (_host(pos_t) == want).all()
     finally:
         m.close()

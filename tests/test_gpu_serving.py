@@ -95,3 +95,21 @@ def test_realtime_stream_reports_latency(shock):
     assert summ["p50_ms"] > 0 and summ["p99_ms"] >= summ["p50_ms"]
     for r in reqs:
         assert r.latency() >= 0 and r.admitted >= r.arrival - 1e-6
+
+
+def test_mphf_server_builds_complete_functions(shock):
+    """Requests served as complete MPHF builds: every request completes, its
+    function is a bijection (checked by the server), the budget holds, and
+    builds overlap."""
+    from paper_2308_09561_amd.serving import MphfServer, mphf_footprint, synthetic_stream
+    reqs = synthetic_stream(10, rate_per_s=1000.0, seed=79, min_keys=2000, max_keys=60000)
+    budget = 3 * mphf_footprint(60000)
+    srv = MphfServer(hbm_budget_bytes=budget, slots=3, bucket_size=600, leaf_target=24, leaf_max=36, verify=True)
+    print("[gpu] mphf serving", flush=True)
+    rep = srv.run(reqs, realtime=False)
+    srv.close()
+    summ = rep.summary()
+    assert summ["completed"] == 10 and rep.max_bytes_in_flight <= budget
+    assert all(r.info["bijection"] for r in reqs)
+    assert summ["p99_ms"] >= summ["p50_ms"] > 0 and 1.5 < summ["bits_per_key"] < 3.0
+    assert rep.max_batches_in_flight >= 2

@@ -13,11 +13,13 @@ from workloads import splitmix64
 SMALL = dict(bucket_size=300, leaf_target=12, leaf_max=18)
 
 
+@pytest.mark.parametrize("rf", [False, True], ids=["plain", "rf"])
 @pytest.mark.parametrize("N", [0, 1, 2, 17, 1000, 6000])
-def test_mphf_is_a_bijection(oracle_mod, N):
-    """The defining property: N distinct keys map one-to-one onto [0, N)."""
+def test_mphf_is_a_bijection(oracle_mod, N, rf):
+    """The defining property: N distinct keys map one-to-one onto [0, N),
+    with plain or rotation-fitting leaves."""
     keys = splitmix64(1100 + N, N)
-    rc, lay = oracle_mod.mphf_build(keys, **SMALL)
+    rc, lay = oracle_mod.mphf_build(keys, rf=rf, **SMALL)
     assert rc == 0
     assert sorted(lay["positions"].tolist()) == list(range(N))
     if N:
