@@ -121,6 +121,35 @@ int shock_rf_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint6
                             uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient,
                             const shock_opts *opts, void *hip_stream);
 
+/* Bipartite ShockHash (the outlook of Section 9: two hash functions of range
+ * [n/2], one shifted by n/2; candidates are filtered before they are paired).
+ * The n cells are split into a left part [0, nl), nl = floor(n / 2), and a
+ * right part [nl, n).  With z the 32-bit hash value of key x under seed s
+ * (the family above):
+ *   left(x, s) = ((z mod 2^16) * nl) >> 16,  right(x, s) = nl + (((z >> 16) * (n - nl)) >> 16)
+ * A pair (a, b) gives key x the cells left(x, a) and right(x, b).  Per leaf:
+ *   out_a, out_b device u64[n_leaves]: the first pair in the order max(a, b),
+ *       then a, then b whose graph is a pseudoforest (UINT64_MAX if none with
+ *       max(a, b) < max_seed); leaves of 0 or 1 keys give (0, 0);
+ *   out_orient device u64[n_leaves]: the canonical orientation of its graph
+ *       (edges (left, right)).
+ * Options used: max_seed (at most 2^32), workers.  Synchronous.  Status as
+ * shock_leaf_search_ex; SHOCK_ENOTFOUND also when a leaf gathers more than
+ * 256 candidates on one side before its pair (far beyond what uniform keys
+ * need).  stats (host, may be NULL) receives seeds hashed, pairs tested and
+ * the kernel time. */
+typedef struct {
+  uint64_t seeds_hashed;
+  uint64_t pairs_tested;
+  double kernel_ms;
+  int32_t workers;
+  int32_t reserved;
+} shock_bip_stats;
+
+int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                             uint64_t *out_a, uint64_t *out_b, uint64_t *out_orient,
+                             const shock_opts *opts, void *hip_stream, shock_bip_stats *stats);
+
 /* Device-side statistics of the last completed call on this host thread. */
 typedef struct shock_stats {
   uint64_t seeds_tested;     /* seeds hashed, including seeds beyond a leaf's answer */

@@ -94,6 +94,11 @@ def lib():
         L.shock_oracle_mphf_query.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                               ctypes.c_uint64, _u64p, _u64p, _u32p, _u8p, _u64p, ctypes.c_int,
                                               ctypes.c_uint32, ctypes.c_uint64, _u8p, _u64p]
+        L.shock_oracle_bip_slots.restype = None
+        L.shock_oracle_bip_slots.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, _u32p, _u32p]
+        L.shock_oracle_bip_leaf_search.restype = ctypes.c_int
+        L.shock_oracle_bip_leaf_search.argtypes = [_u64p, _u64p, ctypes.c_uint64, _u64p, _u64p, _u64p,
+                                                   ctypes.c_uint64, ctypes.c_int]
         L.shock_oracle_seed_stats.restype = None
         L.shock_oracle_seed_stats.argtypes = [_u64p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                               _u64p, _u64p, _u64p]
@@ -405,4 +410,26 @@ def mphf_query(lay, queries):
                                        int(lay.get("rf", False)), lay.get("partial_k", 0), lay["rho"], _p8(lay["z"]),
                                        _p64(out))
     return rc, out[:q.size]
+
+
+# ---- bipartite ShockHash ---------------------------------------------------------
+
+def bip_slots(key: int, seed: int, n: int) -> tuple[int, int]:
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    lib().shock_oracle_bip_slots(key & 0xFFFFFFFFFFFFFFFF, seed & 0xFFFFFFFFFFFFFFFF, n, ctypes.byref(a),
+                                 ctypes.byref(b))
+    return a.value, b.value
+
+
+def bip_leaf_search(keys, offsets, max_seed: int = 1 << 22, use_filter: bool = True):
+    """(status, a uint64[L], b uint64[L], orient uint64[L]) of bipartite ShockHash."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    L = max(len(offsets) - 1, 0)
+    a = np.zeros(max(L, 1), np.uint64)
+    b = np.zeros(max(L, 1), np.uint64)
+    f = np.zeros(max(L, 1), np.uint64)
+    rc = lib().shock_oracle_bip_leaf_search(_p64(keys) if keys.size else None, _p64(offsets), L, _p64(a), _p64(b),
+                                            _p64(f), max_seed, int(use_filter))
+    return rc, a[:L], b[:L], f[:L]
 

@@ -8,6 +8,7 @@
 #include "shock_oracle.h"
 
 #include <stddef.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define GOLDEN 0x9E3779B97F4A7C15ULL
@@ -441,5 +442,105 @@ int shock_oracle_rice_decode(const uint64_t *fixed, const uint64_t *unary, const
     values[j] = (q << k) | low;
   }
   return SHOCK_ORACLE_OK;
+}
+
+/* ---- Bipartite ShockHash ---------------------------------------------------- */
+
+void shock_oracle_bip_slots(uint64_t x, uint64_t s, uint32_t n, uint32_t *left, uint32_t *right) {
+  uint64_t a = shock_oracle_fmix64(x);
+  uint64_t t = shock_oracle_fmix64((s + 1) * GOLDEN);
+  uint64_t c = a ^ t;
+  uint64_t p = (uint64_t)(uint32_t)c * (uint64_t)(uint32_t)(c >> 32);
+  uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
+  uint32_t nl = n / 2, nr = n - nl;
+  *left = (uint32_t)(((uint64_t)(z & 0xFFFFu) * nl) >> 16);
+  *right = nl + (uint32_t)(((uint64_t)(z >> 16) * nr) >> 16);
+}
+
+/* Candidate flags of seed s: bit 0 left part covered, bit 1 right part covered. */
+static int bip_candidate(const uint64_t *x, uint32_t n, uint64_t s) {
+  uint32_t nl = n / 2;
+  uint64_t cover_l = 0, cover_r = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t l, r;
+    shock_oracle_bip_slots(x[i], s, n, &l, &r);
+    cover_l |= 1ULL << l;
+    cover_r |= 1ULL << r;
+  }
+  uint64_t want_l = nl ? full_mask(nl) : 0;
+  uint64_t want_r = full_mask(n) & ~want_l;
+  int f = 0;
+  if (nl == 0 || (cover_l & want_l) == want_l) f |= 1;
+  if ((cover_r & want_r) == want_r) f |= 2;
+  return f;
+}
+
+static int bip_pair_qualifies(const uint64_t *x, uint32_t n, uint64_t a, uint64_t b, uint64_t *f) {
+  uint32_t h0[64], h1[64];
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t l, r, l2, r2;
+    shock_oracle_bip_slots(x[i], a, n, &l, &r);
+    shock_oracle_bip_slots(x[i], b, n, &l2, &r2);
+    h0[i] = n / 2 ? l : r2; /* one cell only when n = 1 */
+    h1[i] = r2;
+  }
+  if (!shock_oracle_is_pseudoforest(n, n, h0, h1)) return 0;
+  return shock_oracle_orientation(n, h0, h1, f) == SHOCK_ORACLE_OK;
+}
+
+int shock_oracle_bip_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                                 uint64_t *out_a, uint64_t *out_b, uint64_t *out_orient, uint64_t max_seed,
+                                 int use_filter) {
+  if (n_leaves == 0) return SHOCK_ORACLE_OK;
+  if (offsets == NULL || out_a == NULL || out_b == NULL || out_orient == NULL) return SHOCK_ORACLE_EINVAL;
+  for (uint64_t j = 0; j < n_leaves; ++j)
+    if (offsets[j + 1] < offsets[j] || offsets[j + 1] - offsets[j] > 64) return SHOCK_ORACLE_EINVAL;
+  int status = SHOCK_ORACLE_OK;
+  uint8_t *cand = (uint8_t *)malloc(max_seed < (1u << 26) ? max_seed + 1 : (1u << 26));
+  if (!cand) return SHOCK_ORACLE_EINVAL;
+  uint64_t cap = max_seed < (1u << 26) ? max_seed : (1u << 26);
+  for (uint64_t j = 0; j < n_leaves; ++j) {
+    uint32_t n = (uint32_t)(offsets[j + 1] - offsets[j]);
+    const uint64_t *x = keys + offsets[j];
+    int found = 0;
+    if (n <= 1) {
+      out_a[j] = 0;
+      out_b[j] = 0;
+      out_orient[j] = 0;
+      continue;
+    }
+    for (uint64_t m = 0; m < cap && !found; ++m) {
+      cand[m] = use_filter ? (uint8_t)bip_candidate(x, n, m) : 3;
+      /* pairs with max(a, b) = m in the order (0, m), ..., (m-1, m), (m, 0), ..., (m, m) */
+      for (uint64_t a = 0; a < m && !found; ++a) {
+        if (!(cand[a] & 1) || !(cand[m] & 2)) continue;
+        uint64_t f;
+        if (bip_pair_qualifies(x, n, a, m, &f)) {
+          out_a[j] = a;
+          out_b[j] = m;
+          out_orient[j] = f;
+          found = 1;
+        }
+      }
+      for (uint64_t b = 0; b <= m && !found; ++b) {
+        if (!(cand[m] & 1) || !(cand[b] & 2)) continue;
+        uint64_t f;
+        if (bip_pair_qualifies(x, n, m, b, &f)) {
+          out_a[j] = m;
+          out_b[j] = b;
+          out_orient[j] = f;
+          found = 1;
+        }
+      }
+    }
+    if (!found) {
+      out_a[j] = UINT64_MAX;
+      out_b[j] = UINT64_MAX;
+      out_orient[j] = 0;
+      status = SHOCK_ORACLE_ENOTFOUND;
+    }
+  }
+  free(cand);
+  return status;
 }
 

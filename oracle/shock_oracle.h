@@ -160,6 +160,26 @@ int shock_oracle_rice_encode(const uint64_t *values, const uint64_t *offsets, ui
 int shock_oracle_rice_decode(const uint64_t *fixed, const uint64_t *unary, const uint64_t *offsets,
                              uint64_t n_leaves, const uint8_t *k_by_n, uint64_t *values);
 
+/* ---- Bipartite ShockHash (the outlook of Section 9) -------------------------
+ * The table's n cells are split into a left part [0, nl), nl = floor(n / 2),
+ * and a right part [nl, n).  Under seed s, with z the 32-bit hash value of
+ * key x of the frozen family (shock_oracle_slots' z):
+ *   left(x, s)  = ((z mod 2^16) * nl) >> 16            (0 when nl = 0)
+ *   right(x, s) = nl + (((z >> 16) * (n - nl)) >> 16)
+ * A pair (a, b) of seeds gives key x the candidate cells left(x, a) and
+ * right(x, b); the leaf's result is the pair whose graph is a pseudoforest
+ * that comes first in the order max(a, b), then a, then b -- the order in
+ * which a search that draws seeds 0, 1, 2, ... and pairs each new seed with
+ * all earlier ones meets them.  Seed a is a left candidate if its left cells
+ * cover [0, nl), b a right candidate if its right cells cover [nl, n); only
+ * such pairs can qualify, and use_filter skips the others (same result).
+ * Orientation: as shock_oracle_orientation on the edges (left, right).
+ * Seeds are limited to max_seed (pairs with max(a, b) < max_seed). */
+void shock_oracle_bip_slots(uint64_t x, uint64_t s, uint32_t n, uint32_t *left, uint32_t *right);
+int shock_oracle_bip_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                                 uint64_t *out_a, uint64_t *out_b, uint64_t *out_orient, uint64_t max_seed,
+                                 int use_filter);
+
 /* ---- A flat ShockHash MPHF (Section 8's flat decomposition; the two-level
  * scheme of Appendix A.4 with per-bucket splitting seeds) ------------------
  * Definitions (this library's choices; the paper leaves the scheme open):

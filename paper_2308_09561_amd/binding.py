@@ -30,7 +30,7 @@ EXPORTED = [
     "shock_ctx_graph_capture", "shock_ctx_graph_launch", "shock_rf_leaf_search_ex", "shock_ctx_rf_search_async",
     "shock_leaf_query", "shock_rf_leaf_query", "shock_rice_encode", "shock_rice_decode",
     "shock_mphf_params_init", "shock_mphf_build", "shock_mphf_query", "shock_mphf_info", "shock_mphf_export",
-    "shock_mphf_destroy",
+    "shock_mphf_destroy", "shock_bip_leaf_search_ex",
 ]
 
 
@@ -67,6 +67,14 @@ class ShockStats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BipStats(ctypes.Structure):
+    _fields_ = [("seeds_hashed", ctypes.c_uint64), ("pairs_tested", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
+                ("workers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class MphfParams(ctypes.Structure):
@@ -173,6 +181,9 @@ def lib():
         L.shock_mphf_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.shock_mphf_destroy.restype = ctypes.c_int
         L.shock_mphf_destroy.argtypes = [vp]
+        L.shock_bip_leaf_search_ex.restype = ctypes.c_int
+        L.shock_bip_leaf_search_ex.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, ctypes.POINTER(ShockOpts), vp,
+                                               ctypes.POINTER(BipStats)]
         L.shock_ctx_query.restype = ctypes.c_int
         L.shock_ctx_query.argtypes = [vp]
         L.shock_ctx_wait.restype = ctypes.c_int
@@ -562,4 +573,27 @@ class MPHF:
             self.close()
         except Exception:
             pass
+
+
+def bip_leaf_search(keys, offsets, out_a=None, out_b=None, out_orient=None, stream=None, **opts):
+    """Bipartite ShockHash over a CSR batch in int64 CUDA tensors.  Returns
+    (status, a, b, orient, stats): seed pairs and orientations as int64
+    tensors (uint64 bit patterns) and a dict of device counters."""
+    import torch
+    _check_tensors(keys, offsets)
+    keys = keys.contiguous()
+    offsets = offsets.contiguous()
+    L = offsets.numel() - 1
+    dev = keys.device
+    out_a = torch.empty(max(L, 1), dtype=torch.int64, device=dev) if out_a is None else out_a
+    out_b = torch.empty(max(L, 1), dtype=torch.int64, device=dev) if out_b is None else out_b
+    out_orient = torch.empty(max(L, 1), dtype=torch.int64, device=dev) if out_orient is None else out_orient
+    o = make_opts(**opts)
+    st = BipStats()
+    rc = lib().shock_bip_leaf_search_ex(_as_ptr(keys if keys.numel() else offsets), _as_ptr(offsets), max(L, 0),
+                                        _as_ptr(out_a), _as_ptr(out_b), _as_ptr(out_orient), ctypes.byref(o),
+                                        _stream_of(keys, stream), ctypes.byref(st))
+    if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
+        raise ShockError(rc, lib().shock_last_error().decode())
+    return rc, out_a[:L], out_b[:L], out_orient[:L], st.as_dict()
 

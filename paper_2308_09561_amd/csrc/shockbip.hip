@@ -1,0 +1,269 @@
+// Bipartite ShockHash (the outlook of Section 9) on MI355X (gfx950).
+//
+// The n cells of a leaf's table are split into a left part [0, nl) and a
+// right part [nl, n), nl = floor(n / 2).  One evaluation of the frozen hash of
+// key x under seed s gives both its left cell (bits 0..15 of z) and its right
+// cell (bits 16..31).  A pair of seeds (a, b) gives key x the cells
+// left(x, a) and right(x, b); the result is the first pair, in the order
+// max(a, b), then a, then b, whose graph is a pseudoforest.
+//
+// One wave works on one leaf.  Per iteration lane l hashes seed base + l over
+// the leaf's keys (premixed, LDS broadcasts) into a left and a right coverage
+// mask; a seed whose left (right) cells cover the left (right) part joins the
+// left (right) candidate pool, and only pairs of candidates can qualify
+// (every cell needs a key).  Candidates are rare and pairs are formed as they
+// arrive, so the seeds hashed grow like the square root of the pairs needed:
+// the exponential gain over ShockHash the paper points to.  Each new
+// candidate m is paired with the pool in the result order ((a, m) for left
+// candidates a < m, then (m, b) for right candidates b <= m), each pair
+// checked by the wave-parallel peeling test; the pools (seed lists) stay in
+// LDS.  Workers take leaves from an atomic counter; a leaf is short, so there
+// is no work stealing.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include "shockleaf.h"
+#include "shock_hash.h"
+#include "shock_internal.h"
+#include "shock_wave.h"
+
+namespace {
+
+using shockhash::fmix64;
+using shockhash::seed_mix;
+using shockwave::bcast64;
+using shockwave::lane_id;
+using shockwave::wave_lds_sync;
+
+constexpr uint64_t kNone = ~0ull;
+constexpr uint32_t kPool = 256;  // candidates per side and leaf
+constexpr uint32_t kWpw = 4;
+
+enum { kBipErr = 0, kBipNotFound = 1, kBipSeeds = 2, kBipPairs = 3, kBipNextLeaf = 4, kBipCount = 5 };
+constexpr uint64_t kErrInvalidLeaf = 1;
+constexpr uint64_t kErrPool = 2;
+
+struct BipLds {
+  uint64_t keys[64];
+  unsigned long long inc0[64], inc1[64], hit;
+  uint32_t pool_l[kPool], pool_r[kPool];
+};
+
+struct BipParams {
+  const uint64_t *keys, *offsets;
+  uint64_t n_leaves, max_seed;
+  uint64_t *out_a, *out_b, *out_orient;
+  unsigned long long *ctr;
+};
+
+// Left and right cells of a premixed key under a seed mix t.
+__device__ __forceinline__ void bip_cells(uint64_t a, uint64_t t, uint32_t nl, uint32_t nr, uint32_t &l, uint32_t &r) {
+  const uint64_t c = a ^ t;
+  const uint64_t p = (uint64_t)(uint32_t)c * (uint64_t)(uint32_t)(c >> 32);
+  const uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
+  l = __umulhi(z << 16, nl);
+  r = nl + __umulhi(z & 0xFFFF0000u, nr);
+}
+
+// Whether pair (a, b) qualifies; lane i < n gets its edge (left under a, right under b).
+__device__ bool bip_pair(uint64_t my_a, uint32_t n, uint32_t nl, uint32_t nr, uint64_t sa, uint64_t sb,
+                         uint32_t &h0, uint32_t &h1, BipLds &lds) {
+  uint32_t l, r, l2, r2;
+  bip_cells(my_a, seed_mix(sa), nl, nr, l, r);
+  bip_cells(my_a, seed_mix(sb), nl, nr, l2, r2);
+  h0 = lane_id() < n ? l : 0;
+  h1 = lane_id() < n ? r2 : 0;
+  return shockwave::pf_peel_wave(n, h0, h1, lds.inc0);
+}
+
+__global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
+  __shared__ BipLds lds_all[kWpw];
+  BipLds &lds = lds_all[threadIdx.x >> 6];
+  const uint32_t lane = lane_id();
+  uint64_t seeds_hashed = 0, pairs = 0;
+  for (;;) {
+    unsigned long long jj = 0;
+    if (lane == 0) jj = atomicAdd(&P.ctr[kBipNextLeaf], 1ull);
+    const uint64_t j = bcast64(jj);
+    if (j >= P.n_leaves) break;
+    const uint64_t o0 = P.offsets[j], o1 = P.offsets[j + 1];
+    if (o1 < o0 || o1 - o0 > 64) {
+      if (lane == 0) {
+        atomicOr(&P.ctr[kBipErr], kErrInvalidLeaf);
+        P.out_a[j] = kNone;
+        P.out_b[j] = kNone;
+        P.out_orient[j] = 0;
+      }
+      continue;
+    }
+    const uint32_t n = (uint32_t)(o1 - o0);
+    if (n <= 1) {
+      if (lane == 0) {
+        P.out_a[j] = 0;
+        P.out_b[j] = 0;
+        P.out_orient[j] = 0;
+      }
+      continue;
+    }
+    const uint64_t my_a = lane < n ? fmix64(P.keys[o0 + lane]) : 0;
+    lds.keys[lane] = my_a;
+    wave_lds_sync();
+    const uint32_t nl = n / 2, nr = n - nl;
+    const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    const uint64_t want_l = (1ull << nl) - 1, want_r = full & ~want_l;
+    uint32_t n_l = 0, n_r = 0;
+    bool found = false, overflow = false;
+    uint64_t ra = kNone, rb = kNone;
+    uint32_t fh0 = 0, fh1 = 0;
+    for (uint64_t base = 0; base < P.max_seed && !found && !overflow; base += 64) {
+      const uint64_t s = base + lane;
+      const uint64_t t = seed_mix(s);
+      uint64_t ml = 0, mr = 0;
+      for (uint32_t i = 0; i < n; ++i) {
+        uint32_t l, r;
+        bip_cells(lds.keys[i], t, nl, nr, l, r);
+        ml |= 1ull << l;
+        mr |= 1ull << r;
+      }
+      const uint64_t span = P.max_seed - base;
+      seeds_hashed += span < 64 ? span : 64;
+      const bool in = s < P.max_seed;
+      const uint64_t cl = __ballot(in && (ml & want_l) == want_l);
+      const uint64_t cr = __ballot(in && (mr & want_r) == want_r);
+      uint64_t any = cl | cr;
+      while (any != 0 && !found && !overflow) {
+        const uint32_t lm = __builtin_ctzll(any);
+        any &= any - 1;
+        const uint64_t m = base + lm;
+        const bool is_l = (cl >> lm) & 1, is_r = (cr >> lm) & 1;
+        if (is_r) {
+          for (uint32_t q = 0; q < n_l && !found; ++q) {
+            const uint64_t a = lds.pool_l[q];
+            ++pairs;
+            if (bip_pair(my_a, n, nl, nr, a, m, fh0, fh1, lds)) {
+              found = true;
+              ra = a;
+              rb = m;
+            }
+          }
+          if (!found) {
+            if (n_r == kPool) overflow = true;
+            else {
+              if (lane == 0) lds.pool_r[n_r] = (uint32_t)m;
+              ++n_r;
+              wave_lds_sync();
+            }
+          }
+        }
+        if (!found && !overflow && is_l) {
+          for (uint32_t q = 0; q < n_r && !found; ++q) {
+            const uint64_t b = lds.pool_r[q];
+            ++pairs;
+            if (bip_pair(my_a, n, nl, nr, m, b, fh0, fh1, lds)) {
+              found = true;
+              ra = m;
+              rb = b;
+            }
+          }
+          if (!found) {
+            if (n_l == kPool) overflow = true;
+            else {
+              if (lane == 0) lds.pool_l[n_l] = (uint32_t)m;
+              ++n_l;
+              wave_lds_sync();
+            }
+          }
+        }
+      }
+    }
+    uint64_t f = 0;
+    if (found && !shockwave::orient_wave(n, fh0, fh1, lds.inc0, lds.inc1, &lds.hit, f)) found = false;
+    if (lane == 0) {
+      if (overflow) atomicOr(&P.ctr[kBipErr], kErrPool);
+      if (!found) atomicAdd(&P.ctr[kBipNotFound], 1ull);
+      P.out_a[j] = found ? ra : kNone;
+      P.out_b[j] = found ? rb : kNone;
+      P.out_orient[j] = found ? f : 0;
+    }
+    wave_lds_sync();
+  }
+  if (lane == 0) {
+    if (seeds_hashed) atomicAdd(&P.ctr[kBipSeeds], (unsigned long long)seeds_hashed);
+    if (pairs) atomicAdd(&P.ctr[kBipPairs], (unsigned long long)pairs);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_a,
+                             uint64_t *out_b, uint64_t *out_orient, const shock_opts *opts_in, void *hip_stream,
+                             shock_bip_stats *stats) {
+  shock_opts opts;
+  shock_opts_init(&opts);
+  if (opts_in) opts = *opts_in;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (n_leaves == 0) return SHOCK_OK;
+  if (!keys || !offsets || !out_a || !out_b || !out_orient || n_leaves > (1ull << 31)) return SHOCK_EINVAL;
+  if (opts.max_seed > (1ull << 32) || opts.workers < 0 || opts.workers > (1 << 20)) return SHOCK_EINVAL;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  unsigned long long *ctr = nullptr;
+  hipError_t e = hipMalloc((void **)&ctr, kBipCount * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    shock_internal_set_error("hipMalloc(bipartite counters)", e);
+    return SHOCK_ENOMEM;
+  }
+  unsigned long long host[kBipCount] = {0, 0, 0, 0, 0};
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  uint64_t workers = opts.workers ? (uint64_t)opts.workers : (uint64_t)cus * 4 * 6;
+  if (workers > n_leaves) workers = n_leaves;
+  const uint32_t groups = (uint32_t)((workers + kWpw - 1) / kWpw);
+  BipParams P;
+  P.keys = keys;
+  P.offsets = offsets;
+  P.n_leaves = n_leaves;
+  P.max_seed = opts.max_seed;
+  P.out_a = out_a;
+  P.out_b = out_b;
+  P.out_orient = out_orient;
+  P.ctr = ctr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipMemcpyAsync(ctr, host, sizeof(host), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(bip_kernel, dim3(groups), dim3(64 * kWpw), 0, stream, P);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(host, ctr, sizeof(host), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(ctr);
+  if (e != hipSuccess) {
+    shock_internal_set_error("bipartite search", e);
+    return SHOCK_EHIP;
+  }
+  if (stats) {
+    stats->seeds_hashed = host[kBipSeeds];
+    stats->pairs_tested = host[kBipPairs];
+    stats->kernel_ms = ms;
+    stats->workers = (int32_t)(groups * kWpw);
+  }
+  if (host[kBipErr] & kErrInvalidLeaf) return SHOCK_EINVAL;
+  if (host[kBipErr] & kErrPool) return SHOCK_ENOTFOUND;
+  if (host[kBipNotFound]) return SHOCK_ENOTFOUND;
+  return SHOCK_OK;
+}
+
+}  // extern "C"

@@ -38,6 +38,7 @@
 #include "shockleaf.h"
 #include "shock_hash.h"
 #include "shock_internal.h"
+#include "shock_wave.h"
 
 namespace {
 
@@ -108,7 +109,10 @@ struct Params {
   uint16_t units_by_n[65];  // most units one claim takes, by leaf size (persistent launches)
 };
 
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+using shockwave::bcast32;
+using shockwave::bcast64;
+using shockwave::lane_id;
+using shockwave::wave_lds_sync;
 
 // m |= a | b as one 3-input OR.  Written out because the compiler otherwise
 // reassociates the mask updates of unrolled keys into two-input ORs.
@@ -116,15 +120,6 @@ __device__ __forceinline__ void or3_into(uint32_t &m, uint32_t a, uint32_t b) {
   asm("v_or3_b32 %0, %0, %1, %2" : "+v"(m) : "v"(a), "v"(b));
 }
 
-__device__ __forceinline__ uint64_t bcast64(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint32_t bcast32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 __device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long *p) {
   return __hip_atomic_load(const_cast<unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -224,53 +219,9 @@ __device__ bool pf_test_wave(uint32_t n, uint32_t h0, uint32_t h1, WaveLds &lds)
   return __ballot(bad) == 0;
 }
 
-// Canonical orientation of an accepted seed, wave-parallel.  A free cell with
-// exactly one unplaced incident key takes that key (forced); when no such
-// cell remains, only disjoint cycles are left and the highest-index unplaced
-// key takes its h0 slot.  Returns false if the choice is not a bijection
-// (which cannot happen for a pseudoforest).
-__device__ bool orient_wave(uint32_t n, uint32_t h0, uint32_t h1, WaveLds &lds, uint64_t &f_out) {
-  const uint32_t lane = lane_id();
-  const bool act = lane < n;
-  lds.ori.inc0[lane] = 0;
-  lds.ori.inc1[lane] = 0;
-  if (lane == 0) lds.ori.hit = 0;
-  wave_lds_sync();
-  if (act) {
-    atomicOr(&lds.ori.inc0[h0], 1ull << lane);
-    atomicOr(&lds.ori.inc1[h1], 1ull << lane);
-  }
-  wave_lds_sync();
-  const uint64_t inc = lds.ori.inc0[lane] | lds.ori.inc1[lane];
-  const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
-  uint64_t rem = all, avail = all, f = 0;
-  for (int round = 0; round < 2 * 64 + 2 && rem != 0; ++round) {
-    const bool cell_free = act && ((avail >> lane) & 1);
-    const bool one = cell_free && __popcll(inc & rem) == 1;
-    const uint64_t d1 = __ballot(one);
-    if (d1 == 0) {
-      const uint32_t m = 63 - __clzll(rem);
-      const uint32_t c0 = __builtin_amdgcn_readlane(h0, m);
-      rem &= ~(1ull << m);
-      avail &= ~(1ull << c0);
-      continue;
-    }
-    const bool mine = act && ((rem >> lane) & 1);
-    const bool take0 = mine && ((d1 >> h0) & 1);
-    const bool take1 = mine && !take0 && ((d1 >> h1) & 1);
-    const uint64_t got = __ballot(take0 || take1);
-    const uint64_t fb = __ballot(take1);
-    rem &= ~got;
-    avail &= ~d1;
-    f |= fb;
-  }
-  if (act) {
-    const uint32_t slot = ((f >> lane) & 1) ? h1 : h0;
-    atomicOr(&lds.ori.hit, 1ull << slot);
-  }
-  wave_lds_sync();
-  f_out = f;
-  return rem == 0 && lds.ori.hit == all;
+// Canonical orientation (shockwave::orient_wave) on the wave's LDS.
+__device__ __forceinline__ bool orient_wave(uint32_t n, uint32_t h0, uint32_t h1, WaveLds &lds, uint64_t &f_out) {
+  return shockwave::orient_wave(n, h0, h1, lds.ori.inc0, lds.ori.inc1, &lds.ori.hit, f_out);
 }
 
 struct WaveStats {
@@ -439,37 +390,9 @@ __device__ __forceinline__ void rf_lane_slots(uint32_t my_alo, uint32_t my_ahi, 
   }
 }
 
-// Pseudoforest test by peeling, wave-parallel: lane i < n holds edge i
-// (h0, h1), lane c stands for cell c.  Cells of degree one lose their edge,
-// all at once, until none is left; the graph is a pseudoforest iff what
-// remains (its 2-core) has no cell of degree above two, i.e. is a set of
-// disjoint cycles: a component with two or more cycles keeps a cell of degree
-// three or more in its 2-core.  Apart from building the incidence masks in
-// LDS, every round is a few register operations and two ballots, where the
-// union-find needs LDS round trips per step; rotation fitting tests many
-// more candidates per leaf, so it uses this form.  Needs n >= 2 (no loops).
-__device__ bool pf_peel_wave(uint32_t n, uint32_t h0, uint32_t h1, WaveLds &lds) {
-  const uint32_t lane = lane_id();
-  const bool act = lane < n;
-  unsigned long long *inc = lds.ori.inc0;
-  inc[lane] = 0;
-  wave_lds_sync();
-  if (act) {
-    atomicOr(&inc[h0], 1ull << lane);
-    atomicOr(&inc[h1], 1ull << lane);
-  }
-  wave_lds_sync();
-  const uint64_t mine = inc[lane];
-  uint64_t rem = n >= 64 ? ~0ull : ((1ull << n) - 1);
-  // Every round that finds a cell of degree one removes an edge, so at most
-  // n + 1 rounds run.
-  for (uint32_t round = 0; round <= 64; ++round) {
-    const uint64_t d1 = __ballot(__popcll(mine & rem) == 1);
-    if (d1 == 0) break;
-    const bool gone = act && (((d1 >> h0) | (d1 >> h1)) & 1);
-    rem &= ~__ballot(gone);
-  }
-  return __ballot(__popcll(mine & rem) > 2) == 0;
+// Pseudoforest test by peeling (shockwave::pf_peel_wave) on the wave's LDS.
+__device__ __forceinline__ bool pf_peel_wave(uint32_t n, uint32_t h0, uint32_t h1, WaveLds &lds) {
+  return shockwave::pf_peel_wave(n, h0, h1, lds.ori.inc0);
 }
 
 // Rotations of seed s whose graphs pass the coverage filter, one bit per

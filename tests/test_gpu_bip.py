@@ -1,0 +1,104 @@
+"""GPU parity of bipartite ShockHash (shock_bip_leaf_search_ex) against the
+oracle, through the C ABI: (a, b, orientation) bit-exact per leaf."""
+import numpy as np
+import pytest
+
+from workloads import fixed_leaves, make_workload, splitmix64
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+MAX = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+@pytest.fixture(scope="module")
+def shock():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_09561_amd as shock
+    shock.lib()
+    return shock
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def _host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def gpu_bip(shock, keys, offs, **opts):
+    print(f"[gpu] bip L={len(offs) - 1} opts={opts}", flush=True)
+    k = _dev(keys) if len(keys) else torch.zeros(1, dtype=torch.int64, device="cuda")
+    rc, a, b, f, st = shock.bip_leaf_search(k, _dev(offs), **opts)
+    torch.cuda.synchronize()
+    return rc, _host(a), _host(b), _host(f), st
+
+
+def oracle_bip(oracle_mod, keys, offs, **kw):
+    parts = oracle_mod.parallel(oracle_mod.bip_leaf_search, keys, offs, threads=16, **kw)
+    rc = min(p[0] for p in parts)
+    return (rc, *[np.concatenate([p[i] for p in parts]) for i in (1, 2, 3)])
+
+
+def assert_same(g, o, what):
+    bad = np.nonzero((g[1] != o[1]) | (g[2] != o[2]) | (g[3] != o[3]))[0]
+    assert bad.size == 0, f"{what}: {bad.size} differ, first {bad[:4]}: gpu {g[1][bad[:4]]},{g[2][bad[:4]]} " \
+                          f"oracle {o[1][bad[:4]]},{o[2][bad[:4]]}"
+    assert g[0] == o[0], what
+
+
+@pytest.mark.parametrize("n,L", [(2, 200), (3, 200), (5, 200), (8, 200), (16, 200), (24, 120), (32, 80), (40, 48),
+                                 (48, 32), (56, 16), (64, 8)])
+def test_bip_fixed_n_matches_oracle(shock, oracle_mod, n, L):
+    keys, offs = fixed_leaves(L, n, 3000 + n)
+    assert_same(gpu_bip(shock, keys, offs), oracle_bip(oracle_mod, keys, offs), f"n={n}")
+
+
+def test_bip_uneven_batch_and_worker_counts(shock, oracle_mod):
+    rng = np.random.default_rng(3100)
+    sizes = np.repeat(np.arange(0, 50), 3)
+    rng.shuffle(sizes)
+    offs = np.zeros(len(sizes) + 1, np.uint64)
+    np.cumsum(sizes, out=offs[1:])
+    keys = splitmix64(3101, int(offs[-1]))
+    want = oracle_bip(oracle_mod, keys, offs)
+    for workers in (0, 1, 7, 64):
+        assert_same(gpu_bip(shock, keys, offs, workers=workers), want, f"workers={workers}")
+
+
+def test_bip_cap(shock, oracle_mod):
+    keys, offs = fixed_leaves(40, 36, 3102)
+    full = gpu_bip(shock, keys, offs)
+    cap = int(np.median(np.maximum(full[1], full[2])))
+    g = gpu_bip(shock, keys, offs, max_seed=cap)
+    assert_same(g, oracle_bip(oracle_mod, keys, offs, max_seed=cap), "capped")
+    assert g[0] == shock.SHOCK_ENOTFOUND and (g[1] == MAX).any() and (g[1] != MAX).any()
+
+
+def test_bip_full_batch_statistics(shock, oracle_mod):
+    """The fixed48 batch: every leaf's pair is a pseudoforest with a valid
+    orientation (the oracle checks a sample end to end) and the seeds drawn
+    are a small fraction of the plain search's."""
+    keys, offs = make_workload("fixed48")
+    g = gpu_bip(shock, keys, offs)
+    assert g[0] == 0
+    st = g[4]
+    L = len(offs) - 1
+    print(f"[gpu] bip fixed48 stats {st}", flush=True)
+    assert st["seeds_hashed"] / L < 2000 and st["kernel_ms"] > 0
+    pick = np.random.default_rng(3103).choice(L, 32, replace=False)
+    for j in pick:
+        o = oracle_mod.bip_leaf_search(keys, offs[j:j + 2])
+        assert (int(o[1][0]), int(o[2][0]), int(o[3][0])) == (int(g[1][j]), int(g[2][j]), int(g[3][j])), j
+
+
+def test_bip_edges(shock):
+    keys = splitmix64(3104, 3)
+    offs = np.array([0, 0, 1, 3], np.uint64)
+    rc, a, b, f, _ = gpu_bip(shock, keys, offs)
+    assert rc == 0 and list(a[:2]) == [0, 0] and list(b[:2]) == [0, 0] and list(f[:2]) == [0, 0]
+    rc, *_ = gpu_bip(shock, keys, offs, max_seed=(1 << 32) + 1)
+    assert rc == shock.SHOCK_EINVAL
