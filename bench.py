@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--untuned", action="store_true", help="ignore the autotuner's cached table for this device")
     ap.add_argument("--rf-steps", type=int, default=3,
                     help="timed steps of the rotation-fitting search on the same batch (0 = skip)")
+    ap.add_argument("--bip-steps", type=int, default=3,
+                    help="timed steps of the bipartite ShockHash search on the same batch (0 = skip)")
     ap.add_argument("--code-leaves", type=int, default=1 << 21,
                     help="leaves of 48 keys for the query and seed-code legs (0 = skip)")
     ap.add_argument("--mphf-keys", type=int, default=1 << 22,
@@ -286,6 +288,43 @@ def main():
                            "traffic": measured_traffic(args.workload, "rf_")}}
         log(f"[bench] rotation fitting: {L / wall_r:.0f} leaves/s, kernel {rf_kernel:.2f} ms, "
             f"frac {rf['roofline']['frac']:.3f}")
+
+    # Bipartite ShockHash on the same batch: a different output (a seed pair).
+    bip = None
+    if args.bip_steps > 0:
+        ba = torch.empty(L, dtype=torch.int64, device=dev)
+        bb = torch.empty(L, dtype=torch.int64, device=dev)
+        bf = torch.empty(L, dtype=torch.int64, device=dev)
+        log(f"[bench] bipartite ShockHash: {args.bip_steps} steps")
+        shock.bip_leaf_search(k_d, o_d, out_a=ba, out_b=bb, out_orient=bf)
+        torch.cuda.synchronize()
+        b_ms, b_seeds, b_pairs = [], 0, 0
+        t5 = time.perf_counter()
+        for _ in range(args.bip_steps):
+            rc, _, _, _, bst = shock.bip_leaf_search(k_d, o_d, out_a=ba, out_b=bb, out_orient=bf)
+            if rc != shock.SHOCK_OK:
+                raise RuntimeError(f"bipartite search failed: {shock.shock_strerror(rc)}")
+            b_ms.append(bst["kernel_ms"])
+            b_seeds += bst["seeds_hashed"]
+            b_pairs += bst["pairs_tested"]
+        wall_b = (time.perf_counter() - t5) / args.bip_steps
+        pair_max = torch.maximum(ba, bb).cpu().numpy().astype(np.float64)
+        n_b = float(sizes.mean())
+        # Lower bound of the algorithmic work: every seed hashed over the
+        # leaf's keys, and two key evaluations per key and tested pair, at
+        # 14 ops per key evaluation (13 as in the plain search, plus the
+        # second half's bit-set); the peeling of each pair is not counted.
+        ops = (b_seeds / args.bip_steps * n_b + b_pairs / args.bip_steps * 2 * n_b) * 14
+        kms = float(np.mean(b_ms))
+        bip = {"leaves_per_s": L / wall_b, "ms_per_step": wall_b * 1e3, "kernel_ms": kms,
+               "mean_max_seed": float(pair_max.mean()), "seeds_hashed_per_leaf": b_seeds / args.bip_steps / L,
+               "pairs_tested_per_leaf": b_pairs / args.bip_steps / L, "vs_plain_search": (L / wall_b) / leaves_per_s,
+               "roofline": {"bound": "alu", "achieved": ops / (kms / 1e3) / 1e12, "peak": PEAK_INT_OPS / 1e12,
+                            "unit": "Tops/s (int32 lane ops, hashing only: a lower bound)",
+                            "frac": ops / (kms / 1e3) / PEAK_INT_OPS,
+                            "traffic": measured_traffic(args.workload, "bip_")}}
+        log(f"[bench] bipartite: {L / wall_b:.0f} leaves/s, kernel {kms:.2f} ms, "
+            f"{bip['seeds_hashed_per_leaf']:.0f} seeds and {bip['pairs_tested_per_leaf']:.0f} pairs per leaf")
 
     # Leaf query and Golomb-Rice seed codes (HBM-bound) on a larger batch of
     # 48-key leaves: uniform keys drawn on the device, the measured batch's
@@ -475,6 +514,7 @@ def main():
         "batched_vs_plain": (leaves_per_s / plain["leaves_per_s"]) if plain else None,
         "latency": latency,
         "rotation_fitting": rf,
+        "bipartite": bip,
         "leaf_query_and_codes": code,
         "flat_mphf": mphf,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
