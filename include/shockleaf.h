@@ -80,7 +80,11 @@ typedef struct shock_opts {
   int32_t partial_k;      /* rotation fitting only: partial-hash period 1 or 8; 0 = 8 above 32 keys, else 1 */
   const uint16_t *block_iters_by_n; /* HOST pointer to 65 claim sizes indexed by leaf size (0 = default), or NULL;
                                        e.g. the autotuner's table; overridden by block_iters when that is set */
-  uint64_t reserved[2];
+  int32_t team;           /* persistent mode: 1 = each wave takes its own fresh leaves; 2 = the waves of a
+                             workgroup share each fresh leaf (a shorter tail: each leaf finishes sooner);
+                             0 = default (2) */
+  int32_t reserved1;
+  uint64_t reserved2;
 } shock_opts;
 
 /* Defaults for every field. */

@@ -48,7 +48,9 @@ class ShockOpts(ctypes.Structure):
         ("leaf_size_hint", ctypes.c_int32),
         ("partial_k", ctypes.c_int32),
         ("block_iters_by_n", ctypes.c_void_p),
-        ("reserved", ctypes.c_uint64 * 2),
+        ("team", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
+        ("reserved2", ctypes.c_uint64),
     ]
 
 
@@ -235,7 +237,7 @@ def _as_ptr(x):
 
 def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_iters=0, waves_per_wg=0,
               workers=0, check_dups=False, cancel_ptr=None, leaf_size_hint=0, block_iters_by_n=None,
-              partial_k=0) -> ShockOpts:
+              partial_k=0, team=0) -> ShockOpts:
     """shock_opts with defaults; block_iters_by_n is a sequence of 65 ints or None."""
     o = ShockOpts()
     lib().shock_opts_init(ctypes.byref(o))
@@ -251,6 +253,7 @@ def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_it
     o.cancel = cancel_ptr
     o.leaf_size_hint = leaf_size_hint
     o.partial_k = partial_k
+    o.team = team
     if block_iters_by_n is not None:
         if len(block_iters_by_n) != 65:
             raise ValueError("block_iters_by_n needs 65 entries (leaf sizes 0..64)")

@@ -37,6 +37,9 @@
 
 #include "shockleaf.h"
 #include "shock_hash.h"
+
+// Wave-wide bitwise OR of a 64-bit value (ROCm's device library, cross-lane DPP).
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_or_u64(unsigned long long);
 #include "shock_internal.h"
 #include "shock_wave.h"
 
@@ -103,6 +106,7 @@ struct Params {
   uint32_t block_iters;  // units per block of a single-leaf (split) launch
   uint32_t workers;
   uint32_t split;  // 1: one leaf, static block striding over the workers (no claim atomics)
+  uint32_t team;   // 1: the waves of a workgroup share each fresh leaf (persistent launches)
   uint32_t partial_k;  // rotation fitting (best holds candidates s * 64 + r): 0 = 8 above 32 keys else 1; or 1 / 8
   uint32_t *__restrict__ out_rot;              // rotation fitting: rotation per leaf
   const unsigned long long *__restrict__ sides;  // [n_leaves] bit i = set of key i
@@ -161,7 +165,6 @@ struct WaveLds {
   uint64_t keys[64];  // premixed keys of the leaf the wave is working on
   uint64_t keys_a[64];  // rotation fitting: premixed keys of the first set, compacted
   uint64_t keys_b[64];  // rotation fitting: premixed keys of the second set, compacted
-  unsigned long long rmask[2];  // rotation fitting: coverage masks of one seed (first, second set)
   union {
     struct {
       uint32_t parent[64];
@@ -402,16 +405,17 @@ __device__ __forceinline__ bool pf_peel_wave(uint32_t n, uint32_t h0, uint32_t h
 __device__ uint64_t rf_rotations(uint32_t n, uint64_t s, bool partial, uint32_t my_alo, uint32_t my_ahi,
                                  uint32_t my_side, WaveLds &lds, uint32_t &h0, uint32_t &h1) {
   const uint32_t lane = lane_id();
-  if (lane < 2) lds.rmask[lane] = 0;
-  wave_lds_sync();
   h0 = 0;
   h1 = 0;
+  uint64_t bits = 0;
   if (lane < n) {
     rf_lane_slots(my_alo, my_ahi, my_side, s, 0, partial, n, h0, h1);
-    atomicOr(&lds.rmask[my_side], (1ull << h0) | (1ull << h1));
+    bits = (1ull << h0) | (1ull << h1);
   }
-  wave_lds_sync();
-  const uint64_t ma = lds.rmask[0], mb = lds.rmask[1];
+  // The two sets' masks by wave OR-reductions (cross-lane DPP), instead of
+  // LDS atomics that serialise on two addresses.
+  const uint64_t ma = __ockl_wfred_or_u64(my_side ? 0ull : bits);
+  const uint64_t mb = __ockl_wfred_or_u64(my_side ? bits : 0ull);
   const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
   const uint64_t rot = lane == 0 ? mb : ((mb << lane) | (mb >> (n - lane))) & full;
   return __ballot(lane < n && (rot | ma) == full);
@@ -757,6 +761,32 @@ __global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
     return;
   }
   bool fresh = true;
+  if (P.team) {
+    // Fresh leaves for the whole workgroup: thread 0 draws one (or ends the
+    // phase, also on cancel) and every wave of the group works on it, so all
+    // waves pass the same barriers.  Then each wave helps on its own.
+    unsigned long long *shared_leaf = reinterpret_cast<unsigned long long *>(wg_exits);
+    for (;;) {
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        unsigned long long next = kNone;
+        if (P.cancel != nullptr && *P.cancel != 0) {
+          atomicOr(&P.gctr[kCtrErr], kErrCancel);
+        } else {
+          const unsigned long long k = atomicAdd(&P.lctr[kLcNextLeaf], 1ull);
+          if (k < P.leaf_count) next = P.leaf_begin + k;
+        }
+        *shared_leaf = next;
+      }
+      __syncthreads();
+      const uint64_t j = *shared_leaf;
+      if (j == kNone) break;
+      if (P.leaf_count > 64 && lane == 0)
+        __hip_atomic_store(&P.wleaf[wid], (uint32_t)j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      work_leaf<SPL, RF>(P, j, wave != 0, lds, st);
+    }
+    fresh = false;
+  }
   uint32_t idle_rounds = 0;
   for (;;) {
     if (P.cancel != nullptr && *P.cancel != 0) {
@@ -1011,6 +1041,7 @@ int check_opts(const shock_opts &opts, uint64_t n_leaves, const void *offsets, c
   if (opts.workers < 0 || opts.workers > (1 << 20)) return SHOCK_EINVAL;
   if (opts.leaf_size_hint < 0 || opts.leaf_size_hint > 64) return SHOCK_EINVAL;
   if (opts.partial_k != 0 && opts.partial_k != 1 && opts.partial_k != 8) return SHOCK_EINVAL;
+  if (opts.team < 0 || opts.team > 2) return SHOCK_EINVAL;
   return SHOCK_OK;
 }
 
@@ -1068,6 +1099,7 @@ Params base_params(const CallBufs &cb, const Plan &pl, const shock_opts &opts, c
   P.unit = pl.rf ? 64ull * kRfSeedsPerLane : 64ull * (uint64_t)pl.spl;
   P.block = P.unit * (uint64_t)pl.units;
   P.partial_k = (uint32_t)opts.partial_k;
+  P.team = opts.team == 1 ? 0u : 1u;
   P.sides = cb.sides;
   P.workers = (uint32_t)pl.workers;
   memcpy(P.units_by_n, pl.units_by_n, sizeof(P.units_by_n));

@@ -99,6 +99,8 @@ LAUNCH_CONFIGS = [
     dict(spl=1, block_iters=2, waves_per_wg=8, workers=2048),
     dict(mode=1, spl=2, block_iters=1),
     dict(mode=1, spl=4, block_iters=2, workers=512),
+    dict(team=2, waves_per_wg=4, block_iters=2),
+    dict(team=2, waves_per_wg=16, workers=64, block_iters=1),
 ]
 
 

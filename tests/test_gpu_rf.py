@@ -83,6 +83,8 @@ LAUNCHES = [
     dict(mode=2, block_iters=1, workers=64),
     dict(mode=2, block_iters=5, workers=4096, waves_per_wg=2),
     dict(mode=2, workers=8, waves_per_wg=8),
+    dict(mode=2, team=1, waves_per_wg=4),
+    dict(mode=2, team=2, waves_per_wg=16, workers=128),
 ]
 
 
