@@ -20,7 +20,7 @@
  * code, Section 8 and Section 5's uniform-hashing footnote):
  *   fmix64 = MurmurHash3's 64-bit finaliser,
  *   a = fmix64(key), t = fmix64((s + 1) * 0x9E3779B97F4A7C15) (mod 2^64),
- *   c = a ^ t, P = lo32(c) * hi32(c) (64-bit product), z = lo32(P) ^ hi32(P),
+ *   P = (lo32(a) ^ lo32(t)) * hi32(a) + t (mod 2^64), z = lo32(P) ^ hi32(P),
  *   h0 = ((z & 0xFFFF) * n) >> 16, r = ((z >> 16) * (n - 1)) >> 16,
  *   h1 = r + (r >= h0) for n >= 2 (never equal to h0: no self-loops,
  *   matching the paper's implementation footnote in Section 5), h1 = 0 if n = 1.
@@ -173,7 +173,9 @@ const char *shock_strerror(int status);
 /* Free the calling thread's cached scratch memory of the current device. */
 int shock_release_scratch(void);
 
-/* Library version of the frozen hash/orientation definition (1). */
+/* Library version of the frozen hash/orientation definition (2: the per-seed
+ * mix enters through one multiply-add; version 1 multiplied lo32(a ^ t) by
+ * hi32(a ^ t)). */
 int shock_spec_version(void);
 
 /* ---- Contexts: asynchronous searches, several in flight, HIP graphs ------

@@ -25,8 +25,7 @@ uint64_t shock_oracle_fmix64(uint64_t k) {
 void shock_oracle_slots(uint64_t x, uint64_t s, uint32_t n, uint32_t *h0, uint32_t *h1) {
   uint64_t a = shock_oracle_fmix64(x);
   uint64_t t = shock_oracle_fmix64((s + 1) * GOLDEN);
-  uint64_t c = a ^ t;
-  uint64_t p = (uint64_t)(uint32_t)c * (uint64_t)(uint32_t)(c >> 32);
+  uint64_t p = (uint64_t)((uint32_t)a ^ (uint32_t)t) * (a >> 32) + t; /* mod 2^64 */
   uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
   uint32_t first = (uint32_t)(((uint64_t)(z & 0xFFFFu) * n) >> 16);
   *h0 = first;
@@ -449,8 +448,7 @@ int shock_oracle_rice_decode(const uint64_t *fixed, const uint64_t *unary, const
 void shock_oracle_bip_slots(uint64_t x, uint64_t s, uint32_t n, uint32_t *left, uint32_t *right) {
   uint64_t a = shock_oracle_fmix64(x);
   uint64_t t = shock_oracle_fmix64((s + 1) * GOLDEN);
-  uint64_t c = a ^ t;
-  uint64_t p = (uint64_t)(uint32_t)c * (uint64_t)(uint32_t)(c >> 32);
+  uint64_t p = (uint64_t)((uint32_t)a ^ (uint32_t)t) * (a >> 32) + t; /* mod 2^64 */
   uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
   uint32_t nl = n / 2, nr = n - nl;
   *left = (uint32_t)(((uint64_t)(z & 0xFFFFu) * nl) >> 16);

@@ -24,8 +24,8 @@
  *                 k *= 0xc4ceb9fe1a85ec53; k ^= k>>33
  *   a(x)        = fmix64(x)                              (per key)
  *   t(s)        = fmix64((s + 1) * 0x9E3779B97F4A7C15)   (per seed, mod 2^64)
- *   c           = a(x) XOR t(s)
- *   P           = lo32(c) * hi32(c)                      (exact 64-bit product)
+ *   P           = (lo32(a) XOR lo32(t)) * hi32(a) + t    (mod 2^64; one
+ *                 32x32+64 multiply-add)
  *   z           = lo32(P) XOR hi32(P)
  *   h0          = ((z mod 2^16) * n) >> 16
  *   r           = ((z >> 16) * (n - 1)) >> 16            (r in [0, n-2])

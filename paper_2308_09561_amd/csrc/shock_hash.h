@@ -3,7 +3,8 @@
 // master hash code (Sections 5 and 8); this is the concrete choice:
 //   a = fmix64(x)                              MurmurHash3's 64-bit finaliser
 //   t = fmix64((s + 1) * 0x9E3779B97F4A7C15)   per seed, mod 2^64
-//   c = a ^ t;  P = lo32(c) * hi32(c);  z = lo32(P) ^ hi32(P)
+//   P = (lo32(a) ^ lo32(t)) * hi32(a) + t  (mod 2^64: one 32x32+64 multiply-add);
+//   z = lo32(P) ^ hi32(P)
 //   h0 = ((z mod 2^16) * n) >> 16;  r = ((z >> 16) * (n - 1)) >> 16
 //   h1 = r + (r >= h0)   (h1 != h0 for n >= 2; no self-loops)
 // Rotation fitting's 1-bit set hash: the top bit of fmix64(x ^ kSideKey).
@@ -35,9 +36,8 @@ __device__ __forceinline__ uint64_t seed_mix(uint64_t s) { return fmix64((s + 1)
 // the per-seed halves (tlo, thi); nm1 = n - 1, n >= 2.
 __device__ __forceinline__ void slot_pair(uint32_t alo, uint32_t ahi, uint32_t tlo, uint32_t thi, uint32_t n,
                                           uint32_t nm1, uint32_t &h0, uint32_t &h1) {
-  const uint32_t clo = alo ^ tlo;
-  const uint32_t chi = ahi ^ thi;
-  const uint64_t p = (uint64_t)clo * (uint64_t)chi;
+  const uint64_t t = ((uint64_t)thi << 32) | tlo;
+  const uint64_t p = (uint64_t)(alo ^ tlo) * (uint64_t)ahi + t;
   const uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
   uint32_t f0 = __umulhi(z << 16, n);            // ((z & 0xFFFF) * n) >> 16
   uint32_t r = __umulhi(z & 0xFFFF0000u, nm1);    // ((z >> 16) * (n-1)) >> 16
