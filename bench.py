@@ -27,12 +27,13 @@ PEAK_INT_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 int32 lanes per clock x 2.4 GHz
 # Algorithmic 32-bit integer operations of the frozen hash and filter, counted
 # as the fewest gfx950 VALU instructions that compute them:
 # per key-evaluation: 1 xor (low halves of key and seed mix), 1 multiply-add
-# 32x32+64->64 (the high half of the key, plus the seed mix), 2 fold + 16-bit
-# field extractions (xor with shift, xor with mask), 2 fastrange
-# multiply-highs, h1 = r + (r >= h0) (compare + add-with-carry), two 64-bit
-# bit-sets and two 3-input ORs into the coverage mask: 12.  Per seed: the seed
-# mix fmix64((s+1)*gamma) (19) and the coverage compare (1): 20.
-OPS_PER_EVAL = 12
+# 32x32+64->64 (the high half of the key, plus the seed mix), 1 fold xor (z),
+# 1 multiply 32x32->64 (z * n: h0 in the high half, the fraction in the low),
+# 1 multiply-high (r from the fraction), h1 = r + (r >= h0) (compare +
+# add-with-carry), two 64-bit bit-sets and two 3-input ORs into the coverage
+# mask: 11.  Per seed: the seed mix fmix64((s+1)*gamma) (19) and the coverage
+# compare (1): 20.
+OPS_PER_EVAL = 11
 OPS_PER_SEED = 20
 # Rotation fitting (Section 4; partial hashing, Appendix A.2), per seed of a
 # leaf with na keys in the first set, nb in the second and period k: nb key

@@ -21,7 +21,7 @@
  *   fmix64 = MurmurHash3's 64-bit finaliser,
  *   a = fmix64(key), t = fmix64((s + 1) * 0x9E3779B97F4A7C15) (mod 2^64),
  *   P = (lo32(a) ^ lo32(t)) * hi32(a) + t (mod 2^64), z = lo32(P) ^ hi32(P),
- *   h0 = ((z & 0xFFFF) * n) >> 16, r = ((z >> 16) * (n - 1)) >> 16,
+ *   Q = z * n (exact 64-bit), h0 = hi32(Q), r = (lo32(Q) * (n - 1)) >> 32,
  *   h1 = r + (r >= h0) for n >= 2 (never equal to h0: no self-loops,
  *   matching the paper's implementation footnote in Section 5), h1 = 0 if n = 1.
  *
@@ -130,7 +130,8 @@ int shock_rf_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint6
  * The n cells are split into a left part [0, nl), nl = floor(n / 2), and a
  * right part [nl, n).  With z the 32-bit hash value of key x under seed s
  * (the family above):
- *   left(x, s) = ((z mod 2^16) * nl) >> 16,  right(x, s) = nl + (((z >> 16) * (n - nl)) >> 16)
+ *   Q = z * nl (exact 64-bit), left(x, s) = hi32(Q),
+ *   right(x, s) = nl + ((lo32(Q) * (n - nl)) >> 32)
  * A pair (a, b) gives key x the cells left(x, a) and right(x, b).  Per leaf:
  *   out_a, out_b device u64[n_leaves]: the first pair in the order max(a, b),
  *       then a, then b whose graph is a pseudoforest (UINT64_MAX if none with
@@ -173,9 +174,10 @@ const char *shock_strerror(int status);
 /* Free the calling thread's cached scratch memory of the current device. */
 int shock_release_scratch(void);
 
-/* Library version of the frozen hash/orientation definition (2: the per-seed
- * mix enters through one multiply-add; version 1 multiplied lo32(a ^ t) by
- * hi32(a ^ t)). */
+/* Library version of the frozen hash/orientation definition (3: h0 and r come
+ * from one multiply-shift range reduction of z and the fraction it leaves;
+ * version 2 reduced the two 16-bit halves of z separately; version 1
+ * multiplied lo32(a ^ t) by hi32(a ^ t)). */
 int shock_spec_version(void);
 
 /* ---- Contexts: asynchronous searches, several in flight, HIP graphs ------

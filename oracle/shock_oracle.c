@@ -27,13 +27,14 @@ void shock_oracle_slots(uint64_t x, uint64_t s, uint32_t n, uint32_t *h0, uint32
   uint64_t t = shock_oracle_fmix64((s + 1) * GOLDEN);
   uint64_t p = (uint64_t)((uint32_t)a ^ (uint32_t)t) * (a >> 32) + t; /* mod 2^64 */
   uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
-  uint32_t first = (uint32_t)(((uint64_t)(z & 0xFFFFu) * n) >> 16);
+  uint64_t q = (uint64_t)z * n; /* z / 2^32 scaled to [0, n): integer part h0, fraction lo32(q) */
+  uint32_t first = (uint32_t)(q >> 32);
   *h0 = first;
   if (n < 2) {
     *h1 = 0; /* a single cell: the only slot there is */
     return;
   }
-  uint32_t r = (uint32_t)(((uint64_t)(z >> 16) * (n - 1)) >> 16);
+  uint32_t r = (uint32_t)(((q & 0xFFFFFFFFu) * (n - 1)) >> 32);
   *h1 = r + (r >= first ? 1u : 0u);
 }
 
@@ -451,8 +452,9 @@ void shock_oracle_bip_slots(uint64_t x, uint64_t s, uint32_t n, uint32_t *left, 
   uint64_t p = (uint64_t)((uint32_t)a ^ (uint32_t)t) * (a >> 32) + t; /* mod 2^64 */
   uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
   uint32_t nl = n / 2, nr = n - nl;
-  *left = (uint32_t)(((uint64_t)(z & 0xFFFFu) * nl) >> 16);
-  *right = nl + (uint32_t)(((uint64_t)(z >> 16) * nr) >> 16);
+  uint64_t q = (uint64_t)z * nl;
+  *left = (uint32_t)(q >> 32);
+  *right = nl + (uint32_t)(((q & 0xFFFFFFFFu) * nr) >> 32);
 }
 
 /* Candidate flags of seed s: bit 0 left part covered, bit 1 right part covered. */

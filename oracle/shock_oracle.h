@@ -27,8 +27,9 @@
  *   P           = (lo32(a) XOR lo32(t)) * hi32(a) + t    (mod 2^64; one
  *                 32x32+64 multiply-add)
  *   z           = lo32(P) XOR hi32(P)
- *   h0          = ((z mod 2^16) * n) >> 16
- *   r           = ((z >> 16) * (n - 1)) >> 16            (r in [0, n-2])
+ *   Q           = z * n                                  (exact 64-bit product)
+ *   h0          = Q >> 32                                (h0 in [0, n-1])
+ *   r           = ((Q mod 2^32) * (n - 1)) >> 32         (r in [0, n-2])
  *   h1          = r + (r >= h0 ? 1 : 0)  for n >= 2;  h1 = 0 for n = 1
  * so h1 != h0 whenever n >= 2: the graph has no self-loops, which is the
  * variant the paper's implementation uses (footnote in Section 5).
@@ -164,8 +165,9 @@ int shock_oracle_rice_decode(const uint64_t *fixed, const uint64_t *unary, const
  * The table's n cells are split into a left part [0, nl), nl = floor(n / 2),
  * and a right part [nl, n).  Under seed s, with z the 32-bit hash value of
  * key x of the frozen family (shock_oracle_slots' z):
- *   left(x, s)  = ((z mod 2^16) * nl) >> 16            (0 when nl = 0)
- *   right(x, s) = nl + (((z >> 16) * (n - nl)) >> 16)
+ *   Q           = z * nl                               (exact 64-bit product)
+ *   left(x, s)  = Q >> 32                              (0 when nl = 0)
+ *   right(x, s) = nl + (((Q mod 2^32) * (n - nl)) >> 32)
  * A pair (a, b) of seeds gives key x the candidate cells left(x, a) and
  * right(x, b); the leaf's result is the pair whose graph is a pseudoforest
  * that comes first in the order max(a, b), then a, then b -- the order in

@@ -1,11 +1,12 @@
-// The library's frozen hash family (spec version 1), shared by the search and
+// The library's frozen hash family (spec version 3), shared by the search and
 // query kernels.  The paper assumes fully random h0, h1 evaluated on a 64-bit
 // master hash code (Sections 5 and 8); this is the concrete choice:
 //   a = fmix64(x)                              MurmurHash3's 64-bit finaliser
 //   t = fmix64((s + 1) * 0x9E3779B97F4A7C15)   per seed, mod 2^64
 //   P = (lo32(a) ^ lo32(t)) * hi32(a) + t  (mod 2^64: one 32x32+64 multiply-add);
-//   z = lo32(P) ^ hi32(P)
-//   h0 = ((z mod 2^16) * n) >> 16;  r = ((z >> 16) * (n - 1)) >> 16
+//   z = lo32(P) ^ hi32(P);  Q = z * n   (exact 64-bit product)
+//   h0 = hi32(Q);  r = (lo32(Q) * (n - 1)) >> 32   (r reuses the fraction
+//   that the multiply-shift range reduction of h0 leaves behind)
 //   h1 = r + (r >= h0)   (h1 != h0 for n >= 2; no self-loops)
 // Rotation fitting's 1-bit set hash: the top bit of fmix64(x ^ kSideKey).
 #pragma once
@@ -39,8 +40,9 @@ __device__ __forceinline__ void slot_pair(uint32_t alo, uint32_t ahi, uint32_t t
   const uint64_t t = ((uint64_t)thi << 32) | tlo;
   const uint64_t p = (uint64_t)(alo ^ tlo) * (uint64_t)ahi + t;
   const uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
-  uint32_t f0 = __umulhi(z << 16, n);            // ((z & 0xFFFF) * n) >> 16
-  uint32_t r = __umulhi(z & 0xFFFF0000u, nm1);    // ((z >> 16) * (n-1)) >> 16
+  const uint64_t q = (uint64_t)z * n;             // one v_mad_u64_u32
+  uint32_t f0 = (uint32_t)(q >> 32);
+  uint32_t r = __umulhi((uint32_t)q, nm1);
   // h1 = r + (r >= h0).  The empty asm statements hide the operands' origin
   // so that the compare stays 32-bit (one v_cmp + one v_addc) instead of
   // being widened to 64 bits for the later 64-bit shift.

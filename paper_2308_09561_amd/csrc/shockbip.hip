@@ -62,8 +62,9 @@ struct BipParams {
 __device__ __forceinline__ void bip_cells(uint64_t a, uint64_t t, uint32_t nl, uint32_t nr, uint32_t &l, uint32_t &r) {
   const uint64_t p = (uint64_t)((uint32_t)a ^ (uint32_t)t) * (a >> 32) + t;
   const uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
-  l = __umulhi(z << 16, nl);
-  r = nl + __umulhi(z & 0xFFFF0000u, nr);
+  const uint64_t q = (uint64_t)z * nl;
+  l = (uint32_t)(q >> 32);
+  r = nl + __umulhi((uint32_t)q, nr);
 }
 
 // Whether pair (a, b) qualifies; lane i < n gets its edge (left under a, right under b).

@@ -1238,7 +1238,7 @@ const char *shock_strerror(int s) {
   }
 }
 
-int shock_spec_version(void) { return 2; }
+int shock_spec_version(void) { return 3; }
 
 int shock_last_stats(shock_stats *out) {
   if (!out) return SHOCK_EINVAL;
