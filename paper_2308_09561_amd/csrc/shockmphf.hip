@@ -23,6 +23,7 @@
 #include <string.h>
 
 #include <chrono>
+#include <vector>
 
 #include "shockcode.h"
 #include "shockmphf.h"
@@ -80,6 +81,10 @@ __device__ __forceinline__ uint64_t wave_excl_scan(uint64_t v) {
 __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+__global__ void fill_u64_kernel(unsigned long long *p, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
 }
 __global__ void fill_u8_kernel(uint8_t *p, uint64_t n) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -274,64 +279,139 @@ __global__ void choice_kernel(const uint64_t *__restrict__ leaf_off, const uint8
     if (lane < leaf_sizes[g]) choice[leaf_off[g] + lane] = (uint8_t)((orient[g] >> lane) & 1);
 }
 
+// Retrieval peeling.  Each cell holds one 64-bit word: the number of keys not
+// yet peeled that hash to it (bits 48..63) plus the sum of their indices (bits
+// 0..47; a sum of fewer than 2^16 indices below 2^32 never carries into the
+// count).  A cell of count one therefore names its key.  Rounds are
+// synchronous: every key with a cell of count one at the start of a round is
+// peeled in that round, at its first such cell.  The cells that can have count
+// one at the start of a round are exactly those whose count fell to one in the
+// previous round (the frontier), so a round touches only its frontier and the
+// keys it peels.
+constexpr uint64_t kCountOne = 1ull << 48;
+constexpr uint32_t kMaxPeelRounds = 1u << 14;
+enum : int { kPkFrBegin = 0, kPkFrEnd, kPkFrTail, kPkStBegin, kPkStTail, kPkRound, kPkWords };
+
+__device__ __forceinline__ uint64_t wave_append(unsigned long long *tail, bool take) {
+  const uint64_t mask = __ballot(take);
+  if (mask == 0) return 0;
+  const uint32_t lane = lane_id();
+  const uint32_t leader = __ffsll((long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(tail, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  return base + __popcll(mask & ((1ull << lane) - 1));
+}
+
 __global__ void xor_count_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
-                                 uint32_t *cnt, uint32_t *round) {
+                                 unsigned long long *cw) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_keys; i += stride) {
     uint64_t c[3];
     xor_cells(keys[i], rmix, seg, c);
-    atomicAdd(&cnt[c[0]], 1u);
-    atomicAdd(&cnt[c[1]], 1u);
-    atomicAdd(&cnt[c[2]], 1u);
-    round[i] = 0;
+    for (int q = 0; q < 3; ++q) atomicAdd(&cw[c[q]], kCountOne + i);
   }
 }
 
-// Round r, detect: every key not yet peeled with a cell of count one (at the
-// start of the round) is peeled in this round at its first such cell.
-__global__ void xor_detect_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
-                                  const uint32_t *__restrict__ cnt, uint32_t *round, uint8_t *peel, uint32_t r,
-                                  unsigned long long *peeled) {
+// The first frontier: every cell of count one.
+__global__ void xor_frontier_kernel(const unsigned long long *__restrict__ cw, uint64_t cells, uint64_t *frontier,
+                                    unsigned long long *pk) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n_keys; i0 += stride) {
-    const uint64_t i = i0 + threadIdx.x;
+  for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x; c0 < cells; c0 += stride) {
+    const uint64_t c = c0 + threadIdx.x;
+    const bool one = c < cells && (cw[c] >> 48) == 1;
+    const uint64_t at = wave_append(&pk[kPkFrTail], one);
+    if (one && at < cells) frontier[at] = c;
+  }
+}
+
+// Opens the next round on the frontier appended by the previous one (none if
+// it is empty: then the round's passes find nothing to do) and records where
+// the previous round's peeled keys end.
+__global__ void xor_advance_kernel(unsigned long long *pk, uint64_t *round_off) {
+  if (threadIdx.x != 0) return;
+  const uint64_t r = pk[kPkRound];
+  const uint64_t st = pk[kPkStTail];
+  round_off[r] = st;
+  pk[kPkStBegin] = st;
+  const uint64_t b = pk[kPkFrEnd], e = pk[kPkFrTail];
+  pk[kPkFrEnd] = e;
+  if (e > b && r < kMaxPeelRounds) {
+    pk[kPkFrBegin] = b;
+    pk[kPkRound] = r + 1;
+  } else {
+    pk[kPkFrBegin] = e;
+  }
+}
+
+// Detect: the key of each frontier cell that still has count one is peeled at
+// its first cell of count one (counts are not changed during this pass); a
+// bitmap keeps a key that owns two frontier cells from being taken twice.
+__global__ void xor_detect_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
+                                  const unsigned long long *__restrict__ cw, const uint64_t *__restrict__ frontier,
+                                  uint64_t cells, uint32_t *taken, uint8_t *peel, uint32_t *stack,
+                                  unsigned long long *pk) {
+  // Ranges are clamped to the arrays (they always fit: a cell joins a frontier
+  // at most once and a key is peeled at most once).
+  const uint64_t e = pk[kPkFrEnd] < cells ? pk[kPkFrEnd] : cells;
+  const uint64_t b = pk[kPkFrBegin] < e ? pk[kPkFrBegin] : e;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k0 = b + (uint64_t)blockIdx.x * blockDim.x; k0 < e; k0 += stride) {
+    const uint64_t k = k0 + threadIdx.x;
     bool got = false;
-    if (i < n_keys && round[i] == 0) {
-      uint64_t c[3];
-      xor_cells(keys[i], rmix, seg, c);
-      for (int q = 0; q < 3; ++q) {
-        if (cnt[c[q]] == 1) {
-          round[i] = r;
+    uint64_t i = 0;
+    if (k < e) {
+      const uint64_t w = cw[frontier[k]];
+      i = w & (kCountOne - 1);
+      if ((w >> 48) == 1 && i < n_keys) {
+        const uint32_t bit = 1u << (i & 31);
+        if (!(atomicOr(&taken[i >> 5], bit) & bit)) {
+          uint64_t c[3];
+          xor_cells(keys[i], rmix, seg, c);
+          uint32_t q = 0;
+          while (q < 2 && (cw[c[q]] >> 48) != 1) ++q;
           peel[i] = (uint8_t)q;
           got = true;
-          break;
         }
       }
     }
-    const uint64_t mask = __ballot(got);
-    if (lane_id() == 0 && mask) atomicAdd(peeled, (unsigned long long)__popcll(mask));
+    const uint64_t at = wave_append(&pk[kPkStTail], got);
+    if (got && at < n_keys) stack[at] = (uint32_t)i;
   }
 }
 
+// Remove the round's keys; a cell whose count falls from two to one joins the
+// next frontier.
 __global__ void xor_remove_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
-                                  uint32_t *cnt, const uint32_t *__restrict__ round, uint32_t r) {
+                                  unsigned long long *cw, const uint32_t *__restrict__ stack, uint64_t *frontier,
+                                  uint64_t cells, unsigned long long *pk) {
+  const uint64_t e = pk[kPkStTail] < n_keys ? pk[kPkStTail] : n_keys;
+  const uint64_t b = pk[kPkStBegin] < e ? pk[kPkStBegin] : e;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_keys; i += stride) {
-    if (round[i] != r) continue;
-    uint64_t c[3];
-    xor_cells(keys[i], rmix, seg, c);
-    atomicSub(&cnt[c[0]], 1u);
-    atomicSub(&cnt[c[1]], 1u);
-    atomicSub(&cnt[c[2]], 1u);
+  for (uint64_t k0 = b + (uint64_t)blockIdx.x * blockDim.x; k0 < e; k0 += stride) {
+    const uint64_t k = k0 + threadIdx.x;
+    uint64_t c[3] = {0, 0, 0};
+    bool two[3] = {false, false, false};
+    if (k < e) {
+      const uint32_t i = stack[k];
+      xor_cells(keys[i], rmix, seg, c);
+      for (int q = 0; q < 3; ++q) two[q] = (atomicSub(&cw[c[q]], kCountOne + i) >> 48) == 2;
+    }
+    for (int q = 0; q < 3; ++q) {
+      const uint64_t at = wave_append(&pk[kPkFrTail], two[q]);
+      if (two[q] && at < cells) frontier[at] = c[q];
+    }
   }
 }
 
-__global__ void xor_assign_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
-                                  const uint32_t *__restrict__ round, const uint8_t *__restrict__ peel,
-                                  const uint8_t *__restrict__ choice, uint8_t *z, uint32_t r) {
+// Assignment of one round's keys (keys of a round write distinct cells and read
+// none written in that round).
+__global__ void xor_assign_kernel(const uint64_t *__restrict__ keys, uint64_t rmix, uint64_t seg,
+                                  const uint32_t *__restrict__ stack, uint64_t begin, uint64_t end,
+                                  const uint8_t *__restrict__ peel, const uint8_t *__restrict__ choice, uint8_t *z) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_keys; i += stride) {
-    if (round[i] != r) continue;
+  for (uint64_t k = begin + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < end; k += stride) {
+    const uint32_t i = stack[k];
     uint64_t c[3];
     xor_cells(keys[i], rmix, seg, c);
     const uint32_t p = peel[i];
@@ -625,50 +705,78 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   tp = std::chrono::steady_clock::now();
   // retrieval of each key's choice
   uint8_t *choice = nullptr, *peel = nullptr, *z = nullptr;
-  uint32_t *cnt = nullptr, *round = nullptr;
+  uint32_t *taken = nullptr, *stack = nullptr;
+  unsigned long long *cw = nullptr, *pk = nullptr;
+  uint64_t *frontier = nullptr, *round_off = nullptr, *pk_host = nullptr;
   const uint64_t seg = (123 * N + 299) / 300 + 8, cells = 3 * seg;
+  const uint64_t taken_words = (N + 31) / 32;
   M->seg = seg;
   HIP_TRY(S.alloc(&choice, N));
   HIP_TRY(S.alloc(&peel, N));
-  HIP_TRY(S.alloc(&round, N));
-  HIP_TRY(S.alloc(&cnt, cells));
+  HIP_TRY(S.alloc(&taken, taken_words));
+  HIP_TRY(S.alloc(&stack, N));
+  HIP_TRY(S.alloc(&cw, cells));
+  HIP_TRY(S.alloc(&frontier, cells));
+  HIP_TRY(S.alloc(&round_off, kMaxPeelRounds + 1));
+  HIP_TRY(S.alloc(&pk, kPkWords));
   HIP_TRY(S.alloc(&z, cells));
+  HIP_TRY(hipHostMalloc((void **)&pk_host, kPkWords * sizeof(uint64_t)));
+  struct PkFree {
+    uint64_t *p;
+    ~PkFree() { (void)hipHostFree(p); }
+  } pk_guard{pk_host};
   if (L)
     hipLaunchKernelGGL(choice_kernel, dim3(grid_for(L, 4)), dim3(256), 0, stream, (const uint64_t *)leaf_off,
                        (const uint8_t *)M->leaf_sizes, (const uint64_t *)orient, L, choice);
   HIP_TRY(hipGetLastError());
+  // Round passes run a fixed grid over device-held ranges; the host checks
+  // for the end of the peeling after each chunk of rounds.
+  const int round_grid = grid_for((cells + 3) / 4, 256) < 2048 ? grid_for((cells + 3) / 4, 256) : 2048;
+  constexpr uint32_t kChunk = 16;
   bool solved = false;
   uint32_t rounds = 0;
   for (uint32_t t = 0; t < P.max_rho_tries && !solved; ++t) {
     const uint64_t rho = t;
     M->rho_tries = t + 1;
     const uint64_t rmix = shockhash::fmix64((rho + 1) * kRetrievalMul);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, cnt, cells, 0u);
-    if (N) hipLaunchKernelGGL(xor_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg, cnt, round);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, cw, cells);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(taken_words, 256)), dim3(256), 0, stream, taken, taken_words,
+                       0u);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, stream, pk, (uint64_t)kPkWords);
+    if (N) hipLaunchKernelGGL(xor_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg, cw);
+    hipLaunchKernelGGL(xor_frontier_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream,
+                       (const unsigned long long *)cw, cells, frontier, pk);
     HIP_TRY(hipGetLastError());
-    uint64_t left = N;
-    uint32_t r = 0;
-    while (left > 0) {
-      ++r;
-      HIP_TRY(hipMemsetAsync(err + 1, 0, 8, stream));
-      hipLaunchKernelGGL(xor_detect_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg,
-                         (const uint32_t *)cnt, round, peel, r, err + 1);
+    for (;;) {
+      for (uint32_t c = 0; c < kChunk; ++c) {
+        hipLaunchKernelGGL(xor_advance_kernel, dim3(1), dim3(64), 0, stream, pk, round_off);
+        hipLaunchKernelGGL(xor_detect_kernel, dim3(round_grid), dim3(256), 0, stream, leaf_keys, N, rmix, seg,
+                           (const unsigned long long *)cw, (const uint64_t *)frontier, cells, taken, peel, stack,
+                           pk);
+        hipLaunchKernelGGL(xor_remove_kernel, dim3(round_grid), dim3(256), 0, stream, leaf_keys, N, rmix, seg, cw,
+                           (const uint32_t *)stack, frontier, cells, pk);
+      }
       HIP_TRY(hipGetLastError());
-      HIP_TRY(hipMemcpyAsync(&host[2], err + 1, 8, hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipMemcpyAsync(pk_host, pk, kPkWords * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
       HIP_TRY(hipStreamSynchronize(stream));
-      const uint64_t peeled = host[2];
-      if (peeled == 0) break;
-      hipLaunchKernelGGL(xor_remove_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg,
-                         cnt, (const uint32_t *)round, r);
-      HIP_TRY(hipGetLastError());
-      left -= peeled;
+      // done when the last round appended no frontier cells
+      if (pk_host[kPkFrTail] == pk_host[kPkFrEnd] || pk_host[kPkRound] >= kMaxPeelRounds) break;
     }
-    if (left > 0) continue;
-    rounds = r;  // every round of a successful peeling removed keys
+    if (pk_host[kPkStTail] != N || pk_host[kPkFrTail] > cells) continue;  // a 2-core is left: next retrieval seed
+    const uint32_t R = (uint32_t)pk_host[kPkRound];
+    std::vector<uint64_t> off(R + 1);
+    HIP_TRY(hipMemcpyAsync(off.data(), round_off, R * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    off[R] = N;
     hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, z, cells);
-    for (uint32_t rr = rounds; rr >= 1; --rr)
-      hipLaunchKernelGGL(xor_assign_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg,
-                         (const uint32_t *)round, (const uint8_t *)peel, (const uint8_t *)choice, z, rr);
+    rounds = 0;
+    for (uint32_t rr = R; rr >= 1; --rr) {
+      const uint64_t b = off[rr - 1], e = off[rr];
+      if (e <= b) continue;
+      ++rounds;
+      hipLaunchKernelGGL(xor_assign_kernel, dim3(grid_for(e - b, 256)), dim3(256), 0, stream, leaf_keys, rmix, seg,
+                         (const uint32_t *)stack, b, e, (const uint8_t *)peel, (const uint8_t *)choice, z);
+    }
     HIP_TRY(hipGetLastError());
     M->rho = rho;
     solved = true;

@@ -277,11 +277,14 @@ def synthetic_stream(n_requests: int, rate_per_s: float, seed: int = 5, min_keys
 
 
 def mphf_footprint(n_keys: int) -> int:
-    """Device bytes an MPHF build of n_keys holds at its peak: the keys, two
-    reordered copies, leaf search outputs and scratch, and the retrieval's
-    counters, rounds, choices and cells (about 36 bytes per key)."""
+    """Device bytes an MPHF build of n_keys holds at its peak, during the
+    retrieval: the keys and their leaf-ordered copy (16 bytes per key), leaf
+    search outputs and scratch, and the retrieval's 1.23 cells per key (an
+    8-byte count word, an 8-byte frontier slot and a value byte each) plus 6
+    bytes per key of choices, peel positions and the peel stack: about 43
+    bytes per key."""
     leaves = n_keys // 8 + 1
-    return 24 * n_keys + (16 + SCRATCH_BYTES_PER_LEAF) * leaves + 12 * n_keys + (1 << 20)
+    return 43 * n_keys + (16 + SCRATCH_BYTES_PER_LEAF) * leaves + (1 << 20)
 
 
 class MphfServer:
