@@ -292,15 +292,35 @@ constexpr uint64_t kCountOne = 1ull << 48;
 constexpr uint32_t kMaxPeelRounds = 1u << 14;
 enum : int { kPkFrBegin = 0, kPkFrEnd, kPkFrTail, kPkStBegin, kPkStTail, kPkRound, kPkWords };
 
-__device__ __forceinline__ uint64_t wave_append(unsigned long long *tail, bool take) {
-  const uint64_t mask = __ballot(take);
-  if (mask == 0) return 0;
-  const uint32_t lane = lane_id();
-  const uint32_t leader = __ffsll((long long)mask) - 1;
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(tail, (unsigned long long)__popcll(mask));
-  base = __shfl(base, leader);
-  return base + __popcll(mask & ((1ull << lane) - 1));
+// Block-wide append: each thread offers cnt slots; returns the index of its
+// first one.  One global atomic per call and block (a counter shared by the
+// whole grid serialises its atomics, about 12 ns each), so callers batch
+// several items per thread.  Every thread of the block must call it.
+constexpr uint32_t kAppendThreads = 256;
+__device__ __forceinline__ uint64_t block_append(unsigned long long *tail, uint32_t cnt) {
+  __shared__ uint32_t wave_sum[kAppendThreads / 64];
+  __shared__ unsigned long long base_s;
+  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  uint32_t x = cnt;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  if (lane == 63) wave_sum[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) {
+      const uint32_t t = wave_sum[w];
+      wave_sum[w] = tot;
+      tot += t;
+    }
+    base_s = tot ? atomicAdd(tail, (unsigned long long)tot) : 0ull;
+  }
+  __syncthreads();
+  const uint64_t at = base_s + wave_sum[wave] + x - cnt;
+  __syncthreads();  // the shared slots are reused by the next call
+  return at;
 }
 
 __global__ void xor_count_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
@@ -313,15 +333,27 @@ __global__ void xor_count_kernel(const uint64_t *__restrict__ keys, uint64_t n_k
   }
 }
 
-// The first frontier: every cell of count one.
-__global__ void xor_frontier_kernel(const unsigned long long *__restrict__ cw, uint64_t cells, uint64_t *frontier,
-                                    unsigned long long *pk) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t c0 = (uint64_t)blockIdx.x * blockDim.x; c0 < cells; c0 += stride) {
-    const uint64_t c = c0 + threadIdx.x;
-    const bool one = c < cells && (cw[c] >> 48) == 1;
-    const uint64_t at = wave_append(&pk[kPkFrTail], one);
-    if (one && at < cells) frontier[at] = c;
+// The first frontier: every cell of count one.  A block takes 8 cells per
+// thread at a time.
+constexpr uint32_t kFrontierPer = 8;
+__global__ __launch_bounds__(kAppendThreads) void xor_frontier_kernel(const unsigned long long *__restrict__ cw,
+                                                                      uint64_t cells, uint64_t *frontier,
+                                                                      unsigned long long *pk) {
+  const uint64_t chunk = (uint64_t)blockDim.x * kFrontierPer;
+  for (uint64_t c0 = (uint64_t)blockIdx.x * chunk; c0 < cells; c0 += (uint64_t)gridDim.x * chunk) {
+    uint32_t ones = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kFrontierPer; ++j) {
+      const uint64_t c = c0 + (uint64_t)j * blockDim.x + threadIdx.x;
+      if (c < cells && (cw[c] >> 48) == 1) ones |= 1u << j;
+    }
+    uint64_t at = block_append(&pk[kPkFrTail], __popc(ones));
+#pragma unroll
+    for (uint32_t j = 0; j < kFrontierPer; ++j)
+      if ((ones >> j) & 1) {
+        if (at < cells) frontier[at] = c0 + (uint64_t)j * blockDim.x + threadIdx.x;
+        ++at;
+      }
   }
 }
 
@@ -346,61 +378,79 @@ __global__ void xor_advance_kernel(unsigned long long *pk, uint64_t *round_off) 
 
 // Detect: the key of each frontier cell that still has count one is peeled at
 // its first cell of count one (counts are not changed during this pass); a
-// bitmap keeps a key that owns two frontier cells from being taken twice.
-__global__ void xor_detect_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
-                                  const unsigned long long *__restrict__ cw, const uint64_t *__restrict__ frontier,
-                                  uint64_t cells, uint32_t *taken, uint8_t *peel, uint32_t *stack,
-                                  unsigned long long *pk) {
+// bitmap keeps a key that owns two frontier cells from being taken twice.  A
+// thread takes up to 4 frontier cells at a time.
+constexpr uint32_t kDetectPer = 4;
+__global__ __launch_bounds__(kAppendThreads) void xor_detect_kernel(
+    const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
+    const unsigned long long *__restrict__ cw, const uint64_t *__restrict__ frontier, uint64_t cells,
+    uint32_t *taken, uint8_t *peel, uint32_t *stack, unsigned long long *pk) {
   // Ranges are clamped to the arrays (they always fit: a cell joins a frontier
   // at most once and a key is peeled at most once).
   const uint64_t e = pk[kPkFrEnd] < cells ? pk[kPkFrEnd] : cells;
   const uint64_t b = pk[kPkFrBegin] < e ? pk[kPkFrBegin] : e;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t k0 = b + (uint64_t)blockIdx.x * blockDim.x; k0 < e; k0 += stride) {
-    const uint64_t k = k0 + threadIdx.x;
-    bool got = false;
-    uint64_t i = 0;
-    if (k < e) {
+  const uint64_t chunk = (uint64_t)blockDim.x * kDetectPer;
+  for (uint64_t k0 = b + (uint64_t)blockIdx.x * chunk; k0 < e; k0 += (uint64_t)gridDim.x * chunk) {
+    uint32_t mine[kDetectPer];
+    uint32_t got = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kDetectPer; ++j) {
+      mine[j] = 0;
+      const uint64_t k = k0 + (uint64_t)j * blockDim.x + threadIdx.x;
+      if (k >= e) continue;
       const uint64_t w = cw[frontier[k]];
-      i = w & (kCountOne - 1);
-      if ((w >> 48) == 1 && i < n_keys) {
-        const uint32_t bit = 1u << (i & 31);
-        if (!(atomicOr(&taken[i >> 5], bit) & bit)) {
-          uint64_t c[3];
-          xor_cells(keys[i], rmix, seg, c);
-          uint32_t q = 0;
-          while (q < 2 && (cw[c[q]] >> 48) != 1) ++q;
-          peel[i] = (uint8_t)q;
-          got = true;
-        }
-      }
+      const uint64_t i = w & (kCountOne - 1);
+      if ((w >> 48) != 1 || i >= n_keys) continue;
+      const uint32_t bit = 1u << (i & 31);
+      if (atomicOr(&taken[i >> 5], bit) & bit) continue;
+      uint64_t c[3];
+      xor_cells(keys[i], rmix, seg, c);
+      uint32_t q = 0;
+      while (q < 2 && (cw[c[q]] >> 48) != 1) ++q;
+      peel[i] = (uint8_t)q;
+      mine[j] = (uint32_t)i;
+      got |= 1u << j;
     }
-    const uint64_t at = wave_append(&pk[kPkStTail], got);
-    if (got && at < n_keys) stack[at] = (uint32_t)i;
+    uint64_t at = block_append(&pk[kPkStTail], __popc(got));
+#pragma unroll
+    for (uint32_t j = 0; j < kDetectPer; ++j)
+      if ((got >> j) & 1) {
+        if (at < n_keys) stack[at] = mine[j];
+        ++at;
+      }
   }
 }
 
 // Remove the round's keys; a cell whose count falls from two to one joins the
-// next frontier.
-__global__ void xor_remove_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg,
-                                  unsigned long long *cw, const uint32_t *__restrict__ stack, uint64_t *frontier,
-                                  uint64_t cells, unsigned long long *pk) {
+// next frontier.  A thread takes up to 2 keys at a time.
+constexpr uint32_t kRemovePer = 2;
+__global__ __launch_bounds__(kAppendThreads) void xor_remove_kernel(
+    const uint64_t *__restrict__ keys, uint64_t n_keys, uint64_t rmix, uint64_t seg, unsigned long long *cw,
+    const uint32_t *__restrict__ stack, uint64_t *frontier, uint64_t cells, unsigned long long *pk) {
   const uint64_t e = pk[kPkStTail] < n_keys ? pk[kPkStTail] : n_keys;
   const uint64_t b = pk[kPkStBegin] < e ? pk[kPkStBegin] : e;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t k0 = b + (uint64_t)blockIdx.x * blockDim.x; k0 < e; k0 += stride) {
-    const uint64_t k = k0 + threadIdx.x;
-    uint64_t c[3] = {0, 0, 0};
-    bool two[3] = {false, false, false};
-    if (k < e) {
+  const uint64_t chunk = (uint64_t)blockDim.x * kRemovePer;
+  for (uint64_t k0 = b + (uint64_t)blockIdx.x * chunk; k0 < e; k0 += (uint64_t)gridDim.x * chunk) {
+    uint64_t cell[3 * kRemovePer];
+    uint32_t fell = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kRemovePer; ++j) {
+      const uint64_t k = k0 + (uint64_t)j * blockDim.x + threadIdx.x;
+      cell[3 * j] = cell[3 * j + 1] = cell[3 * j + 2] = 0;
+      if (k >= e) continue;
       const uint32_t i = stack[k];
-      xor_cells(keys[i], rmix, seg, c);
-      for (int q = 0; q < 3; ++q) two[q] = (atomicSub(&cw[c[q]], kCountOne + i) >> 48) == 2;
+      xor_cells(keys[i], rmix, seg, &cell[3 * j]);
+#pragma unroll
+      for (uint32_t q = 0; q < 3; ++q)
+        if ((atomicSub(&cw[cell[3 * j + q]], kCountOne + i) >> 48) == 2) fell |= 1u << (3 * j + q);
     }
-    for (int q = 0; q < 3; ++q) {
-      const uint64_t at = wave_append(&pk[kPkFrTail], two[q]);
-      if (two[q] && at < cells) frontier[at] = c[q];
-    }
+    uint64_t at = block_append(&pk[kPkFrTail], __popc(fell));
+#pragma unroll
+    for (uint32_t j = 0; j < 3 * kRemovePer; ++j)
+      if ((fell >> j) & 1) {
+        if (at < cells) frontier[at] = cell[j];
+        ++at;
+      }
   }
 }
 
@@ -731,7 +781,7 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   HIP_TRY(hipGetLastError());
   // Round passes run a fixed grid over device-held ranges; the host checks
   // for the end of the peeling after each chunk of rounds.
-  const int round_grid = grid_for((cells + 3) / 4, 256) < 2048 ? grid_for((cells + 3) / 4, 256) : 2048;
+  const int round_grid = grid_for((cells + 3) / 4, 256 * kDetectPer) < 1024 ? grid_for((cells + 3) / 4, 256 * kDetectPer) : 1024;
   constexpr uint32_t kChunk = 16;
   bool solved = false;
   uint32_t rounds = 0;
@@ -744,7 +794,7 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
                        0u);
     hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, stream, pk, (uint64_t)kPkWords);
     if (N) hipLaunchKernelGGL(xor_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg, cw);
-    hipLaunchKernelGGL(xor_frontier_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(xor_frontier_kernel, dim3(grid_for(cells, 256 * kFrontierPer)), dim3(kAppendThreads), 0, stream,
                        (const unsigned long long *)cw, cells, frontier, pk);
     HIP_TRY(hipGetLastError());
     for (;;) {
