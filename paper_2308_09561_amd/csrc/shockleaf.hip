@@ -53,11 +53,13 @@ using shockhash::slot_pair;
 constexpr uint64_t kNone = ~0ull;
 // Rotation fitting: candidates (s, r) are encoded as s * 64 + r, which orders
 // them as the search does (seed first, then rotation).
-constexpr uint32_t kRfSeedsPerLane = 8;  // consecutive seeds per lane; the partial-hash period
+constexpr uint32_t kRfPeriod = 8;        // the partial-hash period k: seeds s - s mod 8 share the first set's hash
+constexpr uint32_t kRfSeedsPerLane = 2;  // consecutive seeds per lane and iteration: a quad covers one period
 
-// Leaf claim word: bits 0..39 next unclaimed unit (a unit is one iteration,
-// 64*SPL consecutive seeds), bits 40..62 workers inside the leaf, bit 63 set
-// once the leaf's result has been written.
+// Leaf claim word: bits 0..39 next unclaimed unit (a unit is one iteration:
+// 64*SPL consecutive seeds, or 64*kRfSeedsPerLane under rotation fitting), bits
+// 40..62 workers inside the leaf, bit 63 set once the leaf's result has been
+// written.
 constexpr uint64_t kBlockMask = (1ull << 40) - 1;
 constexpr uint64_t kInflightOne = 1ull << 40;
 constexpr uint64_t kInflightMask = ((1ull << 23) - 1) << 40;
@@ -165,6 +167,8 @@ struct WaveLds {
   uint64_t keys[64];  // premixed keys of the leaf the wave is working on
   uint64_t keys_a[64];  // rotation fitting: premixed keys of the first set, compacted
   uint64_t keys_b[64];  // rotation fitting: premixed keys of the second set, compacted
+  uint64_t rf_sides;    // rotation fitting: bit i set if key i is in the second set
+  uint32_t rf_na, rf_nb;  // rotation fitting: sizes of the two sets
   union {
     struct {
       uint32_t parent[64];
@@ -382,7 +386,7 @@ __device__ __forceinline__ bool any_rotation_covers(uint64_t ma, uint64_t mb, ui
 // Slots of this lane's key (lane < n) under candidate (s, r).
 __device__ __forceinline__ void rf_lane_slots(uint32_t my_alo, uint32_t my_ahi, uint32_t my_side, uint64_t s, uint32_t r,
                                               bool partial, uint32_t n, uint32_t &h0, uint32_t &h1) {
-  const uint64_t sa = partial ? s - (s % kRfSeedsPerLane) : s;
+  const uint64_t sa = partial ? s - (s % kRfPeriod) : s;
   const uint64_t t = fmix64(((my_side ? s : sa) + 1) * kGolden);
   slot_pair(my_alo, my_ahi, (uint32_t)t, (uint32_t)(t >> 32), n, n - 1, h0, h1);
   if (my_side) {
@@ -421,43 +425,78 @@ __device__ uint64_t rf_rotations(uint32_t n, uint64_t s, bool partial, uint32_t 
   return __ballot(lane < n && (rot | ma) == full);
 }
 
+// DPP quad permutations (within each aligned group of 4 lanes).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  return ((uint64_t)dpp32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp32<CTRL>((uint32_t)v);
+}
+constexpr int kDppXor1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+constexpr int kDppQuad0 = 0x00;  // quad_perm [0, 0, 0, 0]
+
+__device__ __forceinline__ uint64_t quad_or(uint64_t x) {
+  x |= dpp64<kDppXor1>(x);
+  return x | dpp64<kDppXor2>(x);
+}
+
 // Search seeds [base, end) of one leaf for the first candidate (s, r), in the
-// order s ascending then r ascending, whose graph is a pseudoforest.  Lane l
-// of an iteration takes the kRfSeedsPerLane consecutive seeds starting at
-// ib + l * kRfSeedsPerLane, so with partial hashing the first set's mask
-// (seed s - s mod 8) is computed once per lane and iteration.  Returns the
-// encoded candidate s * 64 + r, or kNone.
+// order s ascending then r ascending, whose graph is a pseudoforest.  An
+// iteration covers 64 * kRfSeedsPerLane consecutive seeds from a start aligned
+// to the partial-hash period (seeds outside [base, end) are masked); lane l
+// takes seeds ib + 2l and ib + 2l + 1, so each quad of lanes holds one period.
+// With partial hashing the quad shares the first set's seed s - s mod 8: each
+// lane hashes every 4th key of that set and the quad ORs the masks.  Returns
+// the encoded candidate s * 64 + r, or kNone.
 template <bool WIDE>
 __device__ uint64_t rf_search_block(uint32_t n, uint32_t na, uint32_t nb, bool partial, uint64_t base, uint64_t end,
                                     const unsigned long long *best_j, bool poll, uint32_t my_alo, uint32_t my_ahi,
                                     uint32_t my_side, WaveLds &lds, WaveStats &st) {
+  static_assert(kRfSeedsPerLane == 2 && kRfPeriod == 8, "a quad of lanes covers one partial-hash period");
   const uint32_t lane = lane_id();
   const uint32_t nm1 = n - 1;
   const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
   const uint64_t pad = ~full;
   constexpr uint32_t kSeeds = 64 * kRfSeedsPerLane;
-  for (uint64_t ib = base; ib < end; ib += kSeeds) {
+  const uint64_t ib0 = base - base % kRfPeriod;
+  for (uint64_t ib = ib0; ib < end; ib += kSeeds) {
     const unsigned long long cur_best = poll ? load_relaxed(best_j) : kNone;
     const uint64_t s0 = ib + (uint64_t)lane * kRfSeedsPerLane;
-    uint32_t flags = 0;
-    uint64_t ma = 0;
-#pragma unroll 1
-    for (uint32_t i = 0; i < kRfSeedsPerLane; ++i) {
-      const uint64_t s = s0 + i;
-      const uint64_t t = fmix64((s + 1) * kGolden);
-      // (ib + i) mod 8 = s mod 8 in every lane: a wave-uniform branch.
-      if (!partial) {
-        ma = cover_mask<WIDE>(lds.keys_a, na, (uint32_t)t, (uint32_t)(t >> 32), n, nm1);
-      } else if (i == 0 || ((ib + i) % kRfSeedsPerLane) == 0) {
-        const uint64_t ta = fmix64((s - (s % kRfSeedsPerLane) + 1) * kGolden);
-        ma = cover_mask<WIDE>(lds.keys_a, na, (uint32_t)ta, (uint32_t)(ta >> 32), n, nm1);
+    const uint64_t t0 = fmix64((s0 + 1) * kGolden);
+    const uint64_t t1 = fmix64((s0 + 2) * kGolden);
+    uint64_t ma0, ma1;
+    if (partial) {
+      // the quad's first lane holds seed s0 = ib + 8q, the period start
+      const uint64_t ta = dpp64<kDppQuad0>(t0);
+      uint32_t mlo = 0, mhi = 0;
+      for (uint32_t k = lane & 3; k < na; k += 4) {
+        const uint64_t ak = lds.keys_a[k];
+        uint32_t h0, h1;
+        slot_pair((uint32_t)ak, (uint32_t)(ak >> 32), (uint32_t)ta, (uint32_t)(ta >> 32), n, nm1, h0, h1);
+        if (WIDE) {
+          const uint64_t b0 = 1ull << h0, b1 = 1ull << h1;
+          or3_into(mlo, (uint32_t)b0, (uint32_t)b1);
+          or3_into(mhi, (uint32_t)(b0 >> 32), (uint32_t)(b1 >> 32));
+        } else {
+          or3_into(mlo, 1u << h0, 1u << h1);
+        }
       }
-      const uint64_t mb = cover_mask<WIDE>(lds.keys_b, nb, (uint32_t)t, (uint32_t)(t >> 32), n, nm1);
-      const bool any = any_rotation_covers<WIDE>(ma, mb, n, pad);
-      flags |= (any && s < end) ? (1u << i) : 0u;
+      ma0 = ma1 = quad_or(((uint64_t)mhi << 32) | mlo);
+    } else {
+      ma0 = cover_mask<WIDE>(lds.keys_a, na, (uint32_t)t0, (uint32_t)(t0 >> 32), n, nm1);
+      ma1 = cover_mask<WIDE>(lds.keys_a, na, (uint32_t)t1, (uint32_t)(t1 >> 32), n, nm1);
     }
-    const uint64_t span = end - ib;
-    st.seeds += span < (uint64_t)kSeeds ? span : (uint64_t)kSeeds;
+    const uint64_t mb0 = cover_mask<WIDE>(lds.keys_b, nb, (uint32_t)t0, (uint32_t)(t0 >> 32), n, nm1);
+    const uint64_t mb1 = cover_mask<WIDE>(lds.keys_b, nb, (uint32_t)t1, (uint32_t)(t1 >> 32), n, nm1);
+    uint32_t flags = 0;
+    if (any_rotation_covers<WIDE>(ma0, mb0, n, pad) && s0 >= base && s0 < end) flags |= 1u;
+    if (any_rotation_covers<WIDE>(ma1, mb1, n, pad) && s0 + 1 >= base && s0 + 1 < end) flags |= 2u;
+    const uint64_t lo = ib > base ? ib : base;
+    const uint64_t hi = ib + kSeeds < end ? ib + kSeeds : end;
+    st.seeds += hi - lo;
     uint64_t surv = __ballot(flags != 0);
     while (surv != 0) {
       const uint32_t l = __builtin_ctzll(surv);
@@ -503,6 +542,11 @@ __device__ void rf_stage(const Params &P, uint64_t j, uint32_t n, uint64_t ai, u
   }
   nb = (uint32_t)__popcll(sides);
   na = n - nb;
+  if (lane == 0) {
+    lds.rf_sides = sides;
+    lds.rf_na = na;
+    lds.rf_nb = nb;
+  }
   wave_lds_sync();
 }
 
@@ -530,7 +574,7 @@ __device__ void finalize_leaf(const Params &P, uint64_t j, uint32_t n, WaveLds &
     uint32_t h0 = 0, h1 = 0;
     if (RF) {
       const uint32_t my_side = (uint32_t)((P.sides[j] >> lane) & 1);
-      const bool partial = P.partial_k ? P.partial_k == kRfSeedsPerLane : n > 32;
+      const bool partial = P.partial_k ? P.partial_k == kRfPeriod : n > 32;
       rf_lane_slots((uint32_t)ai, (uint32_t)(ai >> 32), my_side, s, r, partial, n, h0, h1);
     } else {
       const uint64_t t = fmix64((s + 1) * kGolden);
@@ -554,11 +598,10 @@ __device__ uint64_t search_range(const Params &P, uint64_t j, uint32_t n, uint64
   const uint64_t *a = lds.keys;
   if (n <= 1) return RF ? base * 64 : base;  // every seed qualifies
   if (RF) {
-    const uint64_t valid = n >= 64 ? ~0ull : ((1ull << n) - 1);
-    const uint64_t sides = P.sides[j] & valid;
-    const uint32_t nb = (uint32_t)__popcll(sides), na = n - nb;
-    const uint32_t my_side = (uint32_t)((sides >> lane_id()) & 1);
-    const bool partial = P.partial_k ? P.partial_k == kRfSeedsPerLane : n > 32;
+    // the leaf's split, staged in LDS by rf_stage
+    const uint32_t na = bcast32(lds.rf_na), nb = bcast32(lds.rf_nb);
+    const uint32_t my_side = (uint32_t)((lds.rf_sides >> lane_id()) & 1);
+    const bool partial = P.partial_k ? P.partial_k == kRfPeriod : n > 32;
     if (n <= 32) return rf_search_block<false>(n, na, nb, partial, base, end, &P.best[j], poll, my_alo, my_ahi, my_side, lds, st);
     return rf_search_block<true>(n, na, nb, partial, base, end, &P.best[j], poll, my_alo, my_ahi, my_side, lds, st);
   }
@@ -740,9 +783,12 @@ __device__ __forceinline__ void flush_stats(const Params &P, const WaveStats &st
 }
 
 // Plain search (RF false, SPL seeds per lane) or rotation fitting (RF true;
-// SPL unused): separate instances, so each gets its own register budget.
+// SPL unused): separate instances, so each gets its own register budget.  The
+// rotation-fitting instance is held to 96 registers, five waves per SIMD (the
+// occupancy its launch is sized for).
 template <int SPL, bool RF>
-__global__ __launch_bounds__(64 * kMaxWavesPerWg) void search_kernel(Params P) {
+__global__ __launch_bounds__(64 * kMaxWavesPerWg) __attribute__((amdgpu_waves_per_eu(RF ? 5 : 1)))
+void search_kernel(Params P) {
   extern __shared__ unsigned long long lds_raw[];
   const uint32_t wave = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
@@ -1005,7 +1051,7 @@ struct Plan {
 
 // Rotation fitting: claim units are 64 lanes x 8 seeds and a leaf needs
 // about n times fewer seeds, so claims are small.
-int default_rf_units(uint32_t) { return 1; }
+int default_rf_units(uint32_t) { return 2; }
 
 int make_plan(const shock_opts &opts, uint64_t n_leaves, uint32_t n_typical, int rf, Plan &pl) {
   pl.mode = opts.mode == SHOCK_MODE_AUTO ? SHOCK_MODE_PERSISTENT : opts.mode;
