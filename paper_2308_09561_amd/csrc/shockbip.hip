@@ -2,8 +2,8 @@
 //
 // The n cells of a leaf's table are split into a left part [0, nl) and a
 // right part [nl, n), nl = floor(n / 2).  One evaluation of the frozen hash of
-// key x under seed s gives both its left cell (bits 0..15 of z) and its right
-// cell (bits 16..31).  A pair of seeds (a, b) gives key x the cells
+// key x under seed s gives both its left cell (the range reduction of z to
+// [0, nl)) and its right cell (the leftover fraction reduced to [nl, n)).  A pair of seeds (a, b) gives key x the cells
 // left(x, a) and right(x, b); the result is the first pair, in the order
 // max(a, b), then a, then b, whose graph is a pseudoforest.
 //
@@ -17,7 +17,9 @@
 // candidate m is paired with the pool in the result order ((a, m) for left
 // candidates a < m, then (m, b) for right candidates b <= m), each pair
 // checked by the wave-parallel peeling test; the pools (seed lists) stay in
-// LDS.  Workers take leaves from an atomic counter; a leaf is short, so there
+// LDS, and so do the cells of the first kCache candidates of each side (one
+// byte per key), so a pair test reads its partner's cells instead of hashing
+// them again.  Workers take leaves from an atomic counter; a leaf is short, so there
 // is no work stealing.
 #include <hip/hip_runtime.h>
 
@@ -39,6 +41,7 @@ using shockwave::wave_lds_sync;
 
 constexpr uint64_t kNone = ~0ull;
 constexpr uint32_t kPool = 256;  // candidates per side and leaf
+constexpr uint32_t kCache = 16;  // candidates per side whose cells are kept in LDS
 constexpr uint32_t kWpw = 4;
 
 enum { kBipErr = 0, kBipNotFound = 1, kBipSeeds = 2, kBipPairs = 3, kBipNextLeaf = 4, kBipCount = 5 };
@@ -49,6 +52,7 @@ struct BipLds {
   uint64_t keys[64];
   unsigned long long inc0[64], inc1[64], hit;
   uint32_t pool_l[kPool], pool_r[kPool];
+  uint8_t cell_l[kCache][64], cell_r[kCache][64];  // left (right) cell of key i under pool_l[q] (pool_r[q])
 };
 
 struct BipParams {
@@ -67,14 +71,21 @@ __device__ __forceinline__ void bip_cells(uint64_t a, uint64_t t, uint32_t nl, u
   r = nl + __umulhi((uint32_t)q, nr);
 }
 
-// Whether pair (a, b) qualifies; lane i < n gets its edge (left under a, right under b).
-__device__ bool bip_pair(uint64_t my_a, uint32_t n, uint32_t nl, uint32_t nr, uint64_t sa, uint64_t sb,
-                         uint32_t &h0, uint32_t &h1, BipLds &lds) {
-  uint32_t l, r, l2, r2;
-  bip_cells(my_a, seed_mix(sa), nl, nr, l, r);
-  bip_cells(my_a, seed_mix(sb), nl, nr, l2, r2);
-  h0 = lane_id() < n ? l : 0;
-  h1 = lane_id() < n ? r2 : 0;
+// Cell of this lane's key under pool entry q of one side: from the LDS cache
+// or hashed again.
+__device__ __forceinline__ uint32_t pool_cell(uint64_t my_a, uint32_t q, bool left, uint32_t nl, uint32_t nr,
+                                              const BipLds &lds) {
+  if (q < kCache) return left ? lds.cell_l[q][lane_id()] : lds.cell_r[q][lane_id()];
+  uint32_t l, r;
+  bip_cells(my_a, seed_mix(left ? lds.pool_l[q] : lds.pool_r[q]), nl, nr, l, r);
+  return left ? l : r;
+}
+
+// Whether the pair with left cells cl and right cells cr (this lane's key)
+// qualifies; lane i < n gets its edge in h0, h1.
+__device__ bool bip_pair(uint32_t n, uint32_t cl, uint32_t cr, uint32_t &h0, uint32_t &h1, BipLds &lds) {
+  h0 = lane_id() < n ? cl : 0;
+  h1 = lane_id() < n ? cr : 0;
   return shockwave::pf_peel_wave(n, h0, h1, lds.inc0);
 }
 
@@ -138,13 +149,15 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
         any &= any - 1;
         const uint64_t m = base + lm;
         const bool is_l = (cl >> lm) & 1, is_r = (cr >> lm) & 1;
+        // this lane's key's cells under the new candidate m
+        uint32_t ml_cell, mr_cell;
+        bip_cells(my_a, seed_mix(m), nl, nr, ml_cell, mr_cell);
         if (is_r) {
           for (uint32_t q = 0; q < n_l && !found; ++q) {
-            const uint64_t a = lds.pool_l[q];
             ++pairs;
-            if (bip_pair(my_a, n, nl, nr, a, m, fh0, fh1, lds)) {
+            if (bip_pair(n, pool_cell(my_a, q, true, nl, nr, lds), mr_cell, fh0, fh1, lds)) {
               found = true;
-              ra = a;
+              ra = lds.pool_l[q];
               rb = m;
             }
           }
@@ -152,6 +165,7 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
             if (n_r == kPool) overflow = true;
             else {
               if (lane == 0) lds.pool_r[n_r] = (uint32_t)m;
+              if (n_r < kCache) lds.cell_r[n_r][lane] = (uint8_t)mr_cell;
               ++n_r;
               wave_lds_sync();
             }
@@ -159,18 +173,18 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
         }
         if (!found && !overflow && is_l) {
           for (uint32_t q = 0; q < n_r && !found; ++q) {
-            const uint64_t b = lds.pool_r[q];
             ++pairs;
-            if (bip_pair(my_a, n, nl, nr, m, b, fh0, fh1, lds)) {
+            if (bip_pair(n, ml_cell, pool_cell(my_a, q, false, nl, nr, lds), fh0, fh1, lds)) {
               found = true;
               ra = m;
-              rb = b;
+              rb = lds.pool_r[q];
             }
           }
           if (!found) {
             if (n_l == kPool) overflow = true;
             else {
               if (lane == 0) lds.pool_l[n_l] = (uint32_t)m;
+              if (n_l < kCache) lds.cell_l[n_l][lane] = (uint8_t)ml_cell;
               ++n_l;
               wave_lds_sync();
             }
