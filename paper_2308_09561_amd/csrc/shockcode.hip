@@ -346,28 +346,71 @@ __global__ __launch_bounds__(256) void rice_write_kernel(const uint64_t *__restr
 
 // ---- Golomb-Rice decode -----------------------------------------------------
 
+// Position of the r-th set bit (from 0) of a word with more than r set bits.
+__device__ __forceinline__ uint32_t select_bit(uint64_t w, uint32_t r) {
+  uint32_t pos = 0;
+  for (uint32_t half = 32; half != 0; half >>= 1) {
+    const uint32_t c = (uint32_t)__popcll((w >> pos) & ((1ull << half) - 1));
+    if (r >= c) {
+      r -= c;
+      pos += half;
+    }
+  }
+  return pos;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+  const uint32_t lane = lane_id();
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(v, d);
+    if (lane >= (uint32_t)d) v = y > v ? y : v;
+  }
+  return v;
+}
+
+// A wave decodes a block of 64 leaves.  The index gives the block's bit
+// ranges; the loads that depend only on it (the block's unary words) are
+// issued with the offsets.  The ones of the unary segment (one per leaf,
+// ending its quotient) are found in parallel: each lane holds one word, a
+// scan of popcounts gives every word's first one, and lane t finds the word
+// holding the t-th one (a prefix maximum over the words' start slots) and
+// the bit inside it (a binary search on popcounts).
 __global__ __launch_bounds__(256) void rice_decode_kernel(const uint64_t *__restrict__ fixed, uint64_t fixed_words,
                                                           const uint64_t *__restrict__ unary, uint64_t unary_words,
                                                           const uint64_t *__restrict__ index,
                                                           const uint64_t *__restrict__ offsets, uint64_t n_leaves,
                                                           RiceTable T, uint64_t *__restrict__ values) {
-  __shared__ uint64_t ones[4][64];
+  __shared__ uint32_t start_slot[4][64];
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = threadIdx.x >> 6;
-  uint64_t *pos = ones[wave];
+  uint32_t *sel = start_slot[wave];
   const uint64_t n_blocks = (n_leaves + 63) / 64;
   const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
   for (uint64_t b = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; b < n_blocks; b += waves) {
     const uint64_t j = b * 64 + lane;
+    const uint64_t F0 = index[2 * b], U0 = index[2 * b + 1], U1 = index[2 * b + 3];
     bool have = j < n_leaves;
+    uint64_t o0 = 0, o1 = 0;
+    if (have) {
+      o0 = offsets[j];
+      o1 = offsets[j + 1];
+    }
+    const uint64_t W0 = U0 >> 6, W1 = U1 > U0 ? (U1 - 1) >> 6 : W0;
+    auto unary_word = [&](uint64_t w) -> uint64_t {
+      if (U1 <= U0 || w > W1 || w >= unary_words) return 0;
+      uint64_t x = unary[w];
+      if (w == W0) x &= ~0ull << (U0 & 63);
+      if (w == W1 && (U1 & 63) != 0) x &= ~0ull >> (64 - (U1 & 63));
+      return x;
+    };
+    uint64_t word = unary_word(W0 + lane);
     uint32_t k = 0;
     if (have) {
-      const uint64_t o0 = offsets[j], o1 = offsets[j + 1];
       if (o1 < o0 || o1 - o0 > 64) have = false;
       else k = T.k[o1 - o0];
     }
     // low bits
-    const uint64_t F = index[2 * b] + wave_excl_scan(k);
+    const uint64_t F = F0 + wave_excl_scan(k);
     uint64_t low = 0;
     if (have && k) {
       const uint64_t w = F >> 6;
@@ -376,38 +419,35 @@ __global__ __launch_bounds__(256) void rice_decode_kernel(const uint64_t *__rest
       if (sh + k > 64 && w + 1 < fixed_words) low |= fixed[w + 1] << (64 - sh);
       low &= ~0ull >> (64 - k);
     }
-    // quotients: positions of the ones in [U0, U1)
-    const uint64_t U0 = index[2 * b + 1], U1 = index[2 * b + 3];
-    uint64_t found = 0;
-    if (U1 > U0) {
-      const uint64_t W0 = U0 >> 6, W1 = (U1 - 1) >> 6;
-      for (uint64_t base = W0; base <= W1; base += 64) {
-        const uint64_t w = base + lane;
-        uint64_t word = (w <= W1 && w < unary_words) ? unary[w] : 0;
-        if (w == W0) word &= ~0ull << (U0 & 63);
-        if (w == W1 && (U1 & 63) != 0) word &= ~0ull >> (64 - (U1 & 63));
-        uint64_t t = found + wave_excl_scan((uint64_t)__popcll(word));
-        while (word != 0) {
-          const uint32_t bit = __builtin_ctzll(word);
-          word &= word - 1;
-          if (t < 64) pos[t] = w * 64 + bit;
-          ++t;
-        }
-        found = __shfl(t, 63);  // lane 63's count includes every lane's ones
-        if (found >= 64) break;
-      }
+    // the position of the lane-th one of the segment: the end of leaf j's code
+    uint64_t my_end = 0, found = 0;
+    for (uint64_t base = W0; U1 > U0 && base <= W1; base += 64) {
+      const uint32_t cnt = (uint32_t)__popcll(word);
+      const uint64_t t0 = found + wave_excl_scan((uint64_t)cnt);
+      const uint64_t total = __shfl(t0 + cnt, 63) - found;
+      sel[lane] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (cnt != 0 && t0 < 64) sel[t0] = lane + 1;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const uint32_t owner = wave_incl_max(sel[lane]);
+      const uint64_t ow_word = __shfl(word, owner ? owner - 1 : 0);
+      const uint64_t ow_t0 = __shfl(t0, owner ? owner - 1 : 0);
+      if (owner != 0 && lane >= found && lane < found + total)
+        my_end = (base + owner - 1) * 64 + select_bit(ow_word, (uint32_t)(lane - ow_t0));
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      found += total;
+      if (found >= 64 || base + 64 > W1) break;
+      word = unary_word(base + 64 + lane);
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint64_t prev_end = __shfl_up(my_end, 1);
     if (j < n_leaves) {
       uint64_t v = kNone;
       if (have && lane < found) {
-        const uint64_t end = pos[lane];
-        const uint64_t start = lane == 0 ? U0 : pos[lane - 1] + 1;
-        v = ((end - start) << k) | low;
+        const uint64_t start = lane == 0 ? U0 : prev_end + 1;
+        v = ((my_end - start) << k) | low;
       }
       values[j] = v;
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
 }
 
