@@ -171,7 +171,10 @@ int shock_last_stats(shock_stats *out);
 const char *shock_last_error(void);
 const char *shock_strerror(int status);
 
-/* Free the calling thread's cached scratch memory of the current device. */
+/* Free the calling thread's cached scratch memory of the current device: the
+ * search scratch, the Rice encoder's words and the MPHF build arena (sized by
+ * the largest build the thread has run: about 43 bytes per key).  Waits for
+ * the device first.  SHOCK_EHIP if a HIP call fails. */
 int shock_release_scratch(void);
 
 /* Library version of the frozen hash/orientation definition (3: h0 and r come

@@ -85,7 +85,9 @@ void shock_mphf_params_init(shock_mphf_params *p);
  * needing more than 1024 leaves), SHOCK_EDUPKEY if keys repeat within a leaf,
  * SHOCK_ENOTFOUND if a leaf or the retrieval found no seed, SHOCK_ENOMEM /
  * SHOCK_EHIP on allocation or HIP failures.  On success *out owns the
- * structure. */
+ * structure.  The build's scratch comes from an arena cached per host thread
+ * and device (grown as needed, freed by shock_release_scratch), so builds on
+ * other threads and streams are not stalled by frees. */
 int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_params *params, shock_mphf **out,
                      void *hip_stream);
 

@@ -21,6 +21,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <vector>
+
 #include "shockcode.h"
 #include "shock_hash.h"
 #include "shock_internal.h"
@@ -484,6 +486,57 @@ bool load_table(const uint8_t *k_by_n, RiceTable &T) {
     }                                       \
   } while (0)
 
+namespace {
+
+// The encoder's three device words and their pinned host copy, cached per
+// host thread and device (calls on one thread are synchronous), so an encode
+// makes no allocation after the first.
+struct EncodeScratch {
+  uint64_t *dev = nullptr, *host = nullptr;
+};
+thread_local std::vector<EncodeScratch> t_encode;
+
+hipError_t encode_scratch(uint64_t **dev_words, uint64_t **host_words) {
+  int d = 0;
+  hipError_t e = hipGetDevice(&d);
+  if (e != hipSuccess) return e;
+  if ((int)t_encode.size() <= d) t_encode.resize(d + 1);
+  EncodeScratch &S = t_encode[d];
+  if (S.dev == nullptr) {
+    e = hipMalloc((void **)&S.dev, 3 * sizeof(uint64_t));
+    if (e != hipSuccess) {
+      S.dev = nullptr;
+      return e;
+    }
+  }
+  if (S.host == nullptr) {
+    e = hipHostMalloc((void **)&S.host, 3 * sizeof(uint64_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      S.host = nullptr;
+      return e;
+    }
+  }
+  *dev_words = S.dev;
+  *host_words = S.host;
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t shock_internal_release_code_scratch(int dev) {
+  if ((int)t_encode.size() <= dev) return hipSuccess;
+  EncodeScratch &S = t_encode[dev];
+  hipError_t e = hipSuccess;
+  if (S.dev) e = hipFree(S.dev);
+  if (S.host) {
+    const hipError_t f = hipHostFree(S.host);
+    if (e == hipSuccess) e = f;
+  }
+  S.dev = nullptr;
+  S.host = nullptr;
+  return e;
+}
+
 extern "C" {
 
 int shock_leaf_query(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, const uint64_t *seeds,
@@ -517,11 +570,11 @@ int shock_rice_encode(const uint64_t *values, const uint64_t *offsets, uint64_t 
   if (n_leaves > (1ull << 40)) return SHOCK_EINVAL;
   hipStream_t stream = (hipStream_t)hip_stream;
   const uint64_t n_blocks = (n_leaves + 63) / 64;
-  uint64_t *scratch = nullptr;  // [0] error bits, [1..2] totals
-  HIP_TRY(hipMalloc(&scratch, 3 * sizeof(uint64_t)));
-  uint64_t host[3] = {0, 0, 0};
+  uint64_t *scratch = nullptr, *host = nullptr;  // [0] error bits, [1..2] totals
+  HIP_TRY(encode_scratch(&scratch, &host));
   int rc = SHOCK_OK;
-  hipError_t e = hipMemcpyAsync(scratch, host, sizeof(host), hipMemcpyHostToDevice, stream);
+  hipError_t e = hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(1), dim3(64), 0, stream, scratch, (uint64_t)3);
   if (e == hipSuccess && n_blocks > 0) {
     hipLaunchKernelGGL(rice_len_kernel, dim3(grid_for(n_blocks, 4)), dim3(256), 0, stream, values, offsets, n_leaves,
                        T, index, (unsigned long long *)scratch);
@@ -531,7 +584,7 @@ int shock_rice_encode(const uint64_t *values, const uint64_t *offsets, uint64_t 
     hipLaunchKernelGGL(rice_scan_kernel, dim3(1), dim3(1024), 0, stream, index, n_blocks, scratch + 1);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = hipMemcpyAsync(host, scratch, sizeof(host), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(host, scratch, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e == hipSuccess) {
     bits[0] = host[1];
@@ -552,13 +605,8 @@ int shock_rice_encode(const uint64_t *values, const uint64_t *offsets, uint64_t 
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
   }
-  hipError_t ef = hipFree(scratch);
   if (e != hipSuccess) {
     shock_internal_set_error("rice encode", e);
-    return SHOCK_EHIP;
-  }
-  if (ef != hipSuccess) {
-    shock_internal_set_error("hipFree", ef);
     return SHOCK_EHIP;
   }
   return rc;

@@ -1295,12 +1295,14 @@ int shock_last_stats(shock_stats *out) {
 int shock_release_scratch(void) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceSynchronize());
   if ((int)t_scratch.size() > dev && t_scratch[dev].buf) {
-    HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipFree(t_scratch[dev].buf));
     t_scratch[dev].buf = nullptr;
     t_scratch[dev].bytes = 0;
   }
+  HIP_TRY(shock_internal_release_code_scratch(dev));
+  HIP_TRY(shock_internal_release_mphf_scratch(dev));
   return SHOCK_OK;
 }
 

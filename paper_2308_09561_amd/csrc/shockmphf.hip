@@ -605,25 +605,71 @@ struct shock_mphf {
 
 namespace {
 
-// Device allocations of one build, freed on every exit path.
+// Scratch of one build: bump allocations from the calling thread's arena on
+// the current device.  The arena is sized for the whole build before its
+// first kernel and kept for the thread's next build, so a build makes no
+// hipMalloc/hipFree for scratch (hipFree waits for the whole device, which
+// would stall builds running on other streams) once the arena is large
+// enough.  Also holds a few words of pinned host memory for read-backs.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0;
+  uint64_t *pinned = nullptr;  // kPinnedWords words
+};
+constexpr size_t kPinnedWords = 16;
+thread_local std::vector<Arena> t_arena;
+
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 struct Scratch {
-  std::vector<void *> ptrs;
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
+  uint64_t *pinned = nullptr;
   template <typename T>
   hipError_t alloc(T **p, size_t count) {
-    *p = nullptr;
-    hipError_t e = hipMalloc((void **)p, (count ? count : 1) * sizeof(T));
-    if (e == hipSuccess) ptrs.push_back((void *)*p);
-    return e;
-  }
-  void release(void *p) {
-    for (auto &q : ptrs)
-      if (q == p) q = nullptr;
-  }
-  ~Scratch() {
-    for (void *p : ptrs)
-      if (p) (void)hipFree(p);
+    const size_t bytes = align256((count ? count : 1) * sizeof(T));
+    if (used + bytes > cap) return hipErrorOutOfMemory;  // the reservation covers every allocation
+    *p = reinterpret_cast<T *>(base + used);
+    used += bytes;
+    return hipSuccess;
   }
 };
+
+// Reserve `bytes` of scratch for a build on the current device.
+hipError_t reserve_scratch(size_t bytes, Scratch &S) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if ((int)t_arena.size() <= dev) t_arena.resize(dev + 1);
+  Arena &A = t_arena[dev];
+  if (A.pinned == nullptr) {
+    e = hipHostMalloc((void **)&A.pinned, kPinnedWords * sizeof(uint64_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      A.pinned = nullptr;
+      return e;
+    }
+  }
+  if (A.cap < bytes) {
+    if (A.base) {
+      e = hipFree(A.base);  // the previous build on this thread has finished (builds are synchronous)
+      A.base = nullptr;
+      A.cap = 0;
+      if (e != hipSuccess) return e;
+    }
+    const size_t grown = bytes + bytes / 8;
+    e = hipMalloc((void **)&A.base, grown);
+    if (e != hipSuccess) {
+      A.base = nullptr;
+      return e;
+    }
+    A.cap = grown;
+  }
+  S.base = A.base;
+  S.cap = A.cap;
+  S.used = 0;
+  S.pinned = A.pinned;
+  return hipSuccess;
+}
 
 void free_mphf(shock_mphf *m) {
   if (!m) return;
@@ -650,19 +696,23 @@ static double ms_since(std::chrono::steady_clock::time_point t) {
 
 static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params &P, shock_mphf *M,
                       hipStream_t stream) {
-  Scratch S;
   auto tp = std::chrono::steady_clock::now();
   const uint64_t B = N == 0 ? 1 : (N + P.bucket_size - 1) / P.bucket_size;
   M->n_keys = N;
   M->n_buckets = B;
+  // Scratch for the whole build, with the leaf count bounded by its maximum
+  // (each bucket of m keys gets ceil(m / leaf_target) leaves).
+  const uint64_t Lmax = B + (N + P.leaf_target - 1) / P.leaf_target;
+  const uint64_t seg_r = (123 * N + 299) / 300 + 8, cells_r = 3 * seg_r;
+  const size_t scratch_bytes = align256(2 * 8) + align256(B * 4) + 2 * align256(N * 8) + align256((Lmax + 1) * 8) +
+                               2 * align256(Lmax * 8) + align256(Lmax * 4) + 2 * align256(N ? N : 1) +
+                               align256(((N + 31) / 32) * 4) + align256(N * 4) + 2 * align256(cells_r * 8) +
+                               align256((kMaxPeelRounds + 1) * 8) + align256(kPkWords * 8) + align256(cells_r) + 32 * 256;
+  Scratch S;
+  HIP_TRY(reserve_scratch(scratch_bytes, S));
   unsigned long long *err = nullptr;
-  uint64_t *host = nullptr;  // pinned: [0] error bits, [1] n_leaves, [2] peeled count
+  uint64_t *host = S.pinned;  // pinned: [0] error bits, [1] n_leaves; [4, 4 + kPkWords) the retrieval's counters
   HIP_TRY(S.alloc(&err, 2));
-  HIP_TRY(hipHostMalloc((void **)&host, 4 * sizeof(uint64_t)));
-  struct HostFree {
-    uint64_t *p;
-    ~HostFree() { (void)hipHostFree(p); }
-  } host_guard{host};
   uint32_t *counts = nullptr;
   HIP_TRY(S.alloc(&counts, B));
   HIP_TRY(hipMalloc((void **)&M->bucket_offset, (B + 1) * sizeof(uint64_t)));
@@ -701,8 +751,6 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   if (host[0] & kErrSigma) return SHOCK_ENOTFOUND;
-  S.release(grouped);
-  HIP_TRY(hipFree(grouped));
   M->layout_ms = ms_since(tp);
   tp = std::chrono::steady_clock::now();
 
@@ -758,7 +806,7 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   uint32_t *taken = nullptr, *stack = nullptr;
   unsigned long long *cw = nullptr, *pk = nullptr;
   uint64_t *frontier = nullptr, *round_off = nullptr, *pk_host = nullptr;
-  const uint64_t seg = (123 * N + 299) / 300 + 8, cells = 3 * seg;
+  const uint64_t seg = seg_r, cells = cells_r;
   const uint64_t taken_words = (N + 31) / 32;
   M->seg = seg;
   HIP_TRY(S.alloc(&choice, N));
@@ -770,11 +818,8 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   HIP_TRY(S.alloc(&round_off, kMaxPeelRounds + 1));
   HIP_TRY(S.alloc(&pk, kPkWords));
   HIP_TRY(S.alloc(&z, cells));
-  HIP_TRY(hipHostMalloc((void **)&pk_host, kPkWords * sizeof(uint64_t)));
-  struct PkFree {
-    uint64_t *p;
-    ~PkFree() { (void)hipHostFree(p); }
-  } pk_guard{pk_host};
+  static_assert(4 + kPkWords <= kPinnedWords, "pinned words");
+  pk_host = S.pinned + 4;
   if (L)
     hipLaunchKernelGGL(choice_kernel, dim3(grid_for(L, 4)), dim3(256), 0, stream, (const uint64_t *)leaf_off,
                        (const uint8_t *)M->leaf_sizes, (const uint64_t *)orient, L, choice);
@@ -851,6 +896,21 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   HIP_TRY(hipStreamSynchronize(stream));
   M->retrieval_ms = ms_since(tp);
   return SHOCK_OK;
+}
+
+hipError_t shock_internal_release_mphf_scratch(int dev) {
+  if ((int)t_arena.size() <= dev) return hipSuccess;
+  Arena &A = t_arena[dev];
+  hipError_t e = hipSuccess;
+  if (A.base) e = hipFree(A.base);
+  A.base = nullptr;
+  A.cap = 0;
+  if (A.pinned) {
+    const hipError_t f = hipHostFree(A.pinned);
+    if (e == hipSuccess) e = f;
+  }
+  A.pinned = nullptr;
+  return e;
 }
 
 extern "C" {
