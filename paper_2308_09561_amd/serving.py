@@ -277,14 +277,15 @@ def synthetic_stream(n_requests: int, rate_per_s: float, seed: int = 5, min_keys
 
 
 def mphf_footprint(n_keys: int) -> int:
-    """Device bytes an MPHF build of n_keys holds at its peak, during the
-    retrieval: the keys and their leaf-ordered copy (16 bytes per key), leaf
-    search outputs and scratch, and the retrieval's 1.23 cells per key (an
-    8-byte count word, an 8-byte frontier slot and a value byte each) plus 6
-    bytes per key of choices, peel positions and the peel stack: about 43
-    bytes per key."""
+    """Device bytes an MPHF build of n_keys holds at its peak: the keys, the
+    build's scratch arena (a bucket-ordered and a leaf-ordered copy of the
+    keys, 16 bytes per key; the retrieval's 1.23 cells per key with an 8-byte
+    count word, an 8-byte frontier slot and a value byte each; 6 bytes per
+    key of choices, peel positions and the peel stack), and the leaf search
+    outputs and scratch: about 51 bytes per key plus the per-leaf terms.  The
+    arena stays cached by the building thread after the build."""
     leaves = n_keys // 8 + 1
-    return 43 * n_keys + (16 + SCRATCH_BYTES_PER_LEAF) * leaves + (1 << 20)
+    return 51 * n_keys + (16 + SCRATCH_BYTES_PER_LEAF) * leaves + (1 << 20)
 
 
 class MphfServer:
