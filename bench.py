@@ -165,8 +165,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the leaf search is data-parallel over leaves and this build "
-              "runs on a single MI355X; multi-GPU runs are not supported (see DESIGN.md, sharding).",
+        print("bench.py measures one GPU only: leaves are independent, so several GPUs would each search "
+              "a share of the batch's leaves with no exchange; runs on more than one GPU are not supported.",
               file=sys.stderr)
         sys.exit(2)
 
