@@ -132,12 +132,22 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
       const uint64_t s = base + lane;
       const uint64_t t = seed_mix(s);
       uint64_t ml = 0, mr = 0;
-      for (uint32_t i = 0; i < n; ++i) {
+      auto eval_key = [&](uint64_t a) {
         uint32_t l, r;
-        bip_cells(lds.keys[i], t, nl, nr, l, r);
+        bip_cells(a, t, nl, nr, l, r);
         ml |= 1ull << l;
         mr |= 1ull << r;
+      };
+      // four keys' LDS reads in flight at once
+      uint32_t i = 0;
+      for (; i + 4 <= n; i += 4) {
+        const uint64_t a0 = lds.keys[i], a1 = lds.keys[i + 1], a2 = lds.keys[i + 2], a3 = lds.keys[i + 3];
+        eval_key(a0);
+        eval_key(a1);
+        eval_key(a2);
+        eval_key(a3);
       }
+      for (; i < n; ++i) eval_key(lds.keys[i]);
       const uint64_t span = P.max_seed - base;
       seeds_hashed += span < 64 ? span : 64;
       const bool in = s < P.max_seed;
