@@ -42,13 +42,16 @@ __device__ inline bool pf_peel_wave(uint32_t n, uint32_t h0, uint32_t h1, unsign
   wave_lds_sync();
   const uint64_t mine = inc[lane];
   uint64_t rem = n >= 64 ? ~0ull : ((1ull << n) - 1);
-  // Every round that finds a cell of degree one removes an edge, so at most
-  // n + 1 rounds run.
-  for (uint32_t round = 0; round <= 64; ++round) {
+  // Two rounds per iteration with one exit test: a round that finds no cell
+  // of degree one changes nothing, so the pair ends the loop when its second
+  // round finds none.  Every round that finds one removes an edge, so at most
+  // n + 1 rounds (33 iterations) run.
+  for (uint32_t it = 0; it < 33; ++it) {
     const uint64_t d1 = __ballot(__popcll(mine & rem) == 1);
-    if (d1 == 0) break;
-    const bool gone = act && (((d1 >> h0) | (d1 >> h1)) & 1);
-    rem &= ~__ballot(gone);
+    rem &= ~__ballot(act && (((d1 >> h0) | (d1 >> h1)) & 1));
+    const uint64_t d2 = __ballot(__popcll(mine & rem) == 1);
+    rem &= ~__ballot(act && (((d2 >> h0) | (d2 >> h1)) & 1));
+    if (d2 == 0) break;
   }
   return __ballot(__popcll(mine & rem) > 2) == 0;
 }
