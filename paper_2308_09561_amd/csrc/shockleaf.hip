@@ -38,8 +38,6 @@
 #include "shockleaf.h"
 #include "shock_hash.h"
 
-// Wave-wide bitwise OR of a 64-bit value (ROCm's device library, cross-lane DPP).
-extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_or_u64(unsigned long long);
 #include "shock_internal.h"
 #include "shock_wave.h"
 
@@ -169,6 +167,7 @@ struct WaveLds {
   uint64_t keys_b[64];  // rotation fitting: premixed keys of the second set, compacted
   uint64_t rf_sides;    // rotation fitting: bit i set if key i is in the second set
   uint32_t rf_na, rf_nb;  // rotation fitting: sizes of the two sets
+  uint64_t rf_masks[64][4];  // rotation fitting: lane l's coverage masks ma, mb of its two seeds (flagged lanes)
   union {
     struct {
       uint32_t parent[64];
@@ -403,23 +402,15 @@ __device__ __forceinline__ bool pf_peel_wave(uint32_t n, uint32_t h0, uint32_t h
 }
 
 // Rotations of seed s whose graphs pass the coverage filter, one bit per
-// rotation, computed by the whole wave: every key ORs its slots into the
-// mask of its set in LDS, then lane r tests rotation r.  h0, h1 return this
-// lane's slots under (s, 0).
+// rotation: lane r tests rotation r on the seed's two coverage masks ma, mb
+// (wave-uniform, as the lane that tested the seed left them in LDS).  h0, h1
+// return this lane's slots under (s, 0) for the pseudoforest test.
 __device__ uint64_t rf_rotations(uint32_t n, uint64_t s, bool partial, uint32_t my_alo, uint32_t my_ahi,
-                                 uint32_t my_side, WaveLds &lds, uint32_t &h0, uint32_t &h1) {
+                                 uint32_t my_side, uint64_t ma, uint64_t mb, uint32_t &h0, uint32_t &h1) {
   const uint32_t lane = lane_id();
   h0 = 0;
   h1 = 0;
-  uint64_t bits = 0;
-  if (lane < n) {
-    rf_lane_slots(my_alo, my_ahi, my_side, s, 0, partial, n, h0, h1);
-    bits = (1ull << h0) | (1ull << h1);
-  }
-  // The two sets' masks by wave OR-reductions (cross-lane DPP), instead of
-  // LDS atomics that serialise on two addresses.
-  const uint64_t ma = __ockl_wfred_or_u64(my_side ? 0ull : bits);
-  const uint64_t mb = __ockl_wfred_or_u64(my_side ? bits : 0ull);
+  if (lane < n) rf_lane_slots(my_alo, my_ahi, my_side, s, 0, partial, n, h0, h1);
   const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
   const uint64_t rot = lane == 0 ? mb : ((mb << lane) | (mb >> (n - lane))) & full;
   return __ballot(lane < n && (rot | ma) == full);
@@ -494,6 +485,13 @@ __device__ uint64_t rf_search_block(uint32_t n, uint32_t na, uint32_t nb, bool p
     uint32_t flags = 0;
     if (any_rotation_covers<WIDE>(ma0, mb0, n, pad) && s0 >= base && s0 < end) flags |= 1u;
     if (any_rotation_covers<WIDE>(ma1, mb1, n, pad) && s0 + 1 >= base && s0 + 1 < end) flags |= 2u;
+    if (flags != 0) {
+      lds.rf_masks[lane][0] = ma0;
+      lds.rf_masks[lane][1] = mb0;
+      lds.rf_masks[lane][2] = ma1;
+      lds.rf_masks[lane][3] = mb1;
+    }
+    wave_lds_sync();
     const uint64_t lo = ib > base ? ib : base;
     const uint64_t hi = ib + kSeeds < end ? ib + kSeeds : end;
     st.seeds += hi - lo;
@@ -507,7 +505,8 @@ __device__ uint64_t rf_search_block(uint32_t n, uint32_t na, uint32_t nb, bool p
         fl &= fl - 1;
         const uint64_t s = ib + (uint64_t)l * kRfSeedsPerLane + i;
         uint32_t g0, g1;
-        uint64_t rots = rf_rotations(n, s, partial, my_alo, my_ahi, my_side, lds, g0, g1);
+        uint64_t rots = rf_rotations(n, s, partial, my_alo, my_ahi, my_side, lds.rf_masks[l][2 * i],
+                                     lds.rf_masks[l][2 * i + 1], g0, g1);
         while (rots != 0) {
           const uint32_t r = __builtin_ctzll(rots);
           rots &= rots - 1;
