@@ -196,3 +196,28 @@ def test_mphf_rotation_fitting_full_size(shock, oracle_mod):
         assert rc == 0 and (_host(pos_t) == want).all()
     finally:
         m.close()
+
+
+def test_build_arena_reuse_across_sizes(shock, oracle_mod):
+    """Builds on one thread reuse a cached scratch arena: a large build, then
+    smaller ones (stale contents must not leak into them), then a larger one
+    (the arena grows), then again after the cache is released; every build
+    equals the oracle's."""
+    sizes = [6000, 17, 1000, 0, 9000, 2500]
+    for step, N in enumerate(sizes):
+        if step == 4:
+            assert shock.shock_release_scratch() == 0
+        keys = splitmix64(2300 + step, N)
+        m, k = _build(shock, keys, rotation_fitting=bool(step % 2), **SMALL)
+        try:
+            rc, lay = oracle_mod.mphf_build(keys, rf=bool(step % 2), **SMALL)
+            assert rc == 0
+            ex = m.export()
+            assert (ex["seeds"] == lay["seeds"]).all(), step
+            assert ex["rho"] == lay["rho"] and (ex["z"] == lay["z"]).all(), step
+            if N:
+                pos = _host(m.query(k))
+                torch.cuda.synchronize()
+                assert (pos == lay["positions"]).all(), step
+        finally:
+            m.close()
