@@ -949,6 +949,9 @@ int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_par
   const auto t0 = std::chrono::steady_clock::now();
   const int rc = build_impl(keys, n_keys, P, M, (hipStream_t)hip_stream);
   if (rc != SHOCK_OK) {
+    // Kernels of a failed build may still be queued: let them finish before
+    // the thread's scratch arena or the structure's arrays are reused.
+    (void)hipStreamSynchronize((hipStream_t)hip_stream);
     free_mphf(M);
     return rc;
   }
