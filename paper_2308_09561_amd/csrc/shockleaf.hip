@@ -980,9 +980,11 @@ double expected_seeds(uint32_t n) {
 // autotuner found on MI355X: claims shrink by themselves when several workers
 // share a leaf, so large leaves prefer large claims (fewer atomics).
 int default_units(uint32_t n) {
-  if (n <= 20) return 4;
   if (n <= 28) return 32;
-  return 64;
+  if (n <= 36) return 1;
+  if (n <= 44) return 16;
+  if (n <= 60) return 64;
+  return 32;
 }
 
 // Workers for a single-leaf (split) launch: enough blocks to cover about
