@@ -500,18 +500,67 @@ struct QueryArgs {
 };
 
 // Position of the r-th one bit (0-based) at or after bit p of the stream.
-__device__ __forceinline__ uint64_t select_one(const uint64_t *s, uint64_t words, uint64_t p, uint64_t r) {
+// Position of the r-th set bit (from 0) of a word with more than r set bits.
+__device__ __forceinline__ uint32_t select_in_word(uint64_t w, uint32_t r) {
+  uint32_t pos = 0;
+  for (uint32_t half = 32; half != 0; half >>= 1) {
+    const uint32_t c = (uint32_t)__popcll((w >> pos) & ((1ull << half) - 1));
+    if (r >= c) {
+      r -= c;
+      pos += half;
+    }
+  }
+  return pos;
+}
+
+// Positions of the (r-1)-th and r-th ones of the bit stream s at or after
+// bit p (r >= 1), or kNone: one scan of the words.
+__device__ __forceinline__ void select_two(const uint64_t *s, uint64_t words, uint64_t p, uint32_t r, uint64_t &prev,
+                                           uint64_t &cur) {
+  prev = cur = kNone;
   uint64_t w = p >> 6;
   uint64_t word = w < words ? s[w] & (~0ull << (p & 63)) : 0;
+  uint32_t want = r - 1;  // looking for the (r-1)-th one first
   for (;;) {
-    const uint64_t c = (uint64_t)__popcll(word);
-    if (c > r || w + 1 >= words) break;
-    r -= c;
+    const uint32_t c = (uint32_t)__popcll(word);
+    if (c > want) {
+      const uint32_t b = select_in_word(word, want);
+      if (prev == kNone) {
+        prev = w * 64 + b;
+        // the next one: in the rest of this word, or further on
+        const uint64_t rest = b == 63 ? 0 : word & (~0ull << (b + 1));
+        if (rest) {
+          cur = w * 64 + (uint64_t)__builtin_ctzll(rest);
+          return;
+        }
+        want = 0;
+        word = 0;  // continue with the next word
+        if (w + 1 >= words) return;
+        ++w;
+        word = s[w];
+        continue;
+      }
+      cur = w * 64 + b;
+      return;
+    }
+    want -= c;
+    if (w + 1 >= words) return;
     ++w;
     word = s[w];
   }
-  for (uint64_t i = 0; i < r && word; ++i) word &= word - 1;
-  return word ? w * 64 + (uint64_t)__builtin_ctzll(word) : kNone;
+}
+
+// Sum of the bytes v[a, b) with 8-byte word loads (v padded to whole words).
+__device__ __forceinline__ uint32_t byte_sum(const uint8_t *v, uint64_t a, uint64_t b) {
+  uint32_t sum = 0;
+  for (uint64_t w = a & ~7ull; w < b; w += 8) {
+    uint64_t x = *reinterpret_cast<const uint64_t *>(v + w);
+    if (w < a) x &= ~0ull << (8 * (a - w));
+    if (b - w < 8) x &= ~0ull >> (8 * (8 - (b - w)));
+    sum = __builtin_amdgcn_sad_u8((uint32_t)x, 0u, sum);
+    sum = __builtin_amdgcn_sad_u8((uint32_t)(x >> 32), 0u, sum);
+  }
+  return sum;
 }
 
 __global__ __launch_bounds__(256) void mphf_query_kernel(QueryArgs A, const uint64_t *__restrict__ queries,
@@ -532,13 +581,16 @@ __global__ __launch_bounds__(256) void mphf_query_kernel(QueryArgs A, const uint
     const uint64_t lb = A.leaf_base[b];
     const uint32_t j = leaf_of(x, split_mix(A.sigma[b]), L);
     const uint64_t g = lb + j;
-    uint64_t start = 0;
-    for (uint64_t jj = lb; jj < g; ++jj) start += A.leaf_sizes[jj];
+    const uint64_t start = byte_sum(A.leaf_sizes, lb, g);
     const uint32_t n = A.leaf_sizes[g];
     // the leaf's seed: fixed bits after the widths of the leaves before it in its block
     const uint64_t blk = g >> 6;
     uint64_t F = A.index[2 * blk];
-    for (uint64_t gg = blk * 64; gg < g; ++gg) F += K[A.leaf_sizes[gg]];
+    for (uint64_t w = blk * 64; w < g; w += 8) {
+      const uint64_t x = *reinterpret_cast<const uint64_t *>(A.leaf_sizes + w);
+      const uint32_t cnt = g - w < 8 ? (uint32_t)(g - w) : 8u;
+      for (uint32_t q = 0; q < cnt; ++q) F += K[(x >> (8 * q)) & 0xFF];
+    }
     const uint32_t k = K[n];
     uint64_t low = 0;
     if (k) {
@@ -550,9 +602,14 @@ __global__ __launch_bounds__(256) void mphf_query_kernel(QueryArgs A, const uint
     }
     const uint64_t U0 = A.index[2 * blk + 1];
     const uint32_t i = (uint32_t)(g & 63);
-    const uint64_t end = select_one(A.unary, A.unary_words, U0, i);
-    const uint64_t begin = i == 0 ? U0 : select_one(A.unary, A.unary_words, U0, i - 1) + 1;
-    const uint64_t value = end == kNone ? kNone : (((end - begin) << k) | low);
+    uint64_t prev, end;
+    if (i == 0) {
+      select_two(A.unary, A.unary_words, U0, 1, end, prev);  // the 0-th one
+      prev = U0 - 1;
+    } else {
+      select_two(A.unary, A.unary_words, U0, i, prev, end);
+    }
+    const uint64_t value = end == kNone ? kNone : (((end - (prev + 1)) << k) | low);
     // the choice from the retrieval cells
     uint64_t c[3];
     xor_cells(x, A.rmix, A.seg, c);
@@ -730,7 +787,8 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   if (host[0] & kErrTooManyLeaves) return SHOCK_EINVAL;
   const uint64_t L = host[1];
   M->n_leaves = L;
-  HIP_TRY(hipMalloc((void **)&M->leaf_sizes, (L ? L : 1)));
+  // padded to whole 8-byte words plus one, for the query's word loads
+  HIP_TRY(hipMalloc((void **)&M->leaf_sizes, ((L + 7) & ~7ull) + 8));
   uint64_t *grouped = nullptr, *leaf_keys = nullptr, *leaf_off = nullptr;
   HIP_TRY(S.alloc(&grouped, N));
   HIP_TRY(S.alloc(&leaf_keys, N));
