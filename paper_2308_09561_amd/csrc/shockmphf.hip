@@ -169,6 +169,50 @@ __global__ void bucket_scatter_kernel(const uint64_t *__restrict__ keys, uint64_
   }
 }
 
+// The same two passes with per-workgroup histograms in LDS, for tables of up
+// to kLdsBuckets buckets: a workgroup takes kLayoutChunk consecutive keys,
+// counts them per bucket in LDS, and makes one global atomic per bucket it
+// saw (a bucket's counter otherwise takes one atomic per key, serialised
+// across the whole launch).  Within a bucket the keys' order is arbitrary in
+// both forms (each leaf is sorted later).
+constexpr uint32_t kLdsBuckets = 8192;
+constexpr uint32_t kLayoutChunk = 256 * 32;
+
+__global__ __launch_bounds__(256) void bucket_count_lds_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys,
+                                                               uint64_t n_buckets, uint32_t *counts) {
+  __shared__ uint32_t h[kLdsBuckets];
+  for (uint32_t i = threadIdx.x; i < n_buckets; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const uint64_t c0 = (uint64_t)blockIdx.x * kLayoutChunk;
+  const uint64_t c1 = c0 + kLayoutChunk < n_keys ? c0 + kLayoutChunk : n_keys;
+  for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) atomicAdd(&h[bucket_of(keys[i], n_buckets)], 1u);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n_buckets; i += blockDim.x)
+    if (h[i]) atomicAdd(&counts[i], h[i]);
+}
+
+__global__ __launch_bounds__(256) void bucket_scatter_lds_kernel(const uint64_t *__restrict__ keys, uint64_t n_keys,
+                                                                 uint64_t n_buckets,
+                                                                 const uint64_t *__restrict__ bucket_offset,
+                                                                 uint32_t *cursor, uint64_t *__restrict__ grouped) {
+  __shared__ uint32_t h[kLdsBuckets];
+  for (uint32_t i = threadIdx.x; i < n_buckets; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const uint64_t c0 = (uint64_t)blockIdx.x * kLayoutChunk;
+  const uint64_t c1 = c0 + kLayoutChunk < n_keys ? c0 + kLayoutChunk : n_keys;
+  for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) atomicAdd(&h[bucket_of(keys[i], n_buckets)], 1u);
+  __syncthreads();
+  // reserve each bucket's range: h[b] becomes the first slot of this chunk's keys
+  for (uint32_t i = threadIdx.x; i < n_buckets; i += blockDim.x)
+    if (h[i]) h[i] = atomicAdd(&cursor[i], h[i]);
+  __syncthreads();
+  for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    const uint64_t x = keys[i];
+    const uint64_t b = bucket_of(x, n_buckets);
+    grouped[bucket_offset[b] + atomicAdd(&h[b], 1u)] = x;
+  }
+}
+
 // One wave per bucket: the smallest splitting seed whose leaves all fit, then
 // leaf sizes, global leaf key offsets, and the keys scattered into leaf order
 // (unsorted within a leaf).
@@ -777,7 +821,12 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   HIP_TRY(hipMalloc((void **)&M->sigma, B * sizeof(uint32_t)));
   HIP_TRY(hipMemsetAsync(err, 0, 2 * sizeof(unsigned long long), stream));
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(B, 256)), dim3(256), 0, stream, counts, B, 0u);
-  if (N) hipLaunchKernelGGL(bucket_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, keys, N, B, counts);
+  const bool lds_layout = B <= kLdsBuckets;
+  const int layout_grid = (int)((N + kLayoutChunk - 1) / kLayoutChunk);
+  if (N && lds_layout)
+    hipLaunchKernelGGL(bucket_count_lds_kernel, dim3(layout_grid), dim3(256), 0, stream, keys, N, B, counts);
+  else if (N)
+    hipLaunchKernelGGL(bucket_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, keys, N, B, counts);
   hipLaunchKernelGGL(layout_scan_kernel, dim3(1), dim3(1024), 0, stream, counts, B, P.leaf_target, M->bucket_offset,
                      M->leaf_base, err);
   HIP_TRY(hipGetLastError());
@@ -794,8 +843,11 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   HIP_TRY(S.alloc(&leaf_keys, N));
   HIP_TRY(S.alloc(&leaf_off, L + 1));
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(B, 256)), dim3(256), 0, stream, counts, B, 0u);
-  if (N)
+  if (N && !lds_layout)
     hipLaunchKernelGGL(bucket_scatter_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, keys, N, B,
+                       (const uint64_t *)M->bucket_offset, counts, grouped);
+  if (N && lds_layout)
+    hipLaunchKernelGGL(bucket_scatter_lds_kernel, dim3(layout_grid), dim3(256), 0, stream, keys, N, B,
                        (const uint64_t *)M->bucket_offset, counts, grouped);
   hipLaunchKernelGGL(split_kernel, dim3(grid_for(B, 4)), dim3(256), 0, stream, (const uint64_t *)grouped,
                      (const uint64_t *)M->bucket_offset, (const uint64_t *)M->leaf_base, B, P.leaf_max, M->sigma,
