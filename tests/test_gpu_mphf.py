@@ -221,3 +221,26 @@ def test_build_arena_reuse_across_sizes(shock, oracle_mod):
                 assert (pos == lay["positions"]).all(), step
         finally:
             m.close()
+
+
+@pytest.mark.parametrize("rf", [False, True], ids=["plain", "rf"])
+def test_mphf_more_buckets_than_the_lds_histogram(shock, oracle_mod, rf):
+    """9000 buckets: above the 8192 that the layout's LDS histograms hold, so
+    the bucket count and scatter take their global-atomic form; the result
+    must still equal the oracle's."""
+    params = dict(bucket_size=10, leaf_target=5, leaf_max=10)
+    keys = splitmix64(2400 + rf, 90000)
+    m, k = _build(shock, keys, rotation_fitting=rf, **params)
+    try:
+        rc, lay = oracle_mod.mphf_build(keys, rf=rf, **params)
+        assert rc == 0
+        ex = m.export()
+        assert len(ex["bucket_offset"]) == 9001
+        assert (ex["bucket_offset"] == lay["bucket_offset"]).all()
+        assert (ex["leaf_sizes"] == lay["leaf_sizes"]).all()
+        assert (ex["seeds"] == lay["seeds"]).all() and (ex["z"] == lay["z"]).all()
+        pos = _host(m.query(k))
+        torch.cuda.synchronize()
+        assert (pos == lay["positions"]).all()
+    finally:
+        m.close()
