@@ -54,16 +54,19 @@ def rf_ops_per_seed(n: int, na: int, partial_k: int) -> float:
 
 def measured_traffic(workload: str, kind: str = ""):
     """HBM bytes per search launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes (profiles/), or None if the kernel source changed since
-    they were taken or the workload differs.  kind "rf_" is the rotation-fitting
-    kernel."""
+    WRITE_SIZE passes (profiles/), or None if the kernel's device sources
+    changed since they were taken or the workload differs.  The record's
+    source_sha256 is the SHA-256 of its `sources` files concatenated in order.
+    kind "rf_" is the rotation-fitting kernel, "bip_" the bipartite one."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kind}search_kernel_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, rec["source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+    h = hashlib.sha256()
+    for src in rec.get("sources") or [rec["source"]]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
         return None
     return rec["bytes_per_launch"]
 

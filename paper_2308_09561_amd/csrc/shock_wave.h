@@ -21,15 +21,24 @@ __device__ __forceinline__ uint32_t bcast32(uint32_t v) { return __builtin_amdgc
 __device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 // Pseudoforest test by peeling, wave-parallel: lane i < n holds edge i
-// (h0, h1), lane c stands for cell c.  Cells of degree one lose their edge,
-// all at once, until none is left; the graph is a pseudoforest iff what
-// remains (its 2-core) has no cell of degree above two, i.e. is a set of
-// disjoint cycles: a component with two or more cycles keeps a cell of degree
-// three or more in its 2-core.  Apart from building the incidence masks in
-// LDS, every round is a few register operations and two ballots, where the
-// union-find needs LDS round trips per step; rotation fitting tests many
-// more candidates per leaf, so it uses this form.  Needs n >= 2 (no loops).
-// inc: 64 words of the wave's LDS.
+// (h0, h1), lane c stands for cell c.  Each round removes, all at once, every
+// edge at a cell of degree one.
+//
+// The test counts instead of inspecting the 2-core.  With n edges on n cells,
+// the sum over components of (edges - cells) is zero, and the graph is a
+// pseudoforest iff every component has as many edges as cells.  Count only
+// the cells that still have an edge.  In a component with a cycle, each
+// removed edge takes exactly its leaf cell with it, so edges - cells stays the
+// same; a tree stands at -1 until its last edge goes, then at 0.  So over the
+// whole graph, (edges left) - (cells left) stays zero for a pseudoforest and
+// turns positive in the round where the first tree (or, from the start, an
+// empty cell) is gone.  The test rejects there, which for the candidates the
+// searches send (every cell covered, nearly all with a small tree) is after
+// one or two rounds, and accepts when no cell of degree one is left.  Apart
+// from building the incidence masks in LDS, a round is a few register
+// operations, two ballots and two scalar popcounts; the union-find needs LDS
+// round trips per step.  Lanes at or above n and cells they name (a one-key
+// leaf's second cell) take no part.  inc: 64 words of the wave's LDS.
 __device__ inline bool pf_peel_wave(uint32_t n, uint32_t h0, uint32_t h1, unsigned long long *inc) {
   const uint32_t lane = lane_id();
   const bool act = lane < n;
@@ -40,20 +49,18 @@ __device__ inline bool pf_peel_wave(uint32_t n, uint32_t h0, uint32_t h1, unsign
     atomicOr(&inc[h1], 1ull << lane);
   }
   wave_lds_sync();
-  const uint64_t mine = inc[lane];
+  const uint64_t mine = act ? inc[lane] : 0;
   uint64_t rem = n >= 64 ? ~0ull : ((1ull << n) - 1);
-  // Two rounds per iteration with one exit test: a round that finds no cell
-  // of degree one changes nothing, so the pair ends the loop when its second
-  // round finds none.  Every round that finds one removes an edge, so at most
-  // n + 1 rounds (33 iterations) run.
-  for (uint32_t it = 0; it < 33; ++it) {
-    const uint64_t d1 = __ballot(__popcll(mine & rem) == 1);
+  // A round that does not return removes at least one edge, so at most n + 1
+  // rounds run.
+  for (uint32_t round = 0; round <= 64; ++round) {
+    const uint32_t deg = __popcll(mine & rem);
+    if (__popcll(rem) != __popcll(__ballot(deg != 0))) return false;
+    const uint64_t d1 = __ballot(deg == 1);
+    if (d1 == 0) return true;
     rem &= ~__ballot(act && (((d1 >> h0) | (d1 >> h1)) & 1));
-    const uint64_t d2 = __ballot(__popcll(mine & rem) == 1);
-    rem &= ~__ballot(act && (((d2 >> h0) | (d2 >> h1)) & 1));
-    if (d2 == 0) break;
   }
-  return __ballot(__popcll(mine & rem) > 2) == 0;
+  return false;
 }
 
 // Canonical orientation of an accepted seed, wave-parallel.  A free cell with
