@@ -159,7 +159,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
 typedef struct shock_stats {
   uint64_t seeds_tested;     /* seeds hashed, including seeds beyond a leaf's answer */
   uint64_t filter_passes;    /* seeds that passed the coverage filter */
-  uint64_t pf_checks;        /* union-find tests run */
+  uint64_t pf_checks;        /* pseudoforest tests run (union-find; with rotation fitting, peeling per rotation) */
   uint64_t blocks_claimed;   /* seed blocks handed out */
   double kernel_ms;          /* time of the search kernel(s), HIP events on the call's stream */
   int32_t workers;           /* persistent waves launched */
