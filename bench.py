@@ -306,7 +306,7 @@ def main():
         log(f"[bench] bipartite ShockHash: {args.bip_steps} steps")
         shock.bip_leaf_search(k_d, o_d, out_a=ba, out_b=bb, out_orient=bf)
         torch.cuda.synchronize()
-        b_ms, b_seeds, b_pairs = [], 0, 0
+        b_ms, b_seeds, b_pairs, b_peeled = [], 0, 0, 0
         t5 = time.perf_counter()
         for _ in range(args.bip_steps):
             rc, _, _, _, bst = shock.bip_leaf_search(k_d, o_d, out_a=ba, out_b=bb, out_orient=bf)
@@ -315,24 +315,28 @@ def main():
             b_ms.append(bst["kernel_ms"])
             b_seeds += bst["seeds_hashed"]
             b_pairs += bst["pairs_tested"]
+            b_peeled += bst["pairs_peeled"]
         wall_b = (time.perf_counter() - t5) / args.bip_steps
         pair_max = torch.maximum(ba, bb).cpu().numpy().astype(np.float64)
         n_b = float(sizes.mean())
         # Lower bound of the algorithmic work: every seed hashed over the
-        # leaf's keys, and two key evaluations per key and tested pair, at
-        # 14 ops per key evaluation (13 as in the plain search, plus the
-        # second half's bit-set); the peeling of each pair is not counted.
-        ops = (b_seeds / args.bip_steps * n_b + b_pairs / args.bip_steps * 2 * n_b) * 14
+        # leaf's keys at 7 ops per key evaluation (xor, 32x32+64 multiply-add,
+        # fold, multiply by nl, high product by nr, and one shift-or per
+        # half's 32-bit coverage word).  The pair tests (cells read back, the
+        # lone-key filter, peeling) are not counted.
+        ops = b_seeds / args.bip_steps * n_b * 7
         kms = float(np.mean(b_ms))
         bip = {"leaves_per_s": L / wall_b, "ms_per_step": wall_b * 1e3, "kernel_ms": kms,
                "mean_max_seed": float(pair_max.mean()), "seeds_hashed_per_leaf": b_seeds / args.bip_steps / L,
-               "pairs_tested_per_leaf": b_pairs / args.bip_steps / L, "vs_plain_search": (L / wall_b) / leaves_per_s,
+               "pairs_tested_per_leaf": b_pairs / args.bip_steps / L,
+               "pairs_peeled_per_leaf": b_peeled / args.bip_steps / L, "vs_plain_search": (L / wall_b) / leaves_per_s,
                "roofline": {"bound": "alu", "achieved": ops / (kms / 1e3) / 1e12, "peak": PEAK_INT_OPS / 1e12,
                             "unit": "Tops/s (int32 lane ops, hashing only: a lower bound)",
                             "frac": ops / (kms / 1e3) / PEAK_INT_OPS,
                             "traffic": measured_traffic(args.workload, "bip_")}}
         log(f"[bench] bipartite: {L / wall_b:.0f} leaves/s, kernel {kms:.2f} ms, "
-            f"{bip['seeds_hashed_per_leaf']:.0f} seeds and {bip['pairs_tested_per_leaf']:.0f} pairs per leaf")
+            f"{bip['seeds_hashed_per_leaf']:.0f} seeds, {bip['pairs_tested_per_leaf']:.0f} pairs "
+            f"({bip['pairs_peeled_per_leaf']:.0f} peeled) per leaf")
 
     # Leaf query and Golomb-Rice seed codes (HBM-bound) on a larger batch of
     # 48-key leaves: uniform keys drawn on the device, the measured batch's

@@ -141,11 +141,14 @@ int shock_rf_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint6
  * Options used: max_seed (at most 2^32), workers.  Synchronous.  Status as
  * shock_leaf_search_ex; SHOCK_ENOTFOUND also when a leaf gathers more than
  * 256 candidates on one side before its pair (far beyond what uniform keys
- * need).  stats (host, may be NULL) receives seeds hashed, pairs tested and
- * the kernel time. */
+ * need).  stats (host, may be NULL) receives seeds hashed, candidate pairs
+ * formed up to each leaf's answer, the pairs among them that the peeling test
+ * ran on (a pair whose graph has a key alone in both of its cells, a one-edge
+ * tree, is rejected without it), and the kernel time. */
 typedef struct {
   uint64_t seeds_hashed;
   uint64_t pairs_tested;
+  uint64_t pairs_peeled;
   double kernel_ms;
   int32_t workers;
   int32_t reserved;

@@ -72,7 +72,8 @@ class ShockStats(ctypes.Structure):
 
 
 class BipStats(ctypes.Structure):
-    _fields_ = [("seeds_hashed", ctypes.c_uint64), ("pairs_tested", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
+    _fields_ = [("seeds_hashed", ctypes.c_uint64), ("pairs_tested", ctypes.c_uint64), ("pairs_peeled", ctypes.c_uint64),
+                ("kernel_ms", ctypes.c_double),
                 ("workers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):

@@ -15,11 +15,16 @@
 // arrive, so the seeds hashed grow like the square root of the pairs needed:
 // the exponential gain over ShockHash the paper points to.  Each new
 // candidate m is paired with the pool in the result order ((a, m) for left
-// candidates a < m, then (m, b) for right candidates b <= m), each pair
-// checked by the wave-parallel peeling test; the pools (seed lists) stay in
-// LDS, and so do the cells of the first kCache candidates of each side (one
-// byte per key), so a pair test reads its partner's cells instead of hashing
-// them again.  Workers take leaves from an atomic counter; a leaf is short, so there
+// candidates a < m, then (m, b) for right candidates b <= m).  Each
+// candidate, when it arrives, also records which keys are alone in their cell
+// of its half.  A pair in which some key is alone in both of its cells has a
+// one-edge tree, so with n keys on n cells it cannot be a pseudoforest: one
+// AND of the two masks rejects it (most pairs, at full coverage of both
+// halves).  The other pairs are checked by the wave-parallel peeling test.
+// The pools (seed lists) and the first kFilter lone-key masks of each side
+// stay in LDS, and so do the cells of the first kCache candidates of each
+// side (one byte per key), so a pair test reads its partner's cells instead
+// of hashing them again.  Workers take leaves from an atomic counter; a leaf is short, so there
 // is no work stealing.
 #include <hip/hip_runtime.h>
 
@@ -42,9 +47,10 @@ using shockwave::wave_lds_sync;
 constexpr uint64_t kNone = ~0ull;
 constexpr uint32_t kPool = 256;  // candidates per side and leaf
 constexpr uint32_t kCache = 16;  // candidates per side whose cells are kept in LDS
+constexpr uint32_t kFilter = 64;  // candidates per side whose lone-key masks are kept in LDS
 constexpr uint32_t kWpw = 4;
 
-enum { kBipErr = 0, kBipNotFound = 1, kBipSeeds = 2, kBipPairs = 3, kBipNextLeaf = 4, kBipCount = 5 };
+enum { kBipErr = 0, kBipNotFound = 1, kBipSeeds = 2, kBipPairs = 3, kBipNextLeaf = 4, kBipPeeled = 5, kBipCount = 6 };
 constexpr uint64_t kErrInvalidLeaf = 1;
 constexpr uint64_t kErrPool = 2;
 
@@ -53,6 +59,7 @@ struct BipLds {
   unsigned long long inc0[64], inc1[64], hit;
   uint32_t pool_l[kPool], pool_r[kPool];
   uint8_t cell_l[kCache][64], cell_r[kCache][64];  // left (right) cell of key i under pool_l[q] (pool_r[q])
+  uint64_t lone_l[kFilter], lone_r[kFilter];  // keys alone in their left (right) cell under pool_l[q] (pool_r[q])
 };
 
 struct BipParams {
@@ -62,13 +69,21 @@ struct BipParams {
   unsigned long long *ctr;
 };
 
-// Left and right cells of a premixed key under a seed mix t.
-__device__ __forceinline__ void bip_cells(uint64_t a, uint64_t t, uint32_t nl, uint32_t nr, uint32_t &l, uint32_t &r) {
+// Left cell l in [0, nl) and right cell index r in [0, nr) (the cell is
+// nl + r) of a premixed key under a seed mix t.
+__device__ __forceinline__ void bip_cell_idx(uint64_t a, uint64_t t, uint32_t nl, uint32_t nr, uint32_t &l,
+                                             uint32_t &r) {
   const uint64_t p = (uint64_t)((uint32_t)a ^ (uint32_t)t) * (a >> 32) + t;
   const uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
   const uint64_t q = (uint64_t)z * nl;
   l = (uint32_t)(q >> 32);
-  r = nl + __umulhi((uint32_t)q, nr);
+  r = __umulhi((uint32_t)q, nr);
+}
+
+// Left and right cells of a premixed key under a seed mix t.
+__device__ __forceinline__ void bip_cells(uint64_t a, uint64_t t, uint32_t nl, uint32_t nr, uint32_t &l, uint32_t &r) {
+  bip_cell_idx(a, t, nl, nr, l, r);
+  r += nl;
 }
 
 // Cell of this lane's key under pool entry q of one side: from the LDS cache
@@ -79,6 +94,25 @@ __device__ __forceinline__ uint32_t pool_cell(uint64_t my_a, uint32_t q, bool le
   uint32_t l, r;
   bip_cells(my_a, seed_mix(left ? lds.pool_l[q] : lds.pool_r[q]), nl, nr, l, r);
   return left ? l : r;
+}
+
+// Keys (lanes below n) alone in their left cell cl, and alone in their right
+// cell cr, under one seed: a cell histogram as key masks in LDS.
+__device__ __forceinline__ void lone_keys(uint32_t n, uint32_t cl, uint32_t cr, BipLds &lds, uint64_t &lone_l,
+                                          uint64_t &lone_r) {
+  const uint32_t lane = lane_id();
+  const bool act = lane < n;
+  lds.inc0[lane] = 0;
+  wave_lds_sync();
+  if (act) {
+    atomicOr(&lds.inc0[cl], 1ull << lane);
+    atomicOr(&lds.inc0[cr], 1ull << lane);
+  }
+  wave_lds_sync();
+  const uint64_t at_l = act ? lds.inc0[cl] : 0, at_r = act ? lds.inc0[cr] : 0;
+  lone_l = __ballot(act && __popcll(at_l) == 1);
+  lone_r = __ballot(act && __popcll(at_r) == 1);
+  wave_lds_sync();
 }
 
 // Whether the pair with left cells cl and right cells cr (this lane's key)
@@ -93,7 +127,7 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
   __shared__ BipLds lds_all[kWpw];
   BipLds &lds = lds_all[threadIdx.x >> 6];
   const uint32_t lane = lane_id();
-  uint64_t seeds_hashed = 0, pairs = 0;
+  uint64_t seeds_hashed = 0, pairs = 0, peeled = 0;
   for (;;) {
     unsigned long long jj = 0;
     if (lane == 0) jj = atomicAdd(&P.ctr[kBipNextLeaf], 1ull);
@@ -122,8 +156,8 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
     lds.keys[lane] = my_a;
     wave_lds_sync();
     const uint32_t nl = n / 2, nr = n - nl;
-    const uint64_t full = n >= 64 ? ~0ull : ((1ull << n) - 1);
-    const uint64_t want_l = (1ull << nl) - 1, want_r = full & ~want_l;
+    // each half has at most 32 cells: one 32-bit coverage word per half
+    const uint32_t want_l = nl >= 32 ? ~0u : (1u << nl) - 1, want_r = nr >= 32 ? ~0u : (1u << nr) - 1;
     uint32_t n_l = 0, n_r = 0;
     bool found = false, overflow = false;
     uint64_t ra = kNone, rb = kNone;
@@ -131,50 +165,66 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
     for (uint64_t base = 0; base < P.max_seed && !found && !overflow; base += 64) {
       const uint64_t s = base + lane;
       const uint64_t t = seed_mix(s);
-      uint64_t ml = 0, mr = 0;
+      uint32_t ml = 0, mr = 0;
       auto eval_key = [&](uint64_t a) {
         uint32_t l, r;
-        bip_cells(a, t, nl, nr, l, r);
-        ml |= 1ull << l;
-        mr |= 1ull << r;
+        bip_cell_idx(a, t, nl, nr, l, r);
+        ml |= 1u << l;
+        mr |= 1u << r;
       };
-      // four keys' LDS reads in flight at once
+      // eight keys' LDS reads in flight at once
       uint32_t i = 0;
-      for (; i + 4 <= n; i += 4) {
-        const uint64_t a0 = lds.keys[i], a1 = lds.keys[i + 1], a2 = lds.keys[i + 2], a3 = lds.keys[i + 3];
-        eval_key(a0);
-        eval_key(a1);
-        eval_key(a2);
-        eval_key(a3);
+      for (; i + 8 <= n; i += 8) {
+        uint64_t a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = lds.keys[i + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) eval_key(a[u]);
       }
       for (; i < n; ++i) eval_key(lds.keys[i]);
       const uint64_t span = P.max_seed - base;
       seeds_hashed += span < 64 ? span : 64;
       const bool in = s < P.max_seed;
-      const uint64_t cl = __ballot(in && (ml & want_l) == want_l);
-      const uint64_t cr = __ballot(in && (mr & want_r) == want_r);
+      const uint64_t cl = __ballot(in && ml == want_l);
+      const uint64_t cr = __ballot(in && mr == want_r);
       uint64_t any = cl | cr;
       while (any != 0 && !found && !overflow) {
         const uint32_t lm = __builtin_ctzll(any);
         any &= any - 1;
         const uint64_t m = base + lm;
         const bool is_l = (cl >> lm) & 1, is_r = (cr >> lm) & 1;
-        // this lane's key's cells under the new candidate m
+        // this lane's key's cells under the new candidate m, and the keys
+        // alone in their left (right) cell under m
         uint32_t ml_cell, mr_cell;
         bip_cells(my_a, seed_mix(m), nl, nr, ml_cell, mr_cell);
+        uint64_t m_lone_l, m_lone_r;
+        lone_keys(n, ml_cell, mr_cell, lds, m_lone_l, m_lone_r);
         if (is_r) {
-          for (uint32_t q = 0; q < n_l && !found; ++q) {
-            ++pairs;
-            if (bip_pair(n, pool_cell(my_a, q, true, nl, nr, lds), mr_cell, fh0, fh1, lds)) {
-              found = true;
-              ra = lds.pool_l[q];
-              rb = m;
+          for (uint32_t q0 = 0; q0 < n_l && !found; q0 += 64) {
+            // pairs whose graph has an isolated edge (a key alone in both of its
+            // cells: a one-edge tree) cannot qualify and are not peeled
+            const uint32_t q = q0 + lane;
+            const uint64_t lone = q < kFilter ? lds.lone_l[q] : 0;
+            uint64_t todo = __ballot(q < n_l && (lone & m_lone_r) == 0);
+            uint32_t formed = n_l - q0 < 64 ? n_l - q0 : 64;
+            while (todo != 0 && !found) {
+              const uint32_t qq = q0 + __builtin_ctzll(todo);
+              todo &= todo - 1;
+              ++peeled;
+              if (bip_pair(n, pool_cell(my_a, qq, true, nl, nr, lds), mr_cell, fh0, fh1, lds)) {
+                found = true;
+                ra = lds.pool_l[qq];
+                rb = m;
+                formed = qq - q0 + 1;
+              }
             }
+            pairs += formed;
           }
           if (!found) {
             if (n_r == kPool) overflow = true;
             else {
               if (lane == 0) lds.pool_r[n_r] = (uint32_t)m;
+              if (lane == 0 && n_r < kFilter) lds.lone_r[n_r] = m_lone_r;
               if (n_r < kCache) lds.cell_r[n_r][lane] = (uint8_t)mr_cell;
               ++n_r;
               wave_lds_sync();
@@ -182,18 +232,29 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
           }
         }
         if (!found && !overflow && is_l) {
-          for (uint32_t q = 0; q < n_r && !found; ++q) {
-            ++pairs;
-            if (bip_pair(n, ml_cell, pool_cell(my_a, q, false, nl, nr, lds), fh0, fh1, lds)) {
-              found = true;
-              ra = m;
-              rb = lds.pool_r[q];
+          for (uint32_t q0 = 0; q0 < n_r && !found; q0 += 64) {
+            const uint32_t q = q0 + lane;
+            const uint64_t lone = q < kFilter ? lds.lone_r[q] : 0;
+            uint64_t todo = __ballot(q < n_r && (lone & m_lone_l) == 0);
+            uint32_t formed = n_r - q0 < 64 ? n_r - q0 : 64;
+            while (todo != 0 && !found) {
+              const uint32_t qq = q0 + __builtin_ctzll(todo);
+              todo &= todo - 1;
+              ++peeled;
+              if (bip_pair(n, ml_cell, pool_cell(my_a, qq, false, nl, nr, lds), fh0, fh1, lds)) {
+                found = true;
+                ra = m;
+                rb = lds.pool_r[qq];
+                formed = qq - q0 + 1;
+              }
             }
+            pairs += formed;
           }
           if (!found) {
             if (n_l == kPool) overflow = true;
             else {
               if (lane == 0) lds.pool_l[n_l] = (uint32_t)m;
+              if (lane == 0 && n_l < kFilter) lds.lone_l[n_l] = m_lone_l;
               if (n_l < kCache) lds.cell_l[n_l][lane] = (uint8_t)ml_cell;
               ++n_l;
               wave_lds_sync();
@@ -216,6 +277,7 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
   if (lane == 0) {
     if (seeds_hashed) atomicAdd(&P.ctr[kBipSeeds], (unsigned long long)seeds_hashed);
     if (pairs) atomicAdd(&P.ctr[kBipPairs], (unsigned long long)pairs);
+    if (peeled) atomicAdd(&P.ctr[kBipPeeled], (unsigned long long)peeled);
   }
 }
 
@@ -240,12 +302,14 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
     shock_internal_set_error("hipMalloc(bipartite counters)", e);
     return SHOCK_ENOMEM;
   }
-  unsigned long long host[kBipCount] = {0, 0, 0, 0, 0};
+  unsigned long long host[kBipCount] = {0, 0, 0, 0, 0, 0};
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-  uint64_t workers = opts.workers ? (uint64_t)opts.workers : (uint64_t)cus * 4 * 6;
+  // four waves per SIMD: more (six fit the LDS) contend for the VALU and LDS
+  // and slow the longest leaves, which end the launch
+  uint64_t workers = opts.workers ? (uint64_t)opts.workers : (uint64_t)cus * 16;
   if (workers > n_leaves) workers = n_leaves;
   const uint32_t groups = (uint32_t)((workers + kWpw - 1) / kWpw);
   BipParams P;
@@ -281,6 +345,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   if (stats) {
     stats->seeds_hashed = host[kBipSeeds];
     stats->pairs_tested = host[kBipPairs];
+    stats->pairs_peeled = host[kBipPeeled];
     stats->kernel_ms = ms;
     stats->workers = (int32_t)(groups * kWpw);
   }

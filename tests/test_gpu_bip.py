@@ -80,8 +80,9 @@ def test_bip_cap(shock, oracle_mod):
 
 def test_bip_full_batch_statistics(shock, oracle_mod):
     """The fixed48 batch: every leaf's pair is a pseudoforest with a valid
-    orientation (the oracle checks a sample end to end) and the seeds drawn
-    are a small fraction of the plain search's."""
+    orientation (the oracle checks a sample end to end), the seeds drawn are a
+    small fraction of the plain search's, and the lone-key filter spares the
+    peeling test most pairs."""
     keys, offs = make_workload("fixed48")
     g = gpu_bip(shock, keys, offs)
     assert g[0] == 0
@@ -89,6 +90,9 @@ def test_bip_full_batch_statistics(shock, oracle_mod):
     L = len(offs) - 1
     print(f"[gpu] bip fixed48 stats {st}", flush=True)
     assert st["seeds_hashed"] / L < 2000 and st["kernel_ms"] > 0
+    # every leaf peels at least its answer; the lone-key filter rejects most
+    # candidate pairs (a one-edge tree is common when both halves are covered)
+    assert L <= st["pairs_peeled"] < 0.6 * st["pairs_tested"]
     pick = np.random.default_rng(3103).choice(L, 32, replace=False)
     for j in pick:
         o = oracle_mod.bip_leaf_search(keys, offs[j:j + 2])
