@@ -54,3 +54,34 @@ def test_oracle_is_not_imported_by_the_package():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src and "shock_oracle" not in src, f
+
+
+def test_ctypes_structs_match_the_headers(tmp_path):
+    """Every struct the binding passes across the boundary has the size and
+    field offsets the C compiler gives the header's typedef (compiled here
+    with gcc against include/)."""
+    import ctypes
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    from paper_2308_09561_amd import binding as b
+    pairs = [(b.ShockOpts, "shock_opts"), (b.ShockStats, "shock_stats"), (b.BipStats, "shock_bip_stats"),
+             (b.MphfParams, "shock_mphf_params"), (b.MphfStats, "shock_mphf_stats")]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "shockleaf.h"', '#include "shockmphf.h"',
+             "int main(void) {"]
+    want = []
+    for cls, cname in pairs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(cls))
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {f}));')
+            want.append(getattr(cls, f).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == want
