@@ -319,12 +319,13 @@ def main():
         wall_b = (time.perf_counter() - t5) / args.bip_steps
         pair_max = torch.maximum(ba, bb).cpu().numpy().astype(np.float64)
         n_b = float(sizes.mean())
-        # Lower bound of the algorithmic work: every seed hashed over the
-        # leaf's keys at 7 ops per key evaluation (xor, 32x32+64 multiply-add,
-        # fold, multiply by nl, high product by nr, and one shift-or per
-        # half's 32-bit coverage word).  The pair tests (cells read back, the
-        # lone-key filter, peeling) are not counted.
-        ops = b_seeds / args.bip_steps * n_b * 7
+        # Lower bound of the algorithmic work: the seeds up to each leaf's
+        # answer, max(a, b) + 1, hashed over the leaf's keys at 7 ops per key
+        # evaluation (xor, 32x32+64 multiply-add, fold, multiply by nl, high
+        # product by nr, and one shift-or per half's 32-bit coverage word).
+        # Seeds hashed beyond the answer and the pair tests (cells read back,
+        # the lone-key filter, peeling) are not counted.
+        ops = float((pair_max + 1).sum()) * n_b * 7
         kms = float(np.mean(b_ms))
         bip = {"leaves_per_s": L / wall_b, "ms_per_step": wall_b * 1e3, "kernel_ms": kms,
                "mean_max_seed": float(pair_max.mean()), "seeds_hashed_per_leaf": b_seeds / args.bip_steps / L,
