@@ -73,7 +73,8 @@ typedef struct shock_opts {
   int32_t spl;            /* seeds per lane per iteration: 1, 2 or 4; 0 = tuned default for the batch */
   int32_t block_iters;    /* units (64*spl seeds) a worker claims at once, for every leaf size; 0 = by leaf size */
   int32_t waves_per_wg;   /* waves per workgroup = leaves a workgroup works on at once (1..16); 0 = tuned */
-  int32_t workers;        /* persistent waves in the grid; 0 = fill the device */
+  int32_t workers;        /* persistent waves in the grid; 0 = sized to the batch: about one wave per leaf
+                             (one workgroup per leaf for heavy leaves), at least 512, at most every resident wave */
   int32_t check_dups;     /* 1 = reject leaves with repeated keys (SHOCK_EDUPKEY) */
   const volatile int32_t *cancel; /* HOST pointer (pinned or managed memory) or NULL; nonzero = stop */
   int32_t leaf_size_hint; /* typical leaf size, sizes launches where offsets are not read back (contexts); 0 = 48 */
