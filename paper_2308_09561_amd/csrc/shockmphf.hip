@@ -516,6 +516,169 @@ __global__ void xor_assign_kernel(const uint64_t *__restrict__ keys, uint64_t rm
   }
 }
 
+// Small systems: the first frontier, every peeling round and the assignment
+// in one workgroup, the rounds separated by barriers instead of launches and
+// the round state in LDS.  The rounds, the peel cell of every key and so the
+// cells are those of the multi-launch passes above.  Data written earlier in
+// the kernel by other threads is read with agent-scope atomic loads, which
+// bypass the L1, after every thread's stores have completed (s_waitcnt 0)
+// and a barrier.  A stack entry holds the key index and, in its top two
+// bits, the key's peel cell.
+constexpr uint32_t kSmallThreads = 1024;
+constexpr uint64_t kSmallRetrievalKeys = 1u << 16;
+
+__device__ __forceinline__ uint64_t ld_agent64(const void *p) {
+  return __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_agent32(const void *p) {
+  return __hip_atomic_load(reinterpret_cast<const uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void phase_sync() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+// Workgroup-wide append onto an LDS counter: each thread offers cnt slots and
+// gets the index of its first one.  Every thread of the workgroup must call it.
+__device__ __forceinline__ uint32_t small_append(uint32_t *tail, uint32_t cnt, uint32_t *wave_sum, uint32_t *base) {
+  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  uint32_t x = cnt;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  if (lane == 63) wave_sum[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) {
+      const uint32_t t = wave_sum[w];
+      wave_sum[w] = tot;
+      tot += t;
+    }
+    *base = *tail;
+    *tail += tot;
+  }
+  __syncthreads();
+  const uint32_t at = *base + wave_sum[wave] + x - cnt;
+  __syncthreads();
+  return at;
+}
+
+__global__ __launch_bounds__(kSmallThreads) void xor_solve_small_kernel(
+    const uint64_t *__restrict__ keys, uint32_t n_keys, uint64_t rmix, uint64_t seg, unsigned long long *cw,
+    uint32_t cells, uint64_t *frontier, uint32_t *taken, uint32_t *stack, uint64_t *round_off,
+    const uint8_t *__restrict__ choice, uint8_t *z, unsigned long long *pk) {
+  __shared__ uint32_t wave_sum[kSmallThreads / 64];
+  __shared__ uint32_t base_s, fr_begin, fr_end, fr_tail, st_begin, st_tail, round_s;
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) fr_begin = fr_end = fr_tail = st_begin = st_tail = round_s = 0;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < cells; c0 += kSmallThreads) {
+    const uint32_t c = c0 + tid;
+    const bool one = c < cells && (ld_agent64(&cw[c]) >> 48) == 1;
+    const uint32_t at = small_append(&fr_tail, one ? 1u : 0u, wave_sum, &base_s);
+    if (one && at < cells) frontier[at] = c;
+  }
+  phase_sync();
+  for (;;) {
+    if (tid == 0) {
+      // open the next round on the frontier the previous one appended
+      round_off[round_s] = st_tail;
+      st_begin = st_tail;
+      const uint32_t b = fr_end, e = fr_tail;
+      fr_end = e;
+      if (e > b && round_s < kMaxPeelRounds) {
+        fr_begin = b;
+        ++round_s;
+      } else {
+        fr_begin = e;
+      }
+    }
+    __syncthreads();
+    const uint32_t fb = fr_begin, fe = fr_end < cells ? fr_end : cells;
+    if (fb >= fe) break;
+    // detect: each frontier cell still at count one peels its key at the key's
+    // first cell of count one
+    for (uint32_t k0 = fb; k0 < fe; k0 += kSmallThreads) {
+      const uint32_t k = k0 + tid;
+      uint32_t item = 0, got = 0;
+      if (k < fe) {
+        const uint64_t w = ld_agent64(&cw[ld_agent64(&frontier[k])]);
+        const uint64_t i = w & (kCountOne - 1);
+        if ((w >> 48) == 1 && i < n_keys) {
+          const uint32_t bit = 1u << (i & 31);
+          if (!(atomicOr(&taken[i >> 5], bit) & bit)) {
+            uint64_t c[3];
+            xor_cells(keys[i], rmix, seg, c);
+            const uint64_t w0 = ld_agent64(&cw[c[0]]), w1 = ld_agent64(&cw[c[1]]);  // both in flight
+            const uint32_t q = (w0 >> 48) == 1 ? 0u : ((w1 >> 48) == 1 ? 1u : 2u);
+            item = (uint32_t)i | (q << 30);
+            got = 1;
+          }
+        }
+      }
+      const uint32_t at = small_append(&st_tail, got, wave_sum, &base_s);
+      if (got && at < n_keys) stack[at] = item;
+    }
+    phase_sync();
+    // remove the round's keys; cells falling from two to one form the next frontier
+    const uint32_t sb = st_begin, se = st_tail < n_keys ? st_tail : n_keys;
+    for (uint32_t k0 = sb; k0 < se; k0 += kSmallThreads) {
+      const uint32_t k = k0 + tid;
+      uint64_t c[3] = {0, 0, 0};
+      uint32_t fell = 0;
+      if (k < se) {
+        const uint32_t i = ld_agent32(&stack[k]) & ((1u << 30) - 1);
+        xor_cells(keys[i], rmix, seg, c);
+#pragma unroll
+        for (uint32_t q = 0; q < 3; ++q)
+          if ((atomicSub(&cw[c[q]], kCountOne + i) >> 48) == 2) fell |= 1u << q;
+      }
+      uint32_t at = small_append(&fr_tail, __popc(fell), wave_sum, &base_s);
+#pragma unroll
+      for (uint32_t q = 0; q < 3; ++q)
+        if ((fell >> q) & 1) {
+          if (at < cells) frontier[at] = c[q];
+          ++at;
+        }
+    }
+    phase_sync();
+  }
+  const uint32_t R = round_s, peeled = st_tail;
+  if (tid == 0) {
+    pk[kPkRound] = R;
+    pk[kPkStTail] = peeled;
+    pk[kPkFrTail] = fr_tail;
+    pk[kPkFrEnd] = fr_end;
+  }
+  phase_sync();
+  if (peeled != n_keys) return;  // a 2-core is left: the host tries the next retrieval seed
+  // assignment, rounds in reverse (keys of one round write distinct cells and
+  // read none written in that round); only the last round can be empty (a
+  // frontier whose cells all fell to zero), and it is not counted
+  uint32_t nonempty = 0;
+  for (uint32_t r = R; r >= 1; --r) {
+    const uint32_t b = (uint32_t)ld_agent64(&round_off[r - 1]);
+    const uint32_t e = r == R ? peeled : (uint32_t)ld_agent64(&round_off[r]);
+    nonempty += e > b ? 1u : 0u;
+    for (uint32_t k = b + tid; k < e; k += kSmallThreads) {
+      const uint32_t item = ld_agent32(&stack[k]);
+      const uint32_t i = item & ((1u << 30) - 1), p = item >> 30;
+      uint64_t c[3];
+      xor_cells(keys[i], rmix, seg, c);
+      uint32_t acc = choice[i] & 1;
+#pragma unroll
+      for (uint32_t q = 0; q < 3; ++q)
+        if (q != p) acc ^= (ld_agent32(z + (c[q] & ~3ull)) >> (8 * (c[q] & 3))) & 0xFF;
+      z[c[p]] = (uint8_t)acc;
+    }
+    phase_sync();
+  }
+  if (tid == 0) pk[kPkRound] = nonempty;
+}
+
 __global__ void pack_bits_kernel(const uint8_t *__restrict__ z, uint64_t cells, uint64_t *bits) {
   const uint64_t words = (cells + 63) / 64;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -949,6 +1112,20 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
                        0u);
     hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, stream, pk, (uint64_t)kPkWords);
     if (N) hipLaunchKernelGGL(xor_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg, cw);
+    if (N <= kSmallRetrievalKeys) {
+      // one workgroup peels and assigns the whole system
+      hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, z, cells);
+      hipLaunchKernelGGL(xor_solve_small_kernel, dim3(1), dim3(kSmallThreads), 0, stream, leaf_keys, (uint32_t)N, rmix,
+                         seg, cw, (uint32_t)cells, frontier, taken, stack, round_off, (const uint8_t *)choice, z, pk);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(pk_host, pk, kPkWords * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      if (pk_host[kPkStTail] != N) continue;  // a 2-core is left: next retrieval seed
+      rounds = (uint32_t)pk_host[kPkRound];
+      M->rho = rho;
+      solved = true;
+      continue;
+    }
     hipLaunchKernelGGL(xor_frontier_kernel, dim3(grid_for(cells, 256 * kFrontierPer)), dim3(kAppendThreads), 0, stream,
                        (const unsigned long long *)cw, cells, frontier, pk);
     HIP_TRY(hipGetLastError());
