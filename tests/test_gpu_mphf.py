@@ -244,3 +244,23 @@ def test_mphf_more_buckets_than_the_lds_histogram(shock, oracle_mod, rf):
         assert (pos == lay["positions"]).all()
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("N", [65536, 65537])
+def test_mphf_retrieval_on_both_sides_of_the_one_workgroup_limit(shock, oracle_mod, N):
+    """Retrieval systems of up to 2^16 keys are solved by one workgroup, larger
+    ones by the multi-launch rounds; at the limit and one key above it the
+    retrieval seed and cells equal the oracle's."""
+    keys = splitmix64(2500 + N, N)
+    m, k = _build(shock, keys, **SMALL)
+    try:
+        rc, lay = oracle_mod.mphf_build(keys, **SMALL)
+        assert rc == 0
+        ex = m.export()
+        assert (ex["seeds"] == lay["seeds"]).all()
+        assert ex["rho"] == lay["rho"] and (ex["z"] == lay["z"]).all()
+        pos = _host(m.query(k))
+        torch.cuda.synchronize()
+        assert (pos == lay["positions"]).all()
+    finally:
+        m.close()
