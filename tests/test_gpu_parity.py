@@ -208,3 +208,24 @@ def test_stats_are_reported(shock):
     gpu_search(shock, keys, offs)
     st = shock.shock_last_stats()
     assert st["seeds_tested"] > 0 and st["kernel_ms"] > 0 and st["pf_checks"] >= 256
+
+
+@pytest.mark.parametrize("L", [1, 3, 10, 100])
+def test_small_batches_with_default_workers_match_oracle(shock, oracle_mod, L):
+    """Small batches launch with the default worker count sized to the batch
+    (about one wave per leaf, at least 512) instead of every resident wave;
+    plain 40-key and rotation-fitting 48-key leaves still equal the oracle."""
+    keys, offs = fixed_leaves(L, 40, 12_000 + L)
+    g = gpu_search(shock, keys, offs)
+    st = shock.shock_last_stats()
+    assert 512 <= st["workers"] <= max(512, 4 * L), st
+    o = oracle_mod.parallel(oracle_mod.leaf_search, keys, offs)
+    assert_same(g, (0, np.concatenate([r[1] for r in o]), np.concatenate([r[2] for r in o])), f"plain L={L}")
+    Lr = min(L, 20)  # the oracle's rotation fitting takes about 0.3 s per 48-key leaf
+    keys, offs = fixed_leaves(Lr, 48, 12_100 + L)
+    rc, s, r, f = shock.rf_leaf_search(_dev(keys), _dev(offs))
+    torch.cuda.synchronize()
+    o = oracle_mod.parallel(oracle_mod.rf_leaf_search, keys, offs)
+    assert rc == 0 and all(x[0] == 0 for x in o)
+    s_o, r_o, f_o = (np.concatenate([x[i] for x in o]) for i in (1, 2, 3))
+    assert (_host(s) == s_o).all() and (r.cpu().numpy() == r_o).all() and (_host(f) == f_o).all()
