@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-                               "-o", tmp, *_SRCS])
+                               "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -94,6 +94,8 @@ def lib():
         L.shock_oracle_mphf_query.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                               ctypes.c_uint64, _u64p, _u64p, _u32p, _u8p, _u64p, ctypes.c_int,
                                               ctypes.c_uint32, ctypes.c_uint64, _u8p, _u64p]
+        L.shock_oracle_bip_pair_rank.restype = ctypes.c_uint64
+        L.shock_oracle_bip_pair_rank.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.shock_oracle_bip_slots.restype = None
         L.shock_oracle_bip_slots.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, _u32p, _u32p]
         L.shock_oracle_bip_leaf_search.restype = ctypes.c_int
@@ -361,16 +363,21 @@ def xor_get(keys, rho: int, z):
 
 
 def mphf_build(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: int = 56, rf: bool = False,
-               partial_k: int = 0):
+               partial_k: int = 0, bip: bool = False):
     """The whole flat MPHF: layout, leaf seeds and orientations (the leaf
-    search, or rotation fitting with values s * n + r), the retrieval of each
-    key's choice, and every key's position (index i of the input keys ->
-    positions[i])."""
+    search, rotation fitting with values s * n + r, or with bip the bipartite
+    search with values the rank of the pair (a, b) in its search order), the
+    retrieval of each key's choice, and every key's position (index i of the
+    input keys -> positions[i]).  With bip the positions come from the
+    oracle's own query (shock_oracle_mphf_query) over the built structure."""
     rc, lay = mphf_split(keys, bucket_size, leaf_target, leaf_max)
     if rc != OK:
         return rc, None
     lk, offs = lay["leaf_keys"], lay["leaf_offsets"]
-    if rf:
+    if bip:
+        rc, pa, pb, orient = bip_leaf_search(lk, offs)
+        seeds = np.array([bip_pair_rank(int(x), int(y)) for x, y in zip(pa, pb)], dtype=np.uint64)
+    elif rf:
         rc, s_rf, rot, orient = rf_leaf_search(lk, offs, partial_k=partial_k)
         sizes_u = lay["leaf_sizes"].astype(np.uint64)
         seeds = np.where(sizes_u >= 2, s_rf * sizes_u + rot.astype(np.uint64), s_rf)
@@ -386,15 +393,20 @@ def mphf_build(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: i
     rc, rho, z = xor_build(lk, f)
     if rc != OK:
         return rc, None
-    if rf:
+    lay.update({"seeds": seeds, "orient": orient, "choice": f, "rho": rho, "z": z,
+                "leaf_target": leaf_target, "leaf_max": leaf_max, "bucket_size": bucket_size, "rf": bool(rf),
+                "partial_k": partial_k, "bip": bool(bip)})
+    positions = np.zeros(lk.size, np.uint64)
+    if bip:
+        rc, pos_leaf_order = mphf_query(lay, lk)
+        if rc != OK:
+            return rc, None
+    elif rf:
         _, pos_leaf_order = rf_leaf_query(lk, offs, s_rf, rot, orient, partial_k=partial_k)
     else:
         _, pos_leaf_order = leaf_query(lk, offs, seeds, orient)
-    positions = np.zeros(lk.size, np.uint64)
     positions[lay["key_index"].astype(np.int64)] = pos_leaf_order
-    lay.update({"seeds": seeds, "orient": orient, "choice": f, "rho": rho, "z": z, "positions": positions,
-                "leaf_target": leaf_target, "leaf_max": leaf_max, "bucket_size": bucket_size, "rf": bool(rf),
-                "partial_k": partial_k})
+    lay["positions"] = positions
     return OK, lay
 
 
@@ -407,7 +419,8 @@ def mphf_query(lay, queries):
                                        _p64(lay["bucket_offset"]), _p64(lay["leaf_base"]), _p32(lay["sigma"]),
                                        _p8(np.ascontiguousarray(lay["leaf_sizes"])),
                                        _p64(np.ascontiguousarray(lay["seeds"], dtype=np.uint64)),
-                                       int(lay.get("rf", False)), lay.get("partial_k", 0), lay["rho"], _p8(lay["z"]),
+                                       2 if lay.get("bip", False) else int(lay.get("rf", False)),
+                                       lay.get("partial_k", 0), lay["rho"], _p8(lay["z"]),
                                        _p64(out))
     return rc, out[:q.size]
 
@@ -419,6 +432,11 @@ def bip_slots(key: int, seed: int, n: int) -> tuple[int, int]:
     lib().shock_oracle_bip_slots(key & 0xFFFFFFFFFFFFFFFF, seed & 0xFFFFFFFFFFFFFFFF, n, ctypes.byref(a),
                                  ctypes.byref(b))
     return a.value, b.value
+
+
+def bip_pair_rank(a: int, b: int) -> int:
+    """Rank of the seed pair (a, b) in the bipartite search order."""
+    return int(lib().shock_oracle_bip_pair_rank(a, b))
 
 
 def bip_leaf_search(keys, offsets, max_seed: int = 1 << 22, use_filter: bool = True):

@@ -178,6 +178,11 @@ int shock_oracle_rice_decode(const uint64_t *fixed, const uint64_t *unary, const
  * Orientation: as shock_oracle_orientation on the edges (left, right).
  * Seeds are limited to max_seed (pairs with max(a, b) < max_seed). */
 void shock_oracle_bip_slots(uint64_t x, uint64_t s, uint32_t n, uint32_t *left, uint32_t *right);
+/* Rank of the pair (a, b) in that order: with m = max(a, b), the m^2 pairs
+ * of smaller maximum come first, then (0, m) .. (m-1, m), then (m, 0) ..
+ * (m, m); so the rank is m^2 + a if a < m, else m^2 + m + b.  A stored
+ * bipartite leaf value in the flat MPHF. */
+uint64_t shock_oracle_bip_pair_rank(uint64_t a, uint64_t b);
 int shock_oracle_bip_leaf_search(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
                                  uint64_t *out_a, uint64_t *out_b, uint64_t *out_orient, uint64_t max_seed,
                                  int use_filter);
@@ -229,7 +234,10 @@ int shock_oracle_xor_get(const uint64_t *keys, uint64_t n_keys, uint64_t rho, co
  * offset + h_{f(x)}(x, seed) with f(x) read from the retrieval structure.
  * leaf_values u64[n_leaves]: the leaf search's seeds, or with rf = 1 the
  * rotation-fitting candidates stored as s * n + r (slots of
- * shock_oracle_rf_slots with period partial_k; 0 = 8 above 32 keys, else 1). */
+ * shock_oracle_rf_slots with period partial_k; 0 = 8 above 32 keys, else 1),
+ * or with rf = 2 the bipartite pair (a, b) stored as its rank
+ * shock_oracle_bip_pair_rank(a, b): key x's two candidate cells are then the
+ * left cell of x under a and the right cell of x under b. */
 int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_t n_keys, uint32_t leaf_target,
                             uint64_t n_buckets, const uint64_t *bucket_offset, const uint64_t *leaf_base,
                             const uint32_t *sigma, const uint8_t *leaf_sizes, const uint64_t *leaf_values,

@@ -4,6 +4,7 @@
  */
 #include "shock_oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -202,6 +203,30 @@ int shock_oracle_xor_get(const uint64_t *keys, uint64_t n_keys, uint64_t rho, co
   return SHOCK_ORACLE_OK;
 }
 
+/* The pairs of bipartite seeds in the search order (by max(a, b) = m, then a,
+ * then b): for each m, first (a, m) for a = 0 .. m-1, then (m, b) for
+ * b = 0 .. m.  The m^2 pairs with a smaller maximum come before them, so the
+ * rank of (a, b) is m^2 + a if a < m, else m^2 + m + b. */
+uint64_t shock_oracle_bip_pair_rank(uint64_t a, uint64_t b) {
+  uint64_t m = a > b ? a : b;
+  return m * m + (a < m ? a : m + b);
+}
+
+static void bip_pair_of_rank(uint64_t v, uint64_t *a, uint64_t *b) {
+  /* m = floor(sqrt(v)): a floating-point estimate, then corrected exactly */
+  uint64_t m = (uint64_t)sqrt((double)v);
+  while (m > 0 && m * m > v) --m;
+  while ((m + 1) * (m + 1) <= v) ++m;
+  uint64_t r = v - m * m;
+  if (r < m) {
+    *a = r;
+    *b = m;
+  } else {
+    *a = m;
+    *b = r - m;
+  }
+}
+
 int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_t n_keys, uint32_t leaf_target,
                             uint64_t n_buckets, const uint64_t *bucket_offset, const uint64_t *leaf_base,
                             const uint32_t *sigma, const uint8_t *leaf_sizes, const uint64_t *leaf_values,
@@ -225,7 +250,18 @@ int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_
     int f = z[c[0]] ^ z[c[1]] ^ z[c[2]];
     uint32_t h0 = 0, h1 = 0;
     uint64_t v = leaf_values[leaf_base[b] + j];
-    if (rf && n >= 2) {
+    if (rf == 2 && n >= 1) {
+      /* bipartite: v is the rank of the pair (a, b) in the search order */
+      uint64_t a, bs, l, r;
+      bip_pair_of_rank(v, &a, &bs);
+      uint32_t cl, cr;
+      shock_oracle_bip_slots(x, a, n, &cl, &cr);
+      l = cl;
+      shock_oracle_bip_slots(x, bs, n, &cl, &cr);
+      r = cr;
+      h0 = (uint32_t)l;
+      h1 = (uint32_t)r;
+    } else if (rf == 1 && n >= 2) {
       uint32_t k = partial_k ? partial_k : (n > 32 ? 8u : 1u);
       shock_oracle_rf_slots(x, v / n, (uint32_t)(v % n), k, n, &h0, &h1);
     } else if (n >= 1) {
