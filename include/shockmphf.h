@@ -17,7 +17,10 @@
  *   - a leaf's keys, sorted ascending, get the smallest ShockHash seed and the
  *     canonical orientation of shock_leaf_search (include/shockleaf.h), or
  *     with rotation_fitting the smallest candidate (s, r) of
- *     shock_rf_leaf_search_ex, stored as the value v = s * n + r;
+ *     shock_rf_leaf_search_ex, stored as the value v = s * n + r, or with
+ *     bipartite the first seed pair (a, b) of shock_bip_leaf_search_ex,
+ *     stored as its rank in that search's order: with m = max(a, b),
+ *     v = m^2 + a if a < m, else m^2 + m + b;
  *   - the leaf values are Golomb-Rice coded (include/shockcode.h) with the
  *     caller's table of Rice parameters by leaf size;
  *   - each key's choice f(x) is stored in a 1-bit retrieval structure: a
@@ -25,7 +28,9 @@
  *     solved by peeling in synchronous rounds (a simpler stand-in for the
  *     paper's BuRR ribbon retrieval; about 1.23 bits per key instead of
  *     about 1.01);
- *   - the value of key x: (key offset of its leaf) + h_{f(x)}(x, seed).
+ *   - the value of key x: (key offset of its leaf) + h_{f(x)}(x, seed); for a
+ *     bipartite leaf h_0 is x's left cell under a and h_1 its right cell
+ *     under b.
  * For the N distinct keys it was built from, the function is a bijection onto
  * [0, N).  For other keys it returns some value in [0, N) (or UINT64_MAX if
  * the key falls in an empty bucket).
@@ -52,7 +57,11 @@ typedef struct {
   const uint8_t *rice_k_by_n; /* HOST u8[65]: Rice parameter by leaf size (each at most 56); copied at build */
   uint32_t rotation_fitting; /* 1: leaves use rotation fitting (Section 4); default 0 */
   int32_t partial_k;         /* rotation fitting's partial-hash period: 0 (8 above 32 keys, else 1), 1 or 8 */
-  uint64_t reserved[3];
+  uint32_t bipartite;        /* 1: leaves use bipartite ShockHash (Section 9); not with rotation_fitting;
+                                repeated keys are then reported as SHOCK_ENOTFOUND (no retrieval seed
+                                solves them) rather than SHOCK_EDUPKEY; default 0 */
+  uint32_t reserved0;
+  uint64_t reserved[2];
 } shock_mphf_params;
 
 typedef struct shock_mphf shock_mphf;

@@ -213,10 +213,12 @@ uint64_t shock_oracle_bip_pair_rank(uint64_t a, uint64_t b) {
 }
 
 static void bip_pair_of_rank(uint64_t v, uint64_t *a, uint64_t *b) {
-  /* m = floor(sqrt(v)): a floating-point estimate, then corrected exactly */
+  /* m = floor(sqrt(v)): a floating-point estimate, then corrected exactly;
+   * m < 2^32 keeps every square below 2^64 */
   uint64_t m = (uint64_t)sqrt((double)v);
+  if (m > 0xFFFFFFFFULL) m = 0xFFFFFFFFULL;
   while (m > 0 && m * m > v) --m;
-  while ((m + 1) * (m + 1) <= v) ++m;
+  while (m < 0xFFFFFFFFULL && (m + 1) * (m + 1) <= v) ++m;
   uint64_t r = v - m * m;
   if (r < m) {
     *a = r;

@@ -89,7 +89,9 @@ class MphfParams(ctypes.Structure):
         ("rice_k_by_n", ctypes.c_void_p),
         ("rotation_fitting", ctypes.c_uint32),
         ("partial_k", ctypes.c_int32),
-        ("reserved", ctypes.c_uint64 * 3),
+        ("bipartite", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint64 * 2),
     ]
 
 
@@ -507,7 +509,7 @@ class MPHF:
     queried on the GPU.  Raises ShockError if the build fails."""
 
     def __init__(self, keys, bucket_size=2000, leaf_target=40, leaf_max=56, rice_table=None, stream=None,
-                 rotation_fitting=False, partial_k=0):
+                 rotation_fitting=False, partial_k=0, bipartite=False):
         import numpy as np
         if keys.device.type != "cuda" or keys.dtype.itemsize != 8:
             raise ValueError("keys must be a 64-bit device tensor")
@@ -519,6 +521,7 @@ class MPHF:
         lib().shock_mphf_params_init(ctypes.byref(p))
         p.bucket_size, p.leaf_target, p.leaf_max = bucket_size, leaf_target, leaf_max
         p.rotation_fitting, p.partial_k = int(bool(rotation_fitting)), partial_k
+        p.bipartite = int(bool(bipartite))
         table = _table(rice_table)
         p.rice_k_by_n = ctypes.cast(table, ctypes.c_void_p)
         self._h = ctypes.c_void_p()

@@ -54,6 +54,17 @@ __device__ __forceinline__ void slot_pair(uint32_t alo, uint32_t ahi, uint32_t t
   h1 = f1;
 }
 
+// Bipartite ShockHash: the left cell l in [0, nl) and the right cell r in
+// [nl, nl + nr) of a premixed key a under a seed mix t.
+__device__ __forceinline__ void bip_cells(uint64_t a, uint64_t t, uint32_t nl, uint32_t nr, uint32_t &l,
+                                          uint32_t &r) {
+  const uint64_t p = (uint64_t)((uint32_t)a ^ (uint32_t)t) * (a >> 32) + t;
+  const uint32_t z = (uint32_t)p ^ (uint32_t)(p >> 32);
+  const uint64_t q = (uint64_t)z * nl;
+  l = (uint32_t)(q >> 32);
+  r = nl + __umulhi((uint32_t)q, nr);
+}
+
 // 1 if key x belongs to rotation fitting's second set.
 __device__ __forceinline__ uint32_t key_side(uint64_t x) { return (uint32_t)(fmix64(x ^ kSideKey) >> 63); }
 

@@ -38,6 +38,7 @@
 
 namespace {
 
+using shockhash::bip_cells;
 using shockhash::fmix64;
 using shockhash::seed_mix;
 using shockwave::bcast64;
@@ -80,11 +81,7 @@ __device__ __forceinline__ void bip_cell_idx(uint64_t a, uint64_t t, uint32_t nl
   r = __umulhi((uint32_t)q, nr);
 }
 
-// Left and right cells of a premixed key under a seed mix t.
-__device__ __forceinline__ void bip_cells(uint64_t a, uint64_t t, uint32_t nl, uint32_t nr, uint32_t &l, uint32_t &r) {
-  bip_cell_idx(a, t, nl, nr, l, r);
-  r += nl;
-}
+
 
 // Cell of this lane's key under pool entry q of one side: from the LDS cache
 // or hashed again.

@@ -304,6 +304,40 @@ __global__ __launch_bounds__(256) void leaf_sort_kernel(uint64_t *keys, const ui
 }
 
 // Rotation fitting: a leaf's stored value is its candidate index s * n + r.
+// Leaf kinds (shock_mphf::rf).
+constexpr uint32_t kLeafPlain = 0, kLeafRf = 1, kLeafBip = 2;
+
+// Bipartite leaves: the rank of the seed pair (a, b) in the search's order
+// (by m = max(a, b), then a, then b): m^2 pairs precede maximum m, then
+// (0, m) .. (m - 1, m), then (m, 0) .. (m, m).
+__global__ void bip_values_kernel(const uint64_t *__restrict__ pa, const uint64_t *__restrict__ pb, uint64_t *values,
+                                  uint64_t n_leaves) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_leaves; g += stride) {
+    const uint64_t a = pa[g], b = pb[g];
+    if (a == kNone || b == kNone) {
+      values[g] = kNone;
+      continue;
+    }
+    const uint64_t m = a > b ? a : b;
+    values[g] = m * m + (a < m ? a : m + b);
+  }
+}
+
+// The pair (a, b) of rank v: m = floor(sqrt(v)) (a double estimate, within
+// one of the root, corrected to the exact integer root; m stays below 2^32,
+// so no square overflows), r = v - m^2.
+__device__ __forceinline__ void bip_pair_of(uint64_t v, uint64_t &a, uint64_t &b) {
+  constexpr uint64_t kMaxRoot = 0xFFFFFFFFull;
+  uint64_t m = (uint64_t)sqrt((double)v);
+  if (m > kMaxRoot) m = kMaxRoot;
+  while (m > 0 && m * m > v) --m;
+  while (m < kMaxRoot && (m + 1) * (m + 1) <= v) ++m;
+  const uint64_t r = v - m * m;
+  a = r < m ? r : m;
+  b = r < m ? m : r - m;
+}
+
 __global__ void rf_values_kernel(uint64_t *seeds, const uint32_t *__restrict__ rot,
                                  const uint8_t *__restrict__ leaf_sizes, uint64_t n_leaves) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -823,10 +857,19 @@ __global__ __launch_bounds__(256) void mphf_query_kernel(QueryArgs A, const uint
     const uint32_t f = (uint32_t)(((A.zbits[c[0] >> 6] >> (c[0] & 63)) ^ (A.zbits[c[1] >> 6] >> (c[1] & 63)) ^
                                    (A.zbits[c[2] >> 6] >> (c[2] & 63))) & 1);
     uint32_t h0 = 0, h1 = 0;
-    if (n >= 2) {
+    if (A.rf == kLeafBip && n >= 2) {
+      // left cell under a, right cell under b
+      uint64_t pa = 0, pb = 0;
+      bip_pair_of(value, pa, pb);
+      const uint64_t ax = fmix64(x);
+      const uint32_t nl = n / 2, nr = n - n / 2;
+      uint32_t l, r;
+      shockhash::bip_cells(ax, seed_mix(pa), nl, nr, h0, r);
+      shockhash::bip_cells(ax, seed_mix(pb), nl, nr, l, h1);
+    } else if (n >= 2) {
       uint64_t seed = value;
       uint32_t r = 0;
-      if (A.rf) {  // value = s * n + r; the first set hashes with s - s mod k
+      if (A.rf == kLeafRf) {  // value = s * n + r; the first set hashes with s - s mod k
         seed = value / n;
         const uint32_t pk = A.partial_k ? A.partial_k : (n > 32 ? 8u : 1u);
         if (shockhash::key_side(x)) r = (uint32_t)(value - seed * n);
@@ -971,7 +1014,8 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   const size_t scratch_bytes = align256(2 * 8) + align256(B * 4) + 2 * align256(N * 8) + align256((Lmax + 1) * 8) +
                                2 * align256(Lmax * 8) + align256(Lmax * 4) + 2 * align256(N ? N : 1) +
                                align256(((N + 31) / 32) * 4) + align256(N * 4) + 2 * align256(cells_r * 8) +
-                               align256((kMaxPeelRounds + 1) * 8) + align256(kPkWords * 8) + align256(cells_r) + 32 * 256;
+                               align256((kMaxPeelRounds + 1) * 8) + align256(kPkWords * 8) + align256(cells_r) + 32 * 256 +
+                               (M->rf == kLeafBip ? 2 * align256(Lmax * 8) : 0);  // bipartite seed pairs
   Scratch S;
   HIP_TRY(reserve_scratch(scratch_bytes, S));
   unsigned long long *err = nullptr;
@@ -1036,7 +1080,19 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
     shock_opts_init(&o);
     o.check_dups = 1;
     int rc;
-    if (M->rf) {
+    if (M->rf == kLeafBip) {
+      uint64_t *pa = nullptr, *pb = nullptr;
+      HIP_TRY(S.alloc(&pa, L));
+      HIP_TRY(S.alloc(&pb, L));
+      shock_bip_stats bst;
+      rc = shock_bip_leaf_search_ex(leaf_keys, leaf_off, L, pa, pb, orient, &o, stream, &bst);
+      if (rc == SHOCK_OK) {
+        M->search_ms = bst.kernel_ms;
+        hipLaunchKernelGGL(bip_values_kernel, dim3(grid_for(L, 256)), dim3(256), 0, stream, (const uint64_t *)pa,
+                           (const uint64_t *)pb, seeds, L);
+        HIP_TRY(hipGetLastError());
+      }
+    } else if (M->rf == kLeafRf) {
       uint32_t *rot = nullptr;
       HIP_TRY(S.alloc(&rot, L));
       o.partial_k = (int32_t)M->partial_k;
@@ -1051,7 +1107,7 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
     }
     if (rc != SHOCK_OK) return rc;
     shock_stats st;
-    if (shock_last_stats(&st) == SHOCK_OK) M->search_ms = st.kernel_ms;
+    if (M->rf != kLeafBip && shock_last_stats(&st) == SHOCK_OK) M->search_ms = st.kernel_ms;
   }
   M->search_call_ms = ms_since(tp);
   tp = std::chrono::steady_clock::now();
@@ -1219,12 +1275,13 @@ int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_par
   if (P.bucket_size == 0 || P.leaf_target == 0 || P.leaf_max > 64 || P.leaf_target > P.leaf_max) return SHOCK_EINVAL;
   if (P.max_rho_tries == 0 || !P.rice_k_by_n || n_keys >= (1ull << 32)) return SHOCK_EINVAL;
   if (P.rotation_fitting > 1 || (P.partial_k != 0 && P.partial_k != 1 && P.partial_k != 8)) return SHOCK_EINVAL;
+  if (P.bipartite > 1 || (P.bipartite && P.rotation_fitting)) return SHOCK_EINVAL;
   *out = nullptr;
   shock_mphf *M = new shock_mphf;
   M->leaf_target = P.leaf_target;
   M->leaf_max = P.leaf_max;
   M->bucket_size = P.bucket_size;
-  M->rf = P.rotation_fitting;
+  M->rf = P.bipartite ? kLeafBip : (P.rotation_fitting ? kLeafRf : kLeafPlain);
   M->partial_k = (uint32_t)P.partial_k;
   for (int n = 0; n <= 64; ++n) {
     if (P.rice_k_by_n[n] > 56) {

@@ -264,3 +264,50 @@ def test_mphf_retrieval_on_both_sides_of_the_one_workgroup_limit(shock, oracle_m
         assert (pos == lay["positions"]).all()
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("N", [1, 2, 17, 1000, 6000])
+def test_mphf_bipartite_leaves_match_oracle(shock, oracle_mod, N):
+    """Bipartite leaves: every stored part (the leaf values are the ranks of
+    the seed pairs) and every position bit-exact against the oracle."""
+    keys = splitmix64(2800 + N, N)
+    m, k = _build(shock, keys, bipartite=True, **SMALL)
+    try:
+        rc, lay = oracle_mod.mphf_build(keys, bip=True, **SMALL)
+        assert rc == 0
+        ex = m.export()
+        for f in ("bucket_offset", "leaf_base", "sigma", "leaf_sizes", "seeds"):
+            assert (ex[f] == lay[f]).all(), f
+        assert ex["rho"] == lay["rho"] and (ex["z"] == lay["z"]).all()
+        pos = _host(m.query(k))
+        torch.cuda.synchronize()
+        assert (pos == lay["positions"]).all()
+        assert sorted(pos.tolist()) == list(range(N))
+    finally:
+        m.close()
+
+
+def test_mphf_bipartite_leaves_full_size(shock, oracle_mod):
+    """200,000 keys with the default layout and bipartite leaves: a bijection,
+    the layout and a sample of leaf values equal the oracle's, and the
+    oracle's query over the exported structure equals the GPU query."""
+    N = 200_000
+    keys = splitmix64(2900, N)
+    m, k = _build(shock, keys, bipartite=True)
+    try:
+        pos_t = m.query(k)
+        srt, _ = torch.sort(pos_t)
+        assert torch.equal(srt, torch.arange(N, device="cuda", dtype=torch.int64))
+        ex = m.export()
+        rc, lay = oracle_mod.mphf_split(keys, 2000, 40, 56)
+        assert rc == 0
+        offs = lay["leaf_offsets"]
+        pick = np.random.default_rng(2901).choice(lay["n_leaves"], 64, replace=False)
+        for j in pick:
+            _, a, b, _ = oracle_mod.bip_leaf_search(lay["leaf_keys"], offs[j:j + 2])
+            assert int(ex["seeds"][j]) == oracle_mod.bip_pair_rank(int(a[0]), int(b[0])), j
+        struct = dict(lay, seeds=ex["seeds"], rho=ex["rho"], z=ex["z"], leaf_target=40, bip=True)
+        rc, want = oracle_mod.mphf_query(struct, keys)
+        assert rc == 0 and (_host(pos_t) == want).all()
+    finally:
+        m.close()
