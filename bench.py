@@ -405,8 +405,8 @@ def main():
         del keys_q, pos_q
 
     # A complete flat MPHF over uniform keys: build (layout, leaf searches,
-    # seed codes, retrieval) and query of every key, with plain and with
-    # rotation-fitting leaves.
+    # seed codes, retrieval) and query of every key, with plain, with
+    # rotation-fitting and with bipartite leaves.
     mphf = None
     if args.mphf_keys > 0:
         Nm = args.mphf_keys
@@ -416,15 +416,16 @@ def main():
         pos_m = torch.empty(Nm, dtype=torch.int64, device=dev)
         stream = torch.cuda.current_stream(dev)
         mphf = {"keys": Nm, "params": {"bucket_size": 2000, "leaf_target": 40, "leaf_max": 56}}
-        for mode, rf_leaves in (("plain", False), ("rotation_fitting", True)):
+        kinds = (("plain", {}), ("rotation_fitting", {"rotation_fitting": True}), ("bipartite", {"bipartite": True}))
+        for mode, kind in kinds:
             log(f"[bench] flat MPHF of {Nm} keys, {mode} leaves")
             torch.cuda.synchronize()
             t4 = time.perf_counter()
-            m = shock.MPHF(keys_m, rotation_fitting=rf_leaves)  # the first build also loads the kernels
+            m = shock.MPHF(keys_m, **kind)  # the first build also loads the kernels
             cold_s = time.perf_counter() - t4
             m.close()
             t4 = time.perf_counter()
-            m = shock.MPHF(keys_m, rotation_fitting=rf_leaves)
+            m = shock.MPHF(keys_m, **kind)
             build_s = time.perf_counter() - t4
             info = m.info()
             m.query(keys_m, out=pos_m)
@@ -479,19 +480,22 @@ def main():
         latency["p50_ms"] = latency["rate_70pct_capacity"]["p50_ms"]
         latency["p99_ms"] = latency["rate_70pct_capacity"]["p99_ms"]
         if mphf is not None:
-            # The same requests served as complete MPHF builds, at 70% of the
-            # measured build capacity in keys/s.
+            # The same requests served as complete MPHF builds with the leaf
+            # kind that built fastest, at 70% of its measured build capacity
+            # in keys/s.
             from paper_2308_09561_amd.serving import MphfServer
+            kind = max(("rotation_fitting", "bipartite"), key=lambda k: mphf[k]["build_keys_per_s"])
             reqs = synthetic_stream(args.serve_requests, rate_per_s=1.0, seed=5)
             mean_keys = float(np.mean([len(r.keys) for r in reqs]))
-            rate = 0.7 * mphf["rotation_fitting"]["build_keys_per_s"] / mean_keys
+            rate = 0.7 * mphf[kind]["build_keys_per_s"] / mean_keys
             reqs = synthetic_stream(args.serve_requests, rate_per_s=rate, seed=5)
-            srv = MphfServer(hbm_budget_bytes=256 << 20, slots=4, rotation_fitting=True)
-            log(f"[bench] MPHF serving: {len(reqs)} requests at {rate:.1f}/s")
+            srv = MphfServer(hbm_budget_bytes=256 << 20, slots=4, **{kind: True})
+            log(f"[bench] MPHF serving ({kind} leaves): {len(reqs)} requests at {rate:.1f}/s")
             rep_m = srv.run(reqs, realtime=True)
             srv.close()
             summ = rep_m.summary()
             summ["rate_per_s"] = rate
+            summ["leaves"] = kind
             latency["mphf_builds_70pct_capacity"] = summ
             log(f"[bench]   p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, {summ['keys_per_s']:.3g} keys/s, "
                 f"{summ.get('bits_per_key', 0):.3f} bits/key")

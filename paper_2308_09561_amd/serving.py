@@ -293,7 +293,7 @@ class MphfServer:
 
     def __init__(self, hbm_budget_bytes: int = 1 << 30, slots: int = 2, bucket_size: int = 2000,
                  leaf_target: int = 40, leaf_max: int = 56, rice_table=None, verify: bool = False,
-                 rotation_fitting: bool = False, device: str = "cuda:0"):
+                 rotation_fitting: bool = False, bipartite: bool = False, device: str = "cuda:0"):
         import torch
 
         self.torch = torch
@@ -301,7 +301,7 @@ class MphfServer:
         self.budget = int(hbm_budget_bytes)
         self.slots = slots
         self.params = dict(bucket_size=bucket_size, leaf_target=leaf_target, leaf_max=leaf_max, rice_table=rice_table,
-                           rotation_fitting=rotation_fitting)
+                           rotation_fitting=rotation_fitting, bipartite=bipartite)
         self.verify = verify
         self._local = threading.local()
         self.pool = ThreadPoolExecutor(max_workers=slots)
