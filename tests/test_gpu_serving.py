@@ -97,15 +97,17 @@ def test_realtime_stream_reports_latency(shock):
         assert r.latency() >= 0 and r.admitted >= r.arrival - 1e-6
 
 
-def test_mphf_server_builds_complete_functions(shock):
-    """Requests served as complete MPHF builds: every request completes, its
-    function is a bijection (checked by the server), the budget holds, and
-    builds overlap."""
+@pytest.mark.parametrize("kind", ["plain", "bipartite"])
+def test_mphf_server_builds_complete_functions(shock, kind):
+    """Requests served as complete MPHF builds (plain or bipartite leaves):
+    every request completes, its function is a bijection (checked by the
+    server), the budget holds, and builds overlap."""
     from paper_2308_09561_amd.serving import MphfServer, mphf_footprint, synthetic_stream
     reqs = synthetic_stream(10, rate_per_s=1000.0, seed=79, min_keys=2000, max_keys=60000)
     budget = 3 * mphf_footprint(60000)
-    srv = MphfServer(hbm_budget_bytes=budget, slots=3, bucket_size=600, leaf_target=24, leaf_max=36, verify=True)
-    print("[gpu] mphf serving", flush=True)
+    srv = MphfServer(hbm_budget_bytes=budget, slots=3, bucket_size=600, leaf_target=24, leaf_max=36, verify=True,
+                     bipartite=kind == "bipartite")
+    print(f"[gpu] mphf serving, {kind} leaves", flush=True)
     rep = srv.run(reqs, realtime=False)
     srv.close()
     summ = rep.summary()
