@@ -922,6 +922,10 @@ struct Arena {
   char *base = nullptr;
   size_t cap = 0;
   uint64_t *pinned = nullptr;  // kPinnedWords words
+  // a second stream (default priority) on which the retrieval peels while
+  // the leaf search runs on the caller's stream, and two events joining them
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_choice = nullptr, ev_done = nullptr;
 };
 constexpr size_t kPinnedWords = 16;
 thread_local std::vector<Arena> t_arena;
@@ -932,6 +936,7 @@ struct Scratch {
   char *base = nullptr;
   size_t cap = 0, used = 0;
   uint64_t *pinned = nullptr;
+  Arena *arena = nullptr;
   template <typename T>
   hipError_t alloc(T **p, size_t count) {
     const size_t bytes = align256((count ? count : 1) * sizeof(T));
@@ -975,7 +980,17 @@ hipError_t reserve_scratch(size_t bytes, Scratch &S) {
   S.cap = A.cap;
   S.used = 0;
   S.pinned = A.pinned;
+  S.arena = &A;
   return hipSuccess;
+}
+
+// The arena's second stream and events, created on first use.
+hipError_t aux_of(Arena &A) {
+  hipError_t e = hipSuccess;
+  if (!A.aux) e = hipStreamCreateWithFlags(&A.aux, hipStreamNonBlocking);
+  if (e == hipSuccess && !A.ev_choice) e = hipEventCreateWithFlags(&A.ev_choice, hipEventDisableTiming);
+  if (e == hipSuccess && !A.ev_done) e = hipEventCreateWithFlags(&A.ev_done, hipEventDisableTiming);
+  return e;
 }
 
 void free_mphf(shock_mphf *m) {
@@ -1071,6 +1086,68 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   M->layout_ms = ms_since(tp);
   tp = std::chrono::steady_clock::now();
 
+  // Retrieval buffers.  The peeling depends on the keys alone, so for
+  // systems too large for one workgroup it starts here on the arena's second
+  // stream and runs while the leaf search runs on the caller's stream; only
+  // the assignment waits for the leaf orientations.
+  uint8_t *choice = nullptr, *peel = nullptr, *z = nullptr;
+  uint32_t *taken = nullptr, *stack = nullptr;
+  unsigned long long *cw = nullptr, *pk = nullptr;
+  uint64_t *frontier = nullptr, *round_off = nullptr, *pk_host = nullptr;
+  const uint64_t seg = seg_r, cells = cells_r;
+  const uint64_t taken_words = (N + 31) / 32;
+  M->seg = seg;
+  HIP_TRY(S.alloc(&choice, N));
+  HIP_TRY(S.alloc(&peel, N));
+  HIP_TRY(S.alloc(&taken, taken_words));
+  HIP_TRY(S.alloc(&stack, N));
+  HIP_TRY(S.alloc(&cw, cells));
+  HIP_TRY(S.alloc(&frontier, cells));
+  HIP_TRY(S.alloc(&round_off, kMaxPeelRounds + 1));
+  HIP_TRY(S.alloc(&pk, kPkWords));
+  HIP_TRY(S.alloc(&z, cells));
+  static_assert(4 + kPkWords <= kPinnedWords, "pinned words");
+  pk_host = S.pinned + 4;
+  // Round passes run a fixed grid over device-held ranges; the host checks
+  // for the end of the peeling after each chunk of rounds.
+  const int round_grid = grid_for((cells + 3) / 4, 256 * kDetectPer) < 1024 ? grid_for((cells + 3) / 4, 256 * kDetectPer) : 1024;
+  constexpr uint32_t kChunk = 16;
+  const bool big = N > kSmallRetrievalKeys;
+  hipStream_t ps = stream;  // the stream the multi-launch peeling runs on
+  struct AuxGuard {         // no early return leaves work running on the second stream
+    hipStream_t s = nullptr;
+    ~AuxGuard() {
+      if (s) (void)hipStreamSynchronize(s);
+    }
+  } guard;
+  auto rmix_of = [](uint64_t rho) { return shockhash::fmix64((rho + 1) * kRetrievalMul); };
+  auto start_peel = [&](uint64_t rmix) {
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, ps, cw, cells);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(taken_words, 256)), dim3(256), 0, ps, taken, taken_words, 0u);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, ps, pk, (uint64_t)kPkWords);
+    if (N) hipLaunchKernelGGL(xor_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, ps, leaf_keys, N, rmix, seg, cw);
+    hipLaunchKernelGGL(xor_frontier_kernel, dim3(grid_for(cells, 256 * kFrontierPer)), dim3(kAppendThreads), 0, ps,
+                       (const unsigned long long *)cw, cells, frontier, pk);
+  };
+  auto peel_chunk = [&](uint64_t rmix) {
+    for (uint32_t c = 0; c < kChunk; ++c) {
+      hipLaunchKernelGGL(xor_advance_kernel, dim3(1), dim3(64), 0, ps, pk, round_off);
+      hipLaunchKernelGGL(xor_detect_kernel, dim3(round_grid), dim3(256), 0, ps, leaf_keys, N, rmix, seg,
+                         (const unsigned long long *)cw, (const uint64_t *)frontier, cells, taken, peel, stack, pk);
+      hipLaunchKernelGGL(xor_remove_kernel, dim3(round_grid), dim3(256), 0, ps, leaf_keys, N, rmix, seg, cw,
+                         (const uint32_t *)stack, frontier, cells, pk);
+    }
+  };
+  if (big) {
+    HIP_TRY(aux_of(*S.arena));
+    ps = S.arena->aux;
+    guard.s = ps;
+    start_peel(rmix_of(0));
+    peel_chunk(rmix_of(0));
+    peel_chunk(rmix_of(0));
+    HIP_TRY(hipGetLastError());
+  }
+
   // leaf seeds and orientations
   uint64_t *seeds = nullptr, *orient = nullptr;
   HIP_TRY(S.alloc(&seeds, L));
@@ -1131,45 +1208,25 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   M->codes_ms = ms_since(tp);
   tp = std::chrono::steady_clock::now();
   // retrieval of each key's choice
-  uint8_t *choice = nullptr, *peel = nullptr, *z = nullptr;
-  uint32_t *taken = nullptr, *stack = nullptr;
-  unsigned long long *cw = nullptr, *pk = nullptr;
-  uint64_t *frontier = nullptr, *round_off = nullptr, *pk_host = nullptr;
-  const uint64_t seg = seg_r, cells = cells_r;
-  const uint64_t taken_words = (N + 31) / 32;
-  M->seg = seg;
-  HIP_TRY(S.alloc(&choice, N));
-  HIP_TRY(S.alloc(&peel, N));
-  HIP_TRY(S.alloc(&taken, taken_words));
-  HIP_TRY(S.alloc(&stack, N));
-  HIP_TRY(S.alloc(&cw, cells));
-  HIP_TRY(S.alloc(&frontier, cells));
-  HIP_TRY(S.alloc(&round_off, kMaxPeelRounds + 1));
-  HIP_TRY(S.alloc(&pk, kPkWords));
-  HIP_TRY(S.alloc(&z, cells));
-  static_assert(4 + kPkWords <= kPinnedWords, "pinned words");
-  pk_host = S.pinned + 4;
   if (L)
     hipLaunchKernelGGL(choice_kernel, dim3(grid_for(L, 4)), dim3(256), 0, stream, (const uint64_t *)leaf_off,
                        (const uint8_t *)M->leaf_sizes, (const uint64_t *)orient, L, choice);
   HIP_TRY(hipGetLastError());
-  // Round passes run a fixed grid over device-held ranges; the host checks
-  // for the end of the peeling after each chunk of rounds.
-  const int round_grid = grid_for((cells + 3) / 4, 256 * kDetectPer) < 1024 ? grid_for((cells + 3) / 4, 256 * kDetectPer) : 1024;
-  constexpr uint32_t kChunk = 16;
+  if (big) HIP_TRY(hipEventRecord(S.arena->ev_choice, stream));
   bool solved = false;
   uint32_t rounds = 0;
   for (uint32_t t = 0; t < P.max_rho_tries && !solved; ++t) {
     const uint64_t rho = t;
     M->rho_tries = t + 1;
-    const uint64_t rmix = shockhash::fmix64((rho + 1) * kRetrievalMul);
-    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, cw, cells);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(taken_words, 256)), dim3(256), 0, stream, taken, taken_words,
-                       0u);
-    hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, stream, pk, (uint64_t)kPkWords);
-    if (N) hipLaunchKernelGGL(xor_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg, cw);
-    if (N <= kSmallRetrievalKeys) {
+    const uint64_t rmix = rmix_of(rho);
+    if (!big) {
       // one workgroup peels and assigns the whole system
+      hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, cw, cells);
+      hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(taken_words, 256)), dim3(256), 0, stream, taken, taken_words,
+                         0u);
+      hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, stream, pk, (uint64_t)kPkWords);
+      if (N)
+        hipLaunchKernelGGL(xor_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, leaf_keys, N, rmix, seg, cw);
       hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, z, cells);
       hipLaunchKernelGGL(xor_solve_small_kernel, dim3(1), dim3(kSmallThreads), 0, stream, leaf_keys, (uint32_t)N, rmix,
                          seg, cw, (uint32_t)cells, frontier, taken, stack, round_off, (const uint8_t *)choice, z, pk);
@@ -1182,42 +1239,42 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
       solved = true;
       continue;
     }
-    hipLaunchKernelGGL(xor_frontier_kernel, dim3(grid_for(cells, 256 * kFrontierPer)), dim3(kAppendThreads), 0, stream,
-                       (const unsigned long long *)cw, cells, frontier, pk);
+    if (t > 0) {  // the first seed's peeling was started before the leaf search
+      start_peel(rmix);
+      peel_chunk(rmix);
+    }
     HIP_TRY(hipGetLastError());
     for (;;) {
-      for (uint32_t c = 0; c < kChunk; ++c) {
-        hipLaunchKernelGGL(xor_advance_kernel, dim3(1), dim3(64), 0, stream, pk, round_off);
-        hipLaunchKernelGGL(xor_detect_kernel, dim3(round_grid), dim3(256), 0, stream, leaf_keys, N, rmix, seg,
-                           (const unsigned long long *)cw, (const uint64_t *)frontier, cells, taken, peel, stack,
-                           pk);
-        hipLaunchKernelGGL(xor_remove_kernel, dim3(round_grid), dim3(256), 0, stream, leaf_keys, N, rmix, seg, cw,
-                           (const uint32_t *)stack, frontier, cells, pk);
-      }
-      HIP_TRY(hipGetLastError());
-      HIP_TRY(hipMemcpyAsync(pk_host, pk, kPkWords * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
-      HIP_TRY(hipStreamSynchronize(stream));
+      HIP_TRY(hipMemcpyAsync(pk_host, pk, kPkWords * sizeof(uint64_t), hipMemcpyDeviceToHost, ps));
+      HIP_TRY(hipStreamSynchronize(ps));
       // done when the last round appended no frontier cells
       if (pk_host[kPkFrTail] == pk_host[kPkFrEnd] || pk_host[kPkRound] >= kMaxPeelRounds) break;
+      peel_chunk(rmix);
+      HIP_TRY(hipGetLastError());
     }
     if (pk_host[kPkStTail] != N || pk_host[kPkFrTail] > cells) continue;  // a 2-core is left: next retrieval seed
     const uint32_t R = (uint32_t)pk_host[kPkRound];
     std::vector<uint64_t> off(R + 1);
-    HIP_TRY(hipMemcpyAsync(off.data(), round_off, R * sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipMemcpyAsync(off.data(), round_off, R * sizeof(uint64_t), hipMemcpyDeviceToHost, ps));
+    HIP_TRY(hipStreamSynchronize(ps));
     off[R] = N;
-    hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, stream, z, cells);
+    HIP_TRY(hipStreamWaitEvent(ps, S.arena->ev_choice, 0));  // the choices come from the leaf search
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(cells, 256)), dim3(256), 0, ps, z, cells);
     rounds = 0;
     for (uint32_t rr = R; rr >= 1; --rr) {
       const uint64_t b = off[rr - 1], e = off[rr];
       if (e <= b) continue;
       ++rounds;
-      hipLaunchKernelGGL(xor_assign_kernel, dim3(grid_for(e - b, 256)), dim3(256), 0, stream, leaf_keys, rmix, seg,
+      hipLaunchKernelGGL(xor_assign_kernel, dim3(grid_for(e - b, 256)), dim3(256), 0, ps, leaf_keys, rmix, seg,
                          (const uint32_t *)stack, b, e, (const uint8_t *)peel, (const uint8_t *)choice, z);
     }
     HIP_TRY(hipGetLastError());
     M->rho = rho;
     solved = true;
+  }
+  if (big) {
+    HIP_TRY(hipEventRecord(S.arena->ev_done, ps));
+    HIP_TRY(hipStreamWaitEvent(stream, S.arena->ev_done, 0));
   }
   if (!solved) return SHOCK_ENOTFOUND;
   M->peel_rounds = rounds;
@@ -1253,6 +1310,18 @@ hipError_t shock_internal_release_mphf_scratch(int dev) {
     if (e == hipSuccess) e = f;
   }
   A.pinned = nullptr;
+  if (A.aux) {
+    const hipError_t f = hipStreamDestroy(A.aux);
+    if (e == hipSuccess) e = f;
+  }
+  A.aux = nullptr;
+  for (hipEvent_t *ev : {&A.ev_choice, &A.ev_done}) {
+    if (*ev) {
+      const hipError_t f = hipEventDestroy(*ev);
+      if (e == hipSuccess) e = f;
+    }
+    *ev = nullptr;
+  }
   return e;
 }
 
