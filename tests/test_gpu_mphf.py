@@ -115,6 +115,14 @@ def test_mphf_errors(shock):
         with pytest.raises(shock.ShockError) as e:
             _build(shock, splitmix64(2401, 100), **bad)
         assert e.value.status == shock.SHOCK_EINVAL
+    # bipartite leaves have no duplicate check: repeated keys leave the
+    # retrieval unsolvable for every seed, which is reported as not found
+    with pytest.raises(shock.ShockError) as e:
+        _build(shock, keys, bipartite=True, **SMALL)
+    assert e.value.status == shock.SHOCK_ENOTFOUND
+    with pytest.raises(shock.ShockError) as e:
+        _build(shock, splitmix64(2401, 100), bipartite=True, rotation_fitting=True)
+    assert e.value.status == shock.SHOCK_EINVAL
     m, _ = _build(shock, np.zeros(0, np.uint64), **SMALL)
     try:
         assert m.info()["n_keys"] == 0
