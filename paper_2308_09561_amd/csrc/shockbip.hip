@@ -31,6 +31,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <vector>
+
 #include "shockleaf.h"
 #include "shock_hash.h"
 #include "shock_internal.h"
@@ -278,7 +280,48 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
   }
 }
 
+// Per host thread and device: the device counters, two timing events and the
+// CU count, kept between calls (a hipFree per call would wait for the whole
+// device, including other streams' work).
+struct BipCache {
+  unsigned long long *ctr = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int cus = 0;
+};
+thread_local std::vector<BipCache> t_bip;
+
+hipError_t bip_cache(int dev, BipCache *&c) {
+  if ((int)t_bip.size() <= dev) t_bip.resize(dev + 1);
+  c = &t_bip[dev];
+  hipError_t e = hipSuccess;
+  if (!c->ctr) e = hipMalloc((void **)&c->ctr, kBipCount * sizeof(unsigned long long));
+  if (e == hipSuccess && !c->e0) e = hipEventCreate(&c->e0);
+  if (e == hipSuccess && !c->e1) e = hipEventCreate(&c->e1);
+  if (e == hipSuccess && !c->cus) {
+    hipDeviceProp_t prop;
+    c->cus = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 256;
+  }
+  return e;
+}
+
 }  // namespace
+
+hipError_t shock_internal_release_bip_scratch(int dev) {
+  if ((int)t_bip.size() <= dev) return hipSuccess;
+  BipCache &c = t_bip[dev];
+  hipError_t e = hipSuccess;
+  if (c.ctr) e = hipFree(c.ctr);
+  for (hipEvent_t *ev : {&c.e0, &c.e1}) {
+    if (*ev) {
+      const hipError_t f = hipEventDestroy(*ev);
+      if (e == hipSuccess) e = f;
+    }
+    *ev = nullptr;
+  }
+  c.ctr = nullptr;
+  c.cus = 0;
+  return e;
+}
 
 extern "C" {
 
@@ -293,17 +336,17 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   if (!keys || !offsets || !out_a || !out_b || !out_orient || n_leaves > (1ull << 31)) return SHOCK_EINVAL;
   if (opts.max_seed > (1ull << 32) || opts.workers < 0 || opts.workers > (1 << 20)) return SHOCK_EINVAL;
   hipStream_t stream = (hipStream_t)hip_stream;
-  unsigned long long *ctr = nullptr;
-  hipError_t e = hipMalloc((void **)&ctr, kBipCount * sizeof(unsigned long long));
-  if (e != hipSuccess) {
-    shock_internal_set_error("hipMalloc(bipartite counters)", e);
-    return SHOCK_ENOMEM;
-  }
-  unsigned long long host[kBipCount] = {0, 0, 0, 0, 0, 0};
-  int dev = 0, cus = 256;
+  int dev = 0;
   (void)hipGetDevice(&dev);
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  BipCache *cache = nullptr;
+  hipError_t e = bip_cache(dev, cache);
+  if (e != hipSuccess) {
+    shock_internal_set_error("bipartite counters and events", e);
+    return e == hipErrorOutOfMemory ? SHOCK_ENOMEM : SHOCK_EHIP;
+  }
+  unsigned long long *ctr = cache->ctr;
+  unsigned long long host[kBipCount] = {0, 0, 0, 0, 0, 0};
+  const int cus = cache->cus;
   // four waves per SIMD: more (six fit the LDS) contend for the VALU and LDS
   // and slow the longest leaves, which end the launch
   uint64_t workers = opts.workers ? (uint64_t)opts.workers : (uint64_t)cus * 16;
@@ -318,10 +361,8 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   P.out_b = out_b;
   P.out_orient = out_orient;
   P.ctr = ctr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEvent_t e0 = cache->e0, e1 = cache->e1;
   e = hipMemcpyAsync(ctr, host, sizeof(host), hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipEventCreate(&e0);
-  if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e == hipSuccess) e = hipEventRecord(e0, stream);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(bip_kernel, dim3(groups), dim3(64 * kWpw), 0, stream, P);
@@ -332,9 +373,6 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   float ms = 0;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  (void)hipFree(ctr);
   if (e != hipSuccess) {
     shock_internal_set_error("bipartite search", e);
     return SHOCK_EHIP;

@@ -1320,6 +1320,7 @@ int shock_release_scratch(void) {
     t_scratch[dev].bytes = 0;
   }
   HIP_TRY(shock_internal_release_code_scratch(dev));
+  HIP_TRY(shock_internal_release_bip_scratch(dev));
   HIP_TRY(shock_internal_release_mphf_scratch(dev));
   return SHOCK_OK;
 }
