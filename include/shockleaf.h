@@ -176,9 +176,11 @@ const char *shock_last_error(void);
 const char *shock_strerror(int status);
 
 /* Free the calling thread's cached scratch memory of the current device: the
- * search scratch, the Rice encoder's words and the MPHF build arena (sized by
- * the largest build the thread has run: about 43 bytes per key).  Waits for
- * the device first.  SHOCK_EHIP if a HIP call fails. */
+ * search scratch, the Rice encoder's words, the bipartite search's counters
+ * and events, and the MPHF build arena with its second stream and events
+ * (the arena is sized by the largest build the thread has run: about 43
+ * bytes per key).  Waits for the device first.  SHOCK_EHIP if a HIP call
+ * fails. */
 int shock_release_scratch(void);
 
 /* Library version of the frozen hash/orientation definition (3: h0 and r come
