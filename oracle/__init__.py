@@ -41,12 +41,24 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def build_sanitized(path: str) -> str:
+    """The same sources built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code only; any report aborts the process).  Loading it needs the
+    ASan runtime preloaded; tests/test_oracle_sanitized.py does that in a
+    child process and points SHOCK_ORACLE_LIB at this file."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+                           "-o", path, *_SRCS, "-lm"])
+    return path
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = os.environ.get("SHOCK_ORACLE_LIB") or _LIB
+        if path == _LIB and not os.path.exists(_LIB):
             build(force=True)
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         L.shock_oracle_fmix64.restype = ctypes.c_uint64
         L.shock_oracle_fmix64.argtypes = [ctypes.c_uint64]
         L.shock_oracle_slots.restype = None

@@ -9,10 +9,11 @@
 //   of its keys in registers  ->  the persistent leaf search of
 //   shock_leaf_search_ex  ->  Golomb-Rice codes of the seeds  ->  the
 //   retrieval of each key's choice: a 3-hypergraph XOR system peeled in
-//   synchronous rounds (per round one detect pass and one removal pass over
-//   the keys; the host reads one counter per round), then solved rounds in
-//   reverse (keys of one round write distinct cells and read none written in
-//   that round), packed to bits.
+//   synchronous rounds over frontiers of cells (per round one detect pass and
+//   one removal pass over the cells whose count just fell to one; the host
+//   checks for the end every 16 rounds), then solved rounds in reverse (keys
+//   of one round write distinct cells and read none written in that round),
+//   packed to bits.
 // Query: a thread per key: bucket, splitting seed, leaf, the leaf's key offset
 // from the byte sizes, its seed decoded from the Rice streams (the block
 // index, the widths of the leaves before it in its block of 64, and a select

@@ -17,6 +17,8 @@ All arrays are numpy uint64 (torch carries the same bits as int64).
 """
 from __future__ import annotations
 
+import hashlib
+
 import numpy as np
 
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
@@ -86,7 +88,17 @@ WORKLOADS = {
     "hard60": dict(kind="fixed", n_leaves=2048, n=60, seed=4),
     # 16384 leaves x 48 keys: the leaf size of the serving stream.
     "fixed48": dict(kind="fixed", n_leaves=16384, n=48, seed=48),
+    # 32 leaves x 64 keys: the full 64-bit coverage register.
+    "full64": dict(kind="fixed", n_leaves=32, n=64, seed=64),
 }
+
+
+def inputs_digest(keys: np.ndarray, offsets: np.ndarray) -> str:
+    """SHA-256 of a CSR batch, naming the inputs that stored results belong to."""
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(keys, dtype=np.uint64).tobytes())
+    h.update(np.ascontiguousarray(offsets, dtype=np.uint64).tobytes())
+    return h.hexdigest()
 
 
 def make_workload(name: str, n_leaves: int | None = None):
