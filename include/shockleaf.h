@@ -85,7 +85,9 @@ typedef struct shock_opts {
                              workgroup share each fresh leaf (a shorter tail: each leaf finishes sooner);
                              0 = default (2) */
   int32_t reserved1;
-  uint64_t reserved2;
+  uint64_t n_keys;        /* keys in the keys buffer, or 0 = unchecked (the caller guarantees offsets[n_leaves]
+                             is within it); a leaf reaching past n_keys makes the batch SHOCK_EINVAL before any
+                             of its keys is read */
 } shock_opts;
 
 /* Defaults for every field. */

@@ -34,6 +34,7 @@ EXPORTED = [
 ]
 
 
+
 class ShockOpts(ctypes.Structure):
     _fields_ = [
         ("max_seed", ctypes.c_uint64),
@@ -50,7 +51,7 @@ class ShockOpts(ctypes.Structure):
         ("block_iters_by_n", ctypes.c_void_p),
         ("team", ctypes.c_int32),
         ("reserved1", ctypes.c_int32),
-        ("reserved2", ctypes.c_uint64),
+        ("n_keys", ctypes.c_uint64),
     ]
 
 
@@ -240,7 +241,7 @@ def _as_ptr(x):
 
 def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_iters=0, waves_per_wg=0,
               workers=0, check_dups=False, cancel_ptr=None, leaf_size_hint=0, block_iters_by_n=None,
-              partial_k=0, team=0) -> ShockOpts:
+              partial_k=0, team=0, n_keys=0) -> ShockOpts:
     """shock_opts with defaults; block_iters_by_n is a sequence of 65 ints or None."""
     o = ShockOpts()
     lib().shock_opts_init(ctypes.byref(o))
@@ -257,6 +258,7 @@ def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_it
     o.leaf_size_hint = leaf_size_hint
     o.partial_k = partial_k
     o.team = team
+    o.n_keys = n_keys
     if block_iters_by_n is not None:
         if len(block_iters_by_n) != 65:
             raise ValueError("block_iters_by_n needs 65 entries (leaf sizes 0..64)")
@@ -289,12 +291,7 @@ def rf_leaf_search(keys, offsets, out_seeds=None, out_rot=None, out_orient=None,
     """
     import torch
 
-    _check_tensors(keys, offsets)
-    keys = keys.contiguous()
-    offsets = offsets.contiguous()
-    L = offsets.numel() - 1
-    if L < 0:
-        raise ValueError("offsets needs n_leaves + 1 entries")
+    keys, offsets, L = _batch(keys, offsets)
     dev = keys.device
     if out_seeds is None:
         out_seeds = torch.empty(max(L, 1), dtype=torch.int64, device=dev)
@@ -302,9 +299,12 @@ def rf_leaf_search(keys, offsets, out_seeds=None, out_rot=None, out_orient=None,
         out_rot = torch.empty(max(L, 1), dtype=torch.int32, device=dev)
     if out_orient is None:
         out_orient = torch.empty(max(L, 1), dtype=torch.int64, device=dev)
+    _check_out(out_seeds, L, torch.int64, dev, "out_seeds")
+    _check_out(out_rot, L, torch.int32, dev, "out_rot")
+    _check_out(out_orient, L, torch.int64, dev, "out_orient")
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
-    o = make_opts(**opts)
+    o = make_opts(n_keys=keys.numel(), **opts)
     rc = shock_rf_leaf_search_ex(keys if keys.numel() else offsets, offsets, L, out_seeds, out_rot, out_orient, o,
                                  stream)
     if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
@@ -320,22 +320,16 @@ def leaf_search(keys, offsets, out_seeds=None, out_orient=None, stream=None, **o
     """
     import torch
 
-    if keys.device.type != "cuda" or offsets.device.type != "cuda":
-        raise ValueError("keys and offsets must be device (cuda) tensors")
-    if keys.dtype != torch.int64 or offsets.dtype != torch.int64:
-        raise ValueError("keys and offsets must be int64 tensors carrying uint64 bits")
-    keys = keys.contiguous()
-    offsets = offsets.contiguous()
-    L = offsets.numel() - 1
-    if L < 0:
-        raise ValueError("offsets needs n_leaves + 1 entries")
+    keys, offsets, L = _batch(keys, offsets)
     if out_seeds is None:
         out_seeds = torch.empty(max(L, 1), dtype=torch.int64, device=keys.device)
     if out_orient is None:
         out_orient = torch.empty(max(L, 1), dtype=torch.int64, device=keys.device)
+    _check_out(out_seeds, L, torch.int64, keys.device, "out_seeds")
+    _check_out(out_orient, L, torch.int64, keys.device, "out_orient")
     if stream is None:
         stream = torch.cuda.current_stream(keys.device).cuda_stream
-    o = make_opts(**opts)
+    o = make_opts(n_keys=keys.numel(), **opts)
     rc = shock_leaf_search_ex(keys if keys.numel() else offsets, offsets, L, out_seeds, out_orient, o, stream)
     if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
         raise ShockError(rc, lib().shock_last_error().decode())
@@ -347,8 +341,39 @@ def _check_tensors(keys, offsets):
 
     if keys.device.type != "cuda" or offsets.device.type != "cuda":
         raise ValueError("keys and offsets must be device (cuda) tensors")
+    if keys.device != offsets.device:
+        raise ValueError("keys and offsets must be on the same device")
     if keys.dtype != torch.int64 or offsets.dtype != torch.int64:
         raise ValueError("keys and offsets must be int64 tensors carrying uint64 bits")
+
+
+def _batch(keys, offsets):
+    """Checked, contiguous (keys, offsets, n_leaves) of a CSR batch.  The
+    library itself rejects leaves reaching past the keys (n_keys option)."""
+    _check_tensors(keys, offsets)
+    if keys.dim() != 1 or offsets.dim() != 1:
+        raise ValueError("keys and offsets must be one-dimensional")
+    keys = keys.contiguous()
+    offsets = offsets.contiguous()
+    L = offsets.numel() - 1
+    if L < 0:
+        raise ValueError("offsets needs n_leaves + 1 entries")
+    if keys.numel() == 0 and L > 0 and bool(offsets.ne(0).any()):
+        # n_keys = 0 would mean "unchecked": a batch of empty leaves only
+        raise ValueError("the keys buffer is empty but the offsets give leaves keys")
+    return keys, offsets, L
+
+
+def _check_out(t, L, dtype, device, name):
+    """An output tensor the kernels may write L entries of."""
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be a {dtype} tensor")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < L:
+        raise ValueError(f"{name} holds {t.numel()} entries, the batch has {L} leaves")
 
 
 class SearchContext:
@@ -378,11 +403,12 @@ class SearchContext:
     def _args(self, keys, offsets, out_seeds, out_orient, stream, opts):
         import torch
 
-        _check_tensors(keys, offsets)
-        L = offsets.numel() - 1
+        keys, offsets, L = _batch(keys, offsets)
+        _check_out(out_seeds, L, torch.int64, keys.device, "out_seeds")
+        _check_out(out_orient, L, torch.int64, keys.device, "out_orient")
         if stream is None:
             stream = torch.cuda.current_stream(keys.device).cuda_stream
-        o = make_opts(**opts)
+        o = make_opts(n_keys=keys.numel(), **opts)
         self._keep = (keys, offsets, out_seeds, out_orient, o)
         return (self._h, _as_ptr(keys), _as_ptr(offsets), L, _as_ptr(out_seeds), _as_ptr(out_orient),
                 ctypes.byref(o), ctypes.c_void_p(stream))
@@ -402,7 +428,10 @@ class SearchContext:
 
     def rf_search_async(self, keys, offsets, out_seeds, out_rot, out_orient, stream=None, **opts) -> int:
         """Rotation-fitting search; out_rot an int32 device tensor."""
+        import torch
+
         a = self._args(keys, offsets, out_seeds, out_orient, stream, opts)
+        _check_out(out_rot, a[3], torch.int32, keys.device, "out_rot")
         self._keep = self._keep + (out_rot,)
         return lib().shock_ctx_rf_search_async(*a[:5], _as_ptr(out_rot), *a[5:])
 
@@ -587,15 +616,14 @@ def bip_leaf_search(keys, offsets, out_a=None, out_b=None, out_orient=None, stre
     (status, a, b, orient, stats): seed pairs and orientations as int64
     tensors (uint64 bit patterns) and a dict of device counters."""
     import torch
-    _check_tensors(keys, offsets)
-    keys = keys.contiguous()
-    offsets = offsets.contiguous()
-    L = offsets.numel() - 1
+    keys, offsets, L = _batch(keys, offsets)
     dev = keys.device
     out_a = torch.empty(max(L, 1), dtype=torch.int64, device=dev) if out_a is None else out_a
     out_b = torch.empty(max(L, 1), dtype=torch.int64, device=dev) if out_b is None else out_b
     out_orient = torch.empty(max(L, 1), dtype=torch.int64, device=dev) if out_orient is None else out_orient
-    o = make_opts(**opts)
+    for t, name in ((out_a, "out_a"), (out_b, "out_b"), (out_orient, "out_orient")):
+        _check_out(t, L, torch.int64, dev, name)
+    o = make_opts(n_keys=keys.numel(), **opts)
     st = BipStats()
     rc = lib().shock_bip_leaf_search_ex(_as_ptr(keys if keys.numel() else offsets), _as_ptr(offsets), max(L, 0),
                                         _as_ptr(out_a), _as_ptr(out_b), _as_ptr(out_orient), ctypes.byref(o),

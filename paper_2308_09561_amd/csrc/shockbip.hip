@@ -68,6 +68,7 @@ struct BipLds {
 struct BipParams {
   const uint64_t *keys, *offsets;
   uint64_t n_leaves, max_seed;
+  uint64_t n_keys;  // keys in the keys buffer, 0 = unchecked
   uint64_t *out_a, *out_b, *out_orient;
   unsigned long long *ctr;
 };
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
     const uint64_t j = bcast64(jj);
     if (j >= P.n_leaves) break;
     const uint64_t o0 = P.offsets[j], o1 = P.offsets[j + 1];
-    if (o1 < o0 || o1 - o0 > 64) {
+    if (o1 < o0 || o1 - o0 > 64 || (P.n_keys != 0 && o1 > P.n_keys)) {
       if (lane == 0) {
         atomicOr(&P.ctr[kBipErr], kErrInvalidLeaf);
         P.out_a[j] = kNone;
@@ -357,6 +358,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   P.offsets = offsets;
   P.n_leaves = n_leaves;
   P.max_seed = opts.max_seed;
+  P.n_keys = opts.n_keys;
   P.out_a = out_a;
   P.out_b = out_b;
   P.out_orient = out_orient;

@@ -866,16 +866,19 @@ void search_kernel(Params P) {
 
 // Validate the batch, initialise per-leaf state and premix the keys.  One
 // wave per leaf; lane i premixes key i.  Also checks repeated keys on request.
+// A nonzero n_keys bounds the keys buffer: a leaf reaching past it is invalid
+// and none of its keys is read.
 __global__ __launch_bounds__(256) void prepare_kernel(const uint64_t *__restrict__ keys,
                                                       const uint64_t *__restrict__ offsets, uint64_t n_leaves,
-                                                      uint64_t *__restrict__ premix, unsigned long long *state,
-                                                      unsigned long long *best, unsigned long long *gctr,
-                                                      unsigned long long *sides, int check_dups) {
+                                                      uint64_t n_keys, uint64_t *__restrict__ premix,
+                                                      unsigned long long *state, unsigned long long *best,
+                                                      unsigned long long *gctr, unsigned long long *sides,
+                                                      int check_dups) {
   const uint64_t j = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint32_t lane = threadIdx.x & 63;
   if (j >= n_leaves) return;
   const uint64_t o0 = offsets[j], o1 = offsets[j + 1];
-  if (o1 < o0 || o1 - o0 > 64) {
+  if (o1 < o0 || o1 - o0 > 64 || (n_keys != 0 && o1 > n_keys)) {
     if (lane == 0) atomicOr(&gctr[kCtrErr], kErrInvalid);
     return;
   }
@@ -948,9 +951,11 @@ struct Layout {
   size_t premix, state, best, sides, wleaf, gctr, lctr, total;
 };
 
-Layout layout(uint64_t n_leaves, uint32_t workers, uint64_t n_launches) {
-  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  Layout l;
+constexpr size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr Layout layout(uint64_t n_leaves, uint32_t workers, uint64_t n_launches) {
+  auto up = up256;
+  Layout l{};
   size_t o = 0;
   l.premix = o; o = up(o + n_leaves * 64 * 8);
   l.state = o; o = up(o + n_leaves * 8);
@@ -1130,7 +1135,7 @@ CallBufs carve(void *buf, const Layout &lay) {
 }
 
 hipError_t enqueue_prologue(const CallBufs &cb, const Plan &pl, const uint64_t *keys, const uint64_t *offsets,
-                            uint64_t n_leaves, int check_dups, uint32_t workers_cap, hipStream_t stream) {
+                            uint64_t n_leaves, const shock_opts &opts, uint32_t workers_cap, hipStream_t stream) {
   const uint64_t n_l = pl.n_launches * kLcCount;
   uint64_t m = n_l > (uint64_t)workers_cap ? n_l : (uint64_t)workers_cap;
   if (m < (uint64_t)kCtrGlobalCount) m = kCtrGlobalCount;
@@ -1139,7 +1144,7 @@ hipError_t enqueue_prologue(const CallBufs &cb, const Plan &pl, const uint64_t *
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)((n_leaves + 3) / 4)), dim3(256), 0, stream, keys, offsets,
-                     n_leaves, cb.premix, cb.state, cb.best, cb.gctr, cb.sides, check_dups);
+                     n_leaves, opts.n_keys, cb.premix, cb.state, cb.best, cb.gctr, cb.sides, opts.check_dups);
   return hipGetLastError();
 }
 
@@ -1356,7 +1361,7 @@ static int search_sync(const uint64_t *keys, const uint64_t *offsets, uint64_t n
   Plan pl;
   rc = make_plan(opts, n_leaves, 48, rf, pl);
   if (rc != SHOCK_OK) return rc;
-  HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts.check_dups, (uint32_t)workers_cap, stream));
+  HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts, (uint32_t)workers_cap, stream));
   // Validation result and leaf sizes for launch sizing: all offsets for
   // per-leaf launches, the first and last otherwise (mean leaf size).
   std::vector<uint64_t> h_off(mode == SHOCK_MODE_PLAIN_PER_LEAF ? n_leaves + 1 : 2);
@@ -1476,7 +1481,7 @@ static int ctx_enqueue(shock_ctx *c, const uint64_t *keys, const uint64_t *offse
   int rc = make_plan(opts, n_leaves, hint, out_rot != nullptr, pl);
   if (rc != SHOCK_OK) return rc;
   if (pl.workers > (int)c->workers_cap) return SHOCK_EINVAL;
-  HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts.check_dups, c->workers_cap, stream));
+  HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts, c->workers_cap, stream));
   Params P = base_params(cb, pl, opts, offsets, out_seeds, out_orient, out_rot);
   if (with_events) HIP_TRY(hipEventRecord(c->ev_begin, stream));
   HIP_TRY(enqueue_search(P, cb, pl, n_leaves, nullptr, hint, opts.workers != 0, stream));

@@ -85,3 +85,18 @@ def test_ctypes_structs_match_the_headers(tmp_path):
     subprocess.run([gcc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert got == want
+
+
+def test_binding_rejects_short_outputs_and_empty_keys_with_leaves():
+    torch = pytest.importorskip("torch")
+    from paper_2308_09561_amd import binding as b
+    k = torch.zeros(4, dtype=torch.int64)
+    o = torch.tensor([0, 2, 4], dtype=torch.int64)
+    with pytest.raises(ValueError):
+        b._check_out(torch.zeros(1, dtype=torch.int64), 2, torch.int64, k.device, "out_seeds")
+    with pytest.raises(ValueError):
+        b._check_out(torch.zeros(2, dtype=torch.int32), 2, torch.int64, k.device, "out_seeds")
+    with pytest.raises(ValueError):
+        b._check_out(torch.zeros(4, dtype=torch.int64)[::2], 2, torch.int64, k.device, "out_seeds")
+    b._check_out(torch.zeros(2, dtype=torch.int64), 2, torch.int64, k.device, "out_seeds")
+    assert o.numel() == 3

@@ -179,7 +179,8 @@ def test_duplicate_keys(shock, oracle_mod):
 
 def test_invalid_batches_leave_outputs_untouched(shock):
     keys = splitmix64(1, 200)
-    for offs in (np.array([0, 65], np.uint64), np.array([0, 10, 5], np.uint64)):
+    past_end = np.array([0, 60, 120, 180, 240], np.uint64)  # the last leaf reaches past the 200 keys
+    for offs in (np.array([0, 65], np.uint64), np.array([0, 10, 5], np.uint64), past_end):
         k, o = _dev(keys), _dev(offs)
         L = len(offs) - 1
         s = torch.full((L,), 12345, dtype=torch.int64, device="cuda")
@@ -188,6 +189,27 @@ def test_invalid_batches_leave_outputs_untouched(shock):
         torch.cuda.synchronize()
         assert rc == shock.SHOCK_EINVAL
         assert (s == 12345).all() and (f == 678).all()
+
+
+def test_leaves_past_the_keys_are_rejected_by_every_search(shock):
+    """A batch whose offsets reach past the keys tensor is SHOCK_EINVAL for the
+    plain, rotation-fitting and bipartite searches and for a context (the
+    binding passes the keys' length), and no key beyond the tensor is read."""
+    keys = _dev(splitmix64(2, 100))
+    offs = _dev(np.array([0, 50, 110], np.uint64))
+    print("[gpu] offsets past the keys", flush=True)
+    rc, _, _ = shock.leaf_search(keys, offs)
+    assert rc == shock.SHOCK_EINVAL
+    rc, _, _, _ = shock.rf_leaf_search(keys, offs)
+    assert rc == shock.SHOCK_EINVAL
+    rc, *_ = shock.bip_leaf_search(keys, offs)
+    assert rc == shock.SHOCK_EINVAL
+    ctx = shock.SearchContext(4)
+    s = torch.zeros(2, dtype=torch.int64, device="cuda")
+    f = torch.zeros(2, dtype=torch.int64, device="cuda")
+    assert ctx.search_async(keys, offs, s, f) == 0
+    assert ctx.wait()[0] == shock.SHOCK_EINVAL
+    torch.cuda.synchronize()
 
 
 def test_cancel_flag(shock):
