@@ -191,6 +191,29 @@ int shock_release_scratch(void);
  * multiplied lo32(a ^ t) by hi32(a ^ t)). */
 int shock_spec_version(void);
 
+/* ---- A search that allocates nothing -------------------------------------
+ *
+ * For callers that cannot allocate device memory: code running under HIP
+ * graph capture elsewhere in the process, tight serving loops, harnesses that
+ * forbid hipMalloc.  The same search and outputs as shock_leaf_search_ex in
+ * persistent mode (mode AUTO or PERSISTENT; PLAIN_PER_LEAF is SHOCK_EINVAL),
+ * synchronous on hip_stream.  Its scratch is one fixed array of
+ * SHOCK_NOALLOC_SCRATCH_BYTES per GPU, part of the library's device code and
+ * held by every GPU the library runs on until the process ends; the call
+ * makes no hipMalloc, hipFree, hipHostMalloc or event creation (its status
+ * comes back through a plain host copy, and kernel_ms in shock_last_stats
+ * stays 0).  Limits: n_leaves <= SHOCK_NOALLOC_MAX_LEAVES and opts->workers <=
+ * SHOCK_NOALLOC_MAX_WORKERS, else SHOCK_EINVAL before anything is launched.
+ * Every call on one GPU uses that GPU's array and leaves its contents behind;
+ * each call clears what it needs.  Calls on one GPU from several host threads
+ * are serialised by the library; calls from the same process must not
+ * otherwise overlap (the array holds one call's state). */
+#define SHOCK_NOALLOC_MAX_LEAVES 65536
+#define SHOCK_NOALLOC_MAX_WORKERS 32768
+#define SHOCK_NOALLOC_SCRATCH_BYTES (34u << 20)
+int shock_leaf_search_noalloc(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                              uint64_t *out_seeds, uint64_t *out_orient, const shock_opts *opts, void *hip_stream);
+
 /* ---- Contexts: asynchronous searches, several in flight, HIP graphs ------
  *
  * A context owns the scratch for batches of up to max_leaves leaves (about

@@ -30,9 +30,13 @@ EXPORTED = [
     "shock_ctx_graph_capture", "shock_ctx_graph_launch", "shock_rf_leaf_search_ex", "shock_ctx_rf_search_async",
     "shock_leaf_query", "shock_rf_leaf_query", "shock_rice_encode", "shock_rice_decode",
     "shock_mphf_params_init", "shock_mphf_build", "shock_mphf_query", "shock_mphf_info", "shock_mphf_export",
-    "shock_mphf_destroy", "shock_bip_leaf_search_ex",
+    "shock_mphf_destroy", "shock_bip_leaf_search_ex", "shock_leaf_search_noalloc",
 ]
 
+# Limits of shock_leaf_search_noalloc (include/shockleaf.h).
+SHOCK_NOALLOC_MAX_LEAVES = 65536
+SHOCK_NOALLOC_MAX_WORKERS = 32768
+SHOCK_NOALLOC_SCRATCH_BYTES = 34 << 20
 
 
 class ShockOpts(ctypes.Structure):
@@ -140,6 +144,8 @@ def lib():
         L.shock_leaf_search.argtypes = [vp, vp, ctypes.c_uint64, vp, vp]
         L.shock_leaf_search_ex.restype = ctypes.c_int
         L.shock_leaf_search_ex.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(ShockOpts), vp]
+        L.shock_leaf_search_noalloc.restype = ctypes.c_int
+        L.shock_leaf_search_noalloc.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(ShockOpts), vp]
         L.shock_last_stats.restype = ctypes.c_int
         L.shock_last_stats.argtypes = [ctypes.POINTER(ShockStats)]
         L.shock_last_error.restype = ctypes.c_char_p
@@ -334,6 +340,27 @@ def leaf_search(keys, offsets, out_seeds=None, out_orient=None, stream=None, **o
     if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
         raise ShockError(rc, lib().shock_last_error().decode())
     return rc, out_seeds[:L], out_orient[:L]
+
+
+def leaf_search_noalloc(keys, offsets, out_seeds, out_orient, stream=None, **opts):
+    """shock_leaf_search_noalloc: the persistent search with the library's
+    fixed per-GPU scratch array (no device allocation in the call).  The
+    caller passes the output tensors (int64, at least n_leaves entries).
+    Returns the status; raises ShockError on SHOCK_EHIP."""
+    import torch
+
+    keys, offsets, L = _batch(keys, offsets)
+    _check_out(out_seeds, L, torch.int64, keys.device, "out_seeds")
+    _check_out(out_orient, L, torch.int64, keys.device, "out_orient")
+    if stream is None:
+        stream = torch.cuda.current_stream(keys.device).cuda_stream
+    o = make_opts(n_keys=keys.numel(), **opts)
+    rc = lib().shock_leaf_search_noalloc(_as_ptr(keys if keys.numel() else offsets), _as_ptr(offsets), L,
+                                         _as_ptr(out_seeds), _as_ptr(out_orient), ctypes.byref(o),
+                                         ctypes.c_void_p(stream))
+    if rc == SHOCK_EHIP:
+        raise ShockError(rc, lib().shock_last_error().decode())
+    return rc
 
 
 def _check_tensors(keys, offsets):

@@ -1407,7 +1407,104 @@ static int search_sync(const uint64_t *keys, const uint64_t *offsets, uint64_t n
   return rc;
 }
 
+// ---- the search without allocations ---------------------------------------
+//
+// One fixed scratch array per GPU, part of the code object (so the runtime
+// places it when the library's device code is loaded).  In host code `scratch`
+// names only a host-side stand-in: its device address is looked up once per
+// device with hipGetSymbolAddress and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SHOCK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoAllocMaxDevices = 64;
+constexpr uint32_t kNoAllocWorkersCap = SHOCK_NOALLOC_MAX_WORKERS + kMaxWavesPerWg;
+static_assert(layout(SHOCK_NOALLOC_MAX_LEAVES, kNoAllocWorkersCap, 1).total <= SHOCK_NOALLOC_SCRATCH_BYTES,
+              "the no-allocation scratch array must hold the largest batch it accepts");
+
+std::mutex g_noalloc_init_mu;
+void *g_noalloc_ptr[kNoAllocMaxDevices];
+std::mutex g_noalloc_call_mu[kNoAllocMaxDevices];
+
+// Device address of this device's scratch array (looked up on first use).
+int noalloc_scratch(int dev, void **out) {
+  std::lock_guard<std::mutex> lk(g_noalloc_init_mu);
+  if (g_noalloc_ptr[dev] == nullptr) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      set_err("hipGetSymbolAddress(scratch)", e != hipSuccess ? e : hipErrorInvalidSymbol);
+      return SHOCK_EHIP;
+    }
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return SHOCK_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int shock_leaf_search_noalloc(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_seeds,
+                              uint64_t *out_orient, const shock_opts *opts_in, void *hip_stream) {
+  shock_opts opts;
+  shock_opts_init(&opts);
+  if (opts_in) opts = *opts_in;
+  if (opts.max_seed == 0) opts.max_seed = SHOCK_DEFAULT_MAX_SEED;
+  memset(&g_stats, 0, sizeof(g_stats));
+  if (n_leaves == 0) return SHOCK_OK;
+  int rc = check_opts(opts, n_leaves, offsets, out_seeds, out_orient);
+  if (rc != SHOCK_OK) return rc;
+  if (!keys) return SHOCK_EINVAL;
+  if (opts.mode != SHOCK_MODE_AUTO && opts.mode != SHOCK_MODE_PERSISTENT) return SHOCK_EINVAL;
+  if (n_leaves > SHOCK_NOALLOC_MAX_LEAVES || opts.workers > SHOCK_NOALLOC_MAX_WORKERS) {
+    snprintf(g_err, sizeof(g_err), "shock_leaf_search_noalloc: at most %d leaves and %d workers",
+             SHOCK_NOALLOC_MAX_LEAVES, SHOCK_NOALLOC_MAX_WORKERS);
+    return SHOCK_EINVAL;
+  }
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return SHOCK_EINVAL;
+  void *buf = nullptr;
+  rc = noalloc_scratch(dev, &buf);
+  if (rc != SHOCK_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_noalloc_call_mu[dev]);
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const Layout lay = layout(n_leaves, kNoAllocWorkersCap, 1);
+  const CallBufs cb = carve(buf, lay);
+
+  Plan pl;
+  rc = make_plan(opts, n_leaves, 48, 0, pl);
+  if (rc != SHOCK_OK) return rc;
+  HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts, kNoAllocWorkersCap, stream));
+  unsigned long long host_ctr[kCtrGlobalCount];
+  uint64_t h_off[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(host_ctr, cb.gctr, sizeof(host_ctr), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&h_off[0], offsets, 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&h_off[1], offsets + n_leaves, 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (host_ctr[kCtrErr] & kErrInvalid) return SHOCK_EINVAL;
+  if (host_ctr[kCtrErr] & kErrDup) return SHOCK_EDUPKEY;
+
+  const uint32_t n_mean = (uint32_t)((h_off[1] - h_off[0] + n_leaves / 2) / n_leaves);
+  rc = make_plan(opts, n_leaves, n_mean, 0, pl);
+  if (rc != SHOCK_OK) return rc;
+  if (pl.workers > (int)kNoAllocWorkersCap) return SHOCK_EINVAL;
+  Params P = base_params(cb, pl, opts, offsets, out_seeds, out_orient, nullptr);
+  HIP_TRY(enqueue_search(P, cb, pl, n_leaves, nullptr, n_mean, opts.workers != 0, stream));
+  hipLaunchKernelGGL(mark_unfinished_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, stream, cb.gctr,
+                     cb.state, n_leaves, out_seeds, out_orient, nullptr);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(host_ctr, cb.gctr, sizeof(host_ctr), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  rc = status_from(host_ctr, &g_stats);
+  g_stats.workers = (int32_t)P.workers;
+  g_stats.spl = pl.spl;
+  g_stats.block_iters = pl.units;
+  g_stats.waves_per_wg = pl.wpw;
+  return rc;
+}
 
 int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves, uint64_t *out_seeds,
                          uint64_t *out_orient, const shock_opts *opts, void *hip_stream) {

@@ -87,6 +87,18 @@ def test_ctypes_structs_match_the_headers(tmp_path):
     assert got == want
 
 
+def test_noalloc_limits_match_the_header():
+    """The binding's copies of the no-allocation limits are the header's."""
+    from paper_2308_09561_amd import binding as b
+    text = open(os.path.join(ROOT, "include", "shockleaf.h")).read()
+    want = {}
+    for name in ("SHOCK_NOALLOC_MAX_LEAVES", "SHOCK_NOALLOC_MAX_WORKERS", "SHOCK_NOALLOC_SCRATCH_BYTES"):
+        m = re.search(r"#define\s+" + name + r"\s+\(?(\d+)u?(?:\s*<<\s*(\d+))?\)?", text)
+        assert m, name
+        want[name] = int(m.group(1)) << int(m.group(2) or 0)
+        assert getattr(b, name) == want[name], name
+
+
 def test_binding_rejects_short_outputs_and_empty_keys_with_leaves():
     torch = pytest.importorskip("torch")
     from paper_2308_09561_amd import binding as b
