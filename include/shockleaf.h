@@ -57,7 +57,8 @@ extern "C" {
 #define SHOCK_EDUPKEY (-3)   /* check_dups was set and some leaf holds a repeated key; outputs untouched */
 #define SHOCK_ECANCELED (-4) /* the cancel flag was raised; unfinished leaves hold seed = UINT64_MAX */
 #define SHOCK_EHIP (-5)      /* a HIP runtime call failed; see shock_last_error() */
-#define SHOCK_ENOMEM (-6)    /* scratch allocation failed */
+#define SHOCK_ENOMEM (-6)    /* scratch allocation failed, or a request larger than a queue's budget */
+#define SHOCK_EPENDING (-7)  /* the asynchronous call or request has not completed yet */
 
 /* Launch strategies.  All produce bit-identical outputs. */
 #define SHOCK_MODE_AUTO 0
@@ -110,6 +111,29 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
                          uint64_t *out_seeds, uint64_t *out_orient,
                          const shock_opts *opts, void *hip_stream);
 
+/* As shock_leaf_search_ex, but asynchronous: the whole search is enqueued on
+ * hip_stream and the call returns without waiting for the device.  The
+ * return value covers only what is checked before enqueueing (arguments and
+ * options: SHOCK_EINVAL, nothing enqueued) and failures to enqueue or to
+ * allocate (SHOCK_EHIP, SHOCK_ENOMEM).  The batch's own status (SHOCK_OK,
+ * SHOCK_EINVAL for a malformed batch found on the device, whose outputs stay
+ * untouched, SHOCK_ENOTFOUND, SHOCK_EDUPKEY, SHOCK_ECANCELED) is read with
+ * shock_stream_status once the stream has reached the end of the call.
+ * Launch sizes come from opts->leaf_size_hint (offsets are never read back).
+ * The library keeps one scratch area and one status word per (device,
+ * stream); a later call on the same stream reuses them in stream order and
+ * replaces the status.  Calls on one stream must not be made from several
+ * host threads at once.  Keys, offsets and outputs must stay valid until the
+ * stream has passed the call. */
+int shock_leaf_search_async(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                            uint64_t *out_seeds, uint64_t *out_orient, const shock_opts *opts, void *hip_stream);
+
+/* Status of the last shock_leaf_search_async / shock_rf_leaf_search_async
+ * on hip_stream of the current device: SHOCK_EPENDING while the stream has
+ * not yet reached its end (never blocks), then the batch's status as above.
+ * SHOCK_EINVAL if no asynchronous call was made on that stream. */
+int shock_stream_status(void *hip_stream);
+
 /* ShockHash with rotation fitting (Section 4, "Rotation Fitting"; partial
  * hash calculation, Appendix A.2).  Keys are split into two fixed sets by
  * the top bit of fmix64(key ^ 0xD1B54A32D192ED03) (1 = second set).  A
@@ -127,6 +151,12 @@ int shock_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t
 int shock_rf_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
                             uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient,
                             const shock_opts *opts, void *hip_stream);
+
+/* As shock_rf_leaf_search_ex, asynchronous in the manner of
+ * shock_leaf_search_async (status from shock_stream_status). */
+int shock_rf_leaf_search_async(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                               uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient,
+                               const shock_opts *opts, void *hip_stream);
 
 /* Bipartite ShockHash (the outlook of Section 9: two hash functions of range
  * [n/2], one shifted by n/2; candidates are filtered before they are paired).
@@ -265,6 +295,90 @@ int shock_ctx_graph_capture(shock_ctx *ctx, const uint64_t *keys, const uint64_t
 
 /* Replay the captured graph on hip_stream; complete it with shock_ctx_wait. */
 int shock_ctx_graph_launch(shock_ctx *ctx, void *hip_stream);
+
+/* ---- A request queue bound to one device and an HBM budget --------------
+ *
+ * Build requests (CSR batches of leaves in HOST memory) are submitted with
+ * shock_submit and complete asynchronously; shock_poll reports completion.
+ * The queue owns one device arena of hbm_budget_bytes, `slots` HIP streams
+ * (default priority) with pinned staging buffers, and a dispatcher thread.
+ * The dispatcher admits queued requests in submission order: a free slot
+ * takes as many requests from the head of the queue as its staging buffers
+ * and the arena's free memory allow, uploads their keys and offsets, enqueues
+ * one search over all of them (the persistent kernel of shock_leaf_search_ex)
+ * and moves on, so batches on different slots overlap on the device.  When a
+ * slot's batch completes, each request's seeds and orientations are copied
+ * into its host output buffers, its arena block is freed and the next
+ * requests are admitted.  The device memory a batch holds (its keys,
+ * offsets, outputs and search scratch) counts against the budget.  Results
+ * equal those of shock_leaf_search_ex on each request alone: leaves are
+ * searched independently. */
+typedef struct shock_queue shock_queue;
+
+typedef struct shock_queue_params {
+  int32_t device;            /* HIP device ordinal */
+  int32_t slots;             /* batches in flight at once (1..16); 0 = 4 */
+  uint64_t hbm_budget_bytes; /* device arena size; 0 = 256 MiB */
+  uint64_t max_batch_leaves; /* leaves one batch may hold; 0 = 65536 */
+  uint64_t max_batch_keys;   /* keys one batch may hold (pinned staging per slot: 8 bytes each); 0 = 2^22 */
+  shock_opts search;         /* search options of every request: mode AUTO or PERSISTENT, no cancel flag, no
+                                claim table, no check_dups (a batch shares one validation); leaf_size_hint is
+                                ignored: launches are sized by each batch's mean leaf size */
+} shock_queue_params;
+
+void shock_queue_params_init(shock_queue_params *p);
+
+/* Device bytes a batch of n_leaves leaves and n_keys keys holds in a queue's
+ * arena (keys, offsets, outputs and search scratch; about 560 bytes per leaf,
+ * 8 per key and 135 KB per batch).  A request alone above the budget is
+ * rejected by shock_submit. */
+uint64_t shock_queue_batch_bytes(uint64_t n_leaves, uint64_t n_keys);
+
+/* Create a queue.  SHOCK_EINVAL for bad parameters, SHOCK_ENOMEM if the
+ * arena or the staging buffers cannot be allocated, SHOCK_EHIP otherwise. */
+int shock_queue_create(const shock_queue_params *params, shock_queue **out);
+
+/* Submit a request: n_leaves leaves in HOST memory, leaf j =
+ * keys[offsets[j] .. offsets[j+1]) (offsets nondecreasing, each leaf <= 64
+ * keys); results go to the HOST buffers out_seeds[n_leaves] and
+ * out_orient[n_leaves].  All four buffers must stay valid until shock_poll
+ * reports the request done.  Returns SHOCK_OK with *ticket set, SHOCK_EINVAL
+ * for a malformed request (checked here on the host), or SHOCK_ENOMEM for a
+ * request that alone exceeds the budget or one batch's limits (not queued). */
+int shock_submit(shock_queue *q, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
+                 uint64_t *out_seeds, uint64_t *out_orient, uint64_t *ticket);
+
+/* Times of one request on the steady clock (ns) and the batch it ran in. */
+typedef struct shock_ticket_info {
+  int64_t submit_ns, admit_ns, done_ns;
+  uint64_t batch;
+  uint64_t n_leaves;
+} shock_ticket_info;
+
+/* Never blocks.  While the request is queued or running: *done = 0 and
+ * SHOCK_OK.  Once it is complete: *done = 1, *info filled (may be NULL), and
+ * the request's status is returned (as shock_leaf_search_ex, or
+ * SHOCK_ECANCELED); the ticket is then retired.  Unknown ticket:
+ * SHOCK_EINVAL. */
+int shock_poll(shock_queue *q, uint64_t ticket, int *done, shock_ticket_info *info);
+
+/* Withdraw a request that has not been admitted yet: it completes with
+ * SHOCK_ECANCELED and its outputs are untouched.  SHOCK_EPENDING if it is
+ * already running (it will complete normally), SHOCK_EINVAL if unknown or
+ * already complete. */
+int shock_cancel(shock_queue *q, uint64_t ticket);
+
+typedef struct shock_queue_stats {
+  uint64_t submitted, completed, cancelled, batches;
+  uint64_t queued, running;                    /* requests now */
+  uint64_t bytes_in_flight, max_bytes_in_flight;
+  int32_t batches_in_flight, max_batches_in_flight;
+} shock_queue_stats;
+int shock_queue_stats_get(shock_queue *q, shock_queue_stats *out);
+
+/* Stop the dispatcher: running batches finish, queued requests complete with
+ * SHOCK_ECANCELED (without polling), then everything is freed. */
+int shock_queue_destroy(shock_queue *q);
 
 #ifdef __cplusplus
 }

@@ -13,5 +13,6 @@ from .binding import (  # noqa: F401
     shock_strerror, shock_spec_version, shock_release_scratch, leaf_search, SearchContext, make_opts,
     shock_rf_leaf_search_ex, rf_leaf_search, leaf_query, rf_leaf_query, rice_encode, rice_decode, MPHF,
     bip_leaf_search, leaf_search_noalloc, SHOCK_NOALLOC_MAX_LEAVES, SHOCK_NOALLOC_MAX_WORKERS,
-    SHOCK_NOALLOC_SCRATCH_BYTES,
+    SHOCK_NOALLOC_SCRATCH_BYTES, SHOCK_EPENDING, leaf_search_async, rf_leaf_search_async, stream_status,
+    RequestQueue, queue_batch_bytes,
 )

@@ -14,6 +14,7 @@ SHOCK_EDUPKEY = -3
 SHOCK_ECANCELED = -4
 SHOCK_EHIP = -5
 SHOCK_ENOMEM = -6
+SHOCK_EPENDING = -7
 
 SHOCK_MODE_AUTO = 0
 SHOCK_MODE_PLAIN_PER_LEAF = 1
@@ -31,6 +32,9 @@ EXPORTED = [
     "shock_leaf_query", "shock_rf_leaf_query", "shock_rice_encode", "shock_rice_decode",
     "shock_mphf_params_init", "shock_mphf_build", "shock_mphf_query", "shock_mphf_info", "shock_mphf_export",
     "shock_mphf_destroy", "shock_bip_leaf_search_ex", "shock_leaf_search_noalloc",
+    "shock_leaf_search_async", "shock_rf_leaf_search_async", "shock_stream_status", "shock_queue_params_init",
+    "shock_queue_batch_bytes", "shock_queue_create", "shock_submit", "shock_poll", "shock_cancel",
+    "shock_queue_stats_get", "shock_queue_destroy",
 ]
 
 # Limits of shock_leaf_search_noalloc (include/shockleaf.h).
@@ -83,6 +87,37 @@ class BipStats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class QueueParams(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("slots", ctypes.c_int32),
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("max_batch_leaves", ctypes.c_uint64),
+        ("max_batch_keys", ctypes.c_uint64),
+        ("search", ShockOpts),
+    ]
+
+
+class TicketInfo(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64),
+                ("batch", ctypes.c_uint64), ("n_leaves", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class QueueStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("cancelled", ctypes.c_uint64),
+        ("batches", ctypes.c_uint64), ("queued", ctypes.c_uint64), ("running", ctypes.c_uint64),
+        ("bytes_in_flight", ctypes.c_uint64), ("max_bytes_in_flight", ctypes.c_uint64),
+        ("batches_in_flight", ctypes.c_int32), ("max_batches_in_flight", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class MphfParams(ctypes.Structure):
@@ -196,6 +231,28 @@ def lib():
         L.shock_bip_leaf_search_ex.restype = ctypes.c_int
         L.shock_bip_leaf_search_ex.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, ctypes.POINTER(ShockOpts), vp,
                                                ctypes.POINTER(BipStats)]
+        L.shock_leaf_search_async.restype = ctypes.c_int
+        L.shock_leaf_search_async.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(ShockOpts), vp]
+        L.shock_rf_leaf_search_async.restype = ctypes.c_int
+        L.shock_rf_leaf_search_async.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp, ctypes.POINTER(ShockOpts), vp]
+        L.shock_stream_status.restype = ctypes.c_int
+        L.shock_stream_status.argtypes = [vp]
+        L.shock_queue_params_init.restype = None
+        L.shock_queue_params_init.argtypes = [ctypes.POINTER(QueueParams)]
+        L.shock_queue_batch_bytes.restype = ctypes.c_uint64
+        L.shock_queue_batch_bytes.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.shock_queue_create.restype = ctypes.c_int
+        L.shock_queue_create.argtypes = [ctypes.POINTER(QueueParams), ctypes.POINTER(vp)]
+        L.shock_submit.restype = ctypes.c_int
+        L.shock_submit.argtypes = [vp, vp, vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.shock_poll.restype = ctypes.c_int
+        L.shock_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(TicketInfo)]
+        L.shock_cancel.restype = ctypes.c_int
+        L.shock_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.shock_queue_stats_get.restype = ctypes.c_int
+        L.shock_queue_stats_get.argtypes = [vp, ctypes.POINTER(QueueStats)]
+        L.shock_queue_destroy.restype = ctypes.c_int
+        L.shock_queue_destroy.argtypes = [vp]
         L.shock_ctx_query.restype = ctypes.c_int
         L.shock_ctx_query.argtypes = [vp]
         L.shock_ctx_wait.restype = ctypes.c_int
@@ -361,6 +418,129 @@ def leaf_search_noalloc(keys, offsets, out_seeds, out_orient, stream=None, **opt
     if rc == SHOCK_EHIP:
         raise ShockError(rc, lib().shock_last_error().decode())
     return rc
+
+
+def leaf_search_async(keys, offsets, out_seeds, out_orient, stream=None, **opts) -> int:
+    """shock_leaf_search_async: enqueue the search on `stream` (default: the
+    current torch stream) and return at once; the batch's status comes from
+    stream_status(stream) once the stream has passed it.  Keep every tensor
+    alive until then."""
+    import torch
+
+    keys, offsets, L = _batch(keys, offsets)
+    _check_out(out_seeds, L, torch.int64, keys.device, "out_seeds")
+    _check_out(out_orient, L, torch.int64, keys.device, "out_orient")
+    if stream is None:
+        stream = torch.cuda.current_stream(keys.device).cuda_stream
+    o = make_opts(n_keys=keys.numel(), **opts)
+    rc = lib().shock_leaf_search_async(_as_ptr(keys if keys.numel() else offsets), _as_ptr(offsets), L,
+                                       _as_ptr(out_seeds), _as_ptr(out_orient), ctypes.byref(o),
+                                       ctypes.c_void_p(stream))
+    if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
+        raise ShockError(rc, lib().shock_last_error().decode())
+    return rc
+
+
+def rf_leaf_search_async(keys, offsets, out_seeds, out_rot, out_orient, stream=None, **opts) -> int:
+    """shock_rf_leaf_search_async (see leaf_search_async); out_rot int32."""
+    import torch
+
+    keys, offsets, L = _batch(keys, offsets)
+    _check_out(out_seeds, L, torch.int64, keys.device, "out_seeds")
+    _check_out(out_rot, L, torch.int32, keys.device, "out_rot")
+    _check_out(out_orient, L, torch.int64, keys.device, "out_orient")
+    if stream is None:
+        stream = torch.cuda.current_stream(keys.device).cuda_stream
+    o = make_opts(n_keys=keys.numel(), **opts)
+    rc = lib().shock_rf_leaf_search_async(_as_ptr(keys if keys.numel() else offsets), _as_ptr(offsets), L,
+                                          _as_ptr(out_seeds), _as_ptr(out_rot), _as_ptr(out_orient),
+                                          ctypes.byref(o), ctypes.c_void_p(stream))
+    if rc in (SHOCK_EHIP, SHOCK_ENOMEM):
+        raise ShockError(rc, lib().shock_last_error().decode())
+    return rc
+
+
+def stream_status(stream) -> int:
+    """shock_stream_status of a raw stream handle (e.g. torch's cuda_stream)."""
+    return lib().shock_stream_status(ctypes.c_void_p(stream))
+
+
+def queue_batch_bytes(n_leaves: int, n_keys: int) -> int:
+    """Device bytes a batch holds in a RequestQueue's arena."""
+    return int(lib().shock_queue_batch_bytes(n_leaves, n_keys))
+
+
+class RequestQueue:
+    """A shock_queue: host-side build requests (CSR leaves in numpy uint64
+    arrays) searched on one device under an HBM budget by the library's
+    dispatcher thread.  submit() returns a ticket; poll() reports completion
+    and hands back the results."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 256 << 20, slots: int = 4,
+                 max_batch_leaves: int = 65536, max_batch_keys: int = 1 << 22, **search_opts):
+        p = QueueParams()
+        lib().shock_queue_params_init(ctypes.byref(p))
+        p.device = device
+        p.slots = slots
+        p.hbm_budget_bytes = hbm_budget_bytes
+        p.max_batch_leaves = max_batch_leaves
+        p.max_batch_keys = max_batch_keys
+        p.search = make_opts(**search_opts)
+        self._h = ctypes.c_void_p()
+        rc = lib().shock_queue_create(ctypes.byref(p), ctypes.byref(self._h))
+        if rc != SHOCK_OK:
+            raise ShockError(rc, lib().shock_last_error().decode())
+        self._live = {}  # ticket -> (keys, offsets, seeds, orient): kept alive until polled done
+
+    def submit(self, keys, offsets):
+        """(status, ticket): keys and offsets numpy uint64 (host).  SHOCK_ENOMEM
+        for a request larger than the budget or a batch's limits."""
+        import numpy as np
+
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        L = len(offsets) - 1
+        if L < 0:
+            raise ValueError("offsets needs n_leaves + 1 entries")
+        seeds = np.empty(max(L, 1), dtype=np.uint64)
+        orient = np.empty(max(L, 1), dtype=np.uint64)
+        t = ctypes.c_uint64()
+        rc = lib().shock_submit(self._h, keys.ctypes.data if keys.size else None, offsets.ctypes.data, L,
+                                seeds.ctypes.data, orient.ctypes.data, ctypes.byref(t))
+        if rc != SHOCK_OK:
+            return rc, None
+        self._live[t.value] = (keys, offsets, seeds[:L], orient[:L])
+        return rc, t.value
+
+    def poll(self, ticket):
+        """(done, status, info dict or None, seeds, orient); results only once done."""
+        done = ctypes.c_int()
+        info = TicketInfo()
+        rc = lib().shock_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(info))
+        if not done.value:
+            return False, rc, None, None, None
+        _, _, seeds, orient = self._live.pop(ticket)
+        return True, rc, info.as_dict(), seeds, orient
+
+    def cancel(self, ticket) -> int:
+        return lib().shock_cancel(self._h, ticket)
+
+    def stats(self) -> dict:
+        st = QueueStats()
+        lib().shock_queue_stats_get(self._h, ctypes.byref(st))
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().shock_queue_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _check_tensors(keys, offsets):

@@ -6,7 +6,7 @@ import subprocess
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRCS = [os.path.join(PKG, "csrc", f) for f in ("shockleaf.hip", "shockcode.hip", "shockmphf.hip", "shockbip.hip")]
+SRCS = [os.path.join(PKG, "csrc", f) for f in ("shockleaf.hip", "shockcode.hip", "shockmphf.hip", "shockbip.hip", "shockqueue.hip")]
 LIB = os.path.join(PKG, "libshockleaf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1263,9 +1263,70 @@ int get_scratch(size_t bytes, void **buf, unsigned long long **host_ctr) {
   return SHOCK_OK;
 }
 
+// Scratch is laid out for the largest worker count any launch may use.
+constexpr uint32_t kCallWorkersCap = 32 * 256 * 4 + kMaxWavesPerWg;
+
+// Enqueue a whole search (init, validation and premix, search, unfinished
+// marks, counters copied to host_ctr) on `stream` with no host
+// synchronisation.  `buf` holds layout(n_leaves, kCallWorkersCap, launches)
+// bytes; launch sizes come from n_typical.  opts are complete (max_seed set).
+int enqueue_call(void *buf, uint64_t n_leaves, const uint64_t *keys, const uint64_t *offsets, uint64_t *out_seeds,
+                 uint32_t *out_rot, uint64_t *out_orient, const shock_opts &opts, uint32_t n_typical,
+                 hipStream_t stream, unsigned long long *host_ctr, hipEvent_t ev_begin, hipEvent_t ev_search,
+                 Plan &pl) {
+  int rc = make_plan(opts, n_leaves, n_typical, out_rot != nullptr, pl);
+  if (rc != SHOCK_OK) return rc;
+  if (pl.workers > (int)kCallWorkersCap) return SHOCK_EINVAL;
+  const CallBufs cb = carve(buf, layout(n_leaves, kCallWorkersCap, pl.n_launches));
+  HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts, kCallWorkersCap, stream));
+  Params P = base_params(cb, pl, opts, offsets, out_seeds, out_orient, out_rot);
+  if (ev_begin) HIP_TRY(hipEventRecord(ev_begin, stream));
+  HIP_TRY(enqueue_search(P, cb, pl, n_leaves, nullptr, n_typical, opts.workers != 0, stream));
+  if (ev_search) HIP_TRY(hipEventRecord(ev_search, stream));
+  hipLaunchKernelGGL(mark_unfinished_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, stream, cb.gctr,
+                     cb.state, n_leaves, out_seeds, out_orient, out_rot);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(host_ctr, cb.gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
+  return SHOCK_OK;
+}
+
+// Options with defaults filled in, checked as every entry point checks them.
+int complete_opts(const shock_opts *in, uint64_t n_leaves, const void *keys, const void *offsets,
+                  const void *out_seeds, const void *out_orient, int rf, shock_opts &opts) {
+  shock_opts_init(&opts);
+  if (in) opts = *in;
+  if (opts.max_seed == 0) opts.max_seed = SHOCK_DEFAULT_MAX_SEED;
+  const int rc = check_opts(opts, n_leaves, offsets, out_seeds, out_orient);
+  if (rc != SHOCK_OK) return rc;
+  if (!keys) return SHOCK_EINVAL;
+  if (rf && opts.max_seed > (1ull << 57)) return SHOCK_EINVAL;
+  return SHOCK_OK;
+}
+
 }  // namespace
 
 void shock_internal_set_error(const char *what, hipError_t e) { set_err(what, e); }
+
+size_t shock_internal_search_bytes(uint64_t n_leaves, int per_leaf) {
+  return layout(n_leaves, kCallWorkersCap, per_leaf ? n_leaves : 1).total;
+}
+
+size_t shock_internal_counter_bytes(void) { return kCtrGlobalCount * 8; }
+
+int shock_internal_complete_opts(const shock_opts *in, uint64_t n_leaves, const void *keys, const void *offsets,
+                                 const void *out_seeds, const void *out_orient, int rf, shock_opts *out) {
+  return complete_opts(in, n_leaves, keys, offsets, out_seeds, out_orient, rf, *out);
+}
+
+int shock_internal_enqueue(void *buf, uint64_t n_leaves, const uint64_t *keys, const uint64_t *offsets,
+                           uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient, const shock_opts *opts,
+                           uint32_t n_typical, hipStream_t stream, unsigned long long *host_ctr) {
+  Plan pl;
+  return enqueue_call(buf, n_leaves, keys, offsets, out_seeds, out_rot, out_orient, *opts, n_typical, stream,
+                      host_ctr, nullptr, nullptr, pl);
+}
+
+int shock_internal_status(const unsigned long long *host_ctr) { return status_from(host_ctr, nullptr); }
 
 // A search context: its own scratch for batches of up to max_leaves leaves,
 // pinned counters, events and an optional captured graph.
@@ -1303,6 +1364,7 @@ const char *shock_strerror(int s) {
     case SHOCK_ECANCELED: return "cancelled";
     case SHOCK_EHIP: return "HIP runtime error";
     case SHOCK_ENOMEM: return "out of device memory";
+    case SHOCK_EPENDING: return "not complete yet";
     default: return "unknown status";
   }
 }
@@ -1327,6 +1389,7 @@ int shock_release_scratch(void) {
   HIP_TRY(shock_internal_release_code_scratch(dev));
   HIP_TRY(shock_internal_release_bip_scratch(dev));
   HIP_TRY(shock_internal_release_mphf_scratch(dev));
+  HIP_TRY(shock_internal_release_stream_scratch(dev));
   return SHOCK_OK;
 }
 
@@ -1527,7 +1590,7 @@ int shock_ctx_create(uint64_t max_leaves, shock_ctx **out) {
   shock_ctx *c = new shock_ctx();
   HIP_TRY(hipGetDevice(&c->device));
   c->max_leaves = max_leaves;
-  c->workers_cap = 32 * 256 * 4 + kMaxWavesPerWg;
+  c->workers_cap = kCallWorkersCap;
   const Layout lay = layout(max_leaves, c->workers_cap, max_leaves);
   c->bytes = lay.total;
   hipError_t e = hipMalloc(&c->buf, c->bytes);
@@ -1572,23 +1635,12 @@ int shock_ctx_destroy(shock_ctx *c) {
 static int ctx_enqueue(shock_ctx *c, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,
                        uint64_t *out_seeds, uint32_t *out_rot, uint64_t *out_orient, const shock_opts &opts,
                        hipStream_t stream, bool with_events) {
-  const CallBufs cb = carve(c->buf, layout(c->max_leaves, c->workers_cap, c->max_leaves));
   Plan pl;
-  const uint32_t hint = opts.leaf_size_hint ? (uint32_t)opts.leaf_size_hint : 48;
-  int rc = make_plan(opts, n_leaves, hint, out_rot != nullptr, pl);
-  if (rc != SHOCK_OK) return rc;
-  if (pl.workers > (int)c->workers_cap) return SHOCK_EINVAL;
-  HIP_TRY(enqueue_prologue(cb, pl, keys, offsets, n_leaves, opts, c->workers_cap, stream));
-  Params P = base_params(cb, pl, opts, offsets, out_seeds, out_orient, out_rot);
-  if (with_events) HIP_TRY(hipEventRecord(c->ev_begin, stream));
-  HIP_TRY(enqueue_search(P, cb, pl, n_leaves, nullptr, hint, opts.workers != 0, stream));
-  if (with_events) HIP_TRY(hipEventRecord(c->ev_search, stream));
-  hipLaunchKernelGGL(mark_unfinished_kernel, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, stream, cb.gctr,
-                     cb.state, n_leaves, out_seeds, out_orient, out_rot);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(c->host_ctr, cb.gctr, kCtrGlobalCount * 8, hipMemcpyDeviceToHost, stream));
-  c->last_plan = pl;
-  return SHOCK_OK;
+  const int rc = enqueue_call(c->buf, n_leaves, keys, offsets, out_seeds, out_rot, out_orient, opts,
+                              opts.leaf_size_hint ? (uint32_t)opts.leaf_size_hint : 48, stream, c->host_ctr,
+                              with_events ? c->ev_begin : nullptr, with_events ? c->ev_search : nullptr, pl);
+  if (rc == SHOCK_OK) c->last_plan = pl;
+  return rc;
 }
 
 static int ctx_async(shock_ctx *c, const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,

@@ -2,23 +2,29 @@
 
 A request carries N keys.  It is cut into leaves of `leaf_size` keys in input
 order, plus one remainder leaf, and its build is done when every leaf has its
-smallest seed and orientation.  The loop keeps up to `slots` batches in
-flight, each on its own search context and HIP stream:
+smallest seed and orientation.
+
+LeafServer drives the library's native request queue (shock_queue in
+include/shockleaf.h).  This module only turns arrivals into submissions and
+completions into latencies; admission, batching and launches happen in the
+library's dispatcher thread:
 
 * Requests that arrive while others are on the GPU wait in a FIFO queue.
-* A free slot takes as many queued requests, in order, as the HBM budget and
-  the slot's capacity allow.
-* The slot uploads their keys, enqueues the search asynchronously and moves
-  on. Batches on different streams run concurrently: a persistent kernel's
-  idle workers leave once nothing is open in their batch, and a newer batch's
-  workgroups take their place.
-* When a slot's search completes, its results are copied back and its
-  requests are complete.
+* A free slot takes as many queued requests, in order, as the queue's device
+  arena (the HBM budget) and the slot's capacity allow.
+* The slot uploads their keys from pinned staging, enqueues one asynchronous
+  persistent search over all of them, and moves on.  Batches on different
+  streams run concurrently: a persistent kernel's idle workers leave once
+  nothing is open in their batch, and a newer batch's workgroups take their
+  place.
+* When a slot's search completes, its results are copied into each request's
+  host buffers, its arena block is freed and the next requests are admitted.
 
-Latency of a request = completion time - arrival time.  The device memory a
-request holds while admitted (its keys, offsets, outputs and its share of the
-search scratch) counts against the budget.  A request alone larger than the
-budget is rejected; a request still queued past its deadline times out.
+Latency of a request = completion time (the dispatcher's clock) - arrival
+time.  The device memory a batch holds while admitted (keys, offsets, outputs
+and search scratch) is one block of the budget.  A request alone larger than
+the budget is rejected; a request still queued past its deadline is
+withdrawn (timeout).
 
 MphfServer serves the same requests with complete minimal perfect hash
 functions (the flat ShockHash MPHF of include/shockmphf.h): each request is
@@ -36,9 +42,9 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .binding import MPHF, SHOCK_OK, SearchContext
+from .binding import MPHF, SHOCK_ECANCELED, SHOCK_ENOMEM, SHOCK_OK, RequestQueue, queue_batch_bytes
 
-SCRATCH_BYTES_PER_LEAF = 600  # premixed keys, claim word, best seed, counters
+SCRATCH_BYTES_PER_LEAF = 600  # premixed keys, claim word, best seed, counters (MPHF build estimate)
 
 
 @dataclass
@@ -75,21 +81,8 @@ def leaf_offsets(n_keys: int, leaf_size: int) -> np.ndarray:
 
 
 def footprint(n_keys: int, n_leaves: int) -> int:
-    """Device bytes a request holds while admitted."""
-    return 8 * n_keys + 8 * (n_leaves + 1) + 16 * n_leaves + SCRATCH_BYTES_PER_LEAF * n_leaves
-
-
-@dataclass
-class _Batch:
-    slot: int
-    reqs: list
-    leaf_base: list
-    bytes: int
-    keys_d: object = None
-    offs_d: object = None
-    seeds_d: object = None
-    orient_d: object = None
-    launched: float = 0.0
+    """Device bytes a request alone holds while admitted (one batch)."""
+    return queue_batch_bytes(n_leaves, n_keys)
 
 
 @dataclass
@@ -132,64 +125,17 @@ class LeafServer:
 
         if leaf_size < 1 or leaf_size > 64:
             raise ValueError("leaf_size must be in [1, 64]")
-        self.torch = torch
         self.device = torch.device(device)
         self.budget = int(hbm_budget_bytes)
+        self.slots = slots
         self.leaf_size = leaf_size
         self.max_batch_leaves = max_batch_leaves
         self.opts = dict(search_opts or {})
-        self.opts.setdefault("leaf_size_hint", leaf_size)
-        self.ctxs = [SearchContext(max_batch_leaves) for _ in range(slots)]
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        self.opts.pop("leaf_size_hint", None)
 
     def close(self):
-        for c in self.ctxs:
-            c.close()
+        pass
 
-    # -- one batch -----------------------------------------------------------
-    def _launch(self, slot: int, reqs: list, now: float) -> _Batch:
-        torch = self.torch
-        keys = np.concatenate([r.keys for r in reqs]) if len(reqs) > 1 else reqs[0].keys
-        offs_parts, base, leaf_base = [], 0, []
-        lb = 0
-        for r in reqs:
-            offs_parts.append(r.offsets[:-1] + np.uint64(base))
-            leaf_base.append(lb)
-            base += len(r.keys)
-            lb += r.n_leaves
-        offs = np.append(np.concatenate(offs_parts), np.uint64(base))
-        L = len(offs) - 1
-        b = _Batch(slot=slot, reqs=reqs, leaf_base=leaf_base,
-                   bytes=sum(footprint(len(r.keys), r.n_leaves) for r in reqs), launched=now)
-        stream = self.streams[slot]
-        with torch.cuda.stream(stream):
-            kh = torch.from_numpy(np.ascontiguousarray(keys).view(np.int64)).pin_memory()
-            oh = torch.from_numpy(offs.view(np.int64)).pin_memory()
-            b.keys_d = kh.to(self.device, non_blocking=True)
-            b.offs_d = oh.to(self.device, non_blocking=True)
-            b.seeds_d = torch.empty(L, dtype=torch.int64, device=self.device)
-            b.orient_d = torch.empty(L, dtype=torch.int64, device=self.device)
-            rc = self.ctxs[slot].search_async(b.keys_d, b.offs_d, b.seeds_d, b.orient_d,
-                                              stream=stream.cuda_stream, **self.opts)
-        if rc != SHOCK_OK:
-            raise RuntimeError(f"search launch failed with status {rc}")
-        for r in reqs:
-            r.admitted = now
-            r.status = "running"
-        return b
-
-    def _finish(self, b: _Batch, now_fn):
-        rc, _ = self.ctxs[b.slot].wait()
-        seeds = b.seeds_d.cpu().numpy().view(np.uint64)
-        orient = b.orient_d.cpu().numpy().view(np.uint64)
-        t = now_fn()
-        for r, lb in zip(b.reqs, b.leaf_base):
-            r.seeds = seeds[lb:lb + r.n_leaves].copy()
-            r.orient = orient[lb:lb + r.n_leaves].copy()
-            r.completed = t
-            r.status = "done" if rc == SHOCK_OK else f"error {rc}"
-
-    # -- the loop ------------------------------------------------------------
     def run(self, requests: list, realtime: bool = True) -> ServeReport:
         """Serve requests (sorted by arrival).  With realtime=False every
         request is treated as having arrived at time 0 (a backlog)."""
@@ -197,71 +143,51 @@ class LeafServer:
             r.offsets = leaf_offsets(len(r.keys), self.leaf_size)
             r.status = "queued"
             r.admitted = r.completed = None
-        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
-        queue = collections.deque()
-        free_slots = list(range(len(self.ctxs)))
-        inflight = {}
-        bytes_in_flight = 0
-        max_bytes = 0
-        max_batches = 0
-        n_batches = 0
-        t0 = time.perf_counter()
-        now = lambda: time.perf_counter() - t0  # noqa: E731
-        while pending or queue or inflight:
-            t = now()
-            while pending and (not realtime or pending[0].arrival <= t):
-                queue.append(pending.popleft())
-            progressed = False
-            # completions
-            for slot, b in list(inflight.items()):
-                if self.ctxs[slot].query() == 1:
-                    self._finish(b, now)
-                    bytes_in_flight -= b.bytes
-                    del inflight[slot]
-                    free_slots.append(slot)
-                    progressed = True
-            # deadlines of queued requests
-            t = now()
-            kept = collections.deque()
-            for r in queue:
-                if r.deadline is not None and t - r.arrival > r.deadline:
-                    r.status = "timeout"
-                    r.completed = None
-                else:
-                    kept.append(r)
-            queue = kept
-            # admission
-            while free_slots and queue:
-                batch, add_bytes, leaves = [], 0, 0
-                while queue:
-                    r = queue[0]
-                    fb = footprint(len(r.keys), r.n_leaves)
-                    if fb > self.budget or r.n_leaves > self.max_batch_leaves:
-                        queue.popleft()
+            r.seeds = r.orient = None
+        q = RequestQueue(device=self.device.index or 0, hbm_budget_bytes=self.budget, slots=self.slots,
+                         max_batch_leaves=self.max_batch_leaves,
+                         max_batch_keys=self.max_batch_leaves * self.leaf_size, **self.opts)
+        try:
+            pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+            inflight = {}
+            t0 = time.perf_counter_ns()
+            now = lambda: (time.perf_counter_ns() - t0) * 1e-9  # noqa: E731 (same clock as the library's)
+            while pending or inflight:
+                t = now()
+                while pending and (not realtime or pending[0].arrival <= t):
+                    r = pending.popleft()
+                    rc, ticket = q.submit(r.keys, r.offsets)
+                    if rc == SHOCK_ENOMEM:
                         r.status = "rejected"
                         continue
-                    if bytes_in_flight + add_bytes + fb > self.budget or leaves + r.n_leaves > self.max_batch_leaves:
-                        break
-                    batch.append(queue.popleft())
-                    add_bytes += fb
-                    leaves += r.n_leaves
-                if not batch:
-                    break
-                slot = free_slots.pop()
-                inflight[slot] = self._launch(slot, batch, now())
-                bytes_in_flight += add_bytes
-                n_batches += 1
-                max_bytes = max(max_bytes, bytes_in_flight)
-                max_batches = max(max_batches, len(inflight))
-                progressed = True
-            if not progressed:
+                    if rc != SHOCK_OK:
+                        raise RuntimeError(f"submit failed with status {rc}")
+                    inflight[ticket] = r
+                for ticket, r in list(inflight.items()):
+                    done, rc, info, seeds, orient = q.poll(ticket)
+                    if not done:
+                        if r.deadline is not None and now() - r.arrival > r.deadline:
+                            r.deadline = None  # withdrawn now, or already running and left to finish
+                            q.cancel(ticket)
+                        continue
+                    del inflight[ticket]
+                    if rc == SHOCK_ECANCELED:
+                        r.status = "timeout"
+                        continue
+                    r.admitted = (info["admit_ns"] - t0) * 1e-9
+                    r.completed = (info["done_ns"] - t0) * 1e-9
+                    r.seeds, r.orient = seeds, orient
+                    r.status = "done" if rc == SHOCK_OK else f"error {rc}"
                 if inflight:
                     time.sleep(0.0001)
                 elif pending:
                     time.sleep(max(0.0, min(0.001, pending[0].arrival - now())))
-        makespan = now()
-        return ServeReport(requests=list(requests), makespan_s=makespan, max_bytes_in_flight=max_bytes,
-                           max_batches_in_flight=max_batches, batches=n_batches)
+            makespan = now()
+            st = q.stats()
+        finally:
+            q.close()
+        return ServeReport(requests=list(requests), makespan_s=makespan, max_bytes_in_flight=st["max_bytes_in_flight"],
+                           max_batches_in_flight=st["max_batches_in_flight"], batches=st["batches"])
 
 
 def synthetic_stream(n_requests: int, rate_per_s: float, seed: int = 5, min_keys: int = 1000,

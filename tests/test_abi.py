@@ -68,7 +68,9 @@ def test_ctypes_structs_match_the_headers(tmp_path):
         pytest.skip("gcc not available")
     from paper_2308_09561_amd import binding as b
     pairs = [(b.ShockOpts, "shock_opts"), (b.ShockStats, "shock_stats"), (b.BipStats, "shock_bip_stats"),
-             (b.MphfParams, "shock_mphf_params"), (b.MphfStats, "shock_mphf_stats")]
+             (b.MphfParams, "shock_mphf_params"), (b.MphfStats, "shock_mphf_stats"),
+             (b.QueueParams, "shock_queue_params"), (b.TicketInfo, "shock_ticket_info"),
+             (b.QueueStats, "shock_queue_stats")]
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "shockleaf.h"', '#include "shockmphf.h"',
              "int main(void) {"]
     want = []
