@@ -35,6 +35,21 @@ PEAK_INT_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 int32 lanes per clock x 2.4 GHz
 # compare (1): 20.
 OPS_PER_EVAL = 11
 OPS_PER_SEED = 20
+# Leaves of at most 32 keys keep the coverage mask in one 32-bit word: one
+# 32-bit bit-set per slot and one 3-input OR instead of two, 10 per key
+# evaluation.
+OPS_PER_EVAL_NARROW = 10
+
+# The instruction-mix ceiling.  The nominal peak assumes one 32-bit op per
+# lane per clock; gfx950 issues some simple ops (xor, shifts) faster and the
+# 64-bit multiply-add slower, so the ceiling of a loop is the rate of its own
+# instruction mix.  valu_rates.hip (beside this file) runs the search kernel's
+# hash-and-filter loop register-only, with the library's slot_pair and mask
+# updates, and the per-seed mix; profiles/probes_gfx950.md holds the run:
+PROBE_EVALS_PER_S = {True: 3.5421e12, False: 3.8888e12}   # key evaluations/s, 64-bit / 32-bit mask
+PROBE_INSTS_PER_EVAL = {True: 272 / 24, False: 246 / 24}  # VALU per evaluation in the probe's compiled loop
+KERNEL_INSTS_PER_EVAL = {True: 89 / 8, False: 81 / 8}     # ... and in the search kernel's compiled loop
+PROBE_SEED_MIX_PER_S = 2.3727e12                          # seed mixes t(s)/s
 # Rotation fitting (Section 4; partial hashing, Appendix A.2), per seed of a
 # leaf with na keys in the first set, nb in the second and period k: nb key
 # evaluations, na / k amortised ones, the seed mixes (1 + 1/k) * 19, and the
@@ -50,6 +65,32 @@ def rf_ops_per_seed(n: int, na: int, partial_k: int) -> float:
     k = partial_k or (8 if n > 32 else 1)
     rot = RF_OPS_PER_ROT_WIDE if n > 32 else RF_OPS_PER_ROT_NARROW
     return OPS_PER_EVAL * ((n - na) + na / k) + 19 * (1 + 1 / k) + 2 + rot * max(n - 1, 0)
+
+
+def alg_ops(seeds_plus_one: np.ndarray, sizes: np.ndarray) -> float:
+    """Integer operations of the useful work: every seed up to each leaf's
+    answer, OPS_PER_EVAL (or OPS_PER_EVAL_NARROW up to 32 keys) per key
+    evaluation and OPS_PER_SEED per seed."""
+    s1 = seeds_plus_one.astype(np.float64)
+    z = sizes.astype(np.float64)
+    per_eval = np.where(sizes > 32, OPS_PER_EVAL, OPS_PER_EVAL_NARROW)
+    return float((s1 * z * per_eval).sum() + s1.sum() * OPS_PER_SEED)
+
+
+def mix_ceiling(seeds_plus_one: np.ndarray, sizes: np.ndarray) -> float:
+    """Ops/s of the same useful work if every instruction issued at the rate
+    its loop reaches on its own (the probes above): key evaluations at the
+    hash loop's rate scaled to the kernel loop's instruction count, seed mixes
+    at the seed-mix rate, the compare at the nominal rate."""
+    s1 = seeds_plus_one.astype(np.float64)
+    z = sizes.astype(np.float64)
+    wide = sizes > 32
+    t = 0.0
+    for w in (True, False):
+        rate = PROBE_EVALS_PER_S[w] * PROBE_INSTS_PER_EVAL[w] / KERNEL_INSTS_PER_EVAL[w]
+        t += float((s1 * z)[wide == w].sum()) / rate
+    t += float(s1.sum()) * (1.0 / PROBE_SEED_MIX_PER_S + 1.0 / PEAK_INT_OPS)
+    return alg_ops(seeds_plus_one, sizes) / t
 
 
 def measured_traffic(workload: str, kind: str = ""):
@@ -152,9 +193,9 @@ def main():
                     help="leaves of 48 keys for the query and seed-code legs (0 = skip)")
     ap.add_argument("--mphf-keys", type=int, default=1 << 22,
                     help="keys of the flat MPHF build and query leg (0 = skip)")
-    ap.add_argument("--configs", action="store_true",
-                    help="also time the parity workloads plain24 (one launch per leaf), fixed40, uneven32_56 and "
-                         "hard60 once each (not part of the default run)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the parity workloads plain24 (one launch per leaf), fixed40, uneven32_56 and hard60 "
+                         "(each timed once by default)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -194,7 +235,7 @@ def main():
     tuned = False
     if not args.untuned:
         from paper_2308_09561_amd import autotune
-        t = autotune.tuned_opts()
+        t = autotune.tuned_opts(sizes=np.diff(offs))
         tuned = bool(t)
         opts.update({k: v for k, v in t.items() if not opts.get(k)})
 
@@ -228,8 +269,8 @@ def main():
     useful_evals = float(((seeds.astype(np.float64) + 1) * sizes).sum())
     leaves_per_s = L / (ms_per_step / 1e3)
     avg_kernel_ms = float(np.mean(kernel_ms))
-    alg_ops = useful_evals * OPS_PER_EVAL + useful_seeds * OPS_PER_SEED
-    achieved = alg_ops / (avg_kernel_ms / 1e3)
+    achieved = alg_ops(seeds + np.uint64(1), np.diff(offs)) / (avg_kernel_ms / 1e3)
+    ceiling = mix_ceiling(seeds + np.uint64(1), np.diff(offs))
     log(f"[bench] {ms_per_step:.2f} ms/step, kernel {avg_kernel_ms:.2f} ms, {leaves_per_s:.0f} leaves/s")
 
     # Plain per-leaf form: one kernel launch per leaf, queued back to back.
@@ -508,7 +549,7 @@ def main():
     # The other parity workloads, once each: kernel time, useful work and the
     # integer roofline fraction under the same operation count.
     others = None
-    if args.configs:
+    if not args.no_configs:
         others = {}
         for name in ("plain24", "fixed40", "uneven32_56", "hard60"):
             kw, ow = make_workload(name)
@@ -518,7 +559,10 @@ def main():
             sd = torch.empty(Lw, dtype=torch.int64, device=dev)
             fd = torch.empty(Lw, dtype=torch.int64, device=dev)
             mode = shock.SHOCK_MODE_PLAIN_PER_LEAF if name == "plain24" else 0
-            wopts = dict(opts) if mode == 0 else {}
+            wopts = {}
+            if mode == 0 and not args.untuned:
+                from paper_2308_09561_amd import autotune
+                wopts = autotune.tuned_opts(sizes=np.diff(ow))
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             rc, _, _ = shock.leaf_search(kd, od, out_seeds=sd, out_orient=fd, mode=mode, **wopts)
@@ -527,15 +571,20 @@ def main():
             if rc != shock.SHOCK_OK:
                 raise RuntimeError(f"{name}: {shock.shock_strerror(rc)}")
             stw = shock.shock_last_stats()
-            sw = sd.cpu().numpy().view(np.uint64).astype(np.float64) + 1
-            zw = np.diff(ow).astype(np.float64)
-            ops = float((sw * zw).sum()) * OPS_PER_EVAL + float(sw.sum()) * OPS_PER_SEED
+            sw = sd.cpu().numpy().view(np.uint64) + np.uint64(1)
+            zw = np.diff(ow)
+            ops = alg_ops(sw, zw)
+            ach = ops / (stw["kernel_ms"] / 1e3)
+            ceil_w = mix_ceiling(sw, zw)
             others[name] = {"leaves": Lw, "wall_ms": wall_w * 1e3, "kernel_ms": stw["kernel_ms"],
+                            "launch": {k: stw[k] for k in ("workers", "spl", "block_iters", "waves_per_wg")},
                             "leaves_per_s": Lw / wall_w, "useful_seeds_per_s": float(sw.sum()) / wall_w,
-                            "seeds_tested": stw["seeds_tested"], "overshoot": stw["seeds_tested"] / float(sw.sum()) - 1,
-                            "roofline_frac": ops / (stw["kernel_ms"] / 1e3) / PEAK_INT_OPS if stw["kernel_ms"] > 0 else None}
+                            "seeds_tested": stw["seeds_tested"],
+                            "overshoot": stw["seeds_tested"] / float(sw.astype(np.float64).sum()) - 1,
+                            "roofline": {"achieved": ach / 1e12, "frac": ach / PEAK_INT_OPS,
+                                         "mix_ceiling": ceil_w / 1e12, "frac_of_mix_ceiling": ach / ceil_w}}
             log(f"[bench] {name}: {Lw} leaves, {wall_w * 1e3:.1f} ms wall, kernel {stw['kernel_ms']:.1f} ms, "
-                f"{Lw / wall_w:.0f} leaves/s, frac {others[name]['roofline_frac']:.3f}")
+                f"{Lw / wall_w:.0f} leaves/s, frac {ach / PEAK_INT_OPS:.3f} nominal, {ach / ceil_w:.3f} of the mix ceiling")
             del kd, od, sd, fd
 
     out = {
@@ -570,8 +619,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT_OPS / 1e12,
                      "unit": "Tops/s (int32 lane ops)", "frac": achieved / PEAK_INT_OPS,
                      "traffic": measured_traffic(args.workload),
-                     "ops_per_key_eval": OPS_PER_EVAL, "ops_per_seed": OPS_PER_SEED,
-                     "kernel_ms": avg_kernel_ms},
+                     "mix_ceiling": ceiling / 1e12, "frac_of_mix_ceiling": achieved / ceiling,
+                     "ops_per_key_eval": OPS_PER_EVAL, "ops_per_key_eval_up_to_32_keys": OPS_PER_EVAL_NARROW,
+                     "ops_per_seed": OPS_PER_SEED, "kernel_ms": avg_kernel_ms},
         "cpu_baseline": cpu,
     }
     if others is not None:

@@ -322,8 +322,8 @@ typedef struct shock_queue_params {
   uint64_t max_batch_leaves; /* leaves one batch may hold; 0 = 65536 */
   uint64_t max_batch_keys;   /* keys one batch may hold (pinned staging per slot: 8 bytes each); 0 = 2^22 */
   shock_opts search;         /* search options of every request: mode AUTO or PERSISTENT, no cancel flag, no
-                                claim table, no check_dups (a batch shares one validation); leaf_size_hint is
-                                ignored: launches are sized by each batch's mean leaf size */
+                                check_dups (a batch shares one validation); a claim table is copied at creation;
+                                leaf_size_hint is ignored: launches are sized by each batch's mean leaf size */
 } shock_queue_params;
 
 void shock_queue_params_init(shock_queue_params *p);

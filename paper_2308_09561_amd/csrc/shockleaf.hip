@@ -1064,13 +1064,15 @@ int default_rf_units(uint32_t) { return 2; }
 // address) and searches past the answers, which costs far more than it
 // gains: 16384 leaves want every resident wave, but ten 48-key leaves ran 4x
 // faster with 512 waves than with 5120.  Measured on MI355X over 10 to 10000
-// leaves, about one wave per leaf does best for light leaves and one
-// workgroup of 4 per leaf for leaves of more than ~1000 claim units of
-// expected work (plain search above 44 keys), with at least 512 workers.
+// leaves, about one wave per leaf does best for light leaves, with at least
+// 512 workers.  Heavy leaves (more than ~1000 claim units of expected work:
+// plain search above 44 keys) get one wave per 128 units, up to 32: with
+// only four waves per leaf, 256 leaves of 64 keys held one wave per SIMD and
+// ran 20% below a full device.
 int batch_workers(int resident, uint64_t n_leaves, uint32_t n, int rf, int spl) {
   const double unit = 64.0 * (rf ? kRfSeedsPerLane : spl);
   const double units = expected_seeds(n) / (rf && n > 1 ? (double)n : 1.0) / unit;
-  const uint64_t per_leaf = units >= 1000.0 ? 4 : 1;
+  const uint64_t per_leaf = units >= 1000.0 ? (units >= 4096.0 ? 32 : (uint64_t)(units / 128.0)) : 1;
   const uint64_t want = n_leaves * per_leaf < 512 ? 512 : n_leaves * per_leaf;
   return want < (uint64_t)resident ? (int)want : resident;
 }

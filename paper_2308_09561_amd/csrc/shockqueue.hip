@@ -230,6 +230,7 @@ struct shock_queue {
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread th;
+  uint16_t claim_table[65] = {};  // the caller's block_iters_by_n, copied
   shock_queue_stats stats{};
   int fatal = SHOCK_OK;  // a HIP failure in the dispatcher fails every later batch
 };
@@ -491,9 +492,9 @@ int shock_queue_create(const shock_queue_params *params, shock_queue **out) {
   if (p.slots < 1 || p.slots > 16 || p.max_batch_leaves > (1ull << 31) || p.max_batch_keys > (1ull << 34))
     return SHOCK_EINVAL;
   if (p.search.mode != SHOCK_MODE_AUTO && p.search.mode != SHOCK_MODE_PERSISTENT) return SHOCK_EINVAL;
-  // no host pointers are kept, and a repeated key in one request must not
-  // fail the other requests of its batch
-  if (p.search.cancel != nullptr || p.search.block_iters_by_n != nullptr || p.search.check_dups) return SHOCK_EINVAL;
+  // no cancel flag is kept (a batch serves several requests), and a repeated
+  // key in one request must not fail the other requests of its batch
+  if (p.search.cancel != nullptr || p.search.check_dups) return SHOCK_EINVAL;
   {
     // the search options are checked as a search call checks them
     shock_opts chk;
@@ -508,6 +509,10 @@ int shock_queue_create(const shock_queue_params *params, shock_queue **out) {
   Q_TRY(hipSetDevice(p.device));
   shock_queue *q = new shock_queue();
   q->p = p;
+  if (p.search.block_iters_by_n) {  // the claim table is copied: the caller's may go away
+    memcpy(q->claim_table, p.search.block_iters_by_n, sizeof(q->claim_table));
+    q->p.search.block_iters_by_n = q->claim_table;
+  }
   q->slots.resize(p.slots);
   auto fail = [&](const char *what, hipError_t e, int rc) {
     shock_internal_set_error(what, e);

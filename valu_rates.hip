@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
+
+#include "paper_2308_09561_amd/csrc/shock_hash.h"
 #define CHECK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { printf("HIP error %s at %d\n", hipGetErrorString(e_), __LINE__); return 1; } } while (0)
 #define ITERS 2048
 #define NCH 8
@@ -50,6 +52,60 @@ K64(k_mad_u64, "v_mad_u64_u32 %0, vcc, %1, %2, %0")
 K64(k_lshl_b64, "v_lshlrev_b64 %0, %1, %0")
 K64(k_lshl_add_u64, "v_lshl_add_u64 %0, %0, 1, %0")
 
+K32(k_lshl_one, "v_lshlrev_b32_e64 %0, %0, 1")
+
+// The search kernel's hash-and-filter loop, register only: 12 keys x 2 seeds
+// per iteration with the library's own slot_pair and mask updates (the same
+// instructions as the compiled loop: 11 per key evaluation with a 64-bit
+// mask, 10 with a 32-bit one), keys loop-invariant, the seed words moved by
+// one add per seed and iteration.  Counts key evaluations.
+#define HASH_KEYS 12
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_hash_loop(uint32_t* out, uint32_t s1, uint32_t s2) {
+  uint32_t alo[HASH_KEYS], ahi[HASH_KEYS];
+  _Pragma("unroll") for (int i = 0; i < HASH_KEYS; ++i) {
+    const uint64_t a = shockhash::fmix64(((uint64_t)s1 << 32) + i * 977u + s2);
+    alo[i] = (uint32_t)a;
+    ahi[i] = (uint32_t)(a >> 32);
+  }
+  const uint32_t n = (WIDE ? 48 : 32) - (s1 >> 8), nm1 = n - 1;  // s1 = 1: 48 or 32, unknown to the compiler
+  uint32_t tlo[2], thi[2], mlo[2] = {0, 0}, mhi[2] = {0, 0};
+  _Pragma("unroll") for (int j = 0; j < 2; ++j) {
+    const uint64_t t = shockhash::fmix64(threadIdx.x * 2 + j + s1);
+    tlo[j] = (uint32_t)t;
+    thi[j] = (uint32_t)(t >> 32);
+  }
+  for (int it = 0; it < ITERS; ++it) {
+    _Pragma("unroll") for (int i = 0; i < HASH_KEYS; ++i) {
+      _Pragma("unroll") for (int j = 0; j < 2; ++j) {
+        uint32_t h0, h1;
+        shockhash::slot_pair(alo[i], ahi[i], tlo[j], thi[j], n, nm1, h0, h1);
+        if (WIDE) {
+          const uint64_t b0 = 1ull << h0, b1 = 1ull << h1;
+          asm("v_or3_b32 %0, %0, %1, %2" : "+v"(mlo[j]) : "v"((uint32_t)b0), "v"((uint32_t)b1));
+          asm("v_or3_b32 %0, %0, %1, %2" : "+v"(mhi[j]) : "v"((uint32_t)(b0 >> 32)), "v"((uint32_t)(b1 >> 32)));
+        } else {
+          asm("v_or3_b32 %0, %0, %1, %2" : "+v"(mlo[j]) : "v"(1u << h0), "v"(1u << h1));
+        }
+      }
+    }
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) tlo[j] += 0x9E3779B9u;
+  }
+  out[blockIdx.x * 256 + threadIdx.x] = mlo[0] ^ mlo[1] ^ mhi[0] ^ mhi[1];
+}
+
+// The per-seed mix t(s) = fmix64((s + 1) * gamma) of consecutive seeds,
+// 4 chains per thread.  Counts seeds.
+__global__ __launch_bounds__(256) void k_seed_mix(uint32_t* out, uint32_t s1, uint32_t s2) {
+  uint64_t acc[4] = {0, 0, 0, 0};
+  uint64_t s = ((uint64_t)s2 << 32) + threadIdx.x * 4 + s1;
+  for (int it = 0; it < ITERS; ++it) {
+    _Pragma("unroll") for (int c = 0; c < 4; ++c) acc[c] ^= shockhash::seed_mix(s + c);
+    s += 256 * 4;
+  }
+  out[blockIdx.x * 256 + threadIdx.x] = (uint32_t)(acc[0] ^ acc[1] ^ acc[2] ^ acc[3]);
+}
+
 __global__ void k_empty(uint32_t* out) { if (threadIdx.x == 1000000) out[0] = 1; }
 
 __global__ void k_clock(uint64_t* out) {
@@ -78,6 +134,7 @@ int main() {
     {"v_cmp+v_addc (2 insts)", k_cmp_cnd, 2},
     {"v_mad_u64_u32", (kfn)k_mad_u64, 1}, {"v_lshlrev_b64", (kfn)k_lshl_b64, 1},
     {"v_lshl_add_u64", (kfn)k_lshl_add_u64, 1},
+    {"v_lshlrev_b32_e64 (1 << v)", k_lshl_one, 1},
   };
   hipEvent_t e0, e1; CHECK(hipEventCreate(&e0)); CHECK(hipEventCreate(&e1));
   const double peak_lane_ops = (double)p.multiProcessorCount * 64.0 * 2.4e9;
@@ -91,6 +148,28 @@ int main() {
     double lane_insts = 5.0 * blocks * 256.0 * ITERS * NCH * t.insts_per;
     double rate = lane_insts / (ms * 1e-3);
     printf("%-26s %.3e lane-inst/s  = %.3f of 256CU*64*2.4GHz\n", t.name, rate, rate / peak_lane_ops);
+    fflush(stdout);
+  }
+  // The search loop and the seed mix: throughput in the units the benchmark
+  // counts (key evaluations, seeds), and as lane-ops/s at 11 (64-bit mask) or
+  // 10 (32-bit mask) ops per evaluation.
+  struct L { const char* name; kfn f; double units_per_thread_iter; double ops_per_unit; };
+  L loops[] = {
+    {"hash loop, 64-bit mask (key-evals)", k_hash_loop<true>, HASH_KEYS * 2, 11},
+    {"hash loop, 32-bit mask (key-evals)", k_hash_loop<false>, HASH_KEYS * 2, 10},
+    {"seed mix (seeds)", k_seed_mix, 4, 1},
+  };
+  for (auto& t : loops) {
+    hipLaunchKernelGGL(t.f, dim3(blocks), dim3(256), 0, 0, out, 1u, 2u);
+    CHECK(hipDeviceSynchronize());
+    CHECK(hipEventRecord(e0));
+    for (int r = 0; r < 5; ++r) hipLaunchKernelGGL(t.f, dim3(blocks), dim3(256), 0, 0, out, 1u, 2u);
+    CHECK(hipEventRecord(e1)); CHECK(hipEventSynchronize(e1));
+    float ms; CHECK(hipEventElapsedTime(&ms, e0, e1));
+    double units = 5.0 * blocks * 256.0 * ITERS * t.units_per_thread_iter;
+    double rate = units / (ms * 1e-3);
+    printf("%-36s %.4e units/s  = %.4e lane-ops/s = %.4f of 256CU*64*2.4GHz\n", t.name, rate, rate * t.ops_per_unit,
+           rate * t.ops_per_unit / peak_lane_ops);
     fflush(stdout);
   }
   // launch overhead: back-to-back empty kernels
