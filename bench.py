@@ -143,30 +143,90 @@ def cpu_info():
     return model
 
 
+def host_threads() -> int:
+    """Threads the oracle may use: the cores this process may run on, at most
+    16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_leaves(keys, offs, order, budget_s, threads, gpu_seeds=None, gpu_orient=None, cap=None):
+    """Run the oracle on single leaves (in `order`) from `threads` host threads
+    until `budget_s` has passed (at least one leaf per thread).  With `cap`,
+    each leaf's search stops at that many seeds (leaves whose answer lies
+    beyond it count their cap seeds but not as leaves done).  Returns
+    (leaves done, seeds tested, key evaluations, seconds, all equal to the GPU)."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    lock = threading.Lock()
+    nxt = [0]
+    tot = {"leaves": 0, "seeds": 0, "evals": 0, "match": True}
+    t0 = time.perf_counter()
+
+    def work():
+        first = True
+        while True:
+            with lock:
+                if nxt[0] >= len(order) or (not first and time.perf_counter() - t0 >= budget_s):
+                    return
+                j = int(order[nxt[0]])
+                nxt[0] += 1
+            first = False
+            if cap is None:
+                rc, sv, fv = oracle.leaf_search(keys, offs[j:j + 2])
+            else:
+                rc, sv, fv = oracle.leaf_search(keys, offs[j:j + 2], max_seed=cap)
+            n = int(offs[j + 1] - offs[j])
+            found = rc == oracle.OK
+            tested = int(sv[0]) + 1 if found else cap
+            ok = gpu_seeds is None or (int(sv[0]) == int(gpu_seeds[j]) and int(fv[0]) == int(gpu_orient[j]))
+            with lock:
+                tot["leaves"] += int(found)
+                tot["seeds"] += tested
+                tot["evals"] += tested * n
+                tot["match"] &= bool(ok and found) if cap is None else True
+
+    with ThreadPoolExecutor(threads) as ex:
+        for f in [ex.submit(work) for _ in range(threads)]:
+            f.result()
+    return tot["leaves"], tot["seeds"], tot["evals"], time.perf_counter() - t0, tot["match"]
+
+
 def run_cpu_baseline(keys, offs, gpu_seeds, gpu_orient, budget_s):
-    """The oracle, single-threaded, on a bounded prefix of the same batch."""
+    """The oracle on the host's cores on a bounded sample of the same batch,
+    plus single-thread figures on this batch and on a prefix of each other
+    parity workload."""
     import oracle
 
     oracle.lib()
-    n_done = 0
-    t0 = time.perf_counter()
-    seeds_total = 0
-    match = True
+    threads = host_threads()
     L = len(offs) - 1
-    while n_done < L and time.perf_counter() - t0 < budget_s:
-        chunk = min(8, L - n_done)
-        sub = offs[n_done:n_done + chunk + 1]
-        rc, s, f = oracle.leaf_search(keys, sub)
-        seeds_total += int((s.astype(np.float64) + 1).sum())
-        match &= bool((s == gpu_seeds[n_done:n_done + chunk]).all() and (f == gpu_orient[n_done:n_done + chunk]).all())
-        n_done += chunk
-    dt = time.perf_counter() - t0
-    n = int(offs[1] - offs[0])
+    order = np.arange(L)
+    d, seeds, evals, dt, match = _oracle_leaves(keys, offs, order, budget_s, threads, gpu_seeds, gpu_orient)
+    d1, seeds1, evals1, dt1, match1 = _oracle_leaves(keys, offs, order, budget_s / 3, 1, gpu_seeds, gpu_orient)
+    per_config = {}
+    cap = 2_000_000  # seeds per leaf: about a second of one thread
+    for name in ("plain24", "fixed40", "uneven32_56", "hard60"):
+        kw, ow = make_workload(name, 4096)
+        dw, sw, ew, tw, _ = _oracle_leaves(kw, ow, np.arange(len(ow) - 1), budget_s / 6, 1, cap=cap)
+        per_config[name] = {"leaves_completed": dw, "seconds": tw, "leaves_per_s": dw / tw,
+                            "seeds_tested_per_s": sw / tw, "key_evals_per_s": ew / tw,
+                            "sample": f"leaves from the first on for {tw:.1f} s, one thread, each search stopped "
+                                      f"at {cap} seeds (leaves needing more are tested but not completed)"}
     return {
-        "value": n_done / dt, "unit": "leaves/s", "cores": 1, "kind": "oracle",
-        "sample": f"first {n_done} leaves of the same batch, oracle single-threaded ({dt:.1f} s)",
-        "seeds_tested_per_s": seeds_total / dt, "key_evals_per_s": seeds_total * n / dt,
-        "cpu": cpu_info(), "matches_gpu": match,
+        "value": d / dt, "unit": "leaves/s", "cores": threads, "kind": "oracle",
+        "sample": f"{d} leaves of the same batch from the first on, oracle on {threads} host threads ({dt:.1f} s)",
+        "seeds_tested_per_s": seeds / dt, "key_evals_per_s": evals / dt,
+        "cpu": cpu_info(), "nproc": os.cpu_count(), "matches_gpu": bool(match and match1),
+        "single_thread": {"leaves_per_s": d1 / dt1, "seeds_tested_per_s": seeds1 / dt1, "key_evals_per_s": evals1 / dt1,
+                          "sample": f"first {d1} leaves, one thread ({dt1:.1f} s)"},
+        "other_configs_single_thread": per_config,
     }
 
 
@@ -177,12 +237,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fixed48")
     ap.add_argument("--plain-leaves", type=int, default=1024)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of the all-core oracle run (the single-thread figures take as long again)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--spl", type=int, default=0)
     ap.add_argument("--block-iters", type=int, default=0)
     ap.add_argument("--waves-per-wg", type=int, default=0)
-    ap.add_argument("--serve-requests", type=int, default=60,
+    ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests per serving run (0 = skip the serving leg)")
     ap.add_argument("--untuned", action="store_true", help="ignore the autotuner's cached table for this device")
     ap.add_argument("--rf-steps", type=int, default=3,
@@ -196,6 +257,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the parity workloads plain24 (one launch per leaf), fixed40, uneven32_56 and hard60 "
                          "(each timed once by default)")
+    ap.add_argument("--graph-reps", type=int, default=50,
+                    help="calls per timing of the captured graph against eager enqueue (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -291,6 +354,43 @@ def main():
         plain = {"leaves": Lp, "leaves_per_s": Lp / wall_p, "kernel_ms": st_p["kernel_ms"],
                  "seeds_tested_per_s": st_p["seeds_tested"] / wall_p, "same_outputs_as_batched": same}
         log(f"[bench] plain per-leaf: {Lp / wall_p:.0f} leaves/s")
+
+    # Captured graph against eager enqueue: the same context and buffers, one
+    # search of the first L' leaves per call (enqueue + completion wait), for
+    # a small request (about 1e3 keys), a mid-size one (about 1e5) and the
+    # whole batch.
+    graph = None
+    if args.graph_reps > 0:
+        graph = {}
+        stream = torch.cuda.Stream(device=dev)
+        for Lg in (21, 2084, L):
+            ctx = shock.SearchContext(Lg)
+            o_g = o_d[:Lg + 1].clone()
+            s_g = torch.empty(Lg, dtype=torch.int64, device=dev)
+            f_g = torch.empty(Lg, dtype=torch.int64, device=dev)
+            gopts = {k: v for k, v in opts.items() if v}
+            gopts["leaf_size_hint"] = n or 48
+            reps = max(3, args.graph_reps if Lg < L else 3)
+            torch.cuda.synchronize()
+            if ctx.capture(k_d, o_g, s_g, f_g, stream=stream.cuda_stream, **gopts) != 0:
+                raise RuntimeError("graph capture failed")
+            times = {}
+            for how in ("eager", "graph", "eager", "graph"):  # warm both, keep the second round
+                t1 = time.perf_counter()
+                for _ in range(reps):
+                    if how == "eager":
+                        rc = ctx.search_async(k_d, o_g, s_g, f_g, stream=stream.cuda_stream, **gopts)
+                    else:
+                        rc = ctx.launch_graph(stream=stream.cuda_stream)
+                    if rc != 0 or ctx.wait()[0] != 0:
+                        raise RuntimeError(f"{how} search failed")
+                times[how] = (time.perf_counter() - t1) * 1e3 / reps
+            same = bool(torch.equal(s_g, seeds_d[:Lg]) and torch.equal(f_g, orient_d[:Lg]))
+            ctx.close()
+            graph[f"leaves_{Lg}"] = {"eager_ms": times["eager"], "graph_ms": times["graph"],
+                                     "graph_speedup": times["eager"] / times["graph"], "reps": reps,
+                                     "same_outputs": same}
+            log(f"[bench] {Lg} leaves: eager {times['eager']:.3f} ms, graph {times['graph']:.3f} ms per call")
 
     # Rotation fitting on the same batch: a different output (seed, rotation),
     # reported beside the plain search.
@@ -496,50 +596,62 @@ def main():
 
     # Serving: MPHF-build requests (log-uniform 1e3..1e6 keys, Poisson
     # arrivals) cut into 48-key leaves, continuous batching over 4 streams
-    # within a 256 MiB HBM budget.  Two runs over the same first K requests:
-    # the literal rate of 200 requests/s (far beyond one GPU's capacity, so
-    # queueing dominates) and a rate at 70% of the measured batched capacity.
+    # within a 256 MiB HBM budget.  Two runs over the same K requests: the
+    # literal rate of 200 requests/s (far beyond one GPU's capacity, so
+    # queueing dominates) and 70% of the capacity the same server measures on
+    # a backlog of the stream's first requests (all present at time 0).
     latency = None
     if args.serve_requests > 0:
-        from paper_2308_09561_amd.serving import LeafServer, synthetic_stream
+        from paper_2308_09561_amd.serving import LeafServer, MphfServer, synthetic_stream
         latency = {}
-        mean_leaves = None
-        for label, rate in (("rate_200_per_s", 200.0), ("rate_70pct_capacity", None)):
-            if rate is None:
-                rate = 0.7 * leaves_per_s / mean_leaves
-            reqs = synthetic_stream(args.serve_requests, rate_per_s=rate, seed=5)
-            mean_leaves = float(np.mean([(len(r.keys) + 47) // 48 for r in reqs]))
-            srv = LeafServer(hbm_budget_bytes=256 << 20, slots=4, leaf_size=48,
-                             search_opts={k: v for k, v in opts.items() if v})
-            log(f"[bench] serving {label}: {len(reqs)} requests at {rate:.1f}/s")
-            rep_s = srv.run(reqs, realtime=True)
+        backlog_n = min(200, args.serve_requests)
+
+        def capacity(make, label):
+            reqs = synthetic_stream(backlog_n, rate_per_s=1.0, seed=5)
+            srv = make()
+            rep = srv.run(reqs, realtime=False)
             srv.close()
-            summ = rep_s.summary()
+            summ = rep.summary()
+            cap = summ["completed"] / rep.makespan_s
+            log(f"[bench] {label} capacity: {cap:.1f} requests/s on a backlog of {backlog_n}")
+            return cap, summ
+
+        def serve(make, rate, label):
+            reqs = synthetic_stream(args.serve_requests, rate_per_s=rate, seed=5)
+            srv = make()
+            log(f"[bench] {label}: {len(reqs)} requests at {rate:.1f}/s")
+            rep = srv.run(reqs, realtime=True)
+            srv.close()
+            summ = rep.summary()
             summ["rate_per_s"] = rate
-            latency[label] = summ
             log(f"[bench]   p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, {summ['keys_per_s']:.3g} keys/s")
+            return summ
+
+        def leaf_server():
+            return LeafServer(hbm_budget_bytes=256 << 20, slots=4, leaf_size=48,
+                              search_opts={k: v for k, v in opts.items() if v})
+
+        cap, back = capacity(leaf_server, "leaf serving")
+        latency["backlog_capacity"] = {"requests_per_s": cap, "requests": backlog_n, "keys_per_s": back["keys_per_s"]}
+        latency["rate_200_per_s"] = serve(leaf_server, 200.0, "serving rate_200_per_s")
+        latency["rate_70pct_capacity"] = serve(leaf_server, 0.7 * cap, "serving rate_70pct_capacity")
         latency["p50_ms"] = latency["rate_70pct_capacity"]["p50_ms"]
         latency["p99_ms"] = latency["rate_70pct_capacity"]["p99_ms"]
         if mphf is not None:
             # The same requests served as complete MPHF builds with the leaf
-            # kind that built fastest, at 70% of its measured build capacity
-            # in keys/s.
-            from paper_2308_09561_amd.serving import MphfServer
+            # kind that built fastest, at 70% of that server's backlog capacity.
             kind = max(("rotation_fitting", "bipartite"), key=lambda k: mphf[k]["build_keys_per_s"])
-            reqs = synthetic_stream(args.serve_requests, rate_per_s=1.0, seed=5)
-            mean_keys = float(np.mean([len(r.keys) for r in reqs]))
-            rate = 0.7 * mphf[kind]["build_keys_per_s"] / mean_keys
-            reqs = synthetic_stream(args.serve_requests, rate_per_s=rate, seed=5)
-            srv = MphfServer(hbm_budget_bytes=256 << 20, slots=4, **{kind: True})
-            log(f"[bench] MPHF serving ({kind} leaves): {len(reqs)} requests at {rate:.1f}/s")
-            rep_m = srv.run(reqs, realtime=True)
-            srv.close()
-            summ = rep_m.summary()
-            summ["rate_per_s"] = rate
+
+            def mphf_server():
+                return MphfServer(hbm_budget_bytes=256 << 20, slots=4, **{kind: True})
+
+            cap_m, back_m = capacity(mphf_server, f"MPHF serving ({kind} leaves)")
+            summ = serve(mphf_server, 0.7 * cap_m, f"MPHF serving ({kind} leaves)")
             summ["leaves"] = kind
+            summ["backlog_capacity"] = {"requests_per_s": cap_m, "requests": backlog_n,
+                                        "keys_per_s": back_m["keys_per_s"]}
             latency["mphf_builds_70pct_capacity"] = summ
-            log(f"[bench]   p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, {summ['keys_per_s']:.3g} keys/s, "
-                f"{summ.get('bits_per_key', 0):.3f} bits/key")
+            log(f"[bench]   {summ.get('bits_per_key', 0):.3f} bits/key")
 
     cpu = None
     if not args.no_cpu:
@@ -612,6 +724,7 @@ def main():
         "plain_per_leaf": plain,
         "batched_vs_plain": (leaves_per_s / plain["leaves_per_s"]) if plain else None,
         "latency": latency,
+        "graph_vs_eager": graph,
         "rotation_fitting": rf,
         "bipartite": bip,
         "leaf_query_and_codes": code,
