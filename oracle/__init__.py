@@ -102,10 +102,26 @@ def lib():
                                              _u8p]
         L.shock_oracle_xor_get.restype = ctypes.c_int
         L.shock_oracle_xor_get.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, _u8p, _u8p]
+        L.shock_oracle_leaf_size_base.restype = ctypes.c_uint32
+        L.shock_oracle_leaf_size_base.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+        L.shock_oracle_gf2_solve.restype = ctypes.c_int
+        L.shock_oracle_gf2_solve.argtypes = [_u64p, _u8p, ctypes.c_uint64, ctypes.c_uint64, _u8p]
+        L.shock_oracle_ribbon_cols.restype = ctypes.c_uint64
+        L.shock_oracle_ribbon_cols.argtypes = [ctypes.c_uint64]
+        L.shock_oracle_ribbon_row.restype = None
+        L.shock_oracle_ribbon_row.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, _u64p, _u64p]
+        L.shock_oracle_ribbon_build.restype = ctypes.c_int
+        L.shock_oracle_ribbon_build.argtypes = [_u64p, _u8p, ctypes.c_uint64, ctypes.c_uint32,
+                                                ctypes.POINTER(ctypes.c_uint32), _u8p]
+        L.shock_oracle_ribbon_get.restype = ctypes.c_uint8
+        L.shock_oracle_ribbon_get.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, _u8p]
+        L.shock_oracle_mphf_ribbon.restype = ctypes.c_int
+        L.shock_oracle_mphf_ribbon.argtypes = [_u64p, _u8p, ctypes.c_uint64, _u64p, ctypes.c_uint32, _u8p, _u64p, _u8p]
         L.shock_oracle_mphf_query.restype = ctypes.c_int
         L.shock_oracle_mphf_query.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                               ctypes.c_uint64, _u64p, _u64p, _u32p, _u8p, _u64p, ctypes.c_int,
-                                              ctypes.c_uint32, ctypes.c_uint64, _u8p, _u64p]
+                                              ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64, _u8p, _u64p, _u8p,
+                                              _u64p]
         L.shock_oracle_bip_pair_rank.restype = ctypes.c_uint64
         L.shock_oracle_bip_pair_rank.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.shock_oracle_bip_slots.restype = None
@@ -326,7 +342,7 @@ def mphf_buckets(n_keys: int, bucket_size: int) -> int:
     return 1 if n_keys == 0 or bucket_size == 0 else -(-n_keys // bucket_size)
 
 
-def mphf_split(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: int = 56):
+def mphf_split(keys, bucket_size: int = 3000, leaf_target: int = 40, leaf_max: int = 56):
     """(status, dict) of the bucket/leaf layout: bucket_offset, leaf_base,
     sigma, leaf_sizes, leaf_keys, key_index, leaf_offsets (global key offsets)."""
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
@@ -349,6 +365,70 @@ def mphf_split(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: i
     np.cumsum(sizes.astype(np.uint64), out=offs[1:])
     return rc, {"n_buckets": B, "bucket_offset": bo, "leaf_base": lb, "sigma": sg, "leaf_sizes": sizes,
                 "leaf_keys": lk[:N], "key_index": ki[:N], "leaf_offsets": offs, "n_leaves": L}
+
+
+RETRIEVAL_RIBBON = 0
+RETRIEVAL_XOR = 1
+RIBBON_MAX_SEEDS = 256
+
+
+def leaf_size_base(m: int, n_leaves: int) -> int:
+    return int(lib().shock_oracle_leaf_size_base(m, n_leaves))
+
+
+def gf2_solve(rows, b, cols: int):
+    """(solvable, z uint8[cols]) of the system rows (uint64[m][ceil(cols/64)],
+    bit c = column c) x = b, z the canonical solution (non-pivot columns 0)."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    m = rows.shape[0] if rows.ndim == 2 else 0
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    z = np.zeros(max(cols, 1), np.uint8)
+    ok = lib().shock_oracle_gf2_solve(_p64(rows.reshape(-1)) if m else None, _p8(b) if m else None, m, cols, _p8(z))
+    if ok < 0:
+        raise MemoryError("gf2_solve")
+    return bool(ok), z[:cols]
+
+
+def ribbon_cols(m: int) -> int:
+    return int(lib().shock_oracle_ribbon_cols(m))
+
+
+def ribbon_row(key: int, rseed: int, cols: int) -> tuple[int, int]:
+    s, c = ctypes.c_uint64(), ctypes.c_uint64()
+    lib().shock_oracle_ribbon_row(key & 0xFFFFFFFFFFFFFFFF, rseed, cols, ctypes.byref(s), ctypes.byref(c))
+    return s.value, c.value
+
+
+def ribbon_build(keys, values, max_seeds: int = RIBBON_MAX_SEEDS):
+    """(status, rseed, z uint8[cols]) of one bucket's ribbon system."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    values = np.ascontiguousarray(values, dtype=np.uint8)
+    m = keys.size
+    z = np.zeros(max(ribbon_cols(m), 1), np.uint8)
+    r = ctypes.c_uint32()
+    rc = lib().shock_oracle_ribbon_build(_p64(keys) if m else None, _p8(values) if m else None, m, max_seeds,
+                                         ctypes.byref(r), _p8(z))
+    return rc, int(r.value), z[:ribbon_cols(m)]
+
+
+def ribbon_get(key: int, rseed: int, cols: int, z) -> int:
+    return int(lib().shock_oracle_ribbon_get(key & 0xFFFFFFFFFFFFFFFF, rseed, cols,
+                                             _p8(np.ascontiguousarray(z, np.uint8))))
+
+
+def mphf_ribbon(leaf_keys, values, bucket_offset, max_seeds: int = RIBBON_MAX_SEEDS):
+    """(status, rseed uint8[B], bit_offset uint64[B+1], z uint8[total]) of every bucket's system."""
+    lk = np.ascontiguousarray(leaf_keys, dtype=np.uint64)
+    v = np.ascontiguousarray(values, dtype=np.uint8)
+    bo = np.ascontiguousarray(bucket_offset, dtype=np.uint64)
+    B = bo.size - 1
+    total = sum(ribbon_cols(int(bo[b + 1] - bo[b])) for b in range(B))
+    rseed = np.zeros(max(B, 1), np.uint8)
+    boff = np.zeros(B + 1, np.uint64)
+    z = np.zeros(max(total, 1), np.uint8)
+    rc = lib().shock_oracle_mphf_ribbon(_p64(lk) if lk.size else None, _p8(v) if v.size else None, B, _p64(bo),
+                                        max_seeds, _p8(rseed), _p64(boff), _p8(z))
+    return rc, rseed[:B], boff, z[:total]
 
 
 def xor_segment(n_keys: int) -> int:
@@ -374,14 +454,15 @@ def xor_get(keys, rho: int, z):
     return out[:keys.size]
 
 
-def mphf_build(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: int = 56, rf: bool = False,
-               partial_k: int = 0, bip: bool = False):
+def mphf_build(keys, bucket_size: int = 3000, leaf_target: int = 40, leaf_max: int = 56, rf: bool = False,
+               partial_k: int = 0, bip: bool = False, retrieval: int = RETRIEVAL_RIBBON):
     """The whole flat MPHF: layout, leaf seeds and orientations (the leaf
     search, rotation fitting with values s * n + r, or with bip the bipartite
     search with values the rank of the pair (a, b) in its search order), the
-    retrieval of each key's choice, and every key's position (index i of the
-    input keys -> positions[i]).  With bip the positions come from the
-    oracle's own query (shock_oracle_mphf_query) over the built structure."""
+    retrieval of each key's choice (per-bucket ribbon systems, or the XOR
+    system), and every key's position (index i of the input keys ->
+    positions[i]).  With bip the positions come from the oracle's own query
+    (shock_oracle_mphf_query) over the built structure."""
     rc, lay = mphf_split(keys, bucket_size, leaf_target, leaf_max)
     if rc != OK:
         return rc, None
@@ -402,10 +483,16 @@ def mphf_build(keys, bucket_size: int = 2000, leaf_target: int = 40, leaf_max: i
     idx_in_leaf = np.arange(lk.size) - offs[:-1].astype(np.int64)[leaf_of_key] if lk.size else np.zeros(0, np.int64)
     f = ((orient[leaf_of_key] >> idx_in_leaf.astype(np.uint64)) & np.uint64(1)).astype(np.uint8) if lk.size \
         else np.zeros(0, np.uint8)
-    rc, rho, z = xor_build(lk, f)
+    rseed, rbit = np.zeros(0, np.uint8), np.zeros(1, np.uint64)
+    rho = 0
+    if retrieval == RETRIEVAL_RIBBON:
+        rc, rseed, rbit, z = mphf_ribbon(lk, f, lay["bucket_offset"])
+    else:
+        rc, rho, z = xor_build(lk, f)
     if rc != OK:
         return rc, None
-    lay.update({"seeds": seeds, "orient": orient, "choice": f, "rho": rho, "z": z,
+    lay.update({"seeds": seeds, "orient": orient, "choice": f, "rho": rho, "z": z, "retrieval": retrieval,
+                "rseed": rseed, "rbit_offset": rbit,
                 "leaf_target": leaf_target, "leaf_max": leaf_max, "bucket_size": bucket_size, "rf": bool(rf),
                 "partial_k": partial_k, "bip": bool(bip)})
     positions = np.zeros(lk.size, np.uint64)
@@ -432,8 +519,12 @@ def mphf_query(lay, queries):
                                        _p8(np.ascontiguousarray(lay["leaf_sizes"])),
                                        _p64(np.ascontiguousarray(lay["seeds"], dtype=np.uint64)),
                                        2 if lay.get("bip", False) else int(lay.get("rf", False)),
-                                       lay.get("partial_k", 0), lay["rho"], _p8(lay["z"]),
-                                       _p64(out))
+                                       lay.get("partial_k", 0), int(lay.get("retrieval", RETRIEVAL_XOR)),
+                                       lay["rho"], _p8(np.ascontiguousarray(lay.get("rseed", np.zeros(1, np.uint8)),
+                                                                            dtype=np.uint8)),
+                                       _p64(np.ascontiguousarray(lay.get("rbit_offset", np.zeros(1, np.uint64)),
+                                                                 dtype=np.uint64)),
+                                       _p8(np.ascontiguousarray(lay["z"], dtype=np.uint8)), _p64(out))
     return rc, out[:q.size]
 
 

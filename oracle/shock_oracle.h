@@ -194,7 +194,8 @@ int shock_oracle_bip_leaf_search(const uint64_t *keys, const uint64_t *offsets, 
  *   bucket(x) = hi64(fmix64(x ^ 0x5851F42D4C957F2D) * B);
  *   bucket i of m_i keys gets L_i = ceil(m_i / leaf_target) leaves;
  *   leaf(x, sigma, L) = (lo32(fmix64(x ^ fmix64((sigma + 1) * 0xD6E8FEB86659FD93))) * L) >> 32;
- *   sigma_i = the smallest sigma whose leaves all hold at most leaf_max keys;
+ *   sigma_i = the smallest sigma whose leaf sizes all lie in [base_i, base_i + 31]
+ *   (shock_oracle_leaf_size_base) and are at most leaf_max;
  *   leaves are numbered globally bucket by bucket, and a leaf's keys are
  *   sorted ascending (so the leaf search and its canonical orientation are
  *   defined by the key set alone).
@@ -209,6 +210,46 @@ int shock_oracle_mphf_split(const uint64_t *keys, uint64_t n_keys, uint32_t buck
                             uint32_t leaf_max, uint64_t n_buckets, uint64_t *bucket_offset, uint64_t *leaf_base,
                             uint32_t *sigma, uint8_t *leaf_sizes, uint64_t leaf_cap, uint64_t *leaf_keys,
                             uint64_t *key_index, uint64_t *n_leaves);
+
+/* Leaf sizes of a bucket of m keys split into n_leaves leaves lie in
+ * [base, base + 31] with base = max(0, floor(m / n_leaves) - 16), so each is
+ * stored in 5 bits; the splitting seed is the smallest one whose sizes all
+ * lie there and are at most leaf_max. */
+uint32_t shock_oracle_leaf_size_base(uint64_t m, uint32_t n_leaves);
+
+/* ---- Ribbon retrieval (Section 2's retrieval data structures; the paper
+ * uses BuRR, a bumped ribbon).  One linear system over GF(2) per bucket.
+ *
+ * gf2_solve: rows u64[m][ceil(cols / 64)] (bit c of row r is column c),
+ * right-hand sides b u8[m] (0/1).  Returns 1 and z u8[cols] if the system
+ * has a solution, 0 if not (-1 on allocation failure).  z is the canonical
+ * solution: every non-pivot column is 0, where the pivot columns are those
+ * not in the span of the columns before them (the reduced row echelon form
+ * with columns taken from 0 up; a solution with those zeros is unique).
+ *
+ * A bucket of m keys has cols(m) = max(64, m + ceil(m / 50)) columns (about
+ * 2 % more than keys; 0 if m = 0).  Key x's row under ribbon seed r: with
+ * h = fmix64(x ^ fmix64((r + 1) * 0x9E6C63D0676A9A99)), start
+ * s = (hi32(h) * (cols - 63)) >> 32 and coefficient c = fmix64(h) | 1 (bit 0
+ * set), the row holds c's bits at columns s .. s + 63.  The bucket's seed is
+ * the smallest r < max_seeds whose system (values = the keys' choices) has a
+ * solution; its bits are the canonical solution.  The value of x is the
+ * parity of c AND z[s .. s + 63]. */
+int shock_oracle_gf2_solve(const uint64_t *rows, const uint8_t *b, uint64_t m, uint64_t cols, uint8_t *z);
+uint64_t shock_oracle_ribbon_cols(uint64_t m);
+void shock_oracle_ribbon_row(uint64_t x, uint32_t rseed, uint64_t cols, uint64_t *start, uint64_t *coef);
+int shock_oracle_ribbon_build(const uint64_t *keys, const uint8_t *values, uint64_t m, uint32_t max_seeds,
+                              uint32_t *rseed, uint8_t *z);
+uint8_t shock_oracle_ribbon_get(uint64_t x, uint32_t rseed, uint64_t cols, const uint8_t *z);
+/* Every bucket's system: keys in leaf order (bucket b = leaf_keys[bucket_offset[b] ..
+ * bucket_offset[b+1])), values u8[N]; out rseed u8[B], bit_offset u64[B+1]
+ * (prefix sums of cols), z u8[bit_offset[B]]. */
+int shock_oracle_mphf_ribbon(const uint64_t *leaf_keys, const uint8_t *values, uint64_t n_buckets,
+                             const uint64_t *bucket_offset, uint32_t max_seeds, uint8_t *rseed,
+                             uint64_t *bit_offset, uint8_t *z);
+
+#define SHOCK_ORACLE_RETRIEVAL_RIBBON 0
+#define SHOCK_ORACLE_RETRIEVAL_XOR 1
 
 /* 1-bit retrieval by a 3-hypergraph XOR system (a simpler stand-in for the
  * ribbon retrieval of Section 2): M = 3 * seg cells, seg = ceil(1.23 N / 3) + 8,
@@ -237,11 +278,16 @@ int shock_oracle_xor_get(const uint64_t *keys, uint64_t n_keys, uint64_t rho, co
  * shock_oracle_rf_slots with period partial_k; 0 = 8 above 32 keys, else 1),
  * or with rf = 2 the bipartite pair (a, b) stored as its rank
  * shock_oracle_bip_pair_rank(a, b): key x's two candidate cells are then the
- * left cell of x under a and the right cell of x under b. */
+ * left cell of x under a and the right cell of x under b.  f(x) comes from
+ * the ribbon systems (retrieval = SHOCK_ORACLE_RETRIEVAL_RIBBON: rseed u8[B],
+ * rbit_offset u64[B+1], z their bits) or from the XOR system (retrieval =
+ * SHOCK_ORACLE_RETRIEVAL_XOR: rho and z its cells; rseed and rbit_offset
+ * unused). */
 int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_t n_keys, uint32_t leaf_target,
                             uint64_t n_buckets, const uint64_t *bucket_offset, const uint64_t *leaf_base,
                             const uint32_t *sigma, const uint8_t *leaf_sizes, const uint64_t *leaf_values,
-                            int rf, uint32_t partial_k, uint64_t rho, const uint8_t *z, uint64_t *out_pos);
+                            int rf, uint32_t partial_k, int retrieval, uint64_t rho, const uint8_t *rseed,
+                            const uint64_t *rbit_offset, const uint8_t *z, uint64_t *out_pos);
 
 /* Statistics helper: over seeds s0 .. s0+count-1 of one leaf of n keys, count
  * the seeds whose slots cover all n cells and, among them, the pseudoforests.

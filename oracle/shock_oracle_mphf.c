@@ -19,6 +19,12 @@ static uint32_t leaf_of(uint64_t x, uint32_t sigma, uint32_t n_leaves) {
   return (uint32_t)(((uint64_t)(uint32_t)h * n_leaves) >> 32);
 }
 
+uint32_t shock_oracle_leaf_size_base(uint64_t m, uint32_t n_leaves) {
+  if (n_leaves == 0) return 0;
+  uint64_t mean = m / n_leaves;
+  return mean > 16 ? (uint32_t)(mean - 16) : 0;
+}
+
 static int cmp_u64(const void *a, const void *b) {
   uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
   return x < y ? -1 : x > y ? 1 : 0;
@@ -63,7 +69,9 @@ int shock_oracle_mphf_split(const uint64_t *keys, uint64_t n_keys, uint32_t buck
       rc = SHOCK_ORACLE_EINVAL;
       break;
     }
-    /* smallest splitting seed whose leaves all fit */
+    /* smallest splitting seed whose leaf sizes all lie in [lo, lo + 31] and
+     * at most leaf_max */
+    uint32_t lo = shock_oracle_leaf_size_base(m, L);
     uint32_t s = 0;
     for (;; ++s) {
       if (s >= (1u << 16)) {
@@ -71,11 +79,10 @@ int shock_oracle_mphf_split(const uint64_t *keys, uint64_t n_keys, uint32_t buck
         break;
       }
       for (uint32_t j = 0; j < L; ++j) count[j] = 0;
+      for (uint64_t i = 0; i < m; ++i) count[leaf_of(grouped[o + i], s, L)] += 1;
       int fits = 1;
-      for (uint64_t i = 0; i < m; ++i) {
-        uint32_t j = leaf_of(grouped[o + i], s, L);
-        if (++count[j] > leaf_max) fits = 0;
-      }
+      for (uint32_t j = 0; j < L; ++j)
+        if (count[j] > leaf_max || count[j] < lo || count[j] > lo + 31) fits = 0;
       if (fits) break;
     }
     if (rc != SHOCK_ORACLE_OK) break;
@@ -203,6 +210,130 @@ int shock_oracle_xor_get(const uint64_t *keys, uint64_t n_keys, uint64_t rho, co
   return SHOCK_ORACLE_OK;
 }
 
+/* ---- ribbon retrieval -------------------------------------------------------- */
+
+int shock_oracle_gf2_solve(const uint64_t *rows_in, const uint8_t *b_in, uint64_t m, uint64_t cols, uint8_t *z) {
+  uint64_t W = (cols + 63) / 64;
+  uint64_t *a = (uint64_t *)malloc(sizeof(uint64_t) * (m * W + 1));
+  uint8_t *b = (uint8_t *)malloc(m + 1);
+  uint64_t *pivot_col = (uint64_t *)malloc(sizeof(uint64_t) * (m + 1));
+  if (!a || !b || !pivot_col) return -1;
+  if (m) {
+    memcpy(a, rows_in, sizeof(uint64_t) * m * W);
+    memcpy(b, b_in, m);
+  }
+  /* Gauss-Jordan elimination, columns from 0 up: a column with no remaining
+   * row holding it is free; otherwise that row becomes the column's pivot
+   * row and the column is cleared from every other row. */
+  uint64_t rank = 0;
+  for (uint64_t c = 0; c < cols && rank < m; ++c) {
+    uint64_t w = c >> 6, bit = 1ULL << (c & 63);
+    uint64_t p = rank;
+    while (p < m && !(a[p * W + w] & bit)) ++p;
+    if (p == m) continue;
+    if (p != rank) {
+      for (uint64_t q = 0; q < W; ++q) {
+        uint64_t t = a[p * W + q];
+        a[p * W + q] = a[rank * W + q];
+        a[rank * W + q] = t;
+      }
+      uint8_t t = b[p];
+      b[p] = b[rank];
+      b[rank] = t;
+    }
+    for (uint64_t r = 0; r < m; ++r) {
+      if (r == rank || !(a[r * W + w] & bit)) continue;
+      for (uint64_t q = 0; q < W; ++q) a[r * W + q] ^= a[rank * W + q];
+      b[r] ^= b[rank];
+    }
+    pivot_col[rank] = c;
+    ++rank;
+  }
+  /* rows beyond the rank are zero: the system is consistent iff their
+   * right-hand sides are 0 */
+  int ok = 1;
+  for (uint64_t r = rank; r < m; ++r)
+    if (b[r] & 1) ok = 0;
+  if (ok) {
+    memset(z, 0, cols);
+    for (uint64_t r = 0; r < rank; ++r) z[pivot_col[r]] = b[r] & 1;
+  }
+  free(a);
+  free(b);
+  free(pivot_col);
+  return ok;
+}
+
+uint64_t shock_oracle_ribbon_cols(uint64_t m) {
+  if (m == 0) return 0;
+  uint64_t c = m + (m + 49) / 50;
+  return c < 64 ? 64 : c;
+}
+
+void shock_oracle_ribbon_row(uint64_t x, uint32_t rseed, uint64_t cols, uint64_t *start, uint64_t *coef) {
+  uint64_t h = shock_oracle_fmix64(x ^ shock_oracle_fmix64(((uint64_t)rseed + 1) * 0x9E6C63D0676A9A99ULL));
+  *start = ((h >> 32) * (cols - 63)) >> 32;
+  *coef = shock_oracle_fmix64(h) | 1;
+}
+
+int shock_oracle_ribbon_build(const uint64_t *keys, const uint8_t *values, uint64_t m, uint32_t max_seeds,
+                              uint32_t *rseed, uint8_t *z) {
+  if (m == 0) {
+    *rseed = 0;
+    return SHOCK_ORACLE_OK;
+  }
+  uint64_t cols = shock_oracle_ribbon_cols(m), W = (cols + 63) / 64;
+  uint64_t *rows = (uint64_t *)malloc(sizeof(uint64_t) * m * W);
+  if (!rows) return SHOCK_ORACLE_EINVAL;
+  int rc = SHOCK_ORACLE_ENOTFOUND;
+  for (uint32_t r = 0; r < max_seeds; ++r) {
+    memset(rows, 0, sizeof(uint64_t) * m * W);
+    for (uint64_t i = 0; i < m; ++i) {
+      uint64_t s, c;
+      shock_oracle_ribbon_row(keys[i], r, cols, &s, &c);
+      for (uint32_t k = 0; k < 64; ++k)
+        if ((c >> k) & 1) rows[i * W + ((s + k) >> 6)] |= 1ULL << ((s + k) & 63);
+    }
+    int ok = shock_oracle_gf2_solve(rows, values, m, cols, z);
+    if (ok < 0) {
+      rc = SHOCK_ORACLE_EINVAL;
+      break;
+    }
+    if (ok) {
+      *rseed = r;
+      rc = SHOCK_ORACLE_OK;
+      break;
+    }
+  }
+  free(rows);
+  return rc;
+}
+
+uint8_t shock_oracle_ribbon_get(uint64_t x, uint32_t rseed, uint64_t cols, const uint8_t *z) {
+  uint64_t s, c;
+  shock_oracle_ribbon_row(x, rseed, cols, &s, &c);
+  uint8_t v = 0;
+  for (uint32_t k = 0; k < 64; ++k)
+    if ((c >> k) & 1) v ^= z[s + k];
+  return v;
+}
+
+int shock_oracle_mphf_ribbon(const uint64_t *leaf_keys, const uint8_t *values, uint64_t n_buckets,
+                             const uint64_t *bucket_offset, uint32_t max_seeds, uint8_t *rseed,
+                             uint64_t *bit_offset, uint8_t *z) {
+  bit_offset[0] = 0;
+  for (uint64_t b = 0; b < n_buckets; ++b)
+    bit_offset[b + 1] = bit_offset[b] + shock_oracle_ribbon_cols(bucket_offset[b + 1] - bucket_offset[b]);
+  for (uint64_t b = 0; b < n_buckets; ++b) {
+    uint64_t o = bucket_offset[b], m = bucket_offset[b + 1] - o;
+    uint32_t r = 0;
+    int rc = shock_oracle_ribbon_build(leaf_keys + o, values + o, m, max_seeds, &r, z + bit_offset[b]);
+    if (rc != SHOCK_ORACLE_OK) return rc;
+    rseed[b] = (uint8_t)r;
+  }
+  return SHOCK_ORACLE_OK;
+}
+
 /* The pairs of bipartite seeds in the search order (by max(a, b) = m, then a,
  * then b): for each m, first (a, m) for a = 0 .. m-1, then (m, b) for
  * b = 0 .. m.  The m^2 pairs with a smaller maximum come before them, so the
@@ -232,7 +363,8 @@ static void bip_pair_of_rank(uint64_t v, uint64_t *a, uint64_t *b) {
 int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_t n_keys, uint32_t leaf_target,
                             uint64_t n_buckets, const uint64_t *bucket_offset, const uint64_t *leaf_base,
                             const uint32_t *sigma, const uint8_t *leaf_sizes, const uint64_t *leaf_values,
-                            int rf, uint32_t partial_k, uint64_t rho, const uint8_t *z, uint64_t *out_pos) {
+                            int rf, uint32_t partial_k, int retrieval, uint64_t rho, const uint8_t *rseed,
+                            const uint64_t *rbit_offset, const uint8_t *z, uint64_t *out_pos) {
   uint64_t seg = shock_oracle_xor_segment(n_keys);
   for (uint64_t q = 0; q < n_queries; ++q) {
     uint64_t x = queries[q];
@@ -247,9 +379,14 @@ int shock_oracle_mphf_query(const uint64_t *queries, uint64_t n_queries, uint64_
     uint64_t start = bucket_offset[b];
     for (uint32_t jj = 0; jj < j; ++jj) start += leaf_sizes[leaf_base[b] + jj];
     uint32_t n = leaf_sizes[leaf_base[b] + j];
-    uint64_t c[3];
-    xor_cells(x, rho, seg, c);
-    int f = z[c[0]] ^ z[c[1]] ^ z[c[2]];
+    int f;
+    if (retrieval == SHOCK_ORACLE_RETRIEVAL_RIBBON) {
+      f = shock_oracle_ribbon_get(x, rseed[b], shock_oracle_ribbon_cols(m), z + rbit_offset[b]);
+    } else {
+      uint64_t c[3];
+      xor_cells(x, rho, seg, c);
+      f = z[c[0]] ^ z[c[1]] ^ z[c[2]];
+    }
     uint32_t h0 = 0, h1 = 0;
     uint64_t v = leaf_values[leaf_base[b] + j];
     if (rf == 2 && n >= 1) {
