@@ -16,6 +16,9 @@ SHOCK_EHIP = -5
 SHOCK_ENOMEM = -6
 SHOCK_EPENDING = -7
 
+SHOCK_RETRIEVAL_RIBBON = 0
+SHOCK_RETRIEVAL_XOR = 1
+
 SHOCK_MODE_AUTO = 0
 SHOCK_MODE_PLAIN_PER_LEAF = 1
 SHOCK_MODE_PERSISTENT = 2
@@ -31,6 +34,7 @@ EXPORTED = [
     "shock_ctx_graph_capture", "shock_ctx_graph_launch", "shock_rf_leaf_search_ex", "shock_ctx_rf_search_async",
     "shock_leaf_query", "shock_rf_leaf_query", "shock_rice_encode", "shock_rice_decode",
     "shock_mphf_params_init", "shock_mphf_build", "shock_mphf_query", "shock_mphf_info", "shock_mphf_export",
+    "shock_mphf_export_ribbon",
     "shock_mphf_destroy", "shock_bip_leaf_search_ex", "shock_leaf_search_noalloc",
     "shock_leaf_search_async", "shock_rf_leaf_search_async", "shock_stream_status", "shock_queue_params_init",
     "shock_queue_batch_bytes", "shock_queue_create", "shock_submit", "shock_poll", "shock_cancel",
@@ -130,7 +134,7 @@ class MphfParams(ctypes.Structure):
         ("rotation_fitting", ctypes.c_uint32),
         ("partial_k", ctypes.c_int32),
         ("bipartite", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32),
+        ("retrieval", ctypes.c_uint32),
         ("reserved", ctypes.c_uint64 * 2),
     ]
 
@@ -145,7 +149,8 @@ class MphfStats(ctypes.Structure):
         ("bits_retrieval", ctypes.c_uint64), ("bits_total", ctypes.c_uint64),
         ("build_ms", ctypes.c_double), ("search_ms", ctypes.c_double),
         ("layout_ms", ctypes.c_double), ("search_call_ms", ctypes.c_double), ("codes_ms", ctypes.c_double),
-        ("retrieval_ms", ctypes.c_double), ("rho_tries", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+        ("retrieval_ms", ctypes.c_double), ("rho_tries", ctypes.c_uint32), ("retrieval", ctypes.c_uint32),
+        ("max_rseed", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
     ]
 
     def as_dict(self):
@@ -226,6 +231,8 @@ def lib():
         L.shock_mphf_info.argtypes = [vp, ctypes.POINTER(MphfStats)]
         L.shock_mphf_export.restype = ctypes.c_int
         L.shock_mphf_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.shock_mphf_export_ribbon.restype = ctypes.c_int
+        L.shock_mphf_export_ribbon.argtypes = [vp, vp, vp, vp]
         L.shock_mphf_destroy.restype = ctypes.c_int
         L.shock_mphf_destroy.argtypes = [vp]
         L.shock_bip_leaf_search_ex.restype = ctypes.c_int
@@ -744,8 +751,8 @@ class MPHF:
     """A minimal perfect hash function of distinct uint64 keys, built and
     queried on the GPU.  Raises ShockError if the build fails."""
 
-    def __init__(self, keys, bucket_size=2000, leaf_target=40, leaf_max=56, rice_table=None, stream=None,
-                 rotation_fitting=False, partial_k=0, bipartite=False):
+    def __init__(self, keys, bucket_size=3000, leaf_target=40, leaf_max=56, rice_table=None, stream=None,
+                 rotation_fitting=False, partial_k=0, bipartite=False, retrieval=SHOCK_RETRIEVAL_RIBBON):
         import numpy as np
         if keys.device.type != "cuda" or keys.dtype.itemsize != 8:
             raise ValueError("keys must be a 64-bit device tensor")
@@ -758,6 +765,7 @@ class MPHF:
         p.bucket_size, p.leaf_target, p.leaf_max = bucket_size, leaf_target, leaf_max
         p.rotation_fitting, p.partial_k = int(bool(rotation_fitting)), partial_k
         p.bipartite = int(bool(bipartite))
+        p.retrieval = retrieval
         table = _table(rice_table)
         p.rice_k_by_n = ctypes.cast(table, ctypes.c_void_p)
         self._h = ctypes.c_void_p()
@@ -798,13 +806,26 @@ class MPHF:
         sg = np.zeros(max(B, 1), np.uint32)
         sz = np.zeros(max(L, 1), np.uint8)
         sd = np.zeros(max(L, 1), np.uint64)
-        z = np.zeros(3 * st["seg"], np.uint8)
+        xor = st["retrieval"] == SHOCK_RETRIEVAL_XOR
+        z = np.zeros(max(3 * st["seg"], 1), np.uint8)
         rc = lib().shock_mphf_export(self._h, bo.ctypes.data, lb.ctypes.data, sg.ctypes.data, sz.ctypes.data,
-                                     sd.ctypes.data, z.ctypes.data)
+                                     sd.ctypes.data, z.ctypes.data if xor else None)
         if rc != SHOCK_OK:
             raise ShockError(rc, shock_strerror(rc))
-        return {"bucket_offset": bo, "leaf_base": lb, "sigma": sg[:B], "leaf_sizes": sz[:L], "seeds": sd[:L],
-                "z": z, "rho": st["rho"], "seg": st["seg"]}
+        out = {"bucket_offset": bo, "leaf_base": lb, "sigma": sg[:B], "leaf_sizes": sz[:L], "seeds": sd[:L],
+               "rho": st["rho"], "seg": st["seg"], "retrieval": st["retrieval"]}
+        if xor:
+            out["z"] = z[:3 * st["seg"]]
+        else:
+            rs = np.zeros(max(B, 1), np.uint8)
+            rb = np.zeros(B + 1, np.uint64)
+            lib().shock_mphf_export_ribbon(self._h, rs.ctypes.data, rb.ctypes.data, None)
+            bits = np.zeros(max(int(rb[-1]), 1), np.uint8)
+            rc = lib().shock_mphf_export_ribbon(self._h, None, None, bits.ctypes.data)
+            if rc != SHOCK_OK:
+                raise ShockError(rc, shock_strerror(rc))
+            out.update({"rseed": rs[:B], "rbit_offset": rb, "z": bits[:int(rb[-1])]})
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

@@ -46,6 +46,74 @@ constexpr uint32_t kMaxSigma = 1u << 16;
 
 constexpr uint64_t kErrTooManyLeaves = 1;
 constexpr uint64_t kErrSigma = 2;
+constexpr uint64_t kErrRibbon = 4;    // a bucket's ribbon system has no seed below kRibbonSeeds
+constexpr uint64_t kErrCodeSpan = 8;  // a block of buckets spans 2^32 code bits or more
+constexpr uint64_t kErrRibbonInternal = 16;  // internal: a bucket larger than the ribbon launch's LDS, or a walk past its band
+
+// Ribbon retrieval: one GF(2) system per bucket (about 2 % more columns than
+// keys, 64-bit coefficient rows), the smallest seed below kRibbonSeeds whose
+// system is solvable, and its canonical solution (non-pivot columns 0).
+constexpr uint64_t kRibbonMul = 0x9E6C63D0676A9A99ull;
+constexpr uint32_t kRibbonSeeds = 256;
+constexpr uint32_t kRetrievalRibbon = 0, kRetrievalXor = 1;
+
+// The bucket table: blocks of 16 buckets hold absolute offsets, buckets hold
+// 32-bit offsets relative to their block.
+constexpr uint32_t kBlockShift = 4;
+enum : uint32_t { kBkKey = 0, kBkLeaf, kBkRib, kBkFixed, kBkUnary, kBkWords };
+
+// Leaf sizes are 5-bit codes: a bucket of m keys in L leaves has every leaf
+// size in [base, base + 31], base = max(0, floor(m / L) - 16).
+__host__ __device__ __forceinline__ uint32_t size_base(uint64_t m, uint32_t L) {
+  if (L == 0) return 0;
+  const uint64_t mean = m / L;
+  return mean > 16 ? (uint32_t)(mean - 16) : 0u;
+}
+__host__ __device__ __forceinline__ uint64_t ribbon_cols(uint64_t m) {
+  if (m == 0) return 0;
+  const uint64_t c = m + (m + 49) / 50;
+  return c < 64 ? 64 : c;
+}
+__device__ __forceinline__ uint64_t ribbon_mix(uint32_t rseed) { return fmix64(((uint64_t)rseed + 1) * kRibbonMul); }
+// Key x's row: coefficient c (bit 0 set) at columns s .. s + 63 of its bucket's system.
+__device__ __forceinline__ void ribbon_row(uint64_t x, uint64_t rmix, uint64_t cols, uint64_t &s, uint64_t &c) {
+  const uint64_t h = fmix64(x ^ rmix);
+  s = ((h >> 32) * (cols - 63)) >> 32;
+  c = fmix64(h) | 1;
+}
+// 64 bits of a bit array from bit p on (bits past `words` words read as 0).
+__device__ __forceinline__ uint64_t bits_at(const uint64_t *v, uint64_t words, uint64_t p) {
+  const uint64_t w = p >> 6;
+  const uint32_t sh = (uint32_t)(p & 63);
+  uint64_t x = w < words ? v[w] >> sh : 0;
+  if (sh && w + 1 < words) x |= v[w + 1] << (64 - sh);
+  return x;
+}
+// The 5-bit code of leaf g.
+__device__ __forceinline__ uint32_t size_code(const uint64_t *codes, uint64_t g) {
+  const uint64_t p = 5 * g, w = p >> 6;
+  const uint32_t sh = (uint32_t)(p & 63);
+  uint64_t x = codes[w] >> sh;
+  if (sh > 59) x |= codes[w + 1] << (64 - sh);
+  return (uint32_t)(x & 31);
+}
+// Sum of the codes of leaves [a, b): per word, bit t is bit (t + 64 w) mod 5
+// of its field, so the sum is that of the masked popcounts times their weights.
+constexpr uint64_t kField0 = 0x1084210842108421ull;  // bits 0, 5, .., 60
+__device__ __forceinline__ uint32_t code_sum(const uint64_t *codes, uint64_t a, uint64_t b) {
+  uint32_t sum = 0;
+  const uint64_t p0 = 5 * a, p1 = 5 * b;
+  for (uint64_t w = p0 >> 6; (w << 6) < p1; ++w) {
+    const uint64_t wb = w << 6;
+    uint64_t x = codes[w];
+    if (wb < p0) x &= ~0ull << (p0 - wb);
+    if (p1 - wb < 64) x &= (1ull << (p1 - wb)) - 1;
+    const uint32_t ph = (uint32_t)(wb % 5);
+#pragma unroll
+    for (uint32_t r = 0; r < 5; ++r) sum += (uint32_t)__popcll(x & (kField0 << ((r + 5 - ph) % 5))) << r;
+  }
+  return sum;
+}
 
 struct KTable {
   uint8_t k[65];
@@ -106,14 +174,15 @@ __global__ void bucket_count_kernel(const uint64_t *__restrict__ keys, uint64_t 
 // workgroup of 1024 threads, 16 buckets per thread and chunk.
 __global__ __launch_bounds__(1024) void layout_scan_kernel(const uint32_t *counts, uint64_t n_buckets,
                                                            uint32_t leaf_target, uint64_t *bucket_offset,
-                                                           uint64_t *leaf_base, unsigned long long *err) {
+                                                           uint64_t *leaf_base, uint64_t *rib_base,
+                                                           unsigned long long *err) {
   constexpr uint32_t kPer = 16;
-  __shared__ uint64_t wm[16], wl[16];
+  __shared__ uint64_t wm[16], wl[16], wr[16];
   const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  uint64_t carry_m = 0, carry_l = 0;
+  uint64_t carry_m = 0, carry_l = 0, carry_r = 0, most = 0;
   for (uint64_t c = 0; c < n_buckets; c += 1024ull * kPer) {
     const uint64_t b0 = c + (uint64_t)t * kPer;
-    uint64_t sm = 0, sl = 0;
+    uint64_t sm = 0, sl = 0, sr = 0;
     for (uint32_t e = 0; e < kPer; ++e) {
       const uint64_t b = b0 + e;
       if (b < n_buckets) {
@@ -121,41 +190,51 @@ __global__ __launch_bounds__(1024) void layout_scan_kernel(const uint32_t *count
         if (l > kMaxLeavesPerBucket) atomicOr(err, kErrTooManyLeaves);
         sm += m;
         sl += l;
+        sr += ribbon_cols(m);
+        most = m > most ? m : most;
       }
     }
-    const uint64_t xm = wave_excl_scan(sm), xl = wave_excl_scan(sl);
+    const uint64_t xm = wave_excl_scan(sm), xl = wave_excl_scan(sl), xr = wave_excl_scan(sr);
     if (lane == 63) {
       wm[wave] = xm + sm;
       wl[wave] = xl + sl;
+      wr[wave] = xr + sr;
     }
     __syncthreads();
-    uint64_t pm = 0, pl = 0, tm = 0, tl = 0;
+    uint64_t pm = 0, pl = 0, pr = 0, tm = 0, tl = 0, tr = 0;
     for (uint32_t w = 0; w < 16; ++w) {
       if (w < wave) {
         pm += wm[w];
         pl += wl[w];
+        pr += wr[w];
       }
       tm += wm[w];
       tl += wl[w];
+      tr += wr[w];
     }
-    uint64_t rm = carry_m + pm + xm, rl = carry_l + pl + xl;
+    uint64_t rm = carry_m + pm + xm, rl = carry_l + pl + xl, rr = carry_r + pr + xr;
     for (uint32_t e = 0; e < kPer; ++e) {
       const uint64_t b = b0 + e;
       if (b < n_buckets) {
         const uint64_t m = counts[b];
         bucket_offset[b] = rm;
         leaf_base[b] = rl;
+        rib_base[b] = rr;
         rm += m;
         rl += (m + leaf_target - 1) / leaf_target;
+        rr += ribbon_cols(m);
       }
     }
     carry_m += tm;
     carry_l += tl;
+    carry_r += tr;
     __syncthreads();
   }
+  if (most) atomicMax(err + 1, (unsigned long long)most);  // the largest bucket, for the ribbon's LDS
   if (t == 0) {
     bucket_offset[n_buckets] = carry_m;
     leaf_base[n_buckets] = carry_l;
+    rib_base[n_buckets] = carry_r;
   }
 }
 
@@ -220,9 +299,9 @@ __global__ __launch_bounds__(256) void bucket_scatter_lds_kernel(const uint64_t 
 __global__ __launch_bounds__(256) void split_kernel(const uint64_t *__restrict__ grouped,
                                                     const uint64_t *__restrict__ bucket_offset,
                                                     const uint64_t *__restrict__ leaf_base, uint64_t n_buckets,
-                                                    uint32_t leaf_max, uint32_t *sigma, uint8_t *leaf_sizes,
-                                                    uint64_t *leaf_off, uint64_t *__restrict__ leaf_keys,
-                                                    unsigned long long *err) {
+                                                    uint32_t leaf_max, uint16_t *sigma, uint8_t *leaf_sizes,
+                                                    uint8_t *leaf_codes, uint64_t *leaf_off,
+                                                    uint64_t *__restrict__ leaf_keys, unsigned long long *err) {
   __shared__ uint32_t bins_all[4][kMaxLeavesPerBucket];
   const uint32_t lane = lane_id();
   uint32_t *bins = bins_all[threadIdx.x >> 6];
@@ -236,6 +315,8 @@ __global__ __launch_bounds__(256) void split_kernel(const uint64_t *__restrict__
       continue;
     }
     if (L > kMaxLeavesPerBucket) continue;  // flagged by the scan
+    // the smallest seed whose leaf sizes all lie in [lo, lo + 31] and at most leaf_max
+    const uint32_t lo = size_base(m, L), hi = lo + 31 < leaf_max ? lo + 31 : leaf_max;
     uint32_t s = 0;
     bool found = false;
     for (; s < kMaxSigma; ++s) {
@@ -245,9 +326,10 @@ __global__ __launch_bounds__(256) void split_kernel(const uint64_t *__restrict__
       bool over = false;
       for (uint64_t i = lane; i < m; i += 64) {
         const uint32_t c = atomicAdd(&bins[leaf_of(grouped[o + i], tm, L)], 1u) + 1;
-        over |= c > leaf_max;
+        over |= c > hi;
       }
       wave_sync();
+      for (uint32_t j = lane; j < L; j += 64) over |= bins[j] < lo;
       if (__ballot(over) == 0) {
         found = true;
         break;
@@ -257,7 +339,7 @@ __global__ __launch_bounds__(256) void split_kernel(const uint64_t *__restrict__
       if (lane == 0) atomicOr(err, kErrSigma);
       continue;
     }
-    if (lane == 0) sigma[b] = s;
+    if (lane == 0) sigma[b] = (uint16_t)s;
     // sizes -> exclusive starts (in place), chunk by chunk of 64 leaves
     uint64_t carry = 0;
     for (uint32_t j0 = 0; j0 < L; j0 += 64) {
@@ -266,6 +348,7 @@ __global__ __launch_bounds__(256) void split_kernel(const uint64_t *__restrict__
       const uint64_t start = carry + wave_excl_scan(sz);
       if (j < L) {
         leaf_sizes[lb + j] = (uint8_t)sz;
+        leaf_codes[lb + j] = (uint8_t)(sz - lo);
         leaf_off[lb + j] = o + start;
         bins[j] = (uint32_t)start;
       }
@@ -356,6 +439,232 @@ __global__ void choice_kernel(const uint64_t *__restrict__ leaf_off, const uint8
   const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
   for (uint64_t g = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g < n_leaves; g += waves)
     if (lane < leaf_sizes[g]) choice[leaf_off[g] + lane] = (uint8_t)((orient[g] >> lane) & 1);
+}
+
+// ---- the stored tables ------------------------------------------------------------
+
+// 5-bit size codes packed 64 bits a word: leaf g at bits 5g .. 5g + 4.
+__global__ void pack_codes_kernel(const uint8_t *__restrict__ codes8, uint64_t n_leaves, uint64_t words,
+                                  uint64_t *codes) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += stride) {
+    uint64_t v = 0;
+    const uint64_t p0 = w * 64;
+    for (uint64_t g = p0 / 5; g < n_leaves && 5 * g < p0 + 64; ++g) {
+      const uint64_t c = codes8[g] & 31, p = 5 * g;
+      v |= p >= p0 ? c << (p - p0) : c >> (p0 - p);
+    }
+    codes[w] = v;
+  }
+}
+
+// Code offsets of every bucket's first leaf (b in [0, B], entry B = the end):
+// from the Rice encoder's index of blocks of 64 leaves, plus the fixed widths
+// and unary lengths of the leaves before it in its block.
+__global__ void rice_bucket_kernel(const uint64_t *__restrict__ leaf_base, uint64_t n_buckets,
+                                   const uint64_t *__restrict__ index, const uint8_t *__restrict__ leaf_sizes,
+                                   const uint64_t *__restrict__ values, KTable K, uint64_t *fixed_at,
+                                   uint64_t *unary_at) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= n_buckets; b += stride) {
+    const uint64_t g0 = leaf_base[b], blk = g0 >> 6;
+    uint64_t F = index[2 * blk], U = index[2 * blk + 1];
+    for (uint64_t g = blk * 64; g < g0; ++g) {
+      const uint32_t k = K.k[leaf_sizes[g]];
+      F += k;
+      U += (values[g] >> k) + 1;
+    }
+    fixed_at[b] = F;
+    unary_at[b] = U;
+  }
+}
+
+// The bucket table: per block of 16 buckets the absolute key, leaf, ribbon,
+// fixed-code and unary-code offsets of its first bucket; per bucket its key,
+// fixed and unary offsets relative to its block (b in [0, B]; the key offset
+// of entry B closes the last bucket).
+__global__ void bucket_table_kernel(const uint64_t *__restrict__ bucket_offset, const uint64_t *__restrict__ leaf_base,
+                                    const uint64_t *__restrict__ rib_base, const uint64_t *__restrict__ fixed_at,
+                                    const uint64_t *__restrict__ unary_at, uint64_t n_buckets, uint64_t *block,
+                                    uint32_t *key_rel, uint32_t *fixed_rel, uint32_t *unary_rel,
+                                    unsigned long long *err) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= n_buckets; b += stride) {
+    const uint64_t b0 = b & ~((1ull << kBlockShift) - 1);
+    if (b == b0) {
+      uint64_t *e = block + (b >> kBlockShift) * kBkWords;
+      e[kBkKey] = bucket_offset[b];
+      e[kBkLeaf] = leaf_base[b];
+      e[kBkRib] = rib_base[b];
+      e[kBkFixed] = fixed_at[b];
+      e[kBkUnary] = unary_at[b];
+    }
+    key_rel[b] = (uint32_t)(bucket_offset[b] - bucket_offset[b0]);
+    const uint64_t df = fixed_at[b] - fixed_at[b0], du = unary_at[b] - unary_at[b0];
+    if (bucket_offset[b] - bucket_offset[b0] > 0xFFFFFFFFull || df > 0xFFFFFFFFull || du > 0xFFFFFFFFull)
+      atomicOr(err, kErrCodeSpan);
+    if (b < n_buckets) {
+      fixed_rel[b] = (uint32_t)df;
+      unary_rel[b] = (uint32_t)du;
+    }
+  }
+}
+
+// ---- ribbon retrieval ----------------------------------------------------------------
+
+// One wave per bucket.  The wave hashes 64 keys at a time; then every lane
+// runs the same insertion walk on wave-uniform values (scalar registers,
+// broadcast LDS reads), so the walk has no divergent control flow.  A row is
+// stored at its lowest column; a row meeting a stored row there takes their
+// sum and moves on to its next set column; a row that vanishes contradicts
+// the system unless its value vanished too.  Seeds are tried from 0 until
+// none contradicts.  The stored rows are an echelon basis of the row space,
+// so their leading columns are the pivot columns of the reduced row echelon
+// form; back substitution from the last column sets each pivot column and
+// leaves the others 0: the canonical solution.  The wave then writes the
+// bits at the bucket's offset (words shared with the neighbours by atomic OR
+// into the zeroed array).  Slots, values and the solution live in LDS (kLds)
+// or in a global region per bucket.
+// The readlane builtins return int: each half is taken as uint32_t before it
+// is widened, so the low half is never sign-extended into the high one.
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t lane64(uint64_t x, uint32_t q) {
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((uint32_t)(x >> 32), q);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((uint32_t)x, q);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(64) void ribbon_kernel(const uint64_t *__restrict__ keys,
+                                                    const uint8_t *__restrict__ choice,
+                                                    const uint64_t *__restrict__ bucket_offset,
+                                                    const uint64_t *__restrict__ rib_base, uint64_t n_buckets,
+                                                    uint64_t *slots_global, uint64_t lds_cap_words,
+                                                    uint64_t *zbits, uint64_t zwords, uint8_t *rseed,
+                                                    unsigned long long *err) {
+  extern __shared__ uint64_t lds_words[];
+  const uint32_t lane = lane_id();
+  for (uint64_t b = blockIdx.x; b < n_buckets; b += gridDim.x) {
+    const uint64_t o = bucket_offset[b], m = bucket_offset[b + 1] - o;
+    if (m == 0) {
+      if (lane == 0) rseed[b] = 0;
+      continue;
+    }
+    const uint64_t cols = ribbon_cols(m), W = (cols + 63) / 64, rb = rib_base[b];
+    // slots (cols words), their values (cols bytes, as cols / 8 + 1 words) and the solution (W + 1 words)
+    const uint64_t need = cols + cols / 8 + 1 + W + 1;
+    if (kLds && need > lds_cap_words) {  // the launch was sized for a smaller bucket
+      if (lane == 0) atomicOr(err, kErrRibbonInternal);
+      continue;
+    }
+    // a global region per bucket of at most 1.16 cols + 3 words: rb + (rb >> 3) + 3 b + 2 floor(rb / 64)
+    uint64_t *coef = kLds ? lds_words : slots_global + rb + (rb >> 3) + 3 * b + 2 * (rb >> 6);
+    uint8_t *val = reinterpret_cast<uint8_t *>(coef + cols);
+    uint64_t *sol = coef + cols + cols / 8 + 1;
+    uint32_t found = kRibbonSeeds;
+    for (uint32_t r = 0; r < kRibbonSeeds; ++r) {
+      for (uint64_t i = lane; i < cols; i += 64) coef[i] = 0;
+      for (uint64_t i = lane; i < W + 1; i += 64) sol[i] = 0;
+      __builtin_amdgcn_s_waitcnt(0);
+      wave_sync();
+      bool ok = true;
+      const uint64_t rmix = ribbon_mix(r);
+      for (uint64_t i0 = 0; i0 < m && ok; i0 += 64) {
+        const uint64_t il = i0 + lane;
+        uint64_t sl = 0, cl = 0;
+        if (il < m) ribbon_row(keys[o + il], rmix, cols, sl, cl);
+        const uint32_t vl = il < m ? (choice[o + il] & 1u) : 0u;
+        const uint32_t cnt = m - i0 < 64 ? (uint32_t)(m - i0) : 64u;
+        for (uint32_t q = 0; q < cnt && ok; ++q) {
+          uint64_t s = (uint32_t)__builtin_amdgcn_readlane((uint32_t)sl, q);  // s <= cols - 64
+          uint64_t c = lane64(cl, q);
+          uint32_t v = (uint32_t)__builtin_amdgcn_readlane(vl, q) & 1u;
+          for (;;) {
+            // The row's bits stay within its start's 64 columns, so s < cols
+            // always; the bound makes the walk end whatever the slots hold.
+            if (s >= cols) {
+              if (lane == 0) atomicOr(err, kErrRibbonInternal);
+              ok = false;
+              break;
+            }
+            const uint64_t e = uniform64(coef[s]);
+            const uint32_t ev = (uint32_t)__builtin_amdgcn_readfirstlane(val[s]) & 1u;
+            if (e == 0) {
+              if (lane == 0) {
+                coef[s] = c;
+                val[s] = (uint8_t)v;
+              }
+              break;
+            }
+            c ^= e;
+            v ^= ev;
+            if (c == 0) {
+              ok = v == 0;
+              break;
+            }
+            if (c & 1) {  // a stored row always holds its lowest column: s then rises every step
+              if (lane == 0) atomicOr(err, kErrRibbonInternal);
+              ok = false;
+              break;
+            }
+            const uint32_t tz = (uint32_t)__builtin_ctzll(c);
+            c >>= tz;
+            s += tz;
+          }
+        }
+      }
+      if (ok) {
+        // back substitution: win holds z[s + 1 ..] while column s is solved;
+        // the bits of one solution word are gathered before it is stored
+        uint64_t win = 0, word = 0;
+        for (uint64_t s = cols; s-- > 0;) {
+          const uint64_t e = uniform64(coef[s]);
+          uint64_t z = 0;
+          if (e) z = ((uint32_t)__builtin_amdgcn_readfirstlane(val[s]) ^ (uint64_t)__popcll((e >> 1) & win)) & 1;
+          win = (win << 1) | z;
+          word |= z << (s & 63);
+          if ((s & 63) == 0) {
+            if (lane == 0) sol[s >> 6] = word;
+            word = 0;
+          }
+        }
+        found = r;
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      wave_sync();
+      if (ok) break;
+    }
+    if (found == kRibbonSeeds) {
+      if (lane == 0) atomicOr(err, kErrRibbon);
+      continue;
+    }
+    if (lane == 0) rseed[b] = (uint8_t)found;
+    // write bits [rb, rb + cols) of the global array
+    const uint64_t w0 = rb >> 6, w1 = (rb + cols - 1) >> 6;
+    for (uint64_t w = w0 + lane; w <= w1 && w < zwords; w += 64) {
+      const uint64_t gb = w << 6;
+      uint64_t x;
+      if (gb >= rb) {
+        x = bits_at(sol, W, gb - rb);
+      } else {
+        x = sol[0] << (rb - gb);
+      }
+      if (gb + 64 <= rb + cols) {  // the word's bits past the bucket's end are 0 here
+        if (gb >= rb) {
+          zbits[w] = x;
+        } else {
+          atomicOr((unsigned long long *)&zbits[w], (unsigned long long)x);
+        }
+      } else {
+        x &= (1ull << (rb + cols - gb)) - 1;
+        atomicOr((unsigned long long *)&zbits[w], (unsigned long long)x);
+      }
+    }
+  }
 }
 
 // Retrieval peeling.  Each cell holds one 64-bit word: the number of keys not
@@ -730,16 +1039,44 @@ __global__ void pack_bits_kernel(const uint8_t *__restrict__ z, uint64_t cells, 
 // ---- query ------------------------------------------------------------------
 
 struct QueryArgs {
-  const uint64_t *bucket_offset, *leaf_base;
-  const uint32_t *sigma;
-  const uint8_t *leaf_sizes;
-  const uint64_t *fixed, *unary, *index, *zbits;
-  uint64_t fixed_words, unary_words;
+  const uint64_t *block;  // kBkWords per block of 16 buckets
+  const uint32_t *key_rel, *fixed_rel, *unary_rel;
+  const uint16_t *sigma;
+  const uint8_t *rseed;
+  const uint64_t *codes;  // 5-bit leaf size codes
+  const uint64_t *fixed, *unary, *zbits;
+  uint64_t fixed_words, unary_words, zwords;
   uint64_t n_buckets, seg, rmix;
   uint32_t leaf_target;
-  uint32_t rf, partial_k;
+  uint32_t rf, partial_k, retrieval;
   KTable K;
 };
+
+// Where bucket b's keys, leaves, ribbon bits and codes start, and its size.
+struct BucketAt {
+  uint64_t o, m, lb, rb, F, U;
+  uint32_t L;
+};
+__device__ __forceinline__ void bucket_at(const QueryArgs &A, uint64_t b, BucketAt &r) {
+  const uint64_t k = b >> kBlockShift, b0 = k << kBlockShift;
+  const uint64_t *e = A.block + k * kBkWords;
+  uint64_t lb = e[kBkLeaf], rb = e[kBkRib];
+  uint32_t prev = 0;  // key_rel of the block's first bucket is 0
+  for (uint64_t j = b0; j < b; ++j) {
+    const uint32_t next = A.key_rel[j + 1];
+    const uint64_t mj = next - prev;
+    lb += (mj + A.leaf_target - 1) / A.leaf_target;
+    rb += ribbon_cols(mj);
+    prev = next;
+  }
+  r.o = e[kBkKey] + prev;
+  r.m = A.block[((b + 1) >> kBlockShift) * kBkWords + kBkKey] + A.key_rel[b + 1] - r.o;
+  r.L = (uint32_t)((r.m + A.leaf_target - 1) / A.leaf_target);
+  r.lb = lb;
+  r.rb = rb;
+  r.F = e[kBkFixed] + A.fixed_rel[b];
+  r.U = e[kBkUnary] + A.unary_rel[b];
+}
 
 // Position of the r-th one bit (0-based) at or after bit p of the stream.
 // Position of the r-th set bit (from 0) of a word with more than r set bits.
@@ -792,17 +1129,24 @@ __device__ __forceinline__ void select_two(const uint64_t *s, uint64_t words, ui
   }
 }
 
-// Sum of the bytes v[a, b) with 8-byte word loads (v padded to whole words).
-__device__ __forceinline__ uint32_t byte_sum(const uint8_t *v, uint64_t a, uint64_t b) {
-  uint32_t sum = 0;
-  for (uint64_t w = a & ~7ull; w < b; w += 8) {
-    uint64_t x = *reinterpret_cast<const uint64_t *>(v + w);
-    if (w < a) x &= ~0ull << (8 * (a - w));
-    if (b - w < 8) x &= ~0ull >> (8 * (8 - (b - w)));
-    sum = __builtin_amdgcn_sad_u8((uint32_t)x, 0u, sum);
-    sum = __builtin_amdgcn_sad_u8((uint32_t)(x >> 32), 0u, sum);
+// The value stored for leaf j of a bucket: its fixed bits come after the
+// fixed widths of the leaves before it in the bucket, its unary code is the
+// j-th in the bucket's unary stream.
+__device__ __forceinline__ uint64_t leaf_value(const QueryArgs &A, const uint8_t *K, const BucketAt &bk, uint32_t lo,
+                                               uint32_t j, uint32_t n) {
+  uint64_t F = bk.F;
+  for (uint32_t i = 0; i < j; ++i) F += K[lo + size_code(A.codes, bk.lb + i)];
+  const uint32_t k = K[n];
+  uint64_t low = 0;
+  if (k) low = bits_at(A.fixed, A.fixed_words, F) & (~0ull >> (64 - k));
+  uint64_t prev, end;
+  if (j == 0) {
+    select_two(A.unary, A.unary_words, bk.U, 1, end, prev);  // the 0-th one
+    prev = bk.U - 1;
+  } else {
+    select_two(A.unary, A.unary_words, bk.U, j, prev, end);
   }
-  return sum;
+  return end == kNone ? kNone : (((end - (prev + 1)) << k) | low);
 }
 
 __global__ __launch_bounds__(256) void mphf_query_kernel(QueryArgs A, const uint64_t *__restrict__ queries,
@@ -814,49 +1158,29 @@ __global__ __launch_bounds__(256) void mphf_query_kernel(QueryArgs A, const uint
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_queries; t += stride) {
     const uint64_t x = queries[t];
     const uint64_t b = bucket_of(x, A.n_buckets);
-    const uint64_t o = A.bucket_offset[b], m = A.bucket_offset[b + 1] - o;
-    if (m == 0) {
+    BucketAt bk;
+    bucket_at(A, b, bk);
+    if (bk.m == 0) {
       out[t] = kNone;
       continue;
     }
-    const uint32_t L = (uint32_t)((m + A.leaf_target - 1) / A.leaf_target);
-    const uint64_t lb = A.leaf_base[b];
-    const uint32_t j = leaf_of(x, split_mix(A.sigma[b]), L);
-    const uint64_t g = lb + j;
-    const uint64_t start = byte_sum(A.leaf_sizes, lb, g);
-    const uint32_t n = A.leaf_sizes[g];
-    // the leaf's seed: fixed bits after the widths of the leaves before it in its block
-    const uint64_t blk = g >> 6;
-    uint64_t F = A.index[2 * blk];
-    for (uint64_t w = blk * 64; w < g; w += 8) {
-      const uint64_t x = *reinterpret_cast<const uint64_t *>(A.leaf_sizes + w);
-      const uint32_t cnt = g - w < 8 ? (uint32_t)(g - w) : 8u;
-      for (uint32_t q = 0; q < cnt; ++q) F += K[(x >> (8 * q)) & 0xFF];
-    }
-    const uint32_t k = K[n];
-    uint64_t low = 0;
-    if (k) {
-      const uint64_t w = F >> 6;
-      const uint32_t sh = (uint32_t)(F & 63);
-      if (w < A.fixed_words) low = A.fixed[w] >> sh;
-      if (sh + k > 64 && w + 1 < A.fixed_words) low |= A.fixed[w + 1] << (64 - sh);
-      low &= ~0ull >> (64 - k);
-    }
-    const uint64_t U0 = A.index[2 * blk + 1];
-    const uint32_t i = (uint32_t)(g & 63);
-    uint64_t prev, end;
-    if (i == 0) {
-      select_two(A.unary, A.unary_words, U0, 1, end, prev);  // the 0-th one
-      prev = U0 - 1;
+    const uint32_t lo = size_base(bk.m, bk.L);
+    const uint32_t j = leaf_of(x, split_mix(A.sigma[b]), bk.L);
+    const uint64_t start = (uint64_t)j * lo + code_sum(A.codes, bk.lb, bk.lb + j);
+    const uint32_t n = lo + size_code(A.codes, bk.lb + j);
+    const uint64_t value = leaf_value(A, K, bk, lo, j, n);
+    // the choice from the retrieval
+    uint32_t f;
+    if (A.retrieval == kRetrievalRibbon) {
+      uint64_t s, c;
+      ribbon_row(x, ribbon_mix(A.rseed[b]), ribbon_cols(bk.m), s, c);
+      f = (uint32_t)__popcll(c & bits_at(A.zbits, A.zwords, bk.rb + s)) & 1;
     } else {
-      select_two(A.unary, A.unary_words, U0, i, prev, end);
+      uint64_t c[3];
+      xor_cells(x, A.rmix, A.seg, c);
+      f = (uint32_t)(((A.zbits[c[0] >> 6] >> (c[0] & 63)) ^ (A.zbits[c[1] >> 6] >> (c[1] & 63)) ^
+                      (A.zbits[c[2] >> 6] >> (c[2] & 63))) & 1);
     }
-    const uint64_t value = end == kNone ? kNone : (((end - (prev + 1)) << k) | low);
-    // the choice from the retrieval cells
-    uint64_t c[3];
-    xor_cells(x, A.rmix, A.seg, c);
-    const uint32_t f = (uint32_t)(((A.zbits[c[0] >> 6] >> (c[0] & 63)) ^ (A.zbits[c[1] >> 6] >> (c[1] & 63)) ^
-                                   (A.zbits[c[2] >> 6] >> (c[2] & 63))) & 1);
     uint32_t h0 = 0, h1 = 0;
     if (A.rf == kLeafBip && n >= 2) {
       // left cell under a, right cell under b
@@ -881,7 +1205,28 @@ __global__ __launch_bounds__(256) void mphf_query_kernel(QueryArgs A, const uint
       h0 = h0 + r >= n ? h0 + r - n : h0 + r;
       h1 = h1 + r >= n ? h1 + r - n : h1 + r;
     }
-    out[t] = o + start + (f ? h1 : h0);
+    out[t] = bk.o + start + (f ? h1 : h0);
+  }
+}
+
+// Export: every leaf's size and stored value, one thread per bucket.
+__global__ void decode_leaves_kernel(QueryArgs A, uint8_t *sizes, uint64_t *values) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < A.n_buckets; b += stride) {
+    BucketAt bk;
+    bucket_at(A, b, bk);
+    const uint32_t lo = size_base(bk.m, bk.L);
+    uint64_t F = bk.F, U = bk.U;
+    for (uint32_t j = 0; j < bk.L; ++j) {
+      const uint32_t n = lo + size_code(A.codes, bk.lb + j), k = A.K.k[n];
+      const uint64_t low = k ? bits_at(A.fixed, A.fixed_words, F) & (~0ull >> (64 - k)) : 0;
+      F += k;
+      uint64_t p = U;  // the next one at or after U
+      while (p < A.unary_words * 64 && !((A.unary[p >> 6] >> (p & 63)) & 1)) ++p;
+      sizes[bk.lb + j] = (uint8_t)n;
+      values[bk.lb + j] = (p < A.unary_words * 64) ? (((p - U) << k) | low) : kNone;
+      U = p + 1;
+    }
   }
 }
 
@@ -896,19 +1241,22 @@ int grid_for(uint64_t items, uint32_t per_block) {
 struct shock_mphf {
   uint64_t n_keys = 0, n_buckets = 0, n_leaves = 0;
   uint32_t leaf_target = 0, leaf_max = 0, bucket_size = 0;
-  uint32_t rf = 0, partial_k = 0;
-  uint64_t rho = 0, seg = 0;
+  uint32_t rf = 0, partial_k = 0, retrieval = 0;
+  uint64_t rho = 0, seg = 0;  // XOR retrieval
   uint32_t max_sigma = 0, peel_rounds = 0;
   KTable K{};
-  uint64_t *bucket_offset = nullptr, *leaf_base = nullptr;
-  uint32_t *sigma = nullptr;
-  uint8_t *leaf_sizes = nullptr;
-  uint64_t *fixed = nullptr, *unary = nullptr, *index = nullptr, *zbits = nullptr;
-  uint64_t fixed_words = 0, unary_words = 0, index_words = 0, zwords = 0;
-  uint64_t fixed_bits = 0, unary_bits = 0;
+  // bucket table: kBkWords per block of 16 buckets, then per bucket
+  uint64_t *block = nullptr;
+  uint32_t *key_rel = nullptr, *fixed_rel = nullptr, *unary_rel = nullptr;
+  uint16_t *sigma = nullptr;
+  uint8_t *rseed = nullptr;  // ribbon seed per bucket
+  uint64_t *codes = nullptr;  // 5-bit leaf size codes
+  uint64_t *fixed = nullptr, *unary = nullptr, *zbits = nullptr;
+  uint64_t n_blocks = 0, code_words = 0, fixed_words = 0, unary_words = 0, zwords = 0;
+  uint64_t fixed_bits = 0, unary_bits = 0, rib_bits = 0;
   double build_ms = 0, search_ms = 0;
   double layout_ms = 0, search_call_ms = 0, codes_ms = 0, retrieval_ms = 0;
-  uint32_t rho_tries = 0;
+  uint32_t rho_tries = 0, max_rseed = 0;
 };
 
 namespace {
@@ -996,7 +1344,8 @@ hipError_t aux_of(Arena &A) {
 
 void free_mphf(shock_mphf *m) {
   if (!m) return;
-  void *ps[] = {m->bucket_offset, m->leaf_base, m->sigma, m->leaf_sizes, m->fixed, m->unary, m->index, m->zbits};
+  void *ps[] = {m->block, m->key_rel, m->fixed_rel, m->unary_rel, m->sigma, m->rseed,
+                m->codes, m->fixed, m->unary, m->zbits};
   for (void *p : ps)
     if (p) (void)hipFree(p);
   delete m;
@@ -1027,21 +1376,33 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   // (each bucket of m keys gets ceil(m / leaf_target) leaves).
   const uint64_t Lmax = B + (N + P.leaf_target - 1) / P.leaf_target;
   const uint64_t seg_r = (123 * N + 299) / 300 + 8, cells_r = 3 * seg_r;
+  const bool xor_ret = M->retrieval == kRetrievalXor;
+  // ribbon slots in global memory, for buckets too large for the LDS variant
+  const uint64_t rib_max = N + N / 50 + 65 * B;
+  const uint64_t slot_words = rib_max + rib_max / 8 + 2 * (rib_max / 64) + 3 * B + 64;
   const size_t scratch_bytes = align256(2 * 8) + align256(B * 4) + 2 * align256(N * 8) + align256((Lmax + 1) * 8) +
                                2 * align256(Lmax * 8) + align256(Lmax * 4) + 2 * align256(N ? N : 1) +
-                               align256(((N + 31) / 32) * 4) + align256(N * 4) + 2 * align256(cells_r * 8) +
-                               align256((kMaxPeelRounds + 1) * 8) + align256(kPkWords * 8) + align256(cells_r) + 32 * 256 +
-                               (M->rf == kLeafBip ? 2 * align256(Lmax * 8) : 0);  // bipartite seed pairs
+                               3 * align256((B + 1) * 8) + 2 * align256(Lmax + 8) + align256((Lmax / 64 + 3) * 16) +
+                               2 * align256((B + 1) * 8) + align256(slot_words * 8) +
+                               (xor_ret ? align256(((N + 31) / 32) * 4) + align256(N * 4) + 2 * align256(cells_r * 8) +
+                                              align256((kMaxPeelRounds + 1) * 8) + align256(kPkWords * 8) +
+                                              align256(cells_r)
+                                        : 0) +
+                               32 * 256 + (M->rf == kLeafBip ? 2 * align256(Lmax * 8) : 0);  // bipartite seed pairs
   Scratch S;
   HIP_TRY(reserve_scratch(scratch_bytes, S));
   unsigned long long *err = nullptr;
-  uint64_t *host = S.pinned;  // pinned: [0] error bits, [1] n_leaves; [4, 4 + kPkWords) the retrieval's counters
+  // pinned: [0] error bits, [1] n_leaves, [2] largest bucket, [3] ribbon bits;
+  // [4, 4 + kPkWords) the XOR retrieval's counters
+  uint64_t *host = S.pinned;
   HIP_TRY(S.alloc(&err, 2));
   uint32_t *counts = nullptr;
   HIP_TRY(S.alloc(&counts, B));
-  HIP_TRY(hipMalloc((void **)&M->bucket_offset, (B + 1) * sizeof(uint64_t)));
-  HIP_TRY(hipMalloc((void **)&M->leaf_base, (B + 1) * sizeof(uint64_t)));
-  HIP_TRY(hipMalloc((void **)&M->sigma, B * sizeof(uint32_t)));
+  uint64_t *bucket_offset = nullptr, *leaf_base = nullptr, *rib_base = nullptr;
+  HIP_TRY(S.alloc(&bucket_offset, B + 1));
+  HIP_TRY(S.alloc(&leaf_base, B + 1));
+  HIP_TRY(S.alloc(&rib_base, B + 1));
+  HIP_TRY(hipMalloc((void **)&M->sigma, B * sizeof(uint16_t)));
   HIP_TRY(hipMemsetAsync(err, 0, 2 * sizeof(unsigned long long), stream));
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(B, 256)), dim3(256), 0, stream, counts, B, 0u);
   const bool lds_layout = B <= kLdsBuckets;
@@ -1050,17 +1411,20 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
     hipLaunchKernelGGL(bucket_count_lds_kernel, dim3(layout_grid), dim3(256), 0, stream, keys, N, B, counts);
   else if (N)
     hipLaunchKernelGGL(bucket_count_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, keys, N, B, counts);
-  hipLaunchKernelGGL(layout_scan_kernel, dim3(1), dim3(1024), 0, stream, counts, B, P.leaf_target, M->bucket_offset,
-                     M->leaf_base, err);
+  hipLaunchKernelGGL(layout_scan_kernel, dim3(1), dim3(1024), 0, stream, counts, B, P.leaf_target, bucket_offset,
+                     leaf_base, rib_base, err);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipMemcpyAsync(&host[1], M->leaf_base + B, 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&host[2], err + 1, 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&host[1], leaf_base + B, 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&host[3], rib_base + B, 8, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   if (host[0] & kErrTooManyLeaves) return SHOCK_EINVAL;
-  const uint64_t L = host[1];
+  const uint64_t L = host[1], max_m = host[2], rib_total = host[3];
   M->n_leaves = L;
-  // padded to whole 8-byte words plus one, for the query's word loads
-  HIP_TRY(hipMalloc((void **)&M->leaf_sizes, ((L + 7) & ~7ull) + 8));
+  uint8_t *leaf_sizes = nullptr, *codes8 = nullptr;  // one byte per leaf, padded
+  HIP_TRY(S.alloc(&leaf_sizes, L + 8));
+  HIP_TRY(S.alloc(&codes8, L + 8));
   uint64_t *grouped = nullptr, *leaf_keys = nullptr, *leaf_off = nullptr;
   HIP_TRY(S.alloc(&grouped, N));
   HIP_TRY(S.alloc(&leaf_keys, N));
@@ -1068,18 +1432,18 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(B, 256)), dim3(256), 0, stream, counts, B, 0u);
   if (N && !lds_layout)
     hipLaunchKernelGGL(bucket_scatter_kernel, dim3(grid_for(N, 256)), dim3(256), 0, stream, keys, N, B,
-                       (const uint64_t *)M->bucket_offset, counts, grouped);
+                       (const uint64_t *)bucket_offset, counts, grouped);
   if (N && lds_layout)
     hipLaunchKernelGGL(bucket_scatter_lds_kernel, dim3(layout_grid), dim3(256), 0, stream, keys, N, B,
-                       (const uint64_t *)M->bucket_offset, counts, grouped);
+                       (const uint64_t *)bucket_offset, counts, grouped);
   hipLaunchKernelGGL(split_kernel, dim3(grid_for(B, 4)), dim3(256), 0, stream, (const uint64_t *)grouped,
-                     (const uint64_t *)M->bucket_offset, (const uint64_t *)M->leaf_base, B, P.leaf_max, M->sigma,
-                     M->leaf_sizes, leaf_off, leaf_keys, err);
+                     (const uint64_t *)bucket_offset, (const uint64_t *)leaf_base, B, P.leaf_max, M->sigma,
+                     leaf_sizes, codes8, leaf_off, leaf_keys, err);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(leaf_off + L, &N, 8, hipMemcpyHostToDevice, stream));
   if (L)
     hipLaunchKernelGGL(leaf_sort_kernel, dim3(grid_for(L, 4)), dim3(256), 0, stream, leaf_keys,
-                       (const uint64_t *)leaf_off, (const uint8_t *)M->leaf_sizes, L);
+                       (const uint64_t *)leaf_off, (const uint8_t *)leaf_sizes, L);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
@@ -1097,23 +1461,25 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   uint64_t *frontier = nullptr, *round_off = nullptr, *pk_host = nullptr;
   const uint64_t seg = seg_r, cells = cells_r;
   const uint64_t taken_words = (N + 31) / 32;
-  M->seg = seg;
   HIP_TRY(S.alloc(&choice, N));
-  HIP_TRY(S.alloc(&peel, N));
-  HIP_TRY(S.alloc(&taken, taken_words));
-  HIP_TRY(S.alloc(&stack, N));
-  HIP_TRY(S.alloc(&cw, cells));
-  HIP_TRY(S.alloc(&frontier, cells));
-  HIP_TRY(S.alloc(&round_off, kMaxPeelRounds + 1));
-  HIP_TRY(S.alloc(&pk, kPkWords));
-  HIP_TRY(S.alloc(&z, cells));
+  if (xor_ret) {
+    M->seg = seg;
+    HIP_TRY(S.alloc(&peel, N));
+    HIP_TRY(S.alloc(&taken, taken_words));
+    HIP_TRY(S.alloc(&stack, N));
+    HIP_TRY(S.alloc(&cw, cells));
+    HIP_TRY(S.alloc(&frontier, cells));
+    HIP_TRY(S.alloc(&round_off, kMaxPeelRounds + 1));
+    HIP_TRY(S.alloc(&pk, kPkWords));
+    HIP_TRY(S.alloc(&z, cells));
+  }
   static_assert(4 + kPkWords <= kPinnedWords, "pinned words");
   pk_host = S.pinned + 4;
   // Round passes run a fixed grid over device-held ranges; the host checks
   // for the end of the peeling after each chunk of rounds.
   const int round_grid = grid_for((cells + 3) / 4, 256 * kDetectPer) < 1024 ? grid_for((cells + 3) / 4, 256 * kDetectPer) : 1024;
   constexpr uint32_t kChunk = 16;
-  const bool big = N > kSmallRetrievalKeys;
+  const bool big = xor_ret && N > kSmallRetrievalKeys;
   hipStream_t ps = stream;  // the stream the multi-launch peeling runs on
   struct AuxGuard {         // no early return leaves work running on the second stream
     hipStream_t s = nullptr;
@@ -1177,7 +1543,7 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
       rc = shock_rf_leaf_search_ex(leaf_keys, leaf_off, L, seeds, rot, orient, &o, stream);
       if (rc == SHOCK_OK) {
         hipLaunchKernelGGL(rf_values_kernel, dim3(grid_for(L, 256)), dim3(256), 0, stream, seeds,
-                           (const uint32_t *)rot, (const uint8_t *)M->leaf_sizes, L);
+                           (const uint32_t *)rot, (const uint8_t *)leaf_sizes, L);
         HIP_TRY(hipGetLastError());
       }
     } else {
@@ -1189,12 +1555,13 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   }
   M->search_call_ms = ms_since(tp);
   tp = std::chrono::steady_clock::now();
-  // Golomb-Rice codes of the seeds
+  // Golomb-Rice codes of the seeds; the encoder's index of blocks of 64
+  // leaves is scratch: the structure keeps each bucket's code offsets.
   uint64_t bits[2] = {0, 0};
-  const uint64_t n_blocks = (L + 63) / 64;
-  M->index_words = 2 * (n_blocks + 1);
-  HIP_TRY(hipMalloc((void **)&M->index, M->index_words * sizeof(uint64_t)));
-  int rc = shock_rice_encode(seeds, leaf_off, L, M->K.k, nullptr, 0, nullptr, 0, M->index, bits, stream);
+  const uint64_t n_blocks64 = (L + 63) / 64;
+  uint64_t *index = nullptr;
+  HIP_TRY(S.alloc(&index, 2 * (n_blocks64 + 1)));
+  int rc = shock_rice_encode(seeds, leaf_off, L, M->K.k, nullptr, 0, nullptr, 0, index, bits, stream);
   if (rc != SHOCK_OK && rc != SHOCK_EINVAL) return rc;
   M->fixed_bits = bits[0];
   M->unary_bits = bits[1];
@@ -1202,17 +1569,83 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   M->unary_words = (bits[1] + 63) / 64;
   HIP_TRY(hipMalloc((void **)&M->fixed, (M->fixed_words ? M->fixed_words : 1) * 8));
   HIP_TRY(hipMalloc((void **)&M->unary, (M->unary_words ? M->unary_words : 1) * 8));
-  rc = shock_rice_encode(seeds, leaf_off, L, M->K.k, M->fixed, M->fixed_words, M->unary, M->unary_words, M->index,
+  rc = shock_rice_encode(seeds, leaf_off, L, M->K.k, M->fixed, M->fixed_words, M->unary, M->unary_words, index,
                          bits, stream);
   if (rc != SHOCK_OK) return rc;
+  // the bucket table and the 5-bit size codes
+  uint64_t *fixed_at = nullptr, *unary_at = nullptr;
+  HIP_TRY(S.alloc(&fixed_at, B + 1));
+  HIP_TRY(S.alloc(&unary_at, B + 1));
+  M->n_blocks = (B >> kBlockShift) + 1;
+  M->code_words = (5 * L + 63) / 64 + 1;
+  HIP_TRY(hipMalloc((void **)&M->block, M->n_blocks * kBkWords * 8));
+  HIP_TRY(hipMalloc((void **)&M->key_rel, (B + 1) * 4));
+  HIP_TRY(hipMalloc((void **)&M->fixed_rel, B * 4));
+  HIP_TRY(hipMalloc((void **)&M->unary_rel, B * 4));
+  HIP_TRY(hipMalloc((void **)&M->codes, M->code_words * 8));
+  hipLaunchKernelGGL(rice_bucket_kernel, dim3(grid_for(B + 1, 256)), dim3(256), 0, stream,
+                     (const uint64_t *)leaf_base, B, (const uint64_t *)index, (const uint8_t *)leaf_sizes,
+                     (const uint64_t *)seeds, M->K, fixed_at, unary_at);
+  hipLaunchKernelGGL(bucket_table_kernel, dim3(grid_for(B + 1, 256)), dim3(256), 0, stream,
+                     (const uint64_t *)bucket_offset, (const uint64_t *)leaf_base, (const uint64_t *)rib_base,
+                     (const uint64_t *)fixed_at, (const uint64_t *)unary_at, B, M->block, M->key_rel, M->fixed_rel,
+                     M->unary_rel, err);
+  hipLaunchKernelGGL(pack_codes_kernel, dim3(grid_for(M->code_words, 256)), dim3(256), 0, stream,
+                     (const uint8_t *)codes8, L, M->code_words, M->codes);
+  HIP_TRY(hipGetLastError());
 
   M->codes_ms = ms_since(tp);
   tp = std::chrono::steady_clock::now();
   // retrieval of each key's choice
   if (L)
     hipLaunchKernelGGL(choice_kernel, dim3(grid_for(L, 4)), dim3(256), 0, stream, (const uint64_t *)leaf_off,
-                       (const uint8_t *)M->leaf_sizes, (const uint64_t *)orient, L, choice);
+                       (const uint8_t *)leaf_sizes, (const uint64_t *)orient, L, choice);
   HIP_TRY(hipGetLastError());
+  if (!xor_ret) {
+    // one ribbon system per bucket, one wave each; the LDS holds a bucket's
+    // slots, values and solution unless its largest bucket is too large
+    M->rib_bits = rib_total;
+    M->zwords = (rib_total + 63) / 64;
+    HIP_TRY(hipMalloc((void **)&M->zbits, (M->zwords ? M->zwords : 1) * 8));
+    HIP_TRY(hipMalloc((void **)&M->rseed, B));
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(M->zwords, 256)), dim3(256), 0, stream,
+                       (unsigned long long *)M->zbits, M->zwords);
+    const uint64_t max_cols = ribbon_cols(max_m);
+    const size_t lds_bytes = (max_cols + max_cols / 8 + 1 + (max_cols + 63) / 64 + 1) * 8;
+    const int grid = (int)(B < 65536 ? B : 65536);
+    if (lds_bytes <= 65536) {
+      hipLaunchKernelGGL(ribbon_kernel<true>, dim3(grid), dim3(64), lds_bytes, stream, (const uint64_t *)leaf_keys,
+                         (const uint8_t *)choice, (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, B,
+                         (uint64_t *)nullptr, (uint64_t)(lds_bytes / 8), M->zbits, M->zwords, M->rseed, err);
+    } else {
+      uint64_t *slots = nullptr;
+      HIP_TRY(S.alloc(&slots, slot_words));
+      hipLaunchKernelGGL(ribbon_kernel<false>, dim3(grid), dim3(64), 0, stream, (const uint64_t *)leaf_keys,
+                         (const uint8_t *)choice, (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, B,
+                         slots, (uint64_t)0, M->zbits, M->zwords, M->rseed, err);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (host[0] & kErrCodeSpan) return SHOCK_EINVAL;
+    if (host[0] & kErrRibbonInternal) {
+      shock_internal_set_error("ribbon retrieval: a bucket exceeded the launch's LDS or a walk left its band", hipErrorInvalidValue);
+      return SHOCK_EHIP;
+    }
+    if (host[0] & kErrRibbon) return SHOCK_ENOTFOUND;
+    if (B) {
+      std::vector<uint8_t> hs(B);
+      std::vector<uint16_t> hg(B);
+      HIP_TRY(hipMemcpy(hs.data(), M->rseed, B, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(hg.data(), M->sigma, B * 2, hipMemcpyDeviceToHost));
+      for (uint64_t b = 0; b < B; ++b) {
+        M->max_rseed = hs[b] > M->max_rseed ? hs[b] : M->max_rseed;
+        M->max_sigma = hg[b] > M->max_sigma ? hg[b] : M->max_sigma;
+      }
+    }
+    M->retrieval_ms = ms_since(tp);
+    return SHOCK_OK;
+  }
   if (big) HIP_TRY(hipEventRecord(S.arena->ev_choice, stream));
   bool solved = false;
   uint32_t rounds = 0;
@@ -1286,13 +1719,12 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   HIP_TRY(hipGetLastError());
   // the largest splitting seed (for the record)
   if (B) {
-    uint32_t *hs = (uint32_t *)malloc(B * sizeof(uint32_t));
-    if (!hs) return SHOCK_ENOMEM;
-    hipError_t e = hipMemcpyAsync(hs, M->sigma, B * sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    for (uint64_t b = 0; b < B && e == hipSuccess; ++b) M->max_sigma = hs[b] > M->max_sigma ? hs[b] : M->max_sigma;
-    free(hs);
-    HIP_TRY(e);
+    std::vector<uint16_t> hg(B);
+    HIP_TRY(hipMemcpyAsync(hg.data(), M->sigma, B * 2, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (uint64_t b = 0; b < B; ++b) M->max_sigma = hg[b] > M->max_sigma ? hg[b] : M->max_sigma;
+    if (host[0] & kErrCodeSpan) return SHOCK_EINVAL;
   }
   HIP_TRY(hipStreamSynchronize(stream));
   M->retrieval_ms = ms_since(tp);
@@ -1331,11 +1763,12 @@ extern "C" {
 void shock_mphf_params_init(shock_mphf_params *p) {
   if (!p) return;
   memset(p, 0, sizeof(*p));
-  p->bucket_size = 2000;
+  p->bucket_size = 3000;
   p->leaf_target = 40;
   p->leaf_max = 56;
   p->max_rho_tries = 64;
   p->rice_k_by_n = nullptr;
+  p->retrieval = SHOCK_RETRIEVAL_RIBBON;
 }
 
 int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_params *params, shock_mphf **out,
@@ -1346,6 +1779,7 @@ int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_par
   if (P.max_rho_tries == 0 || !P.rice_k_by_n || n_keys >= (1ull << 32)) return SHOCK_EINVAL;
   if (P.rotation_fitting > 1 || (P.partial_k != 0 && P.partial_k != 1 && P.partial_k != 8)) return SHOCK_EINVAL;
   if (P.bipartite > 1 || (P.bipartite && P.rotation_fitting)) return SHOCK_EINVAL;
+  if (P.retrieval != SHOCK_RETRIEVAL_RIBBON && P.retrieval != SHOCK_RETRIEVAL_XOR) return SHOCK_EINVAL;
   *out = nullptr;
   shock_mphf *M = new shock_mphf;
   M->leaf_target = P.leaf_target;
@@ -1353,6 +1787,7 @@ int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_par
   M->bucket_size = P.bucket_size;
   M->rf = P.bipartite ? kLeafBip : (P.rotation_fitting ? kLeafRf : kLeafPlain);
   M->partial_k = (uint32_t)P.partial_k;
+  M->retrieval = P.retrieval == SHOCK_RETRIEVAL_XOR ? kRetrievalXor : kRetrievalRibbon;
   for (int n = 0; n <= 64; ++n) {
     if (P.rice_k_by_n[n] > 56) {
       delete M;
@@ -1374,31 +1809,39 @@ int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_par
   return SHOCK_OK;
 }
 
-int shock_mphf_query(const shock_mphf *m, const uint64_t *queries, uint64_t n_queries, uint64_t *positions,
-                     void *hip_stream) {
-  if (!m) return SHOCK_EINVAL;
-  if (n_queries == 0) return SHOCK_OK;
-  if (!queries || !positions) return SHOCK_EINVAL;
+static QueryArgs query_args(const shock_mphf *m) {
   QueryArgs A;
-  A.bucket_offset = m->bucket_offset;
-  A.leaf_base = m->leaf_base;
+  A.block = m->block;
+  A.key_rel = m->key_rel;
+  A.fixed_rel = m->fixed_rel;
+  A.unary_rel = m->unary_rel;
   A.sigma = m->sigma;
-  A.leaf_sizes = m->leaf_sizes;
+  A.rseed = m->rseed;
+  A.codes = m->codes;
   A.fixed = m->fixed;
   A.unary = m->unary;
-  A.index = m->index;
   A.zbits = m->zbits;
   A.fixed_words = m->fixed_words;
   A.unary_words = m->unary_words;
+  A.zwords = m->zwords;
   A.n_buckets = m->n_buckets;
   A.seg = m->seg;
   A.rmix = shockhash::fmix64((m->rho + 1) * kRetrievalMul);
   A.leaf_target = m->leaf_target;
   A.rf = m->rf;
   A.partial_k = m->partial_k;
+  A.retrieval = m->retrieval;
   A.K = m->K;
-  hipLaunchKernelGGL(mphf_query_kernel, dim3(grid_for(n_queries, 256)), dim3(256), 0, (hipStream_t)hip_stream, A,
-                     queries, n_queries, positions);
+  return A;
+}
+
+int shock_mphf_query(const shock_mphf *m, const uint64_t *queries, uint64_t n_queries, uint64_t *positions,
+                     void *hip_stream) {
+  if (!m) return SHOCK_EINVAL;
+  if (n_queries == 0) return SHOCK_OK;
+  if (!queries || !positions) return SHOCK_EINVAL;
+  hipLaunchKernelGGL(mphf_query_kernel, dim3(grid_for(n_queries, 256)), dim3(256), 0, (hipStream_t)hip_stream,
+                     query_args(m), queries, n_queries, positions);
   HIP_TRY(hipGetLastError());
   return SHOCK_OK;
 }
@@ -1406,8 +1849,9 @@ int shock_mphf_query(const shock_mphf *m, const uint64_t *queries, uint64_t n_qu
 int shock_mphf_info(const shock_mphf *m, shock_mphf_stats *info) {
   if (!m || !info) return SHOCK_EINVAL;
   memset(info, 0, sizeof(*info));
+  const uint64_t B = m->n_buckets;
   info->n_keys = m->n_keys;
-  info->n_buckets = m->n_buckets;
+  info->n_buckets = B;
   info->n_leaves = m->n_leaves;
   info->rho = m->rho;
   info->seg = m->seg;
@@ -1415,10 +1859,14 @@ int shock_mphf_info(const shock_mphf *m, shock_mphf_stats *info) {
   info->peel_rounds = m->peel_rounds;
   info->seed_fixed_bits = m->fixed_bits;
   info->seed_unary_bits = m->unary_bits;
-  info->bits_buckets = (m->n_buckets + 1) * 64 * 2 + m->n_buckets * 32;
-  info->bits_leaf_sizes = m->n_leaves * 8;
-  info->bits_seeds = m->fixed_bits + m->unary_bits + m->index_words * 64 + 65 * 8;
-  info->bits_retrieval = 3 * m->seg;
+  // buckets: per block the key and leaf offsets; per bucket its relative key
+  // offset and splitting seed
+  info->bits_buckets = m->n_blocks * 2 * 64 + (B + 1) * 32 + B * 16;
+  info->bits_leaf_sizes = m->n_leaves * 5;
+  // seeds: the Rice streams, per block their offsets, per bucket the relative
+  // offsets, and the table of Rice parameters
+  info->bits_seeds = m->fixed_bits + m->unary_bits + m->n_blocks * 2 * 64 + B * 64 + 65 * 8;
+  info->bits_retrieval = m->retrieval == kRetrievalXor ? 3 * m->seg : m->rib_bits + B * 8 + m->n_blocks * 64;
   info->bits_total = info->bits_buckets + info->bits_leaf_sizes + info->bits_seeds + info->bits_retrieval;
   info->build_ms = m->build_ms;
   info->search_ms = m->search_ms;
@@ -1427,6 +1875,8 @@ int shock_mphf_info(const shock_mphf *m, shock_mphf_stats *info) {
   info->codes_ms = m->codes_ms;
   info->retrieval_ms = m->retrieval_ms;
   info->rho_tries = m->rho_tries;
+  info->retrieval = m->retrieval == kRetrievalXor ? SHOCK_RETRIEVAL_XOR : SHOCK_RETRIEVAL_RIBBON;
+  info->max_rseed = m->max_rseed;
   return SHOCK_OK;
 }
 
@@ -1434,45 +1884,74 @@ int shock_mphf_export(const shock_mphf *m, uint64_t *bucket_offset, uint64_t *le
                       uint8_t *leaf_sizes, uint64_t *leaf_seeds, uint8_t *cells) {
   if (!m) return SHOCK_EINVAL;
   const uint64_t B = m->n_buckets, L = m->n_leaves;
-  if (bucket_offset) HIP_TRY(hipMemcpy(bucket_offset, m->bucket_offset, (B + 1) * 8, hipMemcpyDeviceToHost));
-  if (leaf_base) HIP_TRY(hipMemcpy(leaf_base, m->leaf_base, (B + 1) * 8, hipMemcpyDeviceToHost));
-  if (sigma) HIP_TRY(hipMemcpy(sigma, m->sigma, B * 4, hipMemcpyDeviceToHost));
-  if (leaf_sizes && L) HIP_TRY(hipMemcpy(leaf_sizes, m->leaf_sizes, L, hipMemcpyDeviceToHost));
-  if (leaf_seeds && L) {
-    uint64_t *off = nullptr, *vals = nullptr;
-    HIP_TRY(hipMalloc((void **)&off, (L + 1) * 8));
-    hipError_t e = hipMalloc((void **)&vals, L * 8);
-    // leaf offsets from the sizes (host prefix sums)
-    uint8_t *hs = (uint8_t *)malloc(L);
-    uint64_t *ho = (uint64_t *)malloc((L + 1) * 8);
-    if (e == hipSuccess && hs && ho) e = hipMemcpy(hs, m->leaf_sizes, L, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && hs && ho) {
-      ho[0] = 0;
-      for (uint64_t g = 0; g < L; ++g) ho[g + 1] = ho[g] + hs[g];
-      e = hipMemcpy(off, ho, (L + 1) * 8, hipMemcpyHostToDevice);
+  if (bucket_offset || leaf_base) {
+    std::vector<uint64_t> blk(m->n_blocks * kBkWords);
+    std::vector<uint32_t> rel(B + 1);
+    HIP_TRY(hipMemcpy(blk.data(), m->block, blk.size() * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(rel.data(), m->key_rel, (B + 1) * 4, hipMemcpyDeviceToHost));
+    uint64_t lb = 0;
+    for (uint64_t b = 0; b <= B; ++b) {
+      const uint64_t o = blk[(b >> kBlockShift) * kBkWords + kBkKey] + rel[b];
+      if (bucket_offset) bucket_offset[b] = o;
+      if (leaf_base) leaf_base[b] = lb;
+      if (b < B) {
+        const uint64_t o1 = blk[((b + 1) >> kBlockShift) * kBkWords + kBkKey] + rel[b + 1];
+        lb += (o1 - o + m->leaf_target - 1) / m->leaf_target;
+      }
     }
-    int rc = SHOCK_OK;
-    if (e == hipSuccess && hs && ho)
-      rc = shock_rice_decode(m->fixed, m->fixed_words, m->unary, m->unary_words, m->index, off, L, m->K.k, vals,
-                             nullptr);
-    if (e == hipSuccess && rc == SHOCK_OK && hs && ho) e = hipMemcpy(leaf_seeds, vals, L * 8, hipMemcpyDeviceToHost);
-    free(hs);
-    free(ho);
-    (void)hipFree(off);
-    if (vals) (void)hipFree(vals);
-    if (!hs || !ho) return SHOCK_ENOMEM;
-    HIP_TRY(e);
-    if (rc != SHOCK_OK) return rc;
   }
-  if (cells) {
-    const uint64_t n = 3 * m->seg;
-    uint64_t *w = (uint64_t *)malloc(m->zwords * 8);
-    if (!w) return SHOCK_ENOMEM;
-    hipError_t e = hipMemcpy(w, m->zbits, m->zwords * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess)
-      for (uint64_t c = 0; c < n; ++c) cells[c] = (uint8_t)((w[c >> 6] >> (c & 63)) & 1);
-    free(w);
+  if (sigma && B) {
+    std::vector<uint16_t> hg(B);
+    HIP_TRY(hipMemcpy(hg.data(), m->sigma, B * 2, hipMemcpyDeviceToHost));
+    for (uint64_t b = 0; b < B; ++b) sigma[b] = hg[b];
+  }
+  if ((leaf_sizes || leaf_seeds) && L) {
+    uint8_t *ds = nullptr;
+    uint64_t *dv = nullptr;
+    HIP_TRY(hipMalloc((void **)&ds, L));
+    hipError_t e = hipMalloc((void **)&dv, L * 8);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(decode_leaves_kernel, dim3(grid_for(B, 256)), dim3(256), 0, 0, query_args(m), ds, dv);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess && leaf_sizes) e = hipMemcpy(leaf_sizes, ds, L, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && leaf_seeds) e = hipMemcpy(leaf_seeds, dv, L * 8, hipMemcpyDeviceToHost);
+    (void)hipFree(ds);
+    if (dv) (void)hipFree(dv);
     HIP_TRY(e);
+  }
+  if (cells && m->retrieval == kRetrievalXor) {
+    const uint64_t n = 3 * m->seg;
+    std::vector<uint64_t> w(m->zwords);
+    HIP_TRY(hipMemcpy(w.data(), m->zbits, m->zwords * 8, hipMemcpyDeviceToHost));
+    for (uint64_t c = 0; c < n; ++c) cells[c] = (uint8_t)((w[c >> 6] >> (c & 63)) & 1);
+  }
+  return SHOCK_OK;
+}
+
+int shock_mphf_export_ribbon(const shock_mphf *m, uint8_t *rseed, uint64_t *bit_offset, uint8_t *bits) {
+  if (!m || m->retrieval != kRetrievalRibbon) return SHOCK_EINVAL;
+  const uint64_t B = m->n_buckets;
+  if (rseed && B) HIP_TRY(hipMemcpy(rseed, m->rseed, B, hipMemcpyDeviceToHost));
+  if (bit_offset) {
+    std::vector<uint64_t> blk(m->n_blocks * kBkWords);
+    std::vector<uint32_t> rel(B + 1);
+    HIP_TRY(hipMemcpy(blk.data(), m->block, blk.size() * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(rel.data(), m->key_rel, (B + 1) * 4, hipMemcpyDeviceToHost));
+    uint64_t rb = 0;
+    for (uint64_t b = 0; b <= B; ++b) {
+      bit_offset[b] = rb;
+      if (b < B) {
+        const uint64_t o = blk[(b >> kBlockShift) * kBkWords + kBkKey] + rel[b];
+        const uint64_t o1 = blk[((b + 1) >> kBlockShift) * kBkWords + kBkKey] + rel[b + 1];
+        rb += ribbon_cols(o1 - o);
+      }
+    }
+  }
+  if (bits && m->rib_bits) {
+    std::vector<uint64_t> w(m->zwords);
+    HIP_TRY(hipMemcpy(w.data(), m->zbits, m->zwords * 8, hipMemcpyDeviceToHost));
+    for (uint64_t c = 0; c < m->rib_bits; ++c) bits[c] = (uint8_t)((w[c >> 6] >> (c & 63)) & 1);
   }
   return SHOCK_OK;
 }

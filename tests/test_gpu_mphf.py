@@ -1,7 +1,8 @@
 """GPU parity of the flat ShockHash MPHF (include/shockmphf.h) against the
 oracle: every stored part bit-exact (bucket offsets, leaf bases, splitting
-seeds, leaf sizes, leaf seeds, retrieval seed and cells), every key's
-position equal, and the bijection onto [0, N) at full size."""
+seeds, leaf sizes, leaf seeds, and the retrieval: each bucket's ribbon seed
+and bits, or the XOR system's seed and cells), every key's position equal,
+and the bijection onto [0, N) at full size."""
 import numpy as np
 import pytest
 
@@ -31,6 +32,27 @@ def _host(t):
     return t.cpu().numpy().view(np.uint64)
 
 
+RIBBON, XOR = 0, 1
+
+
+def _same_retrieval(ex, lay):
+    """The GPU's retrieval parts equal the oracle's."""
+    assert ex["retrieval"] == lay["retrieval"]
+    if ex["retrieval"] == XOR:
+        return ex["rho"] == lay["rho"] and (ex["z"] == lay["z"]).all()
+    return ((ex["rseed"] == lay["rseed"]).all() and (ex["rbit_offset"] == lay["rbit_offset"]).all()
+            and (ex["z"] == lay["z"]).all())
+
+
+def _oracle_struct(lay, ex, **kw):
+    """The oracle's layout with the GPU's exported seeds and retrieval, for
+    the oracle's query over the GPU structure."""
+    d = dict(lay, seeds=ex["seeds"], retrieval=ex["retrieval"], rho=ex["rho"], z=ex["z"], leaf_target=40, **kw)
+    if ex["retrieval"] == RIBBON:
+        d.update(rseed=ex["rseed"], rbit_offset=ex["rbit_offset"])
+    return d
+
+
 def _build(shock, keys, **params):
     print(f"[gpu] mphf build N={len(keys)} {params}", flush=True)
     k = _dev(keys) if len(keys) else torch.zeros(0, dtype=torch.int64, device="cuda")
@@ -39,13 +61,14 @@ def _build(shock, keys, **params):
     return m, k
 
 
+@pytest.mark.parametrize("ret", [RIBBON, XOR], ids=["ribbon", "xor"])
 @pytest.mark.parametrize("rf", [False, True], ids=["plain", "rf"])
 @pytest.mark.parametrize("N", [1, 2, 17, 1000, 6000])
-def test_mphf_matches_oracle(shock, oracle_mod, N, rf):
+def test_mphf_matches_oracle(shock, oracle_mod, N, rf, ret):
     keys = splitmix64(2100 + N, N)
-    m, k = _build(shock, keys, rotation_fitting=rf, **SMALL)
+    m, k = _build(shock, keys, rotation_fitting=rf, retrieval=ret, **SMALL)
     try:
-        rc, lay = oracle_mod.mphf_build(keys, rf=rf, **SMALL)
+        rc, lay = oracle_mod.mphf_build(keys, rf=rf, retrieval=ret, **SMALL)
         assert rc == 0
         ex = m.export()
         assert (ex["bucket_offset"] == lay["bucket_offset"]).all()
@@ -53,7 +76,7 @@ def test_mphf_matches_oracle(shock, oracle_mod, N, rf):
         assert (ex["sigma"] == lay["sigma"]).all()
         assert (ex["leaf_sizes"] == lay["leaf_sizes"]).all()
         assert (ex["seeds"] == lay["seeds"]).all()
-        assert ex["rho"] == lay["rho"] and (ex["z"] == lay["z"]).all()
+        assert _same_retrieval(ex, lay)
         pos = _host(m.query(k))
         torch.cuda.synchronize()
         assert (pos == lay["positions"]).all()
@@ -63,23 +86,24 @@ def test_mphf_matches_oracle(shock, oracle_mod, N, rf):
 
 
 def test_mphf_default_parameters_full_size(shock, oracle_mod):
-    """200,000 keys with the default layout (buckets of 2000, leaves of 40 on
-    average, at most 56): the layout equals the oracle's split, a sample of
-    leaves has the oracle's seeds, the oracle's query over the exported
-    structure equals the GPU query for every key, and the positions are a
-    permutation of [0, N)."""
+    """200,000 keys with the default layout (buckets of 3000, leaves of 40 on
+    average, at most 56, ribbon retrieval): the layout equals the oracle's
+    split, a sample of leaves has the oracle's seeds, a sample of buckets has
+    the oracle's ribbon seed and bits, the oracle's query over the exported
+    structure equals the GPU query for every key, the positions are a
+    permutation of [0, N), and the space is at most 1.65 bits per key."""
     N = 200_000
     keys = splitmix64(2200, N)
     m, k = _build(shock, keys)
     try:
         info = m.info()
         print(f"[gpu] mphf info {info}", flush=True)
-        assert info["n_keys"] == N and 1.5 < info["bits_per_key"] < 2.6
+        assert info["n_keys"] == N and 1.5 < info["bits_per_key"] <= 1.65
         pos_t = m.query(k)
         srt, _ = torch.sort(pos_t)
         assert torch.equal(srt, torch.arange(N, device="cuda", dtype=torch.int64))
         ex = m.export()
-        rc, lay = oracle_mod.mphf_split(keys, 2000, 40, 56)
+        rc, lay = oracle_mod.mphf_split(keys, 3000, 40, 56)
         assert rc == 0
         for f in ("bucket_offset", "leaf_base", "sigma", "leaf_sizes"):
             assert (ex[f] == lay[f]).all(), f
@@ -88,9 +112,20 @@ def test_mphf_default_parameters_full_size(shock, oracle_mod):
         for j in pick:
             _, s, _ = oracle_mod.leaf_search(lay["leaf_keys"], offs[j:j + 2])
             assert int(s[0]) == int(ex["seeds"][j]), j
-        struct = dict(lay, seeds=ex["seeds"], rho=ex["rho"], z=ex["z"], leaf_target=40)
+        # ribbon systems of sampled buckets, from the GPU's own choices (the
+        # positions' structure is checked by the full query below)
+        pos = _host(pos_t)
+        struct = _oracle_struct(lay, ex)
+        for b in np.random.default_rng(2202).choice(lay["n_buckets"], 4, replace=False):
+            o0, o1 = int(lay["bucket_offset"][b]), int(lay["bucket_offset"][b + 1])
+            bk = lay["leaf_keys"][o0:o1]
+            vals = np.array([oracle_mod.ribbon_get(int(x), int(ex["rseed"][b]), oracle_mod.ribbon_cols(o1 - o0),
+                                                   ex["z"][int(ex["rbit_offset"][b]):]) for x in bk], np.uint8)
+            rc, r_o, z_o = oracle_mod.ribbon_build(bk, vals)
+            assert rc == 0 and r_o == int(ex["rseed"][b]), b
+            assert (z_o == ex["z"][int(ex["rbit_offset"][b]):int(ex["rbit_offset"][b + 1])]).all(), b
         rc, want = oracle_mod.mphf_query(struct, keys)
-        assert rc == 0 and (_host(pos_t) == want).all()
+        assert rc == 0 and (pos == want).all()
     finally:
         m.close()
 
@@ -189,7 +224,7 @@ def test_mphf_rotation_fitting_full_size(shock, oracle_mod):
         srt, _ = torch.sort(pos_t)
         assert torch.equal(srt, torch.arange(N, device="cuda", dtype=torch.int64))
         ex = m.export()
-        rc, lay = oracle_mod.mphf_split(keys, 2000, 40, 56)
+        rc, lay = oracle_mod.mphf_split(keys, 3000, 40, 56)
         assert rc == 0
         for f in ("bucket_offset", "leaf_base", "sigma", "leaf_sizes"):
             assert (ex[f] == lay[f]).all(), f
@@ -199,7 +234,7 @@ def test_mphf_rotation_fitting_full_size(shock, oracle_mod):
             n = int(offs[j + 1] - offs[j])
             want = int(s[0]) * n + int(r[0]) if n >= 2 else int(s[0])
             assert want == int(ex["seeds"][j]), j
-        struct = dict(lay, seeds=ex["seeds"], rho=ex["rho"], z=ex["z"], leaf_target=40, rf=True, partial_k=0)
+        struct = _oracle_struct(lay, ex, rf=True, partial_k=0)
         rc, want = oracle_mod.mphf_query(struct, keys)
         assert rc == 0 and (_host(pos_t) == want).all()
     finally:
@@ -222,7 +257,7 @@ def test_build_arena_reuse_across_sizes(shock, oracle_mod):
             assert rc == 0
             ex = m.export()
             assert (ex["seeds"] == lay["seeds"]).all(), step
-            assert ex["rho"] == lay["rho"] and (ex["z"] == lay["z"]).all(), step
+            assert _same_retrieval(ex, lay), step
             if N:
                 pos = _host(m.query(k))
                 torch.cuda.synchronize()
@@ -246,7 +281,7 @@ def test_mphf_more_buckets_than_the_lds_histogram(shock, oracle_mod, rf):
         assert len(ex["bucket_offset"]) == 9001
         assert (ex["bucket_offset"] == lay["bucket_offset"]).all()
         assert (ex["leaf_sizes"] == lay["leaf_sizes"]).all()
-        assert (ex["seeds"] == lay["seeds"]).all() and (ex["z"] == lay["z"]).all()
+        assert (ex["seeds"] == lay["seeds"]).all() and _same_retrieval(ex, lay)
         pos = _host(m.query(k))
         torch.cuda.synchronize()
         assert (pos == lay["positions"]).all()
@@ -260,13 +295,13 @@ def test_mphf_retrieval_on_both_sides_of_the_one_workgroup_limit(shock, oracle_m
     ones by the multi-launch rounds; at the limit and one key above it the
     retrieval seed and cells equal the oracle's."""
     keys = splitmix64(2500 + N, N)
-    m, k = _build(shock, keys, **SMALL)
+    m, k = _build(shock, keys, retrieval=XOR, **SMALL)
     try:
-        rc, lay = oracle_mod.mphf_build(keys, **SMALL)
+        rc, lay = oracle_mod.mphf_build(keys, retrieval=XOR, **SMALL)
         assert rc == 0
         ex = m.export()
         assert (ex["seeds"] == lay["seeds"]).all()
-        assert ex["rho"] == lay["rho"] and (ex["z"] == lay["z"]).all()
+        assert _same_retrieval(ex, lay)
         pos = _host(m.query(k))
         torch.cuda.synchronize()
         assert (pos == lay["positions"]).all()
@@ -286,7 +321,7 @@ def test_mphf_bipartite_leaves_match_oracle(shock, oracle_mod, N):
         ex = m.export()
         for f in ("bucket_offset", "leaf_base", "sigma", "leaf_sizes", "seeds"):
             assert (ex[f] == lay[f]).all(), f
-        assert ex["rho"] == lay["rho"] and (ex["z"] == lay["z"]).all()
+        assert _same_retrieval(ex, lay)
         pos = _host(m.query(k))
         torch.cuda.synchronize()
         assert (pos == lay["positions"]).all()
@@ -307,14 +342,14 @@ def test_mphf_bipartite_leaves_full_size(shock, oracle_mod):
         srt, _ = torch.sort(pos_t)
         assert torch.equal(srt, torch.arange(N, device="cuda", dtype=torch.int64))
         ex = m.export()
-        rc, lay = oracle_mod.mphf_split(keys, 2000, 40, 56)
+        rc, lay = oracle_mod.mphf_split(keys, 3000, 40, 56)
         assert rc == 0
         offs = lay["leaf_offsets"]
         pick = np.random.default_rng(2901).choice(lay["n_leaves"], 64, replace=False)
         for j in pick:
             _, a, b, _ = oracle_mod.bip_leaf_search(lay["leaf_keys"], offs[j:j + 2])
             assert int(ex["seeds"][j]) == oracle_mod.bip_pair_rank(int(a[0]), int(b[0])), j
-        struct = dict(lay, seeds=ex["seeds"], rho=ex["rho"], z=ex["z"], leaf_target=40, bip=True)
+        struct = _oracle_struct(lay, ex, bip=True)
         rc, want = oracle_mod.mphf_query(struct, keys)
         assert rc == 0 and (_host(pos_t) == want).all()
     finally:
