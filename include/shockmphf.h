@@ -79,7 +79,11 @@ typedef struct {
                                 repeated keys are then reported as SHOCK_ENOTFOUND (no retrieval seed
                                 solves them) rather than SHOCK_EDUPKEY; default 0 */
   uint32_t retrieval;        /* SHOCK_RETRIEVAL_RIBBON (default) or SHOCK_RETRIEVAL_XOR */
-  uint64_t reserved[2];
+  uint32_t ribbon_rows;      /* ribbon solver: rows one wave holds per 64-column block, at most 256;
+                                0 = 256.  A bucket that needs more is solved by the sequential walk
+                                instead, with the same result; smaller values only move buckets there */
+  uint32_t reserved0;
+  uint64_t reserved1;
 } shock_mphf_params;
 
 #define SHOCK_RETRIEVAL_RIBBON 0
@@ -105,7 +109,7 @@ typedef struct {
   uint32_t rho_tries;    /* XOR retrieval seeds tried */
   uint32_t retrieval;    /* SHOCK_RETRIEVAL_* */
   uint32_t max_rseed;    /* ribbon retrieval: the largest bucket seed */
-  uint32_t reserved0;
+  uint32_t ribbon_walked; /* ribbon retrieval: buckets solved by the sequential walk */
 } shock_mphf_stats;
 
 /* Defaults as documented above (bucket_size 3000, leaf_target 40, leaf_max

@@ -135,7 +135,9 @@ class MphfParams(ctypes.Structure):
         ("partial_k", ctypes.c_int32),
         ("bipartite", ctypes.c_uint32),
         ("retrieval", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint64 * 2),
+        ("ribbon_rows", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
+        ("reserved1", ctypes.c_uint64),
     ]
 
 
@@ -150,7 +152,7 @@ class MphfStats(ctypes.Structure):
         ("build_ms", ctypes.c_double), ("search_ms", ctypes.c_double),
         ("layout_ms", ctypes.c_double), ("search_call_ms", ctypes.c_double), ("codes_ms", ctypes.c_double),
         ("retrieval_ms", ctypes.c_double), ("rho_tries", ctypes.c_uint32), ("retrieval", ctypes.c_uint32),
-        ("max_rseed", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+        ("max_rseed", ctypes.c_uint32), ("ribbon_walked", ctypes.c_uint32),
     ]
 
     def as_dict(self):
@@ -752,7 +754,8 @@ class MPHF:
     queried on the GPU.  Raises ShockError if the build fails."""
 
     def __init__(self, keys, bucket_size=3000, leaf_target=40, leaf_max=56, rice_table=None, stream=None,
-                 rotation_fitting=False, partial_k=0, bipartite=False, retrieval=SHOCK_RETRIEVAL_RIBBON):
+                 rotation_fitting=False, partial_k=0, bipartite=False, retrieval=SHOCK_RETRIEVAL_RIBBON,
+                 ribbon_rows=0):
         import numpy as np
         if keys.device.type != "cuda" or keys.dtype.itemsize != 8:
             raise ValueError("keys must be a 64-bit device tensor")
@@ -766,6 +769,7 @@ class MPHF:
         p.rotation_fitting, p.partial_k = int(bool(rotation_fitting)), partial_k
         p.bipartite = int(bool(bipartite))
         p.retrieval = retrieval
+        p.ribbon_rows = ribbon_rows
         table = _table(rice_table)
         p.rice_k_by_n = ctypes.cast(table, ctypes.c_void_p)
         self._h = ctypes.c_void_p()

@@ -524,7 +524,7 @@ __global__ void bucket_table_kernel(const uint64_t *__restrict__ bucket_offset, 
 // leaves the others 0: the canonical solution.  The wave then writes the
 // bits at the bucket's offset (words shared with the neighbours by atomic OR
 // into the zeroed array).  Slots, values and the solution live in LDS (kLds)
-// or in a global region per bucket.
+// or in a global region per bucket.  With `only`, just the buckets it marks.
 // The readlane builtins return int: each half is taken as uint32_t before it
 // is widened, so the low half is never sign-extended into the high one.
 __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
@@ -545,10 +545,11 @@ __global__ __launch_bounds__(64) void ribbon_kernel(const uint64_t *__restrict__
                                                     const uint64_t *__restrict__ rib_base, uint64_t n_buckets,
                                                     uint64_t *slots_global, uint64_t lds_cap_words,
                                                     uint64_t *zbits, uint64_t zwords, uint8_t *rseed,
-                                                    unsigned long long *err) {
+                                                    const uint8_t *__restrict__ only, unsigned long long *err) {
   extern __shared__ uint64_t lds_words[];
   const uint32_t lane = lane_id();
   for (uint64_t b = blockIdx.x; b < n_buckets; b += gridDim.x) {
+    if (only && !only[b]) continue;
     const uint64_t o = bucket_offset[b], m = bucket_offset[b + 1] - o;
     if (m == 0) {
       if (lane == 0) rseed[b] = 0;
@@ -664,6 +665,329 @@ __global__ __launch_bounds__(64) void ribbon_kernel(const uint64_t *__restrict__
         atomicOr((unsigned long long *)&zbits[w], (unsigned long long)x);
       }
     }
+  }
+}
+
+// Ribbon retrieval by column blocks: the systems, seeds and solutions of
+// ribbon_kernel with few dependent memory round trips.  Each seed's rows are
+// sorted by the 64-column block of their start (a counting sort of key
+// indices in LDS).  A wave holds the rows that can have a set bit in the
+// current block, each as a 128-bit window over that block and the next (a
+// row's 64 columns never reach past the next block), up to kRowSlots rows per
+// lane.  For each column j of the block, in order, a ballot finds the rows
+// whose lowest set bit is j (earlier columns are already clear in every row);
+// the first of them is the column's pivot and is added to all of them, itself
+// included, which clears column j everywhere.  A row that vanishes with value
+// 1 contradicts the system.  After the block the surviving rows move 64
+// columns on and are compacted in LDS with the rows that start in the next
+// block.  The pivots' columns are the leading columns of an echelon form,
+// hence the pivot columns of the system, so back substitution over the stored
+// pivot rows with the other columns 0 gives the canonical solution; a seed is
+// solvable here exactly when it is for the walk.  The kS waves of a workgroup
+// try kS consecutive seeds of one bucket at once and the smallest that solves
+// wins.  A bucket with more rows in a block than a wave holds (row_cap) is
+// marked in `spill` for the walk.
+constexpr uint32_t kRowSlots = 4;
+constexpr uint32_t kRowCapMax = 64 * kRowSlots;
+constexpr uint64_t kBlockMaxM = 16384;        // larger buckets: the walk
+constexpr uint64_t kErrRibbonSpill = 32;      // buckets marked for the walk
+constexpr uint32_t kRibWaves = 2;             // seeds tried at once per bucket
+enum : uint32_t { kTryContradiction = 0, kTrySolved = 1, kTrySpill = 2 };
+
+__host__ __device__ __forceinline__ uint64_t rib_blocks(uint64_t m) { return (ribbon_cols(m) + 63) / 64; }
+// LDS per wave for buckets of up to max_m keys: the row stage (low and high
+// words, value bytes), block starts and cursors (u32, W + 1 each), the sorted
+// key indices (u16).
+__host__ __device__ __forceinline__ uint32_t rib_lds_wave_bytes(uint64_t max_m) {
+  const uint64_t b = (uint64_t)kRowCapMax * 17 + 8 * (rib_blocks(max_m) + 2) + 2 * max_m;
+  return (uint32_t)((b + 15) & ~15ull);
+}
+// Global scratch per wave: every column's pivot row (low and high words, value byte).
+__host__ __device__ __forceinline__ uint64_t rib_piv_wave_bytes(uint64_t max_m) {
+  return ((17 * 64 * rib_blocks(max_m) + 255) / 256) * 256;
+}
+__device__ __forceinline__ uint32_t ribbon_start(uint64_t x, uint64_t rmix, uint64_t cols) {
+  return (uint32_t)(((fmix64(x ^ rmix) >> 32) * (cols - 63)) >> 32);
+}
+
+// The 64 columns of one block on NS row slots; lane j keeps column j's pivot.
+template <uint32_t NS>
+__device__ __forceinline__ void rib_columns(uint64_t (&lo)[kRowSlots], uint64_t (&hi)[kRowSlots], uint32_t &vv,
+                                            uint64_t &plo, uint64_t &phi, uint32_t &pv) {
+  const uint32_t lane = lane_id();
+  for (uint32_t j = 0; j < 64; ++j) {
+    bool bit[NS];
+    uint64_t bm[NS];
+#pragma unroll
+    for (uint32_t k = 0; k < NS; ++k) {
+      bit[k] = ((lo[k] >> j) & 1) != 0;
+      bm[k] = __ballot(bit[k]);
+    }
+    uint32_t ks = NS, ls = 0;
+#pragma unroll
+    for (int k = (int)NS - 1; k >= 0; --k)
+      if (bm[k]) {
+        ks = (uint32_t)k;
+        ls = (uint32_t)__builtin_ctzll(bm[k]);
+      }
+    if (ks == NS) continue;  // no row has column j: not a pivot column
+    uint64_t Plo = 0, Phi = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < NS; ++k)
+      if (ks == k) {
+        Plo = lane64(lo[k], ls);
+        Phi = lane64(hi[k], ls);
+      }
+    const uint32_t Pv = ((uint32_t)__builtin_amdgcn_readlane(vv, ls) >> ks) & 1u;
+    if (lane == j) {
+      plo = Plo;
+      phi = Phi;
+      pv = Pv;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < NS; ++k)
+      if (bit[k]) {
+        lo[k] ^= Plo;
+        hi[k] ^= Phi;
+        vv ^= Pv << k;
+      }
+  }
+}
+
+// One seed's elimination; the pivot rows go to plo_g / phi_g / pv_g.
+__device__ uint32_t rib_try(const uint64_t *__restrict__ keys, const uint8_t *__restrict__ choice, uint64_t o,
+                           uint32_t m, uint64_t cols, uint32_t W, uint64_t rmix, uint32_t row_cap, uint64_t *st_lo,
+                           uint64_t *st_hi, uint8_t *st_v, uint32_t *cnt, uint32_t *cur, uint16_t *idx,
+                           uint64_t *plo_g, uint64_t *phi_g, uint8_t *pv_g, unsigned long long *err) {
+  const uint32_t lane = lane_id();
+  // counting sort of the key indices by start block: cnt[k] = rows starting before block k
+  for (uint32_t k = lane; k <= W; k += 64) cnt[k] = 0;
+  wave_sync();
+  for (uint32_t i = lane; i < m; i += 64) atomicAdd(&cnt[(ribbon_start(keys[o + i], rmix, cols) >> 6) + 1], 1u);
+  wave_sync();
+  uint32_t carry = 0;
+  for (uint32_t k0 = 0; k0 <= W; k0 += 64) {
+    const uint32_t k = k0 + lane;
+    uint32_t x = k <= W ? cnt[k] : 0u;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d);
+      if (lane >= (uint32_t)d) x += y;
+    }
+    x += carry;
+    if (k <= W) {
+      cnt[k] = x;
+      cur[k] = x;
+    }
+    carry = __shfl(x, 63);
+  }
+  wave_sync();
+  for (uint32_t i = lane; i < m; i += 64) {
+    const uint32_t p = atomicAdd(&cur[ribbon_start(keys[o + i], rmix, cols) >> 6], 1u);
+    idx[p] = (uint16_t)i;
+  }
+  wave_sync();
+  uint64_t lo[kRowSlots], hi[kRowSlots];
+  uint32_t vv = 0, nslot = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kRowSlots; ++k) lo[k] = hi[k] = 0;
+  for (uint32_t blk = 0; blk <= W; ++blk) {
+    // the rows left from the previous block move on 64 columns; one that
+    // vanished with value 1 contradicts the system
+    uint32_t live = 0;
+    bool bad = false, stray = false;
+#pragma unroll
+    for (uint32_t k = 0; k < kRowSlots; ++k) {
+      if (k < nslot) {
+        stray |= lo[k] != 0;
+        const bool alive = hi[k] != 0;
+        const uint32_t v = (vv >> k) & 1u;
+        bad |= !alive && v;
+        const uint64_t am = __ballot(alive);
+        if (alive) {
+          const uint32_t p = live + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(am >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)am, 0u));
+          st_lo[p] = hi[k];
+          st_hi[p] = 0;
+          st_v[p] = (uint8_t)v;
+        }
+        live += (uint32_t)__popcll(am);
+      }
+    }
+    if (__ballot(stray)) {  // every column of the block was cleared: cannot happen
+      if (lane == 0) atomicOr(err, kErrRibbonInternal);
+      return kTryContradiction;
+    }
+    if (__ballot(bad)) return kTryContradiction;
+    if (blk == W) {
+      if (live) {  // rows past the last column: cannot happen
+        if (lane == 0) atomicOr(err, kErrRibbonInternal);
+        return kTryContradiction;
+      }
+      return kTrySolved;
+    }
+    // with the rows that start in this block
+    const uint32_t a0 = cnt[blk], a1 = cnt[blk + 1];
+    const uint32_t total = live + (a1 - a0);
+    if (total > row_cap) return kTrySpill;
+    for (uint32_t t = lane; t < a1 - a0; t += 64) {
+      const uint32_t i = idx[a0 + t];
+      uint64_t s, c;
+      ribbon_row(keys[o + i], rmix, cols, s, c);
+      const uint32_t off = (uint32_t)(s & 63);
+      st_lo[live + t] = c << off;
+      st_hi[live + t] = off ? c >> (64 - off) : 0;
+      st_v[live + t] = (uint8_t)(choice[o + i] & 1);
+    }
+    wave_sync();
+    nslot = (total + 63) >> 6;
+    vv = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kRowSlots; ++k) {
+      const uint32_t p = 64 * k + lane;
+      const bool in = p < total;
+      lo[k] = in ? st_lo[p] : 0;
+      hi[k] = in ? st_hi[p] : 0;
+      vv |= (in ? (uint32_t)(st_v[p] & 1) : 0u) << k;
+    }
+    wave_sync();
+    uint64_t plo = 0, phi = 0;
+    uint32_t pv = 0;
+    switch (nslot) {
+      case 1: rib_columns<1>(lo, hi, vv, plo, phi, pv); break;
+      case 2: rib_columns<2>(lo, hi, vv, plo, phi, pv); break;
+      case 3: rib_columns<3>(lo, hi, vv, plo, phi, pv); break;
+      case 4: rib_columns<4>(lo, hi, vv, plo, phi, pv); break;
+      default: break;  // no rows
+    }
+    plo_g[64 * blk + lane] = plo;
+    phi_g[64 * blk + lane] = phi;
+    pv_g[64 * blk + lane] = (uint8_t)pv;
+  }
+  return kTrySolved;  // not reached
+}
+
+// Back substitution over one wave's pivot rows, last block first: lane j holds
+// column j's row; z of the next block enters through the rows' high words, and
+// within the block column j takes its value plus the parity of its row with
+// the columns after it.  sol: W words.
+__device__ void rib_back(uint32_t W, const uint64_t *plo_g, const uint64_t *phi_g, const uint8_t *pv_g,
+                         uint64_t *sol) {
+  const uint32_t lane = lane_id();
+  uint64_t zn = 0;
+  uint64_t nlo = plo_g[64 * (W - 1) + lane], nhi = phi_g[64 * (W - 1) + lane];
+  uint32_t nv = pv_g[64 * (W - 1) + lane];
+  for (int blk = (int)W - 1; blk >= 0; --blk) {
+    const uint64_t plo = nlo, phi = nhi;
+    const uint32_t pv = nv;
+    if (blk > 0) {
+      nlo = plo_g[64 * (blk - 1) + lane];
+      nhi = phi_g[64 * (blk - 1) + lane];
+      nv = pv_g[64 * (blk - 1) + lane];
+    }
+    const uint64_t pm = __ballot((plo >> lane) & 1);
+    const uint64_t tm = __ballot(((pv ^ (uint32_t)__popcll(phi & zn)) & 1u) != 0);
+    uint64_t zc = 0;
+    for (uint64_t todo = pm; todo;) {
+      const uint32_t j = 63 - (uint32_t)__builtin_clzll(todo);
+      todo &= ~(1ull << j);
+      const uint64_t row = lane64(plo, j);
+      zc |= (((tm >> j) ^ (uint64_t)__popcll(row & zc)) & 1) << j;
+    }
+    if (lane == 0) sol[blk] = zc;
+    zn = zc;
+  }
+}
+
+template <uint32_t kS>
+__global__ __launch_bounds__(64 * kS) void ribbon_block_kernel(
+    const uint64_t *__restrict__ keys, const uint8_t *__restrict__ choice, const uint64_t *__restrict__ bucket_offset,
+    const uint64_t *__restrict__ rib_base, uint64_t n_buckets, uint8_t *piv, uint64_t piv_wave_bytes,
+    uint32_t lds_wave_bytes, uint32_t row_cap, uint64_t *zbits, uint64_t zwords, uint8_t *rseed, uint8_t *spill,
+    unsigned long long *err) {
+  extern __shared__ __align__(16) unsigned char rib_lds[];
+  __shared__ uint32_t outcome[kS];
+  const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+  unsigned char *lw = rib_lds + (size_t)wave * lds_wave_bytes;
+  uint64_t *st_lo = reinterpret_cast<uint64_t *>(lw);
+  uint64_t *st_hi = st_lo + kRowCapMax;
+  uint8_t *st_v = reinterpret_cast<uint8_t *>(st_hi + kRowCapMax);
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(st_v + kRowCapMax);
+  uint8_t *pw = piv + ((uint64_t)blockIdx.x * kS + wave) * piv_wave_bytes;
+  for (uint64_t b = blockIdx.x; b < n_buckets; b += gridDim.x) {
+    const uint64_t o = bucket_offset[b], m = bucket_offset[b + 1] - o;
+    if (m == 0) {
+      if (threadIdx.x == 0) rseed[b] = 0;
+      continue;
+    }
+    const uint64_t cols = ribbon_cols(m), rb = rib_base[b];
+    const uint32_t W = (uint32_t)rib_blocks(m);
+    uint32_t *cur = cnt + W + 1;
+    uint16_t *idx = reinterpret_cast<uint16_t *>(cur + W + 1);
+    uint64_t *plo_g = reinterpret_cast<uint64_t *>(pw), *phi_g = plo_g + 64 * (uint64_t)W;
+    uint8_t *pv_g = reinterpret_cast<uint8_t *>(phi_g + 64 * (uint64_t)W);
+    uint32_t win = kRibbonSeeds;
+    bool spilled = false;
+    for (uint32_t r0 = 0; r0 < kRibbonSeeds; r0 += kS) {
+      const uint32_t res = rib_try(keys, choice, o, (uint32_t)m, cols, W, ribbon_mix(r0 + wave), row_cap, st_lo,
+                                   st_hi, st_v, cnt, cur, idx, plo_g, phi_g, pv_g, err);
+      if (lane == 0) outcome[wave] = res;
+      __syncthreads();
+      uint32_t first = kS;
+      bool sp = false;
+      for (uint32_t w = 0; w < kS; ++w) {
+        const uint32_t x = outcome[w];
+        if (x == kTrySolved) {
+          first = w;
+          break;
+        }
+        if (x == kTrySpill) {  // a smaller seed's outcome is unknown here
+          sp = true;
+          break;
+        }
+      }
+      __syncthreads();
+      if (first < kS) {
+        win = r0 + first;
+        break;
+      }
+      if (sp) {
+        spilled = true;
+        break;
+      }
+    }
+    if (spilled) {
+      if (threadIdx.x == 0) {
+        spill[b] = 1;
+        atomicOr(err, kErrRibbonSpill);
+      }
+      continue;
+    }
+    if (win == kRibbonSeeds) {
+      if (threadIdx.x == 0) atomicOr(err, kErrRibbon);
+      continue;
+    }
+    if (wave != win % kS) continue;
+    uint64_t *sol = st_lo;  // W <= 2 kRowCapMax words of the stage
+    rib_back(W, plo_g, phi_g, pv_g, sol);
+    wave_sync();
+    if (lane == 0) rseed[b] = (uint8_t)win;
+    // bits [rb, rb + cols) of the global array
+    const uint64_t w0 = rb >> 6, w1 = (rb + cols - 1) >> 6;
+    for (uint64_t w = w0 + lane; w <= w1 && w < zwords; w += 64) {
+      const uint64_t gb = w << 6;
+      uint64_t x = gb >= rb ? bits_at(sol, W, gb - rb) : sol[0] << (rb - gb);
+      if (gb + 64 <= rb + cols) {
+        if (gb >= rb) {
+          zbits[w] = x;
+        } else {
+          atomicOr((unsigned long long *)&zbits[w], (unsigned long long)x);
+        }
+      } else {
+        x &= (1ull << (rb + cols - gb)) - 1;
+        atomicOr((unsigned long long *)&zbits[w], (unsigned long long)x);
+      }
+    }
+    wave_sync();  // the stage is the next bucket's
   }
 }
 
@@ -1257,6 +1581,7 @@ struct shock_mphf {
   double build_ms = 0, search_ms = 0;
   double layout_ms = 0, search_call_ms = 0, codes_ms = 0, retrieval_ms = 0;
   uint32_t rho_tries = 0, max_rseed = 0;
+  uint64_t rib_walked = 0;  // ribbon buckets solved by the walk
 };
 
 namespace {
@@ -1275,6 +1600,7 @@ struct Arena {
   // the leaf search runs on the caller's stream, and two events joining them
   hipStream_t aux = nullptr;
   hipEvent_t ev_choice = nullptr, ev_done = nullptr;
+  int cus = 0;  // compute units of the device
 };
 constexpr size_t kPinnedWords = 16;
 thread_local std::vector<Arena> t_arena;
@@ -1325,6 +1651,10 @@ hipError_t reserve_scratch(size_t bytes, Scratch &S) {
     }
     A.cap = grown;
   }
+  if (!A.cus) {
+    hipDeviceProp_t prop;
+    A.cus = hipGetDeviceProperties(&prop, dev) == hipSuccess ? prop.multiProcessorCount : 256;
+  }
   S.base = A.base;
   S.cap = A.cap;
   S.used = 0;
@@ -1362,6 +1692,16 @@ void free_mphf(shock_mphf *m) {
     }                                       \
   } while (0)
 
+// Workgroups of the ribbon block kernel that the LDS of one CU holds (160 KiB,
+// at most 32 waves), for buckets of up to max_m keys; 0 if one workgroup's
+// LDS would pass 64 KiB.
+static uint64_t rib_groups_per_cu(uint64_t max_m) {
+  const uint64_t wg = (uint64_t)kRibWaves * rib_lds_wave_bytes(max_m);
+  if (max_m > kBlockMaxM || wg > 65536) return 0;
+  const uint64_t by_lds = (160ull << 10) / wg, by_waves = 32 / kRibWaves;
+  return by_lds < by_waves ? by_lds : by_waves;
+}
+
 static double ms_since(std::chrono::steady_clock::time_point t) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
 }
@@ -1378,12 +1718,24 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   const uint64_t seg_r = (123 * N + 299) / 300 + 8, cells_r = 3 * seg_r;
   const bool xor_ret = M->retrieval == kRetrievalXor;
   // ribbon slots in global memory, for buckets too large for the LDS variant
+  // of the walk; the same region holds the block kernel's pivot rows, sized
+  // here for buckets of up to 9/8 of the expected size plus 256 (the grid
+  // shrinks to fit if the largest bucket is larger)
   const uint64_t rib_max = N + N / 50 + 65 * B;
   const uint64_t slot_words = rib_max + rib_max / 8 + 2 * (rib_max / 64) + 3 * B + 64;
+  uint64_t m_est = (uint64_t)P.bucket_size + P.bucket_size / 8 + 256;
+  if (m_est > kBlockMaxM) m_est = kBlockMaxM;
+  int dev_now = 0;
+  (void)hipGetDevice(&dev_now);
+  const uint64_t cus_now = ((int)t_arena.size() > dev_now && t_arena[dev_now].cus) ? t_arena[dev_now].cus : 256;
+  uint64_t groups_est = cus_now * rib_groups_per_cu(m_est);
+  if (groups_est > B) groups_est = B;
+  const uint64_t piv_bytes_est = groups_est * kRibWaves * rib_piv_wave_bytes(m_est);
+  const uint64_t rib_area = xor_ret ? 0 : (slot_words * 8 > piv_bytes_est ? slot_words * 8 : piv_bytes_est);
   const size_t scratch_bytes = align256(2 * 8) + align256(B * 4) + 2 * align256(N * 8) + align256((Lmax + 1) * 8) +
                                2 * align256(Lmax * 8) + align256(Lmax * 4) + 2 * align256(N ? N : 1) +
                                3 * align256((B + 1) * 8) + 2 * align256(Lmax + 8) + align256((Lmax / 64 + 3) * 16) +
-                               2 * align256((B + 1) * 8) + align256(slot_words * 8) +
+                               2 * align256((B + 1) * 8) + align256(rib_area) + align256(B) +
                                (xor_ret ? align256(((N + 31) / 32) * 4) + align256(N * 4) + 2 * align256(cells_r * 8) +
                                               align256((kMaxPeelRounds + 1) * 8) + align256(kPkWords * 8) +
                                               align256(cells_r)
@@ -1395,7 +1747,7 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   // pinned: [0] error bits, [1] n_leaves, [2] largest bucket, [3] ribbon bits;
   // [4, 4 + kPkWords) the XOR retrieval's counters
   uint64_t *host = S.pinned;
-  HIP_TRY(S.alloc(&err, 2));
+  HIP_TRY(S.alloc(&err, 3));
   uint32_t *counts = nullptr;
   HIP_TRY(S.alloc(&counts, B));
   uint64_t *bucket_offset = nullptr, *leaf_base = nullptr, *rib_base = nullptr;
@@ -1403,7 +1755,7 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   HIP_TRY(S.alloc(&leaf_base, B + 1));
   HIP_TRY(S.alloc(&rib_base, B + 1));
   HIP_TRY(hipMalloc((void **)&M->sigma, B * sizeof(uint16_t)));
-  HIP_TRY(hipMemsetAsync(err, 0, 2 * sizeof(unsigned long long), stream));
+  HIP_TRY(hipMemsetAsync(err, 0, 3 * sizeof(unsigned long long), stream));
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(B, 256)), dim3(256), 0, stream, counts, B, 0u);
   const bool lds_layout = B <= kLdsBuckets;
   const int layout_grid = (int)((N + kLayoutChunk - 1) / kLayoutChunk);
@@ -1610,26 +1962,60 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
     HIP_TRY(hipMalloc((void **)&M->rseed, B));
     hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(M->zwords, 256)), dim3(256), 0, stream,
                        (unsigned long long *)M->zbits, M->zwords);
+    // the block kernel when a bucket's stage, counts and indices fit its
+    // LDS; buckets it marks, or all if none fit, go to the walk, whose slots,
+    // values and solution sit in LDS unless the largest bucket is too large
+    uint8_t *rib_region = nullptr, *spill = nullptr;
+    HIP_TRY(S.alloc(&rib_region, rib_area));
+    HIP_TRY(S.alloc(&spill, B));
     const uint64_t max_cols = ribbon_cols(max_m);
     const size_t lds_bytes = (max_cols + max_cols / 8 + 1 + (max_cols + 63) / 64 + 1) * 8;
     const int grid = (int)(B < 65536 ? B : 65536);
-    if (lds_bytes <= 65536) {
-      hipLaunchKernelGGL(ribbon_kernel<true>, dim3(grid), dim3(64), lds_bytes, stream, (const uint64_t *)leaf_keys,
-                         (const uint8_t *)choice, (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, B,
-                         (uint64_t *)nullptr, (uint64_t)(lds_bytes / 8), M->zbits, M->zwords, M->rseed, err);
-    } else {
-      uint64_t *slots = nullptr;
-      HIP_TRY(S.alloc(&slots, slot_words));
-      hipLaunchKernelGGL(ribbon_kernel<false>, dim3(grid), dim3(64), 0, stream, (const uint64_t *)leaf_keys,
-                         (const uint8_t *)choice, (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, B,
-                         slots, (uint64_t)0, M->zbits, M->zwords, M->rseed, err);
+    const uint32_t row_cap = P.ribbon_rows ? P.ribbon_rows : kRowCapMax;
+    uint64_t groups = (uint64_t)S.arena->cus * rib_groups_per_cu(max_m);
+    if (groups > B) groups = B;
+    const uint64_t piv_wave = rib_piv_wave_bytes(max_m);
+    if (groups * kRibWaves * piv_wave > rib_area) groups = rib_area / (kRibWaves * piv_wave);
+    bool walk_all = groups == 0;
+    if (!walk_all) {
+      hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(B, 256)), dim3(256), 0, stream, spill, B);
+      const uint32_t lw = rib_lds_wave_bytes(max_m);
+      hipLaunchKernelGGL(ribbon_block_kernel<kRibWaves>, dim3((uint32_t)groups), dim3(64 * kRibWaves),
+                         (size_t)kRibWaves * lw, stream, (const uint64_t *)leaf_keys, (const uint8_t *)choice,
+                         (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, B, rib_region, piv_wave, lw,
+                         row_cap, M->zbits, M->zwords, M->rseed, spill, err);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
     }
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
+    const bool walk_some = !walk_all && (host[0] & kErrRibbonSpill) && !(host[0] & (kErrRibbon | kErrRibbonInternal));
+    if (walk_all || walk_some) {
+      const uint8_t *only = walk_all ? nullptr : spill;
+      if (lds_bytes <= 65536) {
+        hipLaunchKernelGGL(ribbon_kernel<true>, dim3(grid), dim3(64), lds_bytes, stream, (const uint64_t *)leaf_keys,
+                           (const uint8_t *)choice, (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, B,
+                           (uint64_t *)nullptr, (uint64_t)(lds_bytes / 8), M->zbits, M->zwords, M->rseed, only, err);
+      } else {
+        hipLaunchKernelGGL(ribbon_kernel<false>, dim3(grid), dim3(64), 0, stream, (const uint64_t *)leaf_keys,
+                           (const uint8_t *)choice, (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, B,
+                           reinterpret_cast<uint64_t *>(rib_region), (uint64_t)0, M->zbits, M->zwords, M->rseed,
+                           only, err);
+      }
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+    }
+    if (walk_some) {
+      std::vector<uint8_t> hsp(B);
+      HIP_TRY(hipMemcpy(hsp.data(), spill, B, hipMemcpyDeviceToHost));
+      for (uint64_t b = 0; b < B; ++b) M->rib_walked += hsp[b];
+    } else if (walk_all) {
+      M->rib_walked = B;
+    }
     if (host[0] & kErrCodeSpan) return SHOCK_EINVAL;
     if (host[0] & kErrRibbonInternal) {
-      shock_internal_set_error("ribbon retrieval: a bucket exceeded the launch's LDS or a walk left its band", hipErrorInvalidValue);
+      shock_internal_set_error("ribbon retrieval: a bucket exceeded the launch's LDS or a row left its band",
+                               hipErrorInvalidValue);
       return SHOCK_EHIP;
     }
     if (host[0] & kErrRibbon) return SHOCK_ENOTFOUND;
@@ -1780,6 +2166,7 @@ int shock_mphf_build(const uint64_t *keys, uint64_t n_keys, const shock_mphf_par
   if (P.rotation_fitting > 1 || (P.partial_k != 0 && P.partial_k != 1 && P.partial_k != 8)) return SHOCK_EINVAL;
   if (P.bipartite > 1 || (P.bipartite && P.rotation_fitting)) return SHOCK_EINVAL;
   if (P.retrieval != SHOCK_RETRIEVAL_RIBBON && P.retrieval != SHOCK_RETRIEVAL_XOR) return SHOCK_EINVAL;
+  if (P.ribbon_rows > kRowCapMax) return SHOCK_EINVAL;
   *out = nullptr;
   shock_mphf *M = new shock_mphf;
   M->leaf_target = P.leaf_target;
@@ -1877,6 +2264,7 @@ int shock_mphf_info(const shock_mphf *m, shock_mphf_stats *info) {
   info->rho_tries = m->rho_tries;
   info->retrieval = m->retrieval == kRetrievalXor ? SHOCK_RETRIEVAL_XOR : SHOCK_RETRIEVAL_RIBBON;
   info->max_rseed = m->max_rseed;
+  info->ribbon_walked = (uint32_t)m->rib_walked;
   return SHOCK_OK;
 }
 

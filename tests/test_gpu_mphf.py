@@ -85,6 +85,39 @@ def test_mphf_matches_oracle(shock, oracle_mod, N, rf, ret):
         m.close()
 
 
+@pytest.mark.parametrize("rows", [1, 120, 256])
+def test_ribbon_row_capacity_moves_buckets_to_the_walk_with_equal_results(shock, oracle_mod, rows):
+    """The ribbon solver by column blocks hands a bucket to the sequential walk
+    when a block holds more rows than ribbon_rows; either way the ribbon seeds
+    and bits are the oracle's.  One row sends every bucket of two or more keys
+    to the walk, 120 some of them (buckets of about 300 keys put about 80
+    rows in a block, plus the rows left from the block before; 5 of these 20
+    buckets pass 120 at a seed tried), 256 none."""
+    N = 6000
+    keys = splitmix64(2150, N)
+    m, k = _build(shock, keys, ribbon_rows=rows, **SMALL)
+    try:
+        rc, lay = oracle_mod.mphf_build(keys, rf=False, retrieval=RIBBON, **SMALL)
+        assert rc == 0
+        ex, info = m.export(), m.info()
+        print(f"[gpu] ribbon_rows={rows}: walked {info['ribbon_walked']} of {info['n_buckets']}", flush=True)
+        assert _same_retrieval(ex, lay)
+        assert (ex["seeds"] == lay["seeds"]).all()
+        sizes = np.diff(lay["bucket_offset"].astype(np.int64))
+        if rows == 1:
+            assert info["ribbon_walked"] == int((sizes >= 2).sum())
+        elif rows == 120:
+            assert 0 < info["ribbon_walked"] < info["n_buckets"]
+        else:
+            assert info["ribbon_walked"] == 0
+        pos = _host(m.query(k))
+        assert (pos == lay["positions"]).all()
+    finally:
+        m.close()
+    with pytest.raises(shock.ShockError):
+        shock.MPHF(k, ribbon_rows=257, **SMALL)
+
+
 def test_mphf_default_parameters_full_size(shock, oracle_mod):
     """200,000 keys with the default layout (buckets of 3000, leaves of 40 on
     average, at most 56, ribbon retrieval): the layout equals the oracle's
@@ -99,6 +132,7 @@ def test_mphf_default_parameters_full_size(shock, oracle_mod):
         info = m.info()
         print(f"[gpu] mphf info {info}", flush=True)
         assert info["n_keys"] == N and 1.5 < info["bits_per_key"] <= 1.65
+        assert info["ribbon_walked"] == 0  # every bucket by column blocks
         pos_t = m.query(k)
         srt, _ = torch.sort(pos_t)
         assert torch.equal(srt, torch.arange(N, device="cuda", dtype=torch.int64))
