@@ -672,13 +672,15 @@ __global__ __launch_bounds__(64) void ribbon_kernel(const uint64_t *__restrict__
 // ribbon_kernel with few dependent memory round trips.  Each seed's rows are
 // sorted by the 64-column block of their start (a counting sort of key
 // indices in LDS).  A wave holds the rows that can have a set bit in the
-// current block, each as a 128-bit window over that block and the next (a
-// row's 64 columns never reach past the next block), up to kRowSlots rows per
-// lane.  For each column j of the block, in order, a ballot finds the rows
-// whose lowest set bit is j (earlier columns are already clear in every row);
-// the first of them is the column's pivot and is added to all of them, itself
-// included, which clears column j everywhere.  A row that vanishes with value
-// 1 contradicts the system.  After the block the surviving rows move 64
+// current block, each as a 128-bit window over that block and the next, up to
+// kRowSlots rows per lane.  A row starting in the block reaches at most
+// column 126 of the window and a row left from the block before at most 62,
+// so bit 127 is free and carries the row's value, which every row sum then
+// adds along.  For each column j of the block, in order, a ballot finds the
+// rows whose lowest set bit is j (earlier columns are already clear in every
+// row); the first of them is the column's pivot and is added to all of them,
+// itself included, which clears column j everywhere.  A row that vanishes with
+// value 1 contradicts the system.  After the block the surviving rows move 64
 // columns on and are compacted in LDS with the rows that start in the next
 // block.  The pivots' columns are the leading columns of an echelon form,
 // hence the pivot columns of the system, so back substitution over the stored
@@ -692,73 +694,88 @@ constexpr uint32_t kRowCapMax = 64 * kRowSlots;
 constexpr uint64_t kBlockMaxM = 16384;        // larger buckets: the walk
 constexpr uint64_t kErrRibbonSpill = 32;      // buckets marked for the walk
 constexpr uint32_t kRibWaves = 2;             // seeds tried at once per bucket
+constexpr uint64_t kValueBit = 1ull << 63;    // of a row's high word
 enum : uint32_t { kTryContradiction = 0, kTrySolved = 1, kTrySpill = 2 };
 
 __host__ __device__ __forceinline__ uint64_t rib_blocks(uint64_t m) { return (ribbon_cols(m) + 63) / 64; }
 // LDS per wave for buckets of up to max_m keys: the row stage (low and high
-// words, value bytes), block starts and cursors (u32, W + 1 each), the sorted
-// key indices (u16).
+// words), block starts and cursors (u32, W + 1 each), the sorted key indices
+// (u16).
 __host__ __device__ __forceinline__ uint32_t rib_lds_wave_bytes(uint64_t max_m) {
-  const uint64_t b = (uint64_t)kRowCapMax * 17 + 8 * (rib_blocks(max_m) + 2) + 2 * max_m;
+  const uint64_t b = (uint64_t)kRowCapMax * 16 + 8 * (rib_blocks(max_m) + 2) + 2 * max_m;
   return (uint32_t)((b + 15) & ~15ull);
 }
-// Global scratch per wave: every column's pivot row (low and high words, value byte).
+// Global scratch per wave: every column's pivot row (low and high words).
 __host__ __device__ __forceinline__ uint64_t rib_piv_wave_bytes(uint64_t max_m) {
-  return ((17 * 64 * rib_blocks(max_m) + 255) / 256) * 256;
+  return ((16 * 64 * rib_blocks(max_m) + 255) / 256) * 256;
 }
 __device__ __forceinline__ uint32_t ribbon_start(uint64_t x, uint64_t rmix, uint64_t cols) {
   return (uint32_t)(((fmix64(x ^ rmix) >> 32) * (cols - 63)) >> 32);
 }
-
-// The 64 columns of one block on NS row slots; lane j keeps column j's pivot.
-template <uint32_t NS>
-__device__ __forceinline__ void rib_columns(uint64_t (&lo)[kRowSlots], uint64_t (&hi)[kRowSlots], uint32_t &vv,
-                                            uint64_t &plo, uint64_t &phi, uint32_t &pv) {
+// Columns 32 h .. 32 h + 31 of one block on NS row slots; lane j keeps column
+// j's pivot row.
+template <uint32_t NS, uint32_t h>
+__device__ __forceinline__ void rib_half(uint64_t (&lo)[kRowSlots], uint64_t (&hi)[kRowSlots], uint64_t &plo,
+                                         uint64_t &phi) {
   const uint32_t lane = lane_id();
-  for (uint32_t j = 0; j < 64; ++j) {
+  for (uint32_t jj = 0; jj < 32; ++jj) {
     bool bit[NS];
-    uint64_t bm[NS];
+    uint64_t bm[NS], any = 0;
 #pragma unroll
     for (uint32_t k = 0; k < NS; ++k) {
-      bit[k] = ((lo[k] >> j) & 1) != 0;
+      bit[k] = (int32_t)((uint32_t)(lo[k] >> (32 * h)) << (31 - jj)) < 0;
       bm[k] = __ballot(bit[k]);
+      any |= bm[k];
     }
-    uint32_t ks = NS, ls = 0;
-#pragma unroll
-    for (int k = (int)NS - 1; k >= 0; --k)
-      if (bm[k]) {
-        ks = (uint32_t)k;
-        ls = (uint32_t)__builtin_ctzll(bm[k]);
-      }
-    if (ks == NS) continue;  // no row has column j: not a pivot column
-    uint64_t Plo = 0, Phi = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < NS; ++k)
-      if (ks == k) {
-        Plo = lane64(lo[k], ls);
-        Phi = lane64(hi[k], ls);
-      }
-    const uint32_t Pv = ((uint32_t)__builtin_amdgcn_readlane(vv, ls) >> ks) & 1u;
-    if (lane == j) {
+    if (!any) continue;  // no row has this column: not a pivot column
+    uint64_t Plo, Phi;
+    if (bm[0]) {
+      const uint32_t ls = (uint32_t)__builtin_ctzll(bm[0]);
+      Plo = lane64(lo[0], ls);
+      Phi = lane64(hi[0], ls);
+    } else if (NS > 1 && bm[NS > 1 ? 1 : 0]) {
+      const uint32_t ls = (uint32_t)__builtin_ctzll(bm[NS > 1 ? 1 : 0]);
+      Plo = lane64(lo[NS > 1 ? 1 : 0], ls);
+      Phi = lane64(hi[NS > 1 ? 1 : 0], ls);
+    } else if (NS > 2 && bm[NS > 2 ? 2 : 0]) {
+      const uint32_t ls = (uint32_t)__builtin_ctzll(bm[NS > 2 ? 2 : 0]);
+      Plo = lane64(lo[NS > 2 ? 2 : 0], ls);
+      Phi = lane64(hi[NS > 2 ? 2 : 0], ls);
+    } else {
+      const uint32_t ls = (uint32_t)__builtin_ctzll(bm[NS - 1]);
+      Plo = lane64(lo[NS - 1], ls);
+      Phi = lane64(hi[NS - 1], ls);
+    }
+    // lane j takes the pivot row; the rows with column j set take the sum.
+    // The empty asm keeps these as lane-masked moves and sums instead of
+    // selects, which cost a second instruction per word.
+    if (lane == 32 * h + jj) {
+      asm volatile("");
       plo = Plo;
       phi = Phi;
-      pv = Pv;
     }
 #pragma unroll
     for (uint32_t k = 0; k < NS; ++k)
       if (bit[k]) {
+        asm volatile("");
         lo[k] ^= Plo;
         hi[k] ^= Phi;
-        vv ^= Pv << k;
       }
   }
 }
 
-// One seed's elimination; the pivot rows go to plo_g / phi_g / pv_g.
+template <uint32_t NS>
+__device__ __forceinline__ void rib_columns(uint64_t (&lo)[kRowSlots], uint64_t (&hi)[kRowSlots], uint64_t &plo,
+                                            uint64_t &phi) {
+  rib_half<NS, 0>(lo, hi, plo, phi);
+  rib_half<NS, 1>(lo, hi, plo, phi);
+}
+
+// One seed's elimination; the pivot rows go to plo_g / phi_g.
 __device__ uint32_t rib_try(const uint64_t *__restrict__ keys, const uint8_t *__restrict__ choice, uint64_t o,
                            uint32_t m, uint64_t cols, uint32_t W, uint64_t rmix, uint32_t row_cap, uint64_t *st_lo,
-                           uint64_t *st_hi, uint8_t *st_v, uint32_t *cnt, uint32_t *cur, uint16_t *idx,
-                           uint64_t *plo_g, uint64_t *phi_g, uint8_t *pv_g, unsigned long long *err) {
+                           uint64_t *st_hi, uint32_t *cnt, uint32_t *cur, uint16_t *idx, uint64_t *plo_g,
+                           uint64_t *phi_g, unsigned long long *err) {
   const uint32_t lane = lane_id();
   // counting sort of the key indices by start block: cnt[k] = rows starting before block k
   for (uint32_t k = lane; k <= W; k += 64) cnt[k] = 0;
@@ -787,7 +804,7 @@ __device__ uint32_t rib_try(const uint64_t *__restrict__ keys, const uint8_t *__
   }
   wave_sync();
   uint64_t lo[kRowSlots], hi[kRowSlots];
-  uint32_t vv = 0, nslot = 0;
+  uint32_t nslot = 0;
 #pragma unroll
   for (uint32_t k = 0; k < kRowSlots; ++k) lo[k] = hi[k] = 0;
   for (uint32_t blk = 0; blk <= W; ++blk) {
@@ -799,16 +816,14 @@ __device__ uint32_t rib_try(const uint64_t *__restrict__ keys, const uint8_t *__
     for (uint32_t k = 0; k < kRowSlots; ++k) {
       if (k < nslot) {
         stray |= lo[k] != 0;
-        const bool alive = hi[k] != 0;
-        const uint32_t v = (vv >> k) & 1u;
-        bad |= !alive && v;
+        const bool alive = (hi[k] & ~kValueBit) != 0;
+        bad |= !alive && (hi[k] & kValueBit);
         const uint64_t am = __ballot(alive);
         if (alive) {
           const uint32_t p = live + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(am >> 32),
                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)am, 0u));
-          st_lo[p] = hi[k];
-          st_hi[p] = 0;
-          st_v[p] = (uint8_t)v;
+          st_lo[p] = hi[k] & ~kValueBit;
+          st_hi[p] = hi[k] & kValueBit;
         }
         live += (uint32_t)__popcll(am);
       }
@@ -835,33 +850,28 @@ __device__ uint32_t rib_try(const uint64_t *__restrict__ keys, const uint8_t *__
       ribbon_row(keys[o + i], rmix, cols, s, c);
       const uint32_t off = (uint32_t)(s & 63);
       st_lo[live + t] = c << off;
-      st_hi[live + t] = off ? c >> (64 - off) : 0;
-      st_v[live + t] = (uint8_t)(choice[o + i] & 1);
+      st_hi[live + t] = (off ? c >> (64 - off) : 0) | ((uint64_t)(choice[o + i] & 1) << 63);
     }
     wave_sync();
     nslot = (total + 63) >> 6;
-    vv = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kRowSlots; ++k) {
       const uint32_t p = 64 * k + lane;
       const bool in = p < total;
       lo[k] = in ? st_lo[p] : 0;
       hi[k] = in ? st_hi[p] : 0;
-      vv |= (in ? (uint32_t)(st_v[p] & 1) : 0u) << k;
     }
     wave_sync();
     uint64_t plo = 0, phi = 0;
-    uint32_t pv = 0;
     switch (nslot) {
-      case 1: rib_columns<1>(lo, hi, vv, plo, phi, pv); break;
-      case 2: rib_columns<2>(lo, hi, vv, plo, phi, pv); break;
-      case 3: rib_columns<3>(lo, hi, vv, plo, phi, pv); break;
-      case 4: rib_columns<4>(lo, hi, vv, plo, phi, pv); break;
+      case 1: rib_columns<1>(lo, hi, plo, phi); break;
+      case 2: rib_columns<2>(lo, hi, plo, phi); break;
+      case 3: rib_columns<3>(lo, hi, plo, phi); break;
+      case 4: rib_columns<4>(lo, hi, plo, phi); break;
       default: break;  // no rows
     }
     plo_g[64 * blk + lane] = plo;
     phi_g[64 * blk + lane] = phi;
-    pv_g[64 * blk + lane] = (uint8_t)pv;
   }
   return kTrySolved;  // not reached
 }
@@ -870,22 +880,18 @@ __device__ uint32_t rib_try(const uint64_t *__restrict__ keys, const uint8_t *__
 // column j's row; z of the next block enters through the rows' high words, and
 // within the block column j takes its value plus the parity of its row with
 // the columns after it.  sol: W words.
-__device__ void rib_back(uint32_t W, const uint64_t *plo_g, const uint64_t *phi_g, const uint8_t *pv_g,
-                         uint64_t *sol) {
+__device__ void rib_back(uint32_t W, const uint64_t *plo_g, const uint64_t *phi_g, uint64_t *sol) {
   const uint32_t lane = lane_id();
   uint64_t zn = 0;
   uint64_t nlo = plo_g[64 * (W - 1) + lane], nhi = phi_g[64 * (W - 1) + lane];
-  uint32_t nv = pv_g[64 * (W - 1) + lane];
   for (int blk = (int)W - 1; blk >= 0; --blk) {
     const uint64_t plo = nlo, phi = nhi;
-    const uint32_t pv = nv;
     if (blk > 0) {
       nlo = plo_g[64 * (blk - 1) + lane];
       nhi = phi_g[64 * (blk - 1) + lane];
-      nv = pv_g[64 * (blk - 1) + lane];
     }
     const uint64_t pm = __ballot((plo >> lane) & 1);
-    const uint64_t tm = __ballot(((pv ^ (uint32_t)__popcll(phi & zn)) & 1u) != 0);
+    const uint64_t tm = __ballot((((phi >> 63) ^ (uint64_t)__popcll(phi & ~kValueBit & zn)) & 1) != 0);
     uint64_t zc = 0;
     for (uint64_t todo = pm; todo;) {
       const uint32_t j = 63 - (uint32_t)__builtin_clzll(todo);
@@ -910,8 +916,7 @@ __global__ __launch_bounds__(64 * kS) void ribbon_block_kernel(
   unsigned char *lw = rib_lds + (size_t)wave * lds_wave_bytes;
   uint64_t *st_lo = reinterpret_cast<uint64_t *>(lw);
   uint64_t *st_hi = st_lo + kRowCapMax;
-  uint8_t *st_v = reinterpret_cast<uint8_t *>(st_hi + kRowCapMax);
-  uint32_t *cnt = reinterpret_cast<uint32_t *>(st_v + kRowCapMax);
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(st_hi + kRowCapMax);
   uint8_t *pw = piv + ((uint64_t)blockIdx.x * kS + wave) * piv_wave_bytes;
   for (uint64_t b = blockIdx.x; b < n_buckets; b += gridDim.x) {
     const uint64_t o = bucket_offset[b], m = bucket_offset[b + 1] - o;
@@ -924,12 +929,11 @@ __global__ __launch_bounds__(64 * kS) void ribbon_block_kernel(
     uint32_t *cur = cnt + W + 1;
     uint16_t *idx = reinterpret_cast<uint16_t *>(cur + W + 1);
     uint64_t *plo_g = reinterpret_cast<uint64_t *>(pw), *phi_g = plo_g + 64 * (uint64_t)W;
-    uint8_t *pv_g = reinterpret_cast<uint8_t *>(phi_g + 64 * (uint64_t)W);
     uint32_t win = kRibbonSeeds;
     bool spilled = false;
     for (uint32_t r0 = 0; r0 < kRibbonSeeds; r0 += kS) {
       const uint32_t res = rib_try(keys, choice, o, (uint32_t)m, cols, W, ribbon_mix(r0 + wave), row_cap, st_lo,
-                                   st_hi, st_v, cnt, cur, idx, plo_g, phi_g, pv_g, err);
+                                   st_hi, cnt, cur, idx, plo_g, phi_g, err);
       if (lane == 0) outcome[wave] = res;
       __syncthreads();
       uint32_t first = kS;
@@ -968,7 +972,7 @@ __global__ __launch_bounds__(64 * kS) void ribbon_block_kernel(
     }
     if (wave != win % kS) continue;
     uint64_t *sol = st_lo;  // W <= 2 kRowCapMax words of the stage
-    rib_back(W, plo_g, phi_g, pv_g, sol);
+    rib_back(W, plo_g, phi_g, sol);
     wave_sync();
     if (lane == 0) rseed[b] = (uint8_t)win;
     // bits [rb, rb + cols) of the global array
