@@ -202,16 +202,31 @@ def synthetic_stream(n_requests: int, rate_per_s: float, seed: int = 5, min_keys
     return out
 
 
-def mphf_footprint(n_keys: int) -> int:
-    """Device bytes an MPHF build of n_keys holds at its peak: the keys, the
-    build's scratch arena (a bucket-ordered and a leaf-ordered copy of the
-    keys, 16 bytes per key; the retrieval's 1.23 cells per key with an 8-byte
-    count word, an 8-byte frontier slot and a value byte each; 6 bytes per
-    key of choices, peel positions and the peel stack), and the leaf search
-    outputs and scratch: about 51 bytes per key plus the per-leaf terms.  The
-    arena stays cached by the building thread after the build."""
-    leaves = n_keys // 8 + 1
-    return 51 * n_keys + (16 + SCRATCH_BYTES_PER_LEAF) * leaves + (1 << 20)
+def _ribbon_cols(m: int) -> int:
+    return 0 if m == 0 else max(64, m + (m + 49) // 50)
+
+
+def mphf_footprint(n_keys: int, bucket_size: int = 2000, leaf_target: int = 40, bipartite: bool = False) -> int:
+    """Device bytes an MPHF build of n_keys (ribbon retrieval) holds at its
+    peak: the keys; the build's scratch arena (a bucket-ordered and a
+    leaf-ordered copy of the keys, the choices, per-leaf and per-bucket
+    tables, and the ribbon region: the larger of the walk's slots, about 9.5
+    bytes per key, and the block solver's pivot rows, two waves of 16 bytes
+    per column for each bucket it runs at once, sized for buckets of 9/8 of
+    bucket_size plus 256 keys), grown by an eighth; and the leaf search
+    outputs and scratch.  The arena stays cached by the building thread after
+    the build."""
+    N = int(n_keys)
+    B = max(1, -(-N // bucket_size))
+    L = B + -(-N // leaf_target)
+    rib_max = N + N // 50 + 65 * B
+    slot = 8 * (rib_max + rib_max // 8 + 2 * (rib_max // 64) + 3 * B + 64)
+    m_est = min(bucket_size + bucket_size // 8 + 256, 16384)
+    W = -(-_ribbon_cols(m_est) // 64)
+    piv = B * 2 * (-(-16 * 64 * W // 256) * 256)
+    arena = 18 * N + 31 * L + 45 * B + max(slot, piv) + 8192 + (16 * L if bipartite else 0)
+    arena += arena // 8  # the arena grows by an eighth over a reservation
+    return 8 * N + arena + (16 + SCRATCH_BYTES_PER_LEAF) * L + (1 << 20)
 
 
 class MphfServer:
@@ -285,7 +300,8 @@ class MphfServer:
             queue = collections.deque(r for r in queue if not self._expired(r, t))
             while queue and len(inflight) < self.slots:
                 r = queue[0]
-                fb = mphf_footprint(len(r.keys))
+                fb = mphf_footprint(len(r.keys), self.params["bucket_size"], self.params["leaf_target"],
+                                    bool(self.params["bipartite"]))
                 if fb > self.budget:
                     queue.popleft()
                     r.status = "rejected"
