@@ -86,6 +86,12 @@ __device__ __forceinline__ void bip_cell_idx(uint64_t a, uint64_t t, uint32_t nl
 
 
 
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Cell of this lane's key under pool entry q of one side: from the LDS cache
 // or hashed again.
 __device__ __forceinline__ uint32_t pool_cell(uint64_t my_a, uint32_t q, bool left, uint32_t nl, uint32_t nr,
@@ -163,6 +169,10 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
     uint64_t ra = kNone, rb = kNone;
     uint32_t fh0 = 0, fh1 = 0;
     for (uint64_t base = 0; base < P.max_seed && !found && !overflow; base += 64) {
+      // a leaf that runs long gets the SIMD's issue first: the slowest leaves end the launch
+      if (base == 512) __builtin_amdgcn_s_setprio(1);
+      if (base == 1024) __builtin_amdgcn_s_setprio(2);
+      if (base == 1536) __builtin_amdgcn_s_setprio(3);
       const uint64_t s = base + lane;
       const uint64_t t = seed_mix(s);
       uint32_t ml = 0, mr = 0;
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
         // this lane's key's cells under the new candidate m, and the keys
         // alone in their left (right) cell under m
         uint32_t ml_cell, mr_cell;
-        bip_cells(my_a, seed_mix(m), nl, nr, ml_cell, mr_cell);
+        bip_cells(my_a, readlane64(t, lm), nl, nr, ml_cell, mr_cell);  // lane lm mixed seed m
         uint64_t m_lone_l, m_lone_r;
         lone_keys(n, ml_cell, mr_cell, lds, m_lone_l, m_lone_r);
         if (is_r) {
@@ -263,6 +273,7 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
         }
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     uint64_t f = 0;
     if (found && !shockwave::orient_wave(n, fh0, fh1, lds.inc0, lds.inc1, &lds.hit, f)) found = false;
     if (lane == 0) {
@@ -348,9 +359,10 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   unsigned long long *ctr = cache->ctr;
   unsigned long long host[kBipCount] = {0, 0, 0, 0, 0, 0};
   const int cus = cache->cus;
-  // four waves per SIMD: more (six fit the LDS) contend for the VALU and LDS
-  // and slow the longest leaves, which end the launch
-  uint64_t workers = opts.workers ? (uint64_t)opts.workers : (uint64_t)cus * 16;
+  // three waves per SIMD: more (six fit the LDS) contend for the VALU and LDS
+  // and slow the longest leaves, which end the launch (16384 leaves of 48
+  // keys: 0.39 ms at three, 0.42 at four, 0.47 at five, 0.42 at two)
+  uint64_t workers = opts.workers ? (uint64_t)opts.workers : (uint64_t)cus * 12;
   if (workers > n_leaves) workers = n_leaves;
   const uint32_t groups = (uint32_t)((workers + kWpw - 1) / kWpw);
   BipParams P;
