@@ -62,7 +62,7 @@ class ShockOpts(ctypes.Structure):
         ("partial_k", ctypes.c_int32),
         ("block_iters_by_n", ctypes.c_void_p),
         ("team", ctypes.c_int32),
-        ("reserved1", ctypes.c_int32),
+        ("bip_pool", ctypes.c_int32),
         ("n_keys", ctypes.c_uint64),
     ]
 
@@ -313,7 +313,7 @@ def _as_ptr(x):
 
 def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_iters=0, waves_per_wg=0,
               workers=0, check_dups=False, cancel_ptr=None, leaf_size_hint=0, block_iters_by_n=None,
-              partial_k=0, team=0, n_keys=0) -> ShockOpts:
+              partial_k=0, team=0, n_keys=0, bip_pool=0) -> ShockOpts:
     """shock_opts with defaults; block_iters_by_n is a sequence of 65 ints or None."""
     o = ShockOpts()
     lib().shock_opts_init(ctypes.byref(o))
@@ -327,6 +327,7 @@ def make_opts(max_seed=None, start_seed=0, mode=SHOCK_MODE_AUTO, spl=0, block_it
     o.workers = workers
     o.check_dups = int(bool(check_dups))
     o.cancel = cancel_ptr
+    o.bip_pool = bip_pool
     o.leaf_size_hint = leaf_size_hint
     o.partial_k = partial_k
     o.team = team

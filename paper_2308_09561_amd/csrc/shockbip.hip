@@ -69,6 +69,7 @@ struct BipParams {
   const uint64_t *keys, *offsets;
   uint64_t n_leaves, max_seed;
   uint64_t n_keys;  // keys in the keys buffer, 0 = unchecked
+  uint32_t pool;    // candidates kept per side (at most kPool)
   uint64_t *out_a, *out_b, *out_orient;
   unsigned long long *ctr;
 };
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
             pairs += formed;
           }
           if (!found) {
-            if (n_r == kPool) overflow = true;
+            if (n_r == P.pool) overflow = true;
             else {
               if (lane == 0) lds.pool_r[n_r] = (uint32_t)m;
               if (lane == 0 && n_r < kFilter) lds.lone_r[n_r] = m_lone_r;
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
             pairs += formed;
           }
           if (!found) {
-            if (n_l == kPool) overflow = true;
+            if (n_l == P.pool) overflow = true;
             else {
               if (lane == 0) lds.pool_l[n_l] = (uint32_t)m;
               if (lane == 0 && n_l < kFilter) lds.lone_l[n_l] = m_lone_l;
@@ -347,6 +348,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   if (n_leaves == 0) return SHOCK_OK;
   if (!keys || !offsets || !out_a || !out_b || !out_orient || n_leaves > (1ull << 31)) return SHOCK_EINVAL;
   if (opts.max_seed > (1ull << 32) || opts.workers < 0 || opts.workers > (1 << 20)) return SHOCK_EINVAL;
+  if (opts.bip_pool < 0 || opts.bip_pool > (int32_t)kPool) return SHOCK_EINVAL;
   hipStream_t stream = (hipStream_t)hip_stream;
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -371,6 +373,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   P.n_leaves = n_leaves;
   P.max_seed = opts.max_seed;
   P.n_keys = opts.n_keys;
+  P.pool = opts.bip_pool ? (uint32_t)opts.bip_pool : kPool;
   P.out_a = out_a;
   P.out_b = out_b;
   P.out_orient = out_orient;

@@ -99,6 +99,55 @@ def test_bip_full_batch_statistics(shock, oracle_mod):
         assert (int(o[1][0]), int(o[2][0]), int(o[3][0])) == (int(g[1][j]), int(g[2][j]), int(g[3][j])), j
 
 
+def _pool_adds(oracle_mod, leaf_keys, a, b):
+    """Candidates the search adds to each side's pool before it reaches the
+    pair (a, b), in its order: every left (right) candidate below m =
+    max(a, b), and m itself on the right side when it is a right candidate
+    whose pairs with the left pool failed (the answer is then (m, b))."""
+    n = len(leaf_keys)
+    nl = n // 2
+    m = max(a, b)
+
+    def covers(s):
+        cells = [oracle_mod.bip_slots(int(x), s, n) for x in leaf_keys]
+        return {c[0] for c in cells} == set(range(nl)), {c[1] for c in cells} == set(range(nl, n))
+
+    adds_l = adds_r = 0
+    for s in range(m):
+        is_l, is_r = covers(s)
+        adds_l += is_l
+        adds_r += is_r
+    if a == m and covers(m)[1]:
+        adds_r += 1
+    return adds_l, adds_r
+
+
+def test_bip_pool_limit_against_the_oracle(shock, oracle_mod):
+    """With bip_pool = 3 candidates per side, exactly the leaves whose
+    oracle answer comes after a fourth candidate on some side are reported
+    not found (outputs all ones); every other leaf equals the oracle."""
+    cap = 3
+    keys, offs = fixed_leaves(60, 12, 3105)
+    want = oracle_bip(oracle_mod, keys, offs)
+    assert want[0] == 0
+    g = gpu_bip(shock, keys, offs, bip_pool=cap)
+    over = []
+    for j in range(len(offs) - 1):
+        lk = keys[int(offs[j]):int(offs[j + 1])]
+        al, ar = _pool_adds(oracle_mod, lk, int(want[1][j]), int(want[2][j]))
+        over.append(al > cap or ar > cap)
+    over = np.array(over)
+    print(f"[gpu] bip pool {cap}: {over.sum()} of {len(over)} leaves past it", flush=True)
+    assert 0 < over.sum() < len(over)
+    assert g[0] == shock.SHOCK_ENOTFOUND
+    assert (g[1][over] == MAX).all() and (g[2][over] == MAX).all()
+    ok = ~over
+    assert (g[1][ok] == want[1][ok]).all() and (g[2][ok] == want[2][ok]).all() and (g[3][ok] == want[3][ok]).all()
+    # the default pool equals the oracle on the same batch; out-of-range pools are refused
+    assert_same(gpu_bip(shock, keys, offs), want, "default pool")
+    assert gpu_bip(shock, keys, offs, bip_pool=257)[0] == shock.SHOCK_EINVAL
+
+
 def test_bip_edges(shock):
     keys = splitmix64(3104, 3)
     offs = np.array([0, 0, 1, 3], np.uint64)
