@@ -1390,16 +1390,17 @@ __device__ __forceinline__ void bucket_at(const QueryArgs &A, uint64_t b, Bucket
   const uint64_t *e = A.block + k * kBkWords;
   uint64_t lb = e[kBkLeaf], rb = e[kBkRib];
   uint32_t prev = 0;  // key_rel of the block's first bucket is 0
+  const uint32_t lt = A.leaf_target;
   for (uint64_t j = b0; j < b; ++j) {
     const uint32_t next = A.key_rel[j + 1];
-    const uint64_t mj = next - prev;
-    lb += (mj + A.leaf_target - 1) / A.leaf_target;
+    const uint32_t mj = next - prev;  // a bucket holds fewer than 2^32 keys
+    lb += (mj + lt - 1) / lt;         // 32-bit division: a fraction of the 64-bit one's instructions
     rb += ribbon_cols(mj);
     prev = next;
   }
   r.o = e[kBkKey] + prev;
   r.m = A.block[((b + 1) >> kBlockShift) * kBkWords + kBkKey] + A.key_rel[b + 1] - r.o;
-  r.L = (uint32_t)((r.m + A.leaf_target - 1) / A.leaf_target);
+  r.L = ((uint32_t)r.m + lt - 1) / lt;
   r.lb = lb;
   r.rb = rb;
   r.F = e[kBkFixed] + A.fixed_rel[b];
@@ -1462,8 +1463,18 @@ __device__ __forceinline__ void select_two(const uint64_t *s, uint64_t words, ui
 // j-th in the bucket's unary stream.
 __device__ __forceinline__ uint64_t leaf_value(const QueryArgs &A, const uint8_t *K, const BucketAt &bk, uint32_t lo,
                                                uint32_t j, uint32_t n) {
+  // the fixed widths of leaves lb .. lb + j - 1: twelve 5-bit codes per
+  // 64-bit window of the code stream
   uint64_t F = bk.F;
-  for (uint32_t i = 0; i < j; ++i) F += K[lo + size_code(A.codes, bk.lb + i)];
+  for (uint64_t g = bk.lb, ge = bk.lb + j; g < ge;) {
+    const uint64_t p = 5 * g, w = p >> 6;
+    const uint32_t sh = (uint32_t)(p & 63);
+    uint64_t x = A.codes[w] >> sh;
+    if (sh > 4) x |= A.codes[w + 1] << (64 - sh);
+    const uint64_t take = ge - g < 12 ? ge - g : 12;
+    for (uint64_t t = 0; t < take; ++t, x >>= 5) F += K[lo + (uint32_t)(x & 31)];
+    g += take;
+  }
   const uint32_t k = K[n];
   uint64_t low = 0;
   if (k) low = bits_at(A.fixed, A.fixed_words, F) & (~0ull >> (64 - k));
