@@ -1,23 +1,26 @@
 // Flat ShockHash MPHF on MI355X (gfx950): build and query.  Definitions in
 // include/shockmphf.h.
 //
-// Build, all on the device (the host only sizes buffers and steps the rounds):
-//   bucket counts (atomics)  ->  one-workgroup scan of bucket sizes and leaf
-//   counts  ->  scatter keys by bucket  ->  per bucket (a wave): the smallest
-//   splitting seed whose leaves fit (leaf histogram in LDS), then leaf sizes,
-//   offsets and a scatter into leaf order  ->  per leaf (a wave): bitonic sort
-//   of its keys in registers  ->  the persistent leaf search of
-//   shock_leaf_search_ex  ->  Golomb-Rice codes of the seeds  ->  the
-//   retrieval of each key's choice: a 3-hypergraph XOR system peeled in
-//   synchronous rounds over frontiers of cells (per round one detect pass and
-//   one removal pass over the cells whose count just fell to one; the host
-//   checks for the end every 16 rounds), then solved rounds in reverse (keys
-//   of one round write distinct cells and read none written in that round),
-//   packed to bits.
-// Query: a thread per key: bucket, splitting seed, leaf, the leaf's key offset
-// from the byte sizes, its seed decoded from the Rice streams (the block
-// index, the widths of the leaves before it in its block of 64, and a select
-// in the unary stream), three retrieval bits, then the leaf's slot.
+// Build, all on the device (the host only sizes buffers and reads back a few
+// counters):
+//   bucket counts (LDS histograms)  ->  one-workgroup scan of bucket sizes,
+//   leaf counts and ribbon widths  ->  scatter keys by bucket  ->  per bucket
+//   (a wave): the smallest splitting seed whose leaf sizes fit the bucket's
+//   5-bit window (leaf histogram in LDS), then leaf sizes, offsets and a
+//   scatter into leaf order  ->  per leaf (a wave): bitonic sort of its keys
+//   in registers  ->  the leaf search (plain, rotation fitting or bipartite)
+//   ->  Golomb-Rice codes of the leaf values, the packed size codes and the
+//   16-bucket offset table  ->  the retrieval of each key's choice: by
+//   default one ribbon system per bucket, solved by 64-column blocks (two
+//   waves per bucket try consecutive seeds; the sequential walk takes any
+//   bucket with more rows in a block than a wave holds); optionally a
+//   3-hypergraph XOR system peeled in synchronous rounds over frontiers of
+//   cells, then assigned rounds in reverse.
+// Query: a thread per key: bucket, its block of 16 in the offset table,
+// splitting seed, leaf, the leaf's key offset from the 5-bit size codes, its
+// value decoded from the Rice streams (the fixed widths of the leaves before
+// it in its bucket and a select in the unary stream), the retrieval bit (one
+// ribbon row's parity, or three XOR cells), then the leaf's slot.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
