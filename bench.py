@@ -556,9 +556,11 @@ def main():
         keys_m = torch.randint(-(1 << 63), (1 << 63) - 1, (Nm,), generator=gen, device=dev, dtype=torch.int64)
         pos_m = torch.empty(Nm, dtype=torch.int64, device=dev)
         stream = torch.cuda.current_stream(dev)
-        mphf = {"keys": Nm, "params": {"bucket_size": 2000, "leaf_target": 40, "leaf_max": 56}}
+        params = {"bucket_size": 3000, "leaf_target": 40, "leaf_max": 56}  # the library's defaults
+        mphf = {"keys": Nm, "params": dict(params, retrieval="ribbon")}
         kinds = (("plain", {}), ("rotation_fitting", {"rotation_fitting": True}), ("bipartite", {"bipartite": True}))
         for mode, kind in kinds:
+            kind = dict(kind, **params)
             log(f"[bench] flat MPHF of {Nm} keys, {mode} leaves")
             torch.cuda.synchronize()
             t4 = time.perf_counter()
