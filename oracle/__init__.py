@@ -56,8 +56,10 @@ def lib():
     global _lib
     if _lib is None:
         path = os.environ.get("SHOCK_ORACLE_LIB") or _LIB
-        if path == _LIB and not os.path.exists(_LIB):
-            build(force=True)
+        if path == _LIB and (not os.path.exists(_LIB) or
+                             max(os.path.getmtime(f) for f in _SRCS + [os.path.join(_HERE, "shock_oracle.h")])
+                             > os.path.getmtime(_LIB)):
+            build(force=True)  # missing, or older than its sources
         L = ctypes.CDLL(path)
         L.shock_oracle_fmix64.restype = ctypes.c_uint64
         L.shock_oracle_fmix64.argtypes = [ctypes.c_uint64]

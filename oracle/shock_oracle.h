@@ -204,8 +204,8 @@ int shock_oracle_bip_leaf_search(const uint64_t *keys, const uint64_t *offsets, 
  * leaf_sizes u8[leaf_cap], leaf_keys u64[N] (the keys in leaf order),
  * key_index u64[N] (original index of each of those keys), *n_leaves.
  * Returns EINVAL for bad parameters (leaf_max > 64, leaf_target 0 or above
- * leaf_max, bucket_size 0), leaf_cap too small, or a bucket whose splitting
- * seed would exceed 2^16. */
+ * leaf_max, bucket_size 0), leaf_cap too small or a bucket of more than 1024
+ * leaves, and ENOTFOUND for a bucket with no splitting seed below 2^16. */
 int shock_oracle_mphf_split(const uint64_t *keys, uint64_t n_keys, uint32_t bucket_size, uint32_t leaf_target,
                             uint32_t leaf_max, uint64_t n_buckets, uint64_t *bucket_offset, uint64_t *leaf_base,
                             uint32_t *sigma, uint8_t *leaf_sizes, uint64_t leaf_cap, uint64_t *leaf_keys,

@@ -65,7 +65,7 @@ int shock_oracle_mphf_split(const uint64_t *keys, uint64_t n_keys, uint32_t buck
   for (uint64_t b = 0; b < n_buckets && rc == SHOCK_ORACLE_OK; ++b) {
     uint64_t o = bucket_offset[b], m = bucket_offset[b + 1] - o;
     uint32_t L = (uint32_t)(leaf_base[b + 1] - leaf_base[b]);
-    if (L > (1u << 12)) {
+    if (L > 1024) {  /* the library's bound on leaves per bucket */
       rc = SHOCK_ORACLE_EINVAL;
       break;
     }
@@ -74,8 +74,8 @@ int shock_oracle_mphf_split(const uint64_t *keys, uint64_t n_keys, uint32_t buck
     uint32_t lo = shock_oracle_leaf_size_base(m, L);
     uint32_t s = 0;
     for (;; ++s) {
-      if (s >= (1u << 16)) {
-        rc = SHOCK_ORACLE_EINVAL;
+      if (s >= (1u << 16)) {  /* no splitting seed: like a leaf without a seed */
+        rc = SHOCK_ORACLE_ENOTFOUND;
         break;
       }
       for (uint32_t j = 0; j < L; ++j) count[j] = 0;

@@ -79,6 +79,20 @@ def test_mphf_rejects_bad_parameters(oracle_mod):
         assert rc == oracle_mod.EINVAL
 
 
+def test_mphf_split_limits(oracle_mod):
+    """A bucket may hold 1024 leaves but not 1025 (EINVAL), and a bucket
+    whose leaf sizes cannot all fit its window and leaf_max under any of the
+    2^16 splitting seeds is not found (a bucket of about 2400 keys in leaves
+    of 24 on average, at most 29: about 0.87^96 of the splits fit)."""
+    keys = splitmix64(1205, 2050)
+    rc, lay = oracle_mod.mphf_split(keys[:2048], bucket_size=4096, leaf_target=2, leaf_max=8)
+    assert rc == 0 and lay["n_leaves"] == 1024
+    rc, _ = oracle_mod.mphf_split(keys, bucket_size=4096, leaf_target=2, leaf_max=8)
+    assert rc == oracle_mod.EINVAL
+    rc, _ = oracle_mod.mphf_split(splitmix64(9602, 13700), bucket_size=2406, leaf_target=24, leaf_max=29)
+    assert rc == oracle_mod.ENOTFOUND
+
+
 @pytest.mark.parametrize("N", [1, 10, 1000, 100_000])
 def test_xor_retrieval_returns_every_value(oracle_mod, N):
     keys = splitmix64(1300 + N, N)
