@@ -371,7 +371,8 @@ int shock_poll(shock_queue *q, uint64_t ticket, int *done, shock_ticket_info *in
 int shock_cancel(shock_queue *q, uint64_t ticket);
 
 typedef struct shock_queue_stats {
-  uint64_t submitted, completed, cancelled, batches;
+  uint64_t submitted, completed, cancelled, batches;  /* completed counts every request that ended, the
+                                                         cancelled ones (also counted in cancelled) included */
   uint64_t queued, running;                    /* requests now */
   uint64_t bytes_in_flight, max_bytes_in_flight;
   int32_t batches_in_flight, max_batches_in_flight;

@@ -208,3 +208,79 @@ def test_queue_rejections_cancel_and_empty_requests(shock):
         assert (res[th][2] == ref[1]).all() and (res[th][3] == ref[2]).all()
     finally:
         q.close()
+
+
+def test_queue_random_stream_with_cancels(shock, oracle_mod):
+    """200 requests of random sizes (empty ones, single leaves, up to 1500
+    leaves of 1 to 40 keys) under a budget of a few batches, submitted in
+    bursts with random cancels and polls in between: every request ends
+    exactly once, a cancelled one either as cancelled or with its full
+    result, every result equals the oracle's leaf by leaf, and the budget
+    holds throughout."""
+    rng = np.random.default_rng(720)
+    reqs = []
+    for i in range(200):
+        L = int(rng.choice([0, 1, int(rng.integers(2, 200)), int(rng.integers(200, 1500))], p=[.05, .1, .6, .25]))
+        sizes = rng.integers(1, 41, L)
+        offs = np.zeros(L + 1, np.uint64)
+        np.cumsum(sizes.astype(np.uint64), out=offs[1:])
+        reqs.append((splitmix64(7300 + i, int(offs[-1])), offs))
+    budget = 3 * shock.queue_batch_bytes(1500, 1500 * 40)
+    q = shock.RequestQueue(hbm_budget_bytes=budget, slots=int(rng.integers(1, 5)), max_batch_leaves=3000,
+                           max_batch_keys=3000 * 40)
+    print(f"[gpu] queue random stream: {len(reqs)} requests, budget {budget}", flush=True)
+    tickets, cancelled, res = {}, set(), {}
+    try:
+        i = 0
+        while i < len(reqs):
+            for _ in range(int(rng.integers(1, 12))):  # a burst of submits
+                if i == len(reqs):
+                    break
+                rc, t = q.submit(*reqs[i])
+                assert rc == shock.SHOCK_OK, i
+                tickets[t] = i
+                i += 1
+            open_t = [t for t in tickets if t not in res]
+            for t in rng.choice(open_t, size=min(len(open_t), int(rng.integers(0, 3))), replace=False):
+                c = q.cancel(int(t))
+                assert c in (shock.SHOCK_OK, shock.SHOCK_EPENDING, shock.SHOCK_EINVAL)
+                if c == shock.SHOCK_OK:
+                    cancelled.add(int(t))
+            for t in list(open_t):
+                done, rc, info, s, f = q.poll(t)
+                if done:
+                    res[t] = (rc, s, f)
+            time.sleep(float(rng.uniform(0, 0.003)))
+        deadline = time.time() + 120
+        while len(res) < len(tickets):
+            for t in tickets:
+                if t not in res:
+                    done, rc, info, s, f = q.poll(t)
+                    if done:
+                        res[t] = (rc, s, f)
+            assert time.time() < deadline, f"{len(tickets) - len(res)} requests never completed"
+            time.sleep(0.0005)
+        st = q.stats()
+    finally:
+        q.close()
+    assert st["max_bytes_in_flight"] <= budget and st["submitted"] == len(reqs), st
+    assert st["completed"] == len(reqs) and st["cancelled"] == len(cancelled), st
+    keys_all = np.concatenate([k for k, _ in reqs])
+    offs_all = np.zeros(1, np.uint64)
+    for _, o in reqs:
+        offs_all = np.concatenate([offs_all, o[1:] + offs_all[-1]])
+    parts = oracle_mod.parallel(oracle_mod.leaf_search, keys_all, offs_all, threads=16)
+    want_s = np.concatenate([p[1] for p in parts])
+    want_f = np.concatenate([p[2] for p in parts])
+    first = np.concatenate([[0], np.cumsum([len(o) - 1 for _, o in reqs])])
+    n_cancel = 0
+    for t, i in tickets.items():
+        rc, s, f = res[t]
+        assert (rc == shock.SHOCK_ECANCELED) == (t in cancelled), (i, rc)  # withdrawn exactly when cancel said so
+        if rc == shock.SHOCK_ECANCELED:
+            n_cancel += 1
+            continue
+        assert rc == shock.SHOCK_OK, (i, rc)
+        a, b = int(first[i]), int(first[i + 1])
+        assert (s == want_s[a:b]).all() and (f == want_f[a:b]).all(), i
+    print(f"[gpu] queue random stream: {n_cancel} cancelled, {len(reqs) - n_cancel} checked", flush=True)
