@@ -388,3 +388,27 @@ def test_mphf_bipartite_leaves_full_size(shock, oracle_mod):
         assert rc == 0 and (_host(pos_t) == want).all()
     finally:
         m.close()
+
+
+def test_ribbon_large_buckets_block_solver_and_global_walk(shock, oracle_mod):
+    """Two buckets of about 7250 keys: the block solver takes them (its
+    stage, counts and indices fit the LDS), and with ribbon_rows = 1 every
+    bucket goes to the walk, whose slots for buckets this large live in
+    global memory (more than 64 KB of LDS).  Both give the oracle's ribbon
+    seeds and bits."""
+    N = 14500
+    params = dict(bucket_size=7250, leaf_target=40, leaf_max=56, bipartite=True)
+    keys = splitmix64(2160, N)
+    rc, lay = oracle_mod.mphf_build(keys, bucket_size=7250, leaf_target=40, leaf_max=56, bip=True, retrieval=RIBBON)
+    assert rc == 0
+    assert int(np.diff(lay["bucket_offset"].astype(np.int64)).max()) > 7000
+    for rows in (0, 1):
+        m, k = _build(shock, keys, ribbon_rows=rows, **params)
+        try:
+            ex, info = m.export(), m.info()
+            assert info["ribbon_walked"] == (info["n_buckets"] if rows == 1 else 0)
+            assert _same_retrieval(ex, lay), rows
+            pos = _host(m.query(k))
+            assert (pos == lay["positions"]).all()
+        finally:
+            m.close()
