@@ -339,21 +339,25 @@ def main():
     # Plain per-leaf form: one kernel launch per leaf, queued back to back.
     plain = None
     if args.plain_leaves > 0:
-        Lp = min(args.plain_leaves, L)
-        o_p = o_d[:Lp + 1]
-        s_p = torch.empty(Lp, dtype=torch.int64, device=dev)
-        f_p = torch.empty(Lp, dtype=torch.int64, device=dev)
-        shock.leaf_search(k_d, o_p, out_seeds=s_p, out_orient=f_p, mode=shock.SHOCK_MODE_PLAIN_PER_LEAF)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        rc, _, _ = shock.leaf_search(k_d, o_p, out_seeds=s_p, out_orient=f_p, mode=shock.SHOCK_MODE_PLAIN_PER_LEAF)
-        torch.cuda.synchronize()
-        wall_p = time.perf_counter() - t1
-        st_p = shock.shock_last_stats()
-        same = bool((s_p.cpu() == seeds_d[:Lp].cpu()).all() and (f_p.cpu() == orient_d[:Lp].cpu()).all())
-        plain = {"leaves": Lp, "leaves_per_s": Lp / wall_p, "kernel_ms": st_p["kernel_ms"],
-                 "seeds_tested_per_s": st_p["seeds_tested"] / wall_p, "same_outputs_as_batched": same}
-        log(f"[bench] plain per-leaf: {Lp / wall_p:.0f} leaves/s")
+        try:
+            Lp = min(args.plain_leaves, L)
+            o_p = o_d[:Lp + 1]
+            s_p = torch.empty(Lp, dtype=torch.int64, device=dev)
+            f_p = torch.empty(Lp, dtype=torch.int64, device=dev)
+            shock.leaf_search(k_d, o_p, out_seeds=s_p, out_orient=f_p, mode=shock.SHOCK_MODE_PLAIN_PER_LEAF)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rc, _, _ = shock.leaf_search(k_d, o_p, out_seeds=s_p, out_orient=f_p, mode=shock.SHOCK_MODE_PLAIN_PER_LEAF)
+            torch.cuda.synchronize()
+            wall_p = time.perf_counter() - t1
+            st_p = shock.shock_last_stats()
+            same = bool((s_p.cpu() == seeds_d[:Lp].cpu()).all() and (f_p.cpu() == orient_d[:Lp].cpu()).all())
+            plain = {"leaves": Lp, "leaves_per_s": Lp / wall_p, "kernel_ms": st_p["kernel_ms"],
+                     "seeds_tested_per_s": st_p["seeds_tested"] / wall_p, "same_outputs_as_batched": same}
+            log(f"[bench] plain per-leaf: {Lp / wall_p:.0f} leaves/s")
+        except Exception as e:  # a failed leg is reported in the line, not fatal to it
+            log(f"[bench] plain leg failed: {e!r}")
+            plain = {"error": repr(e)}
 
     # Captured graph against eager enqueue: the same context and buffers, one
     # search of the first L' leaves per call (enqueue + completion wait), for
@@ -361,240 +365,260 @@ def main():
     # whole batch.
     graph = None
     if args.graph_reps > 0:
-        graph = {}
-        stream = torch.cuda.Stream(device=dev)
-        for Lg in (21, 2084, L):
-            ctx = shock.SearchContext(Lg)
-            o_g = o_d[:Lg + 1].clone()
-            s_g = torch.empty(Lg, dtype=torch.int64, device=dev)
-            f_g = torch.empty(Lg, dtype=torch.int64, device=dev)
-            gopts = {k: v for k, v in opts.items() if v}
-            gopts["leaf_size_hint"] = n or 48
-            reps = max(3, args.graph_reps if Lg < L else 3)
-            torch.cuda.synchronize()
-            if ctx.capture(k_d, o_g, s_g, f_g, stream=stream.cuda_stream, **gopts) != 0:
-                raise RuntimeError("graph capture failed")
-            times = {}
-            for how in ("eager", "graph", "eager", "graph"):  # warm both, keep the second round
-                t1 = time.perf_counter()
-                for _ in range(reps):
-                    if how == "eager":
-                        rc = ctx.search_async(k_d, o_g, s_g, f_g, stream=stream.cuda_stream, **gopts)
-                    else:
-                        rc = ctx.launch_graph(stream=stream.cuda_stream)
-                    if rc != 0 or ctx.wait()[0] != 0:
-                        raise RuntimeError(f"{how} search failed")
-                times[how] = (time.perf_counter() - t1) * 1e3 / reps
-            same = bool(torch.equal(s_g, seeds_d[:Lg]) and torch.equal(f_g, orient_d[:Lg]))
-            ctx.close()
-            graph[f"leaves_{Lg}"] = {"eager_ms": times["eager"], "graph_ms": times["graph"],
-                                     "graph_speedup": times["eager"] / times["graph"], "reps": reps,
-                                     "same_outputs": same}
-            log(f"[bench] {Lg} leaves: eager {times['eager']:.3f} ms, graph {times['graph']:.3f} ms per call")
+        try:
+            graph = {}
+            stream = torch.cuda.Stream(device=dev)
+            for Lg in (21, 2084, L):
+                ctx = shock.SearchContext(Lg)
+                o_g = o_d[:Lg + 1].clone()
+                s_g = torch.empty(Lg, dtype=torch.int64, device=dev)
+                f_g = torch.empty(Lg, dtype=torch.int64, device=dev)
+                gopts = {k: v for k, v in opts.items() if v}
+                gopts["leaf_size_hint"] = n or 48
+                reps = max(3, args.graph_reps if Lg < L else 3)
+                torch.cuda.synchronize()
+                if ctx.capture(k_d, o_g, s_g, f_g, stream=stream.cuda_stream, **gopts) != 0:
+                    raise RuntimeError("graph capture failed")
+                times = {}
+                for how in ("eager", "graph", "eager", "graph"):  # warm both, keep the second round
+                    t1 = time.perf_counter()
+                    for _ in range(reps):
+                        if how == "eager":
+                            rc = ctx.search_async(k_d, o_g, s_g, f_g, stream=stream.cuda_stream, **gopts)
+                        else:
+                            rc = ctx.launch_graph(stream=stream.cuda_stream)
+                        if rc != 0 or ctx.wait()[0] != 0:
+                            raise RuntimeError(f"{how} search failed")
+                    times[how] = (time.perf_counter() - t1) * 1e3 / reps
+                same = bool(torch.equal(s_g, seeds_d[:Lg]) and torch.equal(f_g, orient_d[:Lg]))
+                ctx.close()
+                graph[f"leaves_{Lg}"] = {"eager_ms": times["eager"], "graph_ms": times["graph"],
+                                         "graph_speedup": times["eager"] / times["graph"], "reps": reps,
+                                         "same_outputs": same}
+                log(f"[bench] {Lg} leaves: eager {times['eager']:.3f} ms, graph {times['graph']:.3f} ms per call")
+        except Exception as e:  # a failed leg is reported in the line, not fatal to it
+            log(f"[bench] graph leg failed: {e!r}")
+            graph = {"error": repr(e)}
 
     # Rotation fitting on the same batch: a different output (seed, rotation),
     # reported beside the plain search.
     rf = None
     if args.rf_steps > 0:
-        rot_d = torch.empty(L, dtype=torch.int32, device=dev)
-        rs_d = torch.empty(L, dtype=torch.int64, device=dev)
-        rf_d = torch.empty(L, dtype=torch.int64, device=dev)
-        rf_opts = {k: v for k, v in opts.items() if k == "waves_per_wg" and v}
+        try:
+            rot_d = torch.empty(L, dtype=torch.int32, device=dev)
+            rs_d = torch.empty(L, dtype=torch.int64, device=dev)
+            rf_d = torch.empty(L, dtype=torch.int64, device=dev)
+            rf_opts = {k: v for k, v in opts.items() if k == "waves_per_wg" and v}
 
-        def rf_step():
-            rc, _, _, _ = shock.rf_leaf_search(k_d, o_d, out_seeds=rs_d, out_rot=rot_d, out_orient=rf_d, **rf_opts)
-            if rc != shock.SHOCK_OK:
-                raise RuntimeError(f"rotation-fitting search failed: {shock.shock_strerror(rc)}")
+            def rf_step():
+                rc, _, _, _ = shock.rf_leaf_search(k_d, o_d, out_seeds=rs_d, out_rot=rot_d, out_orient=rf_d, **rf_opts)
+                if rc != shock.SHOCK_OK:
+                    raise RuntimeError(f"rotation-fitting search failed: {shock.shock_strerror(rc)}")
 
-        log(f"[bench] rotation fitting: {args.rf_steps} steps")
-        rf_step()
-        torch.cuda.synchronize()
-        rf_ms, rf_tested, rf_pf = [], 0, 0
-        t2 = time.perf_counter()
-        for _ in range(args.rf_steps):
+            log(f"[bench] rotation fitting: {args.rf_steps} steps")
             rf_step()
-            st_r = shock.shock_last_stats()
-            rf_ms.append(st_r["kernel_ms"])
-            rf_tested += st_r["seeds_tested"]
-            rf_pf += st_r["pf_checks"]
-        torch.cuda.synchronize()
-        wall_r = (time.perf_counter() - t2) / args.rf_steps
-        rs = rs_d.cpu().numpy().view(np.uint64).astype(np.float64)
-        na = np.add.reduceat(1 - first_set_bit(keys), offs[:-1].astype(np.int64)) if len(keys) else np.zeros(L)
-        ops_seed = np.array([rf_ops_per_seed(int(sizes[j]), int(na[j]), 0) for j in range(L)])
-        rf_alg = float(((rs + 1) * ops_seed).sum())
-        rf_kernel = float(np.mean(rf_ms))
-        rf = {"leaves_per_s": L / wall_r, "ms_per_step": wall_r * 1e3, "kernel_ms": rf_kernel,
-              "mean_seed": float(rs.mean()), "mean_seed_plain": float(seeds.astype(np.float64).mean()),
-              "seeds_tested_per_s": rf_tested / args.rf_steps / wall_r,
-              "candidates_per_s": float(((rs + 1) * sizes).sum()) / wall_r,
-              "overshoot": rf_tested / args.rf_steps / float((rs + 1).sum()) - 1.0,
-              "pf_checks_per_step": rf_pf / args.rf_steps,
-              "vs_plain_search": (L / wall_r) / leaves_per_s,
-              "roofline": {"bound": "alu", "achieved": rf_alg / (rf_kernel / 1e3) / 1e12, "peak": PEAK_INT_OPS / 1e12,
-                           "unit": "Tops/s (int32 lane ops)", "frac": rf_alg / (rf_kernel / 1e3) / PEAK_INT_OPS,
-                           "ops_per_seed_mean": float(ops_seed.mean()),
-                           "traffic": measured_traffic(args.workload, "rf_")}}
-        log(f"[bench] rotation fitting: {L / wall_r:.0f} leaves/s, kernel {rf_kernel:.2f} ms, "
-            f"frac {rf['roofline']['frac']:.3f}")
+            torch.cuda.synchronize()
+            rf_ms, rf_tested, rf_pf = [], 0, 0
+            t2 = time.perf_counter()
+            for _ in range(args.rf_steps):
+                rf_step()
+                st_r = shock.shock_last_stats()
+                rf_ms.append(st_r["kernel_ms"])
+                rf_tested += st_r["seeds_tested"]
+                rf_pf += st_r["pf_checks"]
+            torch.cuda.synchronize()
+            wall_r = (time.perf_counter() - t2) / args.rf_steps
+            rs = rs_d.cpu().numpy().view(np.uint64).astype(np.float64)
+            na = np.add.reduceat(1 - first_set_bit(keys), offs[:-1].astype(np.int64)) if len(keys) else np.zeros(L)
+            ops_seed = np.array([rf_ops_per_seed(int(sizes[j]), int(na[j]), 0) for j in range(L)])
+            rf_alg = float(((rs + 1) * ops_seed).sum())
+            rf_kernel = float(np.mean(rf_ms))
+            rf = {"leaves_per_s": L / wall_r, "ms_per_step": wall_r * 1e3, "kernel_ms": rf_kernel,
+                  "mean_seed": float(rs.mean()), "mean_seed_plain": float(seeds.astype(np.float64).mean()),
+                  "seeds_tested_per_s": rf_tested / args.rf_steps / wall_r,
+                  "candidates_per_s": float(((rs + 1) * sizes).sum()) / wall_r,
+                  "overshoot": rf_tested / args.rf_steps / float((rs + 1).sum()) - 1.0,
+                  "pf_checks_per_step": rf_pf / args.rf_steps,
+                  "vs_plain_search": (L / wall_r) / leaves_per_s,
+                  "roofline": {"bound": "alu", "achieved": rf_alg / (rf_kernel / 1e3) / 1e12, "peak": PEAK_INT_OPS / 1e12,
+                               "unit": "Tops/s (int32 lane ops)", "frac": rf_alg / (rf_kernel / 1e3) / PEAK_INT_OPS,
+                               "ops_per_seed_mean": float(ops_seed.mean()),
+                               "traffic": measured_traffic(args.workload, "rf_")}}
+            log(f"[bench] rotation fitting: {L / wall_r:.0f} leaves/s, kernel {rf_kernel:.2f} ms, "
+                f"frac {rf['roofline']['frac']:.3f}")
+        except Exception as e:  # a failed leg is reported in the line, not fatal to it
+            log(f"[bench] rf leg failed: {e!r}")
+            rf = {"error": repr(e)}
 
     # Bipartite ShockHash on the same batch: a different output (a seed pair).
     bip = None
     if args.bip_steps > 0:
-        ba = torch.empty(L, dtype=torch.int64, device=dev)
-        bb = torch.empty(L, dtype=torch.int64, device=dev)
-        bf = torch.empty(L, dtype=torch.int64, device=dev)
-        log(f"[bench] bipartite ShockHash: {args.bip_steps} steps")
-        shock.bip_leaf_search(k_d, o_d, out_a=ba, out_b=bb, out_orient=bf)
-        torch.cuda.synchronize()
-        b_ms, b_seeds, b_pairs, b_peeled = [], 0, 0, 0
-        t5 = time.perf_counter()
-        for _ in range(args.bip_steps):
-            rc, _, _, _, bst = shock.bip_leaf_search(k_d, o_d, out_a=ba, out_b=bb, out_orient=bf)
-            if rc != shock.SHOCK_OK:
-                raise RuntimeError(f"bipartite search failed: {shock.shock_strerror(rc)}")
-            b_ms.append(bst["kernel_ms"])
-            b_seeds += bst["seeds_hashed"]
-            b_pairs += bst["pairs_tested"]
-            b_peeled += bst["pairs_peeled"]
-        wall_b = (time.perf_counter() - t5) / args.bip_steps
-        pair_max = torch.maximum(ba, bb).cpu().numpy().astype(np.float64)
-        n_b = float(sizes.mean())
-        # Lower bound of the algorithmic work: the seeds up to each leaf's
-        # answer, max(a, b) + 1, hashed over the leaf's keys at 7 ops per key
-        # evaluation (xor, 32x32+64 multiply-add, fold, multiply by nl, high
-        # product by nr, and one shift-or per half's 32-bit coverage word).
-        # Seeds hashed beyond the answer and the pair tests (cells read back,
-        # the lone-key filter, peeling) are not counted.
-        ops = float((pair_max + 1).sum()) * n_b * 7
-        kms = float(np.mean(b_ms))
-        bip = {"leaves_per_s": L / wall_b, "ms_per_step": wall_b * 1e3, "kernel_ms": kms,
-               "mean_max_seed": float(pair_max.mean()), "seeds_hashed_per_leaf": b_seeds / args.bip_steps / L,
-               "pairs_tested_per_leaf": b_pairs / args.bip_steps / L,
-               "pairs_peeled_per_leaf": b_peeled / args.bip_steps / L, "vs_plain_search": (L / wall_b) / leaves_per_s,
-               "roofline": {"bound": "alu", "achieved": ops / (kms / 1e3) / 1e12, "peak": PEAK_INT_OPS / 1e12,
-                            "unit": "Tops/s (int32 lane ops, hashing only: a lower bound)",
-                            "frac": ops / (kms / 1e3) / PEAK_INT_OPS,
-                            "traffic": measured_traffic(args.workload, "bip_")}}
-        log(f"[bench] bipartite: {L / wall_b:.0f} leaves/s, kernel {kms:.2f} ms, "
-            f"{bip['seeds_hashed_per_leaf']:.0f} seeds, {bip['pairs_tested_per_leaf']:.0f} pairs "
-            f"({bip['pairs_peeled_per_leaf']:.0f} peeled) per leaf")
+        try:
+            ba = torch.empty(L, dtype=torch.int64, device=dev)
+            bb = torch.empty(L, dtype=torch.int64, device=dev)
+            bf = torch.empty(L, dtype=torch.int64, device=dev)
+            log(f"[bench] bipartite ShockHash: {args.bip_steps} steps")
+            shock.bip_leaf_search(k_d, o_d, out_a=ba, out_b=bb, out_orient=bf)
+            torch.cuda.synchronize()
+            b_ms, b_seeds, b_pairs, b_peeled = [], 0, 0, 0
+            t5 = time.perf_counter()
+            for _ in range(args.bip_steps):
+                rc, _, _, _, bst = shock.bip_leaf_search(k_d, o_d, out_a=ba, out_b=bb, out_orient=bf)
+                if rc != shock.SHOCK_OK:
+                    raise RuntimeError(f"bipartite search failed: {shock.shock_strerror(rc)}")
+                b_ms.append(bst["kernel_ms"])
+                b_seeds += bst["seeds_hashed"]
+                b_pairs += bst["pairs_tested"]
+                b_peeled += bst["pairs_peeled"]
+            wall_b = (time.perf_counter() - t5) / args.bip_steps
+            pair_max = torch.maximum(ba, bb).cpu().numpy().astype(np.float64)
+            n_b = float(sizes.mean())
+            # Lower bound of the algorithmic work: the seeds up to each leaf's
+            # answer, max(a, b) + 1, hashed over the leaf's keys at 7 ops per key
+            # evaluation (xor, 32x32+64 multiply-add, fold, multiply by nl, high
+            # product by nr, and one shift-or per half's 32-bit coverage word).
+            # Seeds hashed beyond the answer and the pair tests (cells read back,
+            # the lone-key filter, peeling) are not counted.
+            ops = float((pair_max + 1).sum()) * n_b * 7
+            kms = float(np.mean(b_ms))
+            bip = {"leaves_per_s": L / wall_b, "ms_per_step": wall_b * 1e3, "kernel_ms": kms,
+                   "mean_max_seed": float(pair_max.mean()), "seeds_hashed_per_leaf": b_seeds / args.bip_steps / L,
+                   "pairs_tested_per_leaf": b_pairs / args.bip_steps / L,
+                   "pairs_peeled_per_leaf": b_peeled / args.bip_steps / L, "vs_plain_search": (L / wall_b) / leaves_per_s,
+                   "roofline": {"bound": "alu", "achieved": ops / (kms / 1e3) / 1e12, "peak": PEAK_INT_OPS / 1e12,
+                                "unit": "Tops/s (int32 lane ops, hashing only: a lower bound)",
+                                "frac": ops / (kms / 1e3) / PEAK_INT_OPS,
+                                "traffic": measured_traffic(args.workload, "bip_")}}
+            log(f"[bench] bipartite: {L / wall_b:.0f} leaves/s, kernel {kms:.2f} ms, "
+                f"{bip['seeds_hashed_per_leaf']:.0f} seeds, {bip['pairs_tested_per_leaf']:.0f} pairs "
+                f"({bip['pairs_peeled_per_leaf']:.0f} peeled) per leaf")
+        except Exception as e:  # a failed leg is reported in the line, not fatal to it
+            log(f"[bench] bip leg failed: {e!r}")
+            bip = {"error": repr(e)}
 
     # Leaf query and Golomb-Rice seed codes (HBM-bound) on a larger batch of
     # 48-key leaves: uniform keys drawn on the device, the measured batch's
     # seeds and orientations repeated.
     code = None
     if args.code_leaves > 0:
-        from paper_2308_09561_amd import rice
-        Lq = args.code_leaves
-        gen = torch.Generator(device=dev)
-        gen.manual_seed(4848)
-        keys_q = torch.randint(-(1 << 63), (1 << 63) - 1, (Lq * 48,), generator=gen, device=dev, dtype=torch.int64)
-        offs_q = torch.arange(0, Lq + 1, device=dev, dtype=torch.int64) * 48
-        reps = (Lq + L - 1) // L
-        seeds_q = seeds_d.repeat(reps)[:Lq].contiguous()
-        orient_q = orient_d.repeat(reps)[:Lq].contiguous()
-        pos_q = torch.empty(Lq * 48, dtype=torch.int64, device=dev)
-        stream = torch.cuda.current_stream(dev)
+        try:
+            from paper_2308_09561_amd import rice
+            Lq = args.code_leaves
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(4848)
+            keys_q = torch.randint(-(1 << 63), (1 << 63) - 1, (Lq * 48,), generator=gen, device=dev, dtype=torch.int64)
+            offs_q = torch.arange(0, Lq + 1, device=dev, dtype=torch.int64) * 48
+            reps = (Lq + L - 1) // L
+            seeds_q = seeds_d.repeat(reps)[:Lq].contiguous()
+            orient_q = orient_d.repeat(reps)[:Lq].contiguous()
+            pos_q = torch.empty(Lq * 48, dtype=torch.int64, device=dev)
+            stream = torch.cuda.current_stream(dev)
 
-        def timed(fn, repeats=5):
-            fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(repeats):
+            def timed(fn, repeats=5):
                 fn()
-            e1.record(stream)
-            e1.synchronize()
-            return e0.elapsed_time(e1) / repeats
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(repeats):
+                    fn()
+                e1.record(stream)
+                e1.synchronize()
+                return e0.elapsed_time(e1) / repeats
 
-        log(f"[bench] leaf query and seed codes: {Lq} leaves x 48 keys")
-        q_ms = timed(lambda: shock.leaf_query(keys_q, offs_q, seeds_q, orient_q, out_pos=pos_q))
-        q_bytes = Lq * 48 * 16 + Lq * 24  # keys in, positions out; offsets, seed, orientation per leaf
-        copy_ms = timed(lambda: pos_q.copy_(keys_q))  # a plain device copy of the same size, for reference
-        table = rice.plain_table()
-        rc, fx, un, idx, bits = shock.rice_encode(seeds_q, offs_q, table)
-        if rc != shock.SHOCK_OK:
-            raise RuntimeError(f"rice encode failed: {rc}")
-        t3 = time.perf_counter()
-        for _ in range(3):
-            shock.rice_encode(seeds_q, offs_q, table)
-        enc_ms = (time.perf_counter() - t3) / 3 * 1e3
-        vals_q = torch.empty(Lq, dtype=torch.int64, device=dev)
-        d_ms = timed(lambda: shock.rice_decode(fx, un, idx, offs_q, table, out_values=vals_q))
-        same = bool(torch.equal(vals_q, seeds_q))
-        stream_bytes = (bits[0] + bits[1]) / 8
-        d_bytes = stream_bytes + Lq * 16 + idx.numel() * 8  # streams, offsets, values out, index
-        p48 = rice.success_probability(48)
-        code = {
-            "leaves": Lq, "keys": Lq * 48,
-            "query": {"ms": q_ms, "keys_per_s": Lq * 48 / (q_ms / 1e3),
-                      "roofline": {"bound": "hbm", "achieved": q_bytes / (q_ms / 1e3) / 1e9, "peak": 8000.0,
-                                   "unit": "GB/s", "frac": q_bytes / (q_ms / 1e3) / 8e12, "traffic": None,
-                                   "bytes_per_launch": q_bytes,
-                                   "plain_copy_GBps": Lq * 48 * 16 / (copy_ms / 1e3) / 1e9}},
-            "rice": {"k_48": table[48], "bits_per_leaf": (bits[0] + bits[1]) / Lq,
-                     "expected_bits_per_leaf": rice.expected_length(table[48], p48),
-                     "bits_per_key": (bits[0] + bits[1]) / Lq / 48,
-                     "encode_ms_sync": enc_ms, "encode_leaves_per_s": Lq / (enc_ms / 1e3),
-                     "decode_ms": d_ms, "decode_leaves_per_s": Lq / (d_ms / 1e3), "decode_round_trip": same,
-                     "decode_roofline": {"bound": "hbm", "achieved": d_bytes / (d_ms / 1e3) / 1e9, "peak": 8000.0,
-                                         "unit": "GB/s", "frac": d_bytes / (d_ms / 1e3) / 8e12}},
-        }
-        log(f"[bench]   query {q_ms:.3f} ms ({code['query']['roofline']['achieved']:.0f} GB/s), "
-            f"encode {enc_ms:.2f} ms, decode {d_ms:.3f} ms, {code['rice']['bits_per_leaf']:.2f} bits/leaf")
-        del keys_q, pos_q
+            log(f"[bench] leaf query and seed codes: {Lq} leaves x 48 keys")
+            q_ms = timed(lambda: shock.leaf_query(keys_q, offs_q, seeds_q, orient_q, out_pos=pos_q))
+            q_bytes = Lq * 48 * 16 + Lq * 24  # keys in, positions out; offsets, seed, orientation per leaf
+            copy_ms = timed(lambda: pos_q.copy_(keys_q))  # a plain device copy of the same size, for reference
+            table = rice.plain_table()
+            rc, fx, un, idx, bits = shock.rice_encode(seeds_q, offs_q, table)
+            if rc != shock.SHOCK_OK:
+                raise RuntimeError(f"rice encode failed: {rc}")
+            t3 = time.perf_counter()
+            for _ in range(3):
+                shock.rice_encode(seeds_q, offs_q, table)
+            enc_ms = (time.perf_counter() - t3) / 3 * 1e3
+            vals_q = torch.empty(Lq, dtype=torch.int64, device=dev)
+            d_ms = timed(lambda: shock.rice_decode(fx, un, idx, offs_q, table, out_values=vals_q))
+            same = bool(torch.equal(vals_q, seeds_q))
+            stream_bytes = (bits[0] + bits[1]) / 8
+            d_bytes = stream_bytes + Lq * 16 + idx.numel() * 8  # streams, offsets, values out, index
+            p48 = rice.success_probability(48)
+            code = {
+                "leaves": Lq, "keys": Lq * 48,
+                "query": {"ms": q_ms, "keys_per_s": Lq * 48 / (q_ms / 1e3),
+                          "roofline": {"bound": "hbm", "achieved": q_bytes / (q_ms / 1e3) / 1e9, "peak": 8000.0,
+                                       "unit": "GB/s", "frac": q_bytes / (q_ms / 1e3) / 8e12, "traffic": None,
+                                       "bytes_per_launch": q_bytes,
+                                       "plain_copy_GBps": Lq * 48 * 16 / (copy_ms / 1e3) / 1e9}},
+                "rice": {"k_48": table[48], "bits_per_leaf": (bits[0] + bits[1]) / Lq,
+                         "expected_bits_per_leaf": rice.expected_length(table[48], p48),
+                         "bits_per_key": (bits[0] + bits[1]) / Lq / 48,
+                         "encode_ms_sync": enc_ms, "encode_leaves_per_s": Lq / (enc_ms / 1e3),
+                         "decode_ms": d_ms, "decode_leaves_per_s": Lq / (d_ms / 1e3), "decode_round_trip": same,
+                         "decode_roofline": {"bound": "hbm", "achieved": d_bytes / (d_ms / 1e3) / 1e9, "peak": 8000.0,
+                                             "unit": "GB/s", "frac": d_bytes / (d_ms / 1e3) / 8e12}},
+            }
+            log(f"[bench]   query {q_ms:.3f} ms ({code['query']['roofline']['achieved']:.0f} GB/s), "
+                f"encode {enc_ms:.2f} ms, decode {d_ms:.3f} ms, {code['rice']['bits_per_leaf']:.2f} bits/leaf")
+            del keys_q, pos_q
+        except Exception as e:  # a failed leg is reported in the line, not fatal to it
+            log(f"[bench] code leg failed: {e!r}")
+            code = {"error": repr(e)}
 
     # A complete flat MPHF over uniform keys: build (layout, leaf searches,
     # seed codes, retrieval) and query of every key, with plain, with
     # rotation-fitting and with bipartite leaves.
     mphf = None
     if args.mphf_keys > 0:
-        Nm = args.mphf_keys
-        gen = torch.Generator(device=dev)
-        gen.manual_seed(2222)
-        keys_m = torch.randint(-(1 << 63), (1 << 63) - 1, (Nm,), generator=gen, device=dev, dtype=torch.int64)
-        pos_m = torch.empty(Nm, dtype=torch.int64, device=dev)
-        stream = torch.cuda.current_stream(dev)
-        params = {"bucket_size": 3000, "leaf_target": 40, "leaf_max": 56}  # the library's defaults
-        mphf = {"keys": Nm, "params": dict(params, retrieval="ribbon")}
-        kinds = (("plain", {}), ("rotation_fitting", {"rotation_fitting": True}), ("bipartite", {"bipartite": True}))
-        for mode, kind in kinds:
-            kind = dict(kind, **params)
-            log(f"[bench] flat MPHF of {Nm} keys, {mode} leaves")
-            torch.cuda.synchronize()
-            t4 = time.perf_counter()
-            m = shock.MPHF(keys_m, **kind)  # the first build also loads the kernels
-            cold_s = time.perf_counter() - t4
-            m.close()
-            t4 = time.perf_counter()
-            m = shock.MPHF(keys_m, **kind)
-            build_s = time.perf_counter() - t4
-            info = m.info()
-            m.query(keys_m, out=pos_m)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(5):
+        try:
+            Nm = args.mphf_keys
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(2222)
+            keys_m = torch.randint(-(1 << 63), (1 << 63) - 1, (Nm,), generator=gen, device=dev, dtype=torch.int64)
+            pos_m = torch.empty(Nm, dtype=torch.int64, device=dev)
+            stream = torch.cuda.current_stream(dev)
+            params = {"bucket_size": 3000, "leaf_target": 40, "leaf_max": 56}  # the library's defaults
+            mphf = {"keys": Nm, "params": dict(params, retrieval="ribbon")}
+            kinds = (("plain", {}), ("rotation_fitting", {"rotation_fitting": True}), ("bipartite", {"bipartite": True}))
+            for mode, kind in kinds:
+                kind = dict(kind, **params)
+                log(f"[bench] flat MPHF of {Nm} keys, {mode} leaves")
+                torch.cuda.synchronize()
+                t4 = time.perf_counter()
+                m = shock.MPHF(keys_m, **kind)  # the first build also loads the kernels
+                cold_s = time.perf_counter() - t4
+                m.close()
+                t4 = time.perf_counter()
+                m = shock.MPHF(keys_m, **kind)
+                build_s = time.perf_counter() - t4
+                info = m.info()
                 m.query(keys_m, out=pos_m)
-            e1.record(stream)
-            e1.synchronize()
-            q_ms = e0.elapsed_time(e1) / 5
-            srt, _ = torch.sort(pos_m)
-            ok = bool(torch.equal(srt, torch.arange(Nm, device=dev, dtype=torch.int64)))
-            m.close()
-            mphf[mode] = {
-                "build_s": build_s, "build_keys_per_s": Nm / build_s, "first_build_s": cold_s,
-                "phases_ms": {k: info[k] for k in ("layout_ms", "search_call_ms", "codes_ms", "retrieval_ms")},
-                "leaf_search_kernel_ms": info["search_ms"], "bits_per_key": info["bits_per_key"],
-                "bits_per_key_parts": {k: info[k] / Nm for k in ("bits_buckets", "bits_leaf_sizes", "bits_seeds",
-                                                                 "bits_retrieval")},
-                "n_leaves": info["n_leaves"], "peel_rounds": info["peel_rounds"], "max_sigma": info["max_sigma"],
-                "query_ms": q_ms, "query_keys_per_s": Nm / (q_ms / 1e3), "bijection": ok}
-            log(f"[bench]   build {build_s * 1e3:.1f} ms ({Nm / build_s:.3g} keys/s, leaf search "
-                f"{info['search_ms']:.1f} ms), {info['bits_per_key']:.3f} bits/key, query {q_ms:.3f} ms, "
-                f"bijection {ok}")
-        del keys_m, pos_m
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(5):
+                    m.query(keys_m, out=pos_m)
+                e1.record(stream)
+                e1.synchronize()
+                q_ms = e0.elapsed_time(e1) / 5
+                srt, _ = torch.sort(pos_m)
+                ok = bool(torch.equal(srt, torch.arange(Nm, device=dev, dtype=torch.int64)))
+                m.close()
+                mphf[mode] = {
+                    "build_s": build_s, "build_keys_per_s": Nm / build_s, "first_build_s": cold_s,
+                    "phases_ms": {k: info[k] for k in ("layout_ms", "search_call_ms", "codes_ms", "retrieval_ms")},
+                    "leaf_search_kernel_ms": info["search_ms"], "bits_per_key": info["bits_per_key"],
+                    "bits_per_key_parts": {k: info[k] / Nm for k in ("bits_buckets", "bits_leaf_sizes", "bits_seeds",
+                                                                     "bits_retrieval")},
+                    "n_leaves": info["n_leaves"], "peel_rounds": info["peel_rounds"], "max_sigma": info["max_sigma"],
+                    "query_ms": q_ms, "query_keys_per_s": Nm / (q_ms / 1e3), "bijection": ok}
+                log(f"[bench]   build {build_s * 1e3:.1f} ms ({Nm / build_s:.3g} keys/s, leaf search "
+                    f"{info['search_ms']:.1f} ms), {info['bits_per_key']:.3f} bits/key, query {q_ms:.3f} ms, "
+                    f"bijection {ok}")
+            del keys_m, pos_m
+        except Exception as e:  # a failed leg is reported in the line, not fatal to it
+            log(f"[bench] mphf leg failed: {e!r}")
+            mphf = {"error": repr(e)}
 
     # Serving: MPHF-build requests (log-uniform 1e3..1e6 keys, Poisson
     # arrivals) cut into 48-key leaves, continuous batching over 4 streams
@@ -604,102 +628,114 @@ def main():
     # a backlog of the stream's first requests (all present at time 0).
     latency = None
     if args.serve_requests > 0:
-        from paper_2308_09561_amd.serving import LeafServer, MphfServer, synthetic_stream
-        latency = {}
-        backlog_n = min(200, args.serve_requests)
+        try:
+            from paper_2308_09561_amd.serving import LeafServer, MphfServer, synthetic_stream
+            latency = {}
+            backlog_n = min(200, args.serve_requests)
 
-        def capacity(make, label):
-            reqs = synthetic_stream(backlog_n, rate_per_s=1.0, seed=5)
-            srv = make()
-            rep = srv.run(reqs, realtime=False)
-            srv.close()
-            summ = rep.summary()
-            cap = summ["completed"] / rep.makespan_s
-            log(f"[bench] {label} capacity: {cap:.1f} requests/s on a backlog of {backlog_n}")
-            return cap, summ
+            def capacity(make, label):
+                reqs = synthetic_stream(backlog_n, rate_per_s=1.0, seed=5)
+                srv = make()
+                rep = srv.run(reqs, realtime=False)
+                srv.close()
+                summ = rep.summary()
+                cap = summ["completed"] / rep.makespan_s
+                log(f"[bench] {label} capacity: {cap:.1f} requests/s on a backlog of {backlog_n}")
+                return cap, summ
 
-        def serve(make, rate, label):
-            reqs = synthetic_stream(args.serve_requests, rate_per_s=rate, seed=5)
-            srv = make()
-            log(f"[bench] {label}: {len(reqs)} requests at {rate:.1f}/s")
-            rep = srv.run(reqs, realtime=True)
-            srv.close()
-            summ = rep.summary()
-            summ["rate_per_s"] = rate
-            log(f"[bench]   p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, {summ['keys_per_s']:.3g} keys/s")
-            return summ
+            def serve(make, rate, label):
+                reqs = synthetic_stream(args.serve_requests, rate_per_s=rate, seed=5)
+                srv = make()
+                log(f"[bench] {label}: {len(reqs)} requests at {rate:.1f}/s")
+                rep = srv.run(reqs, realtime=True)
+                srv.close()
+                summ = rep.summary()
+                summ["rate_per_s"] = rate
+                log(f"[bench]   p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, {summ['keys_per_s']:.3g} keys/s")
+                return summ
 
-        def leaf_server():
-            return LeafServer(hbm_budget_bytes=256 << 20, slots=4, leaf_size=48,
-                              search_opts={k: v for k, v in opts.items() if v})
+            def leaf_server():
+                return LeafServer(hbm_budget_bytes=256 << 20, slots=4, leaf_size=48,
+                                  search_opts={k: v for k, v in opts.items() if v})
 
-        cap, back = capacity(leaf_server, "leaf serving")
-        latency["backlog_capacity"] = {"requests_per_s": cap, "requests": backlog_n, "keys_per_s": back["keys_per_s"]}
-        latency["rate_200_per_s"] = serve(leaf_server, 200.0, "serving rate_200_per_s")
-        latency["rate_70pct_capacity"] = serve(leaf_server, 0.7 * cap, "serving rate_70pct_capacity")
-        latency["p50_ms"] = latency["rate_70pct_capacity"]["p50_ms"]
-        latency["p99_ms"] = latency["rate_70pct_capacity"]["p99_ms"]
-        if mphf is not None:
-            # The same requests served as complete MPHF builds with the leaf
-            # kind that built fastest, at 70% of that server's backlog capacity.
-            kind = max(("rotation_fitting", "bipartite"), key=lambda k: mphf[k]["build_keys_per_s"])
+            cap, back = capacity(leaf_server, "leaf serving")
+            latency["backlog_capacity"] = {"requests_per_s": cap, "requests": backlog_n, "keys_per_s": back["keys_per_s"]}
+            latency["rate_200_per_s"] = serve(leaf_server, 200.0, "serving rate_200_per_s")
+            latency["rate_70pct_capacity"] = serve(leaf_server, 0.7 * cap, "serving rate_70pct_capacity")
+            latency["p50_ms"] = latency["rate_70pct_capacity"]["p50_ms"]
+            latency["p99_ms"] = latency["rate_70pct_capacity"]["p99_ms"]
+            if mphf is not None and "error" not in mphf:
+                # The same requests served as complete MPHF builds with the leaf
+                # kind that built fastest, at 70% of that server's backlog capacity.
+                kind = max(("rotation_fitting", "bipartite"), key=lambda k: mphf[k]["build_keys_per_s"])
 
-            def mphf_server():
-                return MphfServer(hbm_budget_bytes=256 << 20, slots=4, **{kind: True})
+                def mphf_server():
+                    return MphfServer(hbm_budget_bytes=256 << 20, slots=4, **{kind: True})
 
-            cap_m, back_m = capacity(mphf_server, f"MPHF serving ({kind} leaves)")
-            summ = serve(mphf_server, 0.7 * cap_m, f"MPHF serving ({kind} leaves)")
-            summ["leaves"] = kind
-            summ["backlog_capacity"] = {"requests_per_s": cap_m, "requests": backlog_n,
-                                        "keys_per_s": back_m["keys_per_s"]}
-            latency["mphf_builds_70pct_capacity"] = summ
-            log(f"[bench]   {summ.get('bits_per_key', 0):.3f} bits/key")
+                cap_m, back_m = capacity(mphf_server, f"MPHF serving ({kind} leaves)")
+                summ = serve(mphf_server, 0.7 * cap_m, f"MPHF serving ({kind} leaves)")
+                summ["leaves"] = kind
+                summ["backlog_capacity"] = {"requests_per_s": cap_m, "requests": backlog_n,
+                                            "keys_per_s": back_m["keys_per_s"]}
+                latency["mphf_builds_70pct_capacity"] = summ
+                log(f"[bench]   {summ.get('bits_per_key', 0):.3f} bits/key")
+        except Exception as e:  # a failed leg is reported in the line, not fatal to it
+            log(f"[bench] latency leg failed: {e!r}")
+            latency = {"error": repr(e)}
 
     cpu = None
     if not args.no_cpu:
-        log(f"[bench] cpu baseline (oracle, ~{args.cpu_budget:.0f} s)")
-        cpu = run_cpu_baseline(keys, offs, seeds, orient, args.cpu_budget)
+        try:
+            log(f"[bench] cpu baseline (oracle, ~{args.cpu_budget:.0f} s)")
+            cpu = run_cpu_baseline(keys, offs, seeds, orient, args.cpu_budget)
+        except Exception as e:  # a failed leg is reported in the line, not fatal to it
+            log(f"[bench] cpu leg failed: {e!r}")
+            cpu = {"error": repr(e)}
 
     # The other parity workloads, once each: kernel time, useful work and the
     # integer roofline fraction under the same operation count.
     others = None
     if not args.no_configs:
-        others = {}
-        for name in ("plain24", "fixed40", "uneven32_56", "hard60"):
-            kw, ow = make_workload(name)
-            kd = torch.from_numpy(kw.view(np.int64)).to(dev)
-            od = torch.from_numpy(ow.view(np.int64)).to(dev)
-            Lw = len(ow) - 1
-            sd = torch.empty(Lw, dtype=torch.int64, device=dev)
-            fd = torch.empty(Lw, dtype=torch.int64, device=dev)
-            mode = shock.SHOCK_MODE_PLAIN_PER_LEAF if name == "plain24" else 0
-            wopts = {}
-            if mode == 0 and not args.untuned:
-                from paper_2308_09561_amd import autotune
-                wopts = autotune.tuned_opts(sizes=np.diff(ow))
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            rc, _, _ = shock.leaf_search(kd, od, out_seeds=sd, out_orient=fd, mode=mode, **wopts)
-            torch.cuda.synchronize()
-            wall_w = time.perf_counter() - t1
-            if rc != shock.SHOCK_OK:
-                raise RuntimeError(f"{name}: {shock.shock_strerror(rc)}")
-            stw = shock.shock_last_stats()
-            sw = sd.cpu().numpy().view(np.uint64) + np.uint64(1)
-            zw = np.diff(ow)
-            ops = alg_ops(sw, zw)
-            ach = ops / (stw["kernel_ms"] / 1e3)
-            ceil_w = mix_ceiling(sw, zw)
-            others[name] = {"leaves": Lw, "wall_ms": wall_w * 1e3, "kernel_ms": stw["kernel_ms"],
-                            "launch": {k: stw[k] for k in ("workers", "spl", "block_iters", "waves_per_wg")},
-                            "leaves_per_s": Lw / wall_w, "useful_seeds_per_s": float(sw.sum()) / wall_w,
-                            "seeds_tested": stw["seeds_tested"],
-                            "overshoot": stw["seeds_tested"] / float(sw.astype(np.float64).sum()) - 1,
-                            "roofline": {"achieved": ach / 1e12, "frac": ach / PEAK_INT_OPS,
-                                         "mix_ceiling": ceil_w / 1e12, "frac_of_mix_ceiling": ach / ceil_w}}
-            log(f"[bench] {name}: {Lw} leaves, {wall_w * 1e3:.1f} ms wall, kernel {stw['kernel_ms']:.1f} ms, "
-                f"{Lw / wall_w:.0f} leaves/s, frac {ach / PEAK_INT_OPS:.3f} nominal, {ach / ceil_w:.3f} of the mix ceiling")
-            del kd, od, sd, fd
+        try:
+            others = {}
+            for name in ("plain24", "fixed40", "uneven32_56", "hard60"):
+                kw, ow = make_workload(name)
+                kd = torch.from_numpy(kw.view(np.int64)).to(dev)
+                od = torch.from_numpy(ow.view(np.int64)).to(dev)
+                Lw = len(ow) - 1
+                sd = torch.empty(Lw, dtype=torch.int64, device=dev)
+                fd = torch.empty(Lw, dtype=torch.int64, device=dev)
+                mode = shock.SHOCK_MODE_PLAIN_PER_LEAF if name == "plain24" else 0
+                wopts = {}
+                if mode == 0 and not args.untuned:
+                    from paper_2308_09561_amd import autotune
+                    wopts = autotune.tuned_opts(sizes=np.diff(ow))
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                rc, _, _ = shock.leaf_search(kd, od, out_seeds=sd, out_orient=fd, mode=mode, **wopts)
+                torch.cuda.synchronize()
+                wall_w = time.perf_counter() - t1
+                if rc != shock.SHOCK_OK:
+                    raise RuntimeError(f"{name}: {shock.shock_strerror(rc)}")
+                stw = shock.shock_last_stats()
+                sw = sd.cpu().numpy().view(np.uint64) + np.uint64(1)
+                zw = np.diff(ow)
+                ops = alg_ops(sw, zw)
+                ach = ops / (stw["kernel_ms"] / 1e3)
+                ceil_w = mix_ceiling(sw, zw)
+                others[name] = {"leaves": Lw, "wall_ms": wall_w * 1e3, "kernel_ms": stw["kernel_ms"],
+                                "launch": {k: stw[k] for k in ("workers", "spl", "block_iters", "waves_per_wg")},
+                                "leaves_per_s": Lw / wall_w, "useful_seeds_per_s": float(sw.sum()) / wall_w,
+                                "seeds_tested": stw["seeds_tested"],
+                                "overshoot": stw["seeds_tested"] / float(sw.astype(np.float64).sum()) - 1,
+                                "roofline": {"achieved": ach / 1e12, "frac": ach / PEAK_INT_OPS,
+                                             "mix_ceiling": ceil_w / 1e12, "frac_of_mix_ceiling": ach / ceil_w}}
+                log(f"[bench] {name}: {Lw} leaves, {wall_w * 1e3:.1f} ms wall, kernel {stw['kernel_ms']:.1f} ms, "
+                    f"{Lw / wall_w:.0f} leaves/s, frac {ach / PEAK_INT_OPS:.3f} nominal, {ach / ceil_w:.3f} of the mix ceiling")
+                del kd, od, sd, fd
+        except Exception as e:  # a failed leg is reported in the line, not fatal to it
+            log(f"[bench] others leg failed: {e!r}")
+            others = {"error": repr(e)}
 
     out = {
         "metric": METRIC,
@@ -724,7 +760,7 @@ def main():
         "overshoot": seeds_tested / args.steps / useful_seeds - 1.0,
         "pf_checks_per_step": pf_checks / args.steps,
         "plain_per_leaf": plain,
-        "batched_vs_plain": (leaves_per_s / plain["leaves_per_s"]) if plain else None,
+        "batched_vs_plain": (leaves_per_s / plain["leaves_per_s"]) if plain and "error" not in plain else None,
         "latency": latency,
         "graph_vs_eager": graph,
         "rotation_fitting": rf,
