@@ -85,8 +85,10 @@ typedef struct shock_opts {
   int32_t team;           /* persistent mode: 1 = each wave takes its own fresh leaves; 2 = the waves of a
                              workgroup share each fresh leaf (a shorter tail: each leaf finishes sooner);
                              0 = default (2) */
-  int32_t bip_pool;       /* bipartite search only: candidates kept per side and leaf, 1..256; 0 = 256.  A
-                             leaf that gathers more on one side before its pair is reported not found */
+  int32_t bip_pool;       /* bipartite search only: candidates kept per side and leaf, 1..7168; 0 = 7168.
+                             A first pass keeps min(512, max(1, bip_pool / 2)) and lists the leaves that
+                             gather more; a second searches those again keeping bip_pool.  A leaf that
+                             gathers more than bip_pool on one side before its pair is reported not found */
   uint64_t n_keys;        /* keys in the keys buffer, or 0 = unchecked (the caller guarantees offsets[n_leaves]
                              is within it); a leaf reaching past n_keys makes the batch SHOCK_EINVAL before any
                              of its keys is read */
@@ -174,7 +176,7 @@ int shock_rf_leaf_search_async(const uint64_t *keys, const uint64_t *offsets, ui
  *       (edges (left, right)).
  * Options used: max_seed (at most 2^32), workers, bip_pool.  Synchronous.
  * Status as shock_leaf_search_ex; SHOCK_ENOTFOUND also when a leaf gathers
- * more than bip_pool (default 256) candidates on one side before its pair
+ * more than bip_pool (default 7168) candidates on one side before its pair
  * (far beyond what uniform keys need); such a leaf's outputs are those of a
  * leaf without a pair.  stats (host, may be NULL) receives seeds hashed, candidate pairs
  * formed up to each leaf's answer, the pairs among them that the peeling test

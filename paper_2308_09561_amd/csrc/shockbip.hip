@@ -48,28 +48,43 @@ using shockwave::lane_id;
 using shockwave::wave_lds_sync;
 
 constexpr uint64_t kNone = ~0ull;
-constexpr uint32_t kPool = 256;  // candidates per side and leaf
+// Two passes.  The first keeps up to kPool candidates per side (four waves per
+// workgroup, the pools with the rest of the wave's LDS); a leaf that gathers
+// more is listed and searched again from its first seed by the second, one
+// wave per workgroup with pools of up to kPoolBig (most of 64 KB of LDS).
+// With a smaller limit L per side the first keeps L / 2 (at least 1) and the
+// second L, so both passes run on small inputs too.  Uniform
+// keys rarely need the second: leaves of 64 keys gather about 450 candidates
+// per side, of 48 keys a few dozen.
+constexpr uint32_t kPool = 512;      // candidates per side and leaf, first pass
+constexpr uint32_t kPoolBig = 7168;  // second pass
 constexpr uint32_t kCache = 16;  // candidates per side whose cells are kept in LDS
 constexpr uint32_t kFilter = 64;  // candidates per side whose lone-key masks are kept in LDS
 constexpr uint32_t kWpw = 4;
 
-enum { kBipErr = 0, kBipNotFound = 1, kBipSeeds = 2, kBipPairs = 3, kBipNextLeaf = 4, kBipPeeled = 5, kBipCount = 6 };
+enum {
+  kBipErr = 0, kBipNotFound = 1, kBipSeeds = 2, kBipPairs = 3, kBipNextLeaf = 4, kBipPeeled = 5, kBipSpilled = 6,
+  kBipCount = 7
+};
 constexpr uint64_t kErrInvalidLeaf = 1;
 constexpr uint64_t kErrPool = 2;
 
+template <uint32_t kP>
 struct BipLds {
   uint64_t keys[64];
   unsigned long long inc0[64], inc1[64], hit;
-  uint32_t pool_l[kPool], pool_r[kPool];
+  uint32_t pool_l[kP], pool_r[kP];
   uint8_t cell_l[kCache][64], cell_r[kCache][64];  // left (right) cell of key i under pool_l[q] (pool_r[q])
   uint64_t lone_l[kFilter], lone_r[kFilter];  // keys alone in their left (right) cell under pool_l[q] (pool_r[q])
 };
 
 struct BipParams {
   const uint64_t *keys, *offsets;
-  uint64_t n_leaves, max_seed;
+  uint64_t n_leaves, max_seed;  // n_leaves: of the batch, or of `list`
   uint64_t n_keys;  // keys in the keys buffer, 0 = unchecked
-  uint32_t pool;    // candidates kept per side (at most kPool)
+  uint32_t pool;    // candidates kept per side (at most the kernel's pool)
+  const uint32_t *list;  // second pass: the leaves to search, or NULL (all)
+  uint32_t *spill;       // first pass: where leaves past the pool are listed, or NULL (reported not found)
   uint64_t *out_a, *out_b, *out_orient;
   unsigned long long *ctr;
 };
@@ -95,8 +110,9 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l) {
 
 // Cell of this lane's key under pool entry q of one side: from the LDS cache
 // or hashed again.
+template <class Lds>
 __device__ __forceinline__ uint32_t pool_cell(uint64_t my_a, uint32_t q, bool left, uint32_t nl, uint32_t nr,
-                                              const BipLds &lds) {
+                                              const Lds &lds) {
   if (q < kCache) return left ? lds.cell_l[q][lane_id()] : lds.cell_r[q][lane_id()];
   uint32_t l, r;
   bip_cells(my_a, seed_mix(left ? lds.pool_l[q] : lds.pool_r[q]), nl, nr, l, r);
@@ -105,7 +121,8 @@ __device__ __forceinline__ uint32_t pool_cell(uint64_t my_a, uint32_t q, bool le
 
 // Keys (lanes below n) alone in their left cell cl, and alone in their right
 // cell cr, under one seed: a cell histogram as key masks in LDS.
-__device__ __forceinline__ void lone_keys(uint32_t n, uint32_t cl, uint32_t cr, BipLds &lds, uint64_t &lone_l,
+template <class Lds>
+__device__ __forceinline__ void lone_keys(uint32_t n, uint32_t cl, uint32_t cr, Lds &lds, uint64_t &lone_l,
                                           uint64_t &lone_r) {
   const uint32_t lane = lane_id();
   const bool act = lane < n;
@@ -124,22 +141,25 @@ __device__ __forceinline__ void lone_keys(uint32_t n, uint32_t cl, uint32_t cr, 
 
 // Whether the pair with left cells cl and right cells cr (this lane's key)
 // qualifies; lane i < n gets its edge in h0, h1.
-__device__ bool bip_pair(uint32_t n, uint32_t cl, uint32_t cr, uint32_t &h0, uint32_t &h1, BipLds &lds) {
+template <class Lds>
+__device__ bool bip_pair(uint32_t n, uint32_t cl, uint32_t cr, uint32_t &h0, uint32_t &h1, Lds &lds) {
   h0 = lane_id() < n ? cl : 0;
   h1 = lane_id() < n ? cr : 0;
   return shockwave::pf_peel_wave(n, h0, h1, lds.inc0);
 }
 
-__global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
-  __shared__ BipLds lds_all[kWpw];
-  BipLds &lds = lds_all[threadIdx.x >> 6];
+template <uint32_t kP, uint32_t kW>
+__global__ __launch_bounds__(64 * kW) void bip_kernel(BipParams P) {
+  __shared__ BipLds<kP> lds_all[kW];
+  BipLds<kP> &lds = lds_all[threadIdx.x >> 6];
   const uint32_t lane = lane_id();
   uint64_t seeds_hashed = 0, pairs = 0, peeled = 0;
   for (;;) {
     unsigned long long jj = 0;
     if (lane == 0) jj = atomicAdd(&P.ctr[kBipNextLeaf], 1ull);
-    const uint64_t j = bcast64(jj);
-    if (j >= P.n_leaves) break;
+    const uint64_t idx = bcast64(jj);
+    if (idx >= P.n_leaves) break;
+    const uint64_t j = P.list ? P.list[idx] : idx;
     const uint64_t o0 = P.offsets[j], o1 = P.offsets[j + 1];
     if (o1 < o0 || o1 - o0 > 64 || (P.n_keys != 0 && o1 > P.n_keys)) {
       if (lane == 0) {
@@ -278,8 +298,12 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
     uint64_t f = 0;
     if (found && !shockwave::orient_wave(n, fh0, fh1, lds.inc0, lds.inc1, &lds.hit, f)) found = false;
     if (lane == 0) {
-      if (overflow) atomicOr(&P.ctr[kBipErr], kErrPool);
-      if (!found) atomicAdd(&P.ctr[kBipNotFound], 1ull);
+      if (overflow && P.spill) {  // searched again by the second pass
+        P.spill[atomicAdd(&P.ctr[kBipSpilled], 1ull)] = (uint32_t)j;
+      } else {
+        if (overflow) atomicOr(&P.ctr[kBipErr], kErrPool);
+        if (!found) atomicAdd(&P.ctr[kBipNotFound], 1ull);
+      }
       P.out_a[j] = found ? ra : kNone;
       P.out_b[j] = found ? rb : kNone;
       P.out_orient[j] = found ? f : 0;
@@ -298,6 +322,8 @@ __global__ __launch_bounds__(64 * kWpw) void bip_kernel(BipParams P) {
 // device, including other streams' work).
 struct BipCache {
   unsigned long long *ctr = nullptr;
+  uint32_t *spill = nullptr;  // the first pass's list of leaves past its pool
+  uint64_t spill_cap = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int cus = 0;
 };
@@ -324,6 +350,12 @@ hipError_t shock_internal_release_bip_scratch(int dev) {
   BipCache &c = t_bip[dev];
   hipError_t e = hipSuccess;
   if (c.ctr) e = hipFree(c.ctr);
+  if (c.spill) {
+    const hipError_t f = hipFree(c.spill);
+    if (e == hipSuccess) e = f;
+  }
+  c.spill = nullptr;
+  c.spill_cap = 0;
   for (hipEvent_t *ev : {&c.e0, &c.e1}) {
     if (*ev) {
       const hipError_t f = hipEventDestroy(*ev);
@@ -348,7 +380,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   if (n_leaves == 0) return SHOCK_OK;
   if (!keys || !offsets || !out_a || !out_b || !out_orient || n_leaves > (1ull << 31)) return SHOCK_EINVAL;
   if (opts.max_seed > (1ull << 32) || opts.workers < 0 || opts.workers > (1 << 20)) return SHOCK_EINVAL;
-  if (opts.bip_pool < 0 || opts.bip_pool > (int32_t)kPool) return SHOCK_EINVAL;
+  if (opts.bip_pool < 0 || opts.bip_pool > (int32_t)kPoolBig) return SHOCK_EINVAL;
   hipStream_t stream = (hipStream_t)hip_stream;
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -359,7 +391,24 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
     return e == hipErrorOutOfMemory ? SHOCK_ENOMEM : SHOCK_EHIP;
   }
   unsigned long long *ctr = cache->ctr;
-  unsigned long long host[kBipCount] = {0, 0, 0, 0, 0, 0};
+  unsigned long long host[kBipCount] = {0, 0, 0, 0, 0, 0, 0};
+  // candidates kept per side in all; the first pass keeps half of them, at
+  // most kPool, and lists the leaves past that for the second
+  const uint32_t cap = opts.bip_pool ? (uint32_t)opts.bip_pool : kPoolBig;
+  const uint32_t first = cap / 2 == 0 ? 1 : (cap / 2 < kPool ? cap / 2 : kPool);
+  const bool second = cap > first;
+  if (second && cache->spill_cap < n_leaves) {
+    if (cache->spill) (void)hipFree(cache->spill);
+    cache->spill = nullptr;
+    cache->spill_cap = 0;
+    e = hipMalloc((void **)&cache->spill, n_leaves * sizeof(uint32_t));
+    if (e != hipSuccess) {
+      cache->spill = nullptr;
+      shock_internal_set_error("bipartite second-pass list", e);
+      return e == hipErrorOutOfMemory ? SHOCK_ENOMEM : SHOCK_EHIP;
+    }
+    cache->spill_cap = n_leaves;
+  }
   const int cus = cache->cus;
   // three waves per SIMD: more (six fit the LDS) contend for the VALU and LDS
   // and slow the longest leaves, which end the launch (16384 leaves of 48
@@ -373,7 +422,9 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   P.n_leaves = n_leaves;
   P.max_seed = opts.max_seed;
   P.n_keys = opts.n_keys;
-  P.pool = opts.bip_pool ? (uint32_t)opts.bip_pool : kPool;
+  P.pool = first;
+  P.list = nullptr;
+  P.spill = second ? cache->spill : nullptr;
   P.out_a = out_a;
   P.out_b = out_b;
   P.out_orient = out_orient;
@@ -382,7 +433,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   e = hipMemcpyAsync(ctr, host, sizeof(host), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipEventRecord(e0, stream);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(bip_kernel, dim3(groups), dim3(64 * kWpw), 0, stream, P);
+    hipLaunchKernelGGL((bip_kernel<kPool, kWpw>), dim3(groups), dim3(64 * kWpw), 0, stream, P);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipEventRecord(e1, stream);
@@ -390,6 +441,29 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   float ms = 0;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e == hipSuccess && host[kBipSpilled] > 0) {
+    // the second pass over the listed leaves, one wave per workgroup
+    const uint64_t nsp = host[kBipSpilled];
+    P.list = cache->spill;
+    P.n_leaves = nsp;
+    P.pool = cap;
+    P.spill = nullptr;
+    host[kBipNextLeaf] = 0;
+    e = hipMemcpyAsync(ctr + kBipNextLeaf, &host[kBipNextLeaf], sizeof(unsigned long long), hipMemcpyHostToDevice,
+                       stream);
+    const uint64_t g2 = nsp < (uint64_t)cus * 2 ? nsp : (uint64_t)cus * 2;
+    if (e == hipSuccess) e = hipEventRecord(e0, stream);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL((bip_kernel<kPoolBig, 1>), dim3((uint32_t)g2), dim3(64), 0, stream, P);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, ctr, sizeof(host), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    float ms2 = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms2, e0, e1);
+    ms += ms2;  // the two passes' kernel time
+  }
   if (e != hipSuccess) {
     shock_internal_set_error("bipartite search", e);
     return SHOCK_EHIP;

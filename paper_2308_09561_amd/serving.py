@@ -214,8 +214,9 @@ def mphf_footprint(n_keys: int, bucket_size: int = 2000, leaf_target: int = 40, 
     bytes per key, and the block solver's pivot rows, two waves of 16 bytes
     per column for each bucket it runs at once, sized for buckets of 9/8 of
     bucket_size plus 256 keys), grown by an eighth; and the leaf search
-    outputs and scratch.  The arena stays cached by the building thread after
-    the build."""
+    outputs and scratch (bipartite: also the second pass's leaf list, kept by
+    the device).  The arena stays cached by the building thread after the
+    build."""
     N = int(n_keys)
     B = max(1, -(-N // bucket_size))
     L = B + -(-N // leaf_target)
@@ -226,7 +227,7 @@ def mphf_footprint(n_keys: int, bucket_size: int = 2000, leaf_target: int = 40, 
     piv = B * 2 * (-(-16 * 64 * W // 256) * 256)
     arena = 18 * N + 31 * L + 45 * B + max(slot, piv) + 8192 + (16 * L if bipartite else 0)
     arena += arena // 8  # the arena grows by an eighth over a reservation
-    return 8 * N + arena + (16 + SCRATCH_BYTES_PER_LEAF) * L + (1 << 20)
+    return 8 * N + arena + (16 + SCRATCH_BYTES_PER_LEAF + (4 if bipartite else 0)) * L + (1 << 20)
 
 
 class MphfServer:

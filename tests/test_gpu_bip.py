@@ -122,11 +122,15 @@ def _pool_adds(oracle_mod, leaf_keys, a, b):
     return adds_l, adds_r
 
 
-def test_bip_pool_limit_against_the_oracle(shock, oracle_mod):
-    """With bip_pool = 3 candidates per side, exactly the leaves whose
-    oracle answer comes after a fourth candidate on some side are reported
-    not found (outputs all ones); every other leaf equals the oracle."""
-    cap = 3
+@pytest.mark.parametrize("cap", [3, 4])
+def test_bip_pool_limit_against_the_oracle(shock, oracle_mod, cap):
+    """With bip_pool = cap candidates per side, exactly the leaves whose
+    oracle answer comes after candidate cap + 1 on some side are reported
+    not found (outputs all ones); every other leaf equals the oracle.  The
+    first pass keeps cap / 2, so the leaves between the two limits are found
+    by the second pass (25 of these 60 leaves at cap 3, 8 at cap 4; 7 and 3
+    go past the limit)."""
+
     keys, offs = fixed_leaves(60, 12, 3105)
     want = oracle_bip(oracle_mod, keys, offs)
     assert want[0] == 0
@@ -139,13 +143,17 @@ def test_bip_pool_limit_against_the_oracle(shock, oracle_mod):
     over = np.array(over)
     print(f"[gpu] bip pool {cap}: {over.sum()} of {len(over)} leaves past it", flush=True)
     assert 0 < over.sum() < len(over)
+    second = np.array([max(_pool_adds(oracle_mod, keys[int(offs[j]):int(offs[j + 1])], int(want[1][j]),
+                                      int(want[2][j]))) > cap // 2 for j in range(len(offs) - 1)]) & ~over
+    print(f"[gpu] bip pool {cap}: {second.sum()} leaves found by the second pass", flush=True)
+    assert second.sum() > 0
     assert g[0] == shock.SHOCK_ENOTFOUND
     assert (g[1][over] == MAX).all() and (g[2][over] == MAX).all()
     ok = ~over
     assert (g[1][ok] == want[1][ok]).all() and (g[2][ok] == want[2][ok]).all() and (g[3][ok] == want[3][ok]).all()
     # the default pool equals the oracle on the same batch; out-of-range pools are refused
     assert_same(gpu_bip(shock, keys, offs), want, "default pool")
-    assert gpu_bip(shock, keys, offs, bip_pool=257)[0] == shock.SHOCK_EINVAL
+    assert gpu_bip(shock, keys, offs, bip_pool=7169)[0] == shock.SHOCK_EINVAL
 
 
 def test_bip_edges(shock):
