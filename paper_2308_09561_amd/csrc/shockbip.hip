@@ -63,15 +63,20 @@ constexpr uint32_t kCache = 16;  // candidates per side whose cells are kept in 
 constexpr uint32_t kFilter = 64;  // candidates per side whose lone-key masks are kept in LDS
 constexpr uint32_t kWpw = 4;
 
-enum { kBipErr = 0, kBipNotFound = 1, kBipSeeds = 2, kBipPairs = 3, kBipPeeled = 4, kBipSpilled = 5, kBipCount = 6 };
+// Device counters: three words for the batch, then one 256-byte line per
+// slice of the batch: the slice's leaf counter and the statistics of the
+// waves that started on it.
+enum { kBipErr = 0, kBipNotFound = 1, kBipSpilled = 2 };
+enum { kSliceNext = 0, kSliceSeeds = 1, kSlicePairs = 2, kSlicePeeled = 3 };
 // Leaves are taken from kRanges counters, each over its own slice of the
-// batch and 256 bytes from the next.  A workgroup starts on slice
-// blockIdx % kRanges (two slices per XCD, which takes workgroups in turn)
-// and moves to the next slice when its own runs dry.  A single counter
-// for every wave is a queue: device-scope atomics on one address are
-// serialised, and at twelve waves per CU the wait for a fresh leaf grew
-// fivefold over one wave per SIMD (16384 leaves of 48 keys: 0.40 ms with one
-// counter, 0.35 with 16).
+// batch.  A workgroup starts on slice blockIdx % kRanges (two slices per
+// XCD, which takes workgroups in turn); when that slice runs dry, its waves
+// read all the counters at once and move to the next slice with leaves
+// left.  A single counter for every wave is a queue: device-scope atomics on
+// one address are serialised, and at twelve waves per CU the wait for a
+// fresh leaf grew fivefold over one wave per SIMD (16384 leaves of 48 keys:
+// 0.40 ms with one counter, 0.335 with 16).  The statistics are added on the
+// slices' lines for the same reason.
 constexpr uint32_t kBipRange = 8, kRangeStride = 32, kRanges = 16;
 constexpr uint32_t kCtrWords = kBipRange + kRanges * kRangeStride;
 constexpr uint64_t kErrInvalidLeaf = 1;
@@ -162,20 +167,31 @@ __global__ __launch_bounds__(64 * kW) void bip_kernel(BipParams P) {
   BipLds<kP> &lds = lds_all[threadIdx.x >> 6];
   const uint32_t lane = lane_id();
   uint64_t seeds_hashed = 0, pairs = 0, peeled = 0;
-  uint32_t slice = blockIdx.x % kRanges, dry = 0;  // the slice taken from; slices found empty
+  const uint32_t home = blockIdx.x % kRanges;
+  uint32_t slice = home;  // the slice leaves are taken from
   for (;;) {
     uint64_t idx = kNone;
-    while (dry < kRanges) {
+    for (;;) {
       const uint64_t lo = P.n_leaves * slice / kRanges, hi = P.n_leaves * (slice + 1) / kRanges;
       unsigned long long c = 0;
-      if (lane == 0) c = atomicAdd(&P.ctr[kBipRange + slice * kRangeStride], 1ull);
+      if (lane == 0) c = atomicAdd(&P.ctr[kBipRange + slice * kRangeStride + kSliceNext], 1ull);
       c = bcast64(c);
       if (c < hi - lo) {
         idx = lo + c;
         break;
       }
-      slice = slice + 1 == kRanges ? 0 : slice + 1;
-      ++dry;
+      // the slice is dry (counters only grow): lane i reads slice i's counter.
+      // Each pass finds one more slice dry, so at most kRanges passes run.
+      bool open = false;
+      if (lane < kRanges) {
+        const unsigned long long v = __hip_atomic_load(&P.ctr[kBipRange + lane * kRangeStride + kSliceNext],
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        open = v < P.n_leaves * (lane + 1) / kRanges - P.n_leaves * lane / kRanges;
+      }
+      const uint64_t opened = __ballot(open);
+      if (opened == 0) break;
+      const uint64_t after = opened & ~((2ull << slice) - 1);  // open slices past this one
+      slice = __builtin_ctzll(after ? after : opened);
     }
     if (idx == kNone) break;
     const uint64_t j = P.list ? P.list[idx] : idx;
@@ -330,9 +346,10 @@ __global__ __launch_bounds__(64 * kW) void bip_kernel(BipParams P) {
     wave_lds_sync();
   }
   if (lane == 0) {
-    if (seeds_hashed) atomicAdd(&P.ctr[kBipSeeds], (unsigned long long)seeds_hashed);
-    if (pairs) atomicAdd(&P.ctr[kBipPairs], (unsigned long long)pairs);
-    if (peeled) atomicAdd(&P.ctr[kBipPeeled], (unsigned long long)peeled);
+    unsigned long long *line = P.ctr + kBipRange + home * kRangeStride;
+    if (seeds_hashed) atomicAdd(line + kSliceSeeds, (unsigned long long)seeds_hashed);
+    if (pairs) atomicAdd(line + kSlicePairs, (unsigned long long)pairs);
+    if (peeled) atomicAdd(line + kSlicePeeled, (unsigned long long)peeled);
   }
 }
 
@@ -410,7 +427,12 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
     return e == hipErrorOutOfMemory ? SHOCK_ENOMEM : SHOCK_EHIP;
   }
   unsigned long long *ctr = cache->ctr;
-  unsigned long long host[kCtrWords] = {};  // counters, then the slices' leaf counters
+  unsigned long long host[kCtrWords] = {};  // the batch's counters, then the slices' lines
+  uint64_t sums[4] = {0, 0, 0, 0};          // statistics over the slices and passes
+  auto add_slices = [&]() {
+    for (uint32_t r = 0; r < kRanges; ++r)
+      for (uint32_t w = kSliceSeeds; w <= kSlicePeeled; ++w) sums[w] += host[kBipRange + r * kRangeStride + w];
+  };
   // candidates kept per side in all; the first pass keeps half of them, at
   // most kPool, and lists the leaves past that for the second
   const uint32_t cap = opts.bip_pool ? (uint32_t)opts.bip_pool : kPoolBig;
@@ -429,10 +451,9 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
     cache->spill_cap = n_leaves;
   }
   const int cus = cache->cus;
-  // three waves per SIMD: more (six fit the LDS) contend for the VALU and LDS
-  // and slow the longest leaves, which end the launch (16384 leaves of 48
-  // keys: 0.39 ms at three, 0.42 at four, 0.47 at five, 0.42 at two)
-  uint64_t workers = opts.workers ? (uint64_t)opts.workers : (uint64_t)cus * 12;
+  // four waves per SIMD, as many as the LDS holds (16384 leaves of 48 keys:
+  // 0.31 ms at four, 0.33 at three, 0.39 at two)
+  uint64_t workers = opts.workers ? (uint64_t)opts.workers : (uint64_t)cus * 16;
   if (workers > n_leaves) workers = n_leaves;
   const uint32_t groups = (uint32_t)((workers + kWpw - 1) / kWpw);
   BipParams P;
@@ -456,10 +477,11 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipEventRecord(e1, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(host, ctr, kBipCount * sizeof(host[0]), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(host, ctr, sizeof(host), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   float ms = 0;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e == hipSuccess) add_slices();
   if (e == hipSuccess && host[kBipSpilled] > 0) {
     // the second pass over the listed leaves, one wave per workgroup
     const uint64_t nsp = host[kBipSpilled];
@@ -477,10 +499,11 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(e1, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(host, ctr, kBipCount * sizeof(host[0]), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, ctr, sizeof(host), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     float ms2 = 0;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms2, e0, e1);
+    if (e == hipSuccess) add_slices();
     ms += ms2;  // the two passes' kernel time
   }
   if (e != hipSuccess) {
@@ -488,9 +511,9 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
     return SHOCK_EHIP;
   }
   if (stats) {
-    stats->seeds_hashed = host[kBipSeeds];
-    stats->pairs_tested = host[kBipPairs];
-    stats->pairs_peeled = host[kBipPeeled];
+    stats->seeds_hashed = sums[kSliceSeeds];
+    stats->pairs_tested = sums[kSlicePairs];
+    stats->pairs_peeled = sums[kSlicePeeled];
     stats->kernel_ms = ms;
     stats->workers = (int32_t)(groups * kWpw);
   }
