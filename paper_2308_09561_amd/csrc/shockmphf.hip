@@ -339,7 +339,17 @@ __global__ __launch_bounds__(256) void split_kernel(const uint64_t *__restrict__
       }
     }
     if (!found) {
-      if (lane == 0) atomicOr(err, kErrSigma);
+      // the build fails; its leaves are still written (empty, at the bucket's
+      // start), so the sort queued behind this kernel reads no stale offsets
+      for (uint32_t j = lane; j < L; j += 64) {
+        leaf_sizes[lb + j] = 0;
+        leaf_codes[lb + j] = 0;
+        leaf_off[lb + j] = o;
+      }
+      if (lane == 0) {
+        sigma[b] = 0;
+        atomicOr(err, kErrSigma);
+      }
       continue;
     }
     if (lane == 0) sigma[b] = (uint16_t)s;
