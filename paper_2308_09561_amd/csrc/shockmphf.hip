@@ -702,11 +702,18 @@ __global__ __launch_bounds__(64) void ribbon_kernel(const uint64_t *__restrict__
 // try kS consecutive seeds of one bucket at once and the smallest that solves
 // wins.  A bucket with more rows in a block than a wave holds (row_cap) is
 // marked in `spill` for the walk.
+//
+// Two launches.  The first tries seeds 0 and 1 of every bucket (about three
+// buckets in four end there) and lists the others; the second takes the
+// listed buckets from seed 2 on, with as many waves per bucket as the LDS
+// holds.  One launch of two waves per bucket took as long as its slowest
+// bucket's rounds of two seeds (seeds up to 11 on 1399 buckets), with most
+// SIMDs idle after the first round.
 constexpr uint32_t kRowSlots = 4;
 constexpr uint32_t kRowCapMax = 64 * kRowSlots;
 constexpr uint64_t kBlockMaxM = 16384;        // larger buckets: the walk
 constexpr uint64_t kErrRibbonSpill = 32;      // buckets marked for the walk
-constexpr uint32_t kRibWaves = 2;             // seeds tried at once per bucket
+constexpr uint32_t kRibWaves = 2;             // seeds tried at once per bucket, first launch
 constexpr uint64_t kValueBit = 1ull << 63;    // of a row's high word
 enum : uint32_t { kTryContradiction = 0, kTrySolved = 1, kTrySpill = 2 };
 
@@ -920,9 +927,12 @@ __device__ void rib_back(uint32_t W, const uint64_t *plo_g, const uint64_t *phi_
 template <uint32_t kS>
 __global__ __launch_bounds__(64 * kS) void ribbon_block_kernel(
     const uint64_t *__restrict__ keys, const uint8_t *__restrict__ choice, const uint64_t *__restrict__ bucket_offset,
-    const uint64_t *__restrict__ rib_base, uint64_t n_buckets, uint8_t *piv, uint64_t piv_wave_bytes,
-    uint32_t lds_wave_bytes, uint32_t row_cap, uint64_t *zbits, uint64_t zwords, uint8_t *rseed, uint8_t *spill,
-    unsigned long long *err) {
+    const uint64_t *__restrict__ rib_base, uint64_t n_items, const uint32_t *__restrict__ list, uint32_t seed0,
+    uint32_t *defer, unsigned long long *defer_n, uint8_t *piv, uint64_t piv_wave_bytes, uint32_t lds_wave_bytes,
+    uint32_t row_cap, uint64_t *zbits, uint64_t zwords, uint8_t *rseed, uint8_t *spill, unsigned long long *err) {
+  // items: buckets 0 .. n_items - 1, or those of `list`; seeds from seed0 on.
+  // With `defer`, one round of kS seeds, and a bucket none of them settles is
+  // appended to `defer` instead of failing.
   extern __shared__ __align__(16) unsigned char rib_lds[];
   __shared__ uint32_t outcome[kS];
   const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
@@ -931,7 +941,9 @@ __global__ __launch_bounds__(64 * kS) void ribbon_block_kernel(
   uint64_t *st_hi = st_lo + kRowCapMax;
   uint32_t *cnt = reinterpret_cast<uint32_t *>(st_hi + kRowCapMax);
   uint8_t *pw = piv + ((uint64_t)blockIdx.x * kS + wave) * piv_wave_bytes;
-  for (uint64_t b = blockIdx.x; b < n_buckets; b += gridDim.x) {
+  const uint32_t seed_end = defer ? seed0 + kS : kRibbonSeeds;
+  for (uint64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const uint64_t b = list ? list[it] : it;
     const uint64_t o = bucket_offset[b], m = bucket_offset[b + 1] - o;
     if (m == 0) {
       if (threadIdx.x == 0) rseed[b] = 0;
@@ -944,9 +956,11 @@ __global__ __launch_bounds__(64 * kS) void ribbon_block_kernel(
     uint64_t *plo_g = reinterpret_cast<uint64_t *>(pw), *phi_g = plo_g + 64 * (uint64_t)W;
     uint32_t win = kRibbonSeeds;
     bool spilled = false;
-    for (uint32_t r0 = 0; r0 < kRibbonSeeds; r0 += kS) {
-      const uint32_t res = rib_try(keys, choice, o, (uint32_t)m, cols, W, ribbon_mix(r0 + wave), row_cap, st_lo,
-                                   st_hi, cnt, cur, idx, plo_g, phi_g, err);
+    for (uint32_t r0 = seed0; r0 < seed_end; r0 += kS) {
+      const uint32_t seed = r0 + wave;  // seeds past the last are not tried
+      const uint32_t res = seed < kRibbonSeeds ? rib_try(keys, choice, o, (uint32_t)m, cols, W, ribbon_mix(seed),
+                                                         row_cap, st_lo, st_hi, cnt, cur, idx, plo_g, phi_g, err)
+                                               : kTryContradiction;
       if (lane == 0) outcome[wave] = res;
       __syncthreads();
       uint32_t first = kS;
@@ -980,10 +994,13 @@ __global__ __launch_bounds__(64 * kS) void ribbon_block_kernel(
       continue;
     }
     if (win == kRibbonSeeds) {
-      if (threadIdx.x == 0) atomicOr(err, kErrRibbon);
+      if (threadIdx.x == 0) {
+        if (defer) defer[atomicAdd(defer_n, 1ull)] = (uint32_t)b;
+        else atomicOr(err, kErrRibbon);
+      }
       continue;
     }
-    if (wave != win % kS) continue;
+    if (wave != (win - seed0) % kS) continue;  // the wave that solved seed win
     uint64_t *sol = st_lo;  // W <= 2 kRowCapMax words of the stage
     rib_back(W, plo_g, phi_g, sol);
     wave_sync();
@@ -1720,13 +1737,13 @@ void free_mphf(shock_mphf *m) {
     }                                       \
   } while (0)
 
-// Workgroups of the ribbon block kernel that the LDS of one CU holds (160 KiB,
-// at most 32 waves), for buckets of up to max_m keys; 0 if one workgroup's
-// LDS would pass 64 KiB.
-static uint64_t rib_groups_per_cu(uint64_t max_m) {
-  const uint64_t wg = (uint64_t)kRibWaves * rib_lds_wave_bytes(max_m);
+// Workgroups of kS waves of the ribbon block kernel that the LDS of one CU
+// holds (160 KiB, at most 32 waves), for buckets of up to max_m keys; 0 if one
+// workgroup's LDS would pass 64 KiB.
+static uint64_t rib_groups_per_cu(uint64_t max_m, uint32_t kS = kRibWaves) {
+  const uint64_t wg = (uint64_t)kS * rib_lds_wave_bytes(max_m);
   if (max_m > kBlockMaxM || wg > 65536) return 0;
-  const uint64_t by_lds = (160ull << 10) / wg, by_waves = 32 / kRibWaves;
+  const uint64_t by_lds = (160ull << 10) / wg, by_waves = 32 / kS;
   return by_lds < by_waves ? by_lds : by_waves;
 }
 
@@ -1763,7 +1780,8 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
   const size_t scratch_bytes = align256(2 * 8) + align256(B * 4) + 2 * align256(N * 8) + align256((Lmax + 1) * 8) +
                                2 * align256(Lmax * 8) + align256(Lmax * 4) + 2 * align256(N ? N : 1) +
                                3 * align256((B + 1) * 8) + 2 * align256(Lmax + 8) + align256((Lmax / 64 + 3) * 16) +
-                               2 * align256((B + 1) * 8) + align256(rib_area) + align256(B) +
+                               2 * align256((B + 1) * 8) + align256(rib_area) + align256(B) + align256(B * 4) +
+                               align256(8) +
                                (xor_ret ? align256(((N + 31) / 32) * 4) + align256(N * 4) + 2 * align256(cells_r * 8) +
                                               align256((kMaxPeelRounds + 1) * 8) + align256(kPkWords * 8) +
                                               align256(cells_r)
@@ -1994,8 +2012,12 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
     // LDS; buckets it marks, or all if none fit, go to the walk, whose slots,
     // values and solution sit in LDS unless the largest bucket is too large
     uint8_t *rib_region = nullptr, *spill = nullptr;
+    uint32_t *defer = nullptr;
+    unsigned long long *defer_n = nullptr;
     HIP_TRY(S.alloc(&rib_region, rib_area));
     HIP_TRY(S.alloc(&spill, B));
+    HIP_TRY(S.alloc(&defer, B));
+    HIP_TRY(S.alloc(&defer_n, 1));
     const uint64_t max_cols = ribbon_cols(max_m);
     const size_t lds_bytes = (max_cols + max_cols / 8 + 1 + (max_cols + 63) / 64 + 1) * 8;
     const int grid = (int)(B < 65536 ? B : 65536);
@@ -2007,14 +2029,49 @@ static int build_impl(const uint64_t *keys, uint64_t N, const shock_mphf_params 
     bool walk_all = groups == 0;
     if (!walk_all) {
       hipLaunchKernelGGL(fill_u8_kernel, dim3(grid_for(B, 256)), dim3(256), 0, stream, spill, B);
+      hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, stream, defer_n, (uint64_t)1);
       const uint32_t lw = rib_lds_wave_bytes(max_m);
+      // seeds 0 and 1 of every bucket
       hipLaunchKernelGGL(ribbon_block_kernel<kRibWaves>, dim3((uint32_t)groups), dim3(64 * kRibWaves),
                          (size_t)kRibWaves * lw, stream, (const uint64_t *)leaf_keys, (const uint8_t *)choice,
-                         (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, B, rib_region, piv_wave, lw,
-                         row_cap, M->zbits, M->zwords, M->rseed, spill, err);
+                         (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, B, (const uint32_t *)nullptr,
+                         0u, defer, defer_n, rib_region, piv_wave, lw, row_cap, M->zbits, M->zwords, M->rseed, spill,
+                         err);
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipMemcpyAsync(&host[4], defer_n, 8, hipMemcpyDeviceToHost, stream));
       HIP_TRY(hipStreamSynchronize(stream));
+      const uint64_t nd = host[4];
+      if (nd && !(host[0] & kErrRibbonInternal)) {
+        // the listed buckets from seed 2 on, five (or four, or two) seeds at a
+        // time: as many waves per workgroup as its LDS and the pivot region
+        // hold (two always fit: the first launch ran with at least one group)
+        auto fits = [&](uint32_t k) { return k * lw <= 65536 && k * piv_wave <= rib_area; };
+        const uint32_t ks2 = fits(5) ? 5 : (fits(4) ? 4 : kRibWaves);
+        uint64_t g2 = (uint64_t)S.arena->cus * rib_groups_per_cu(max_m, ks2);
+        if (g2 > nd) g2 = nd;
+        if (g2 * ks2 * piv_wave > rib_area) g2 = rib_area / (ks2 * piv_wave);
+        const dim3 grid2((uint32_t)g2), block2(64 * ks2);
+        const size_t lds2 = (size_t)ks2 * lw;
+        if (ks2 == 5)
+          hipLaunchKernelGGL(ribbon_block_kernel<5>, grid2, block2, lds2, stream, (const uint64_t *)leaf_keys,
+                             (const uint8_t *)choice, (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, nd,
+                             (const uint32_t *)defer, 2u, (uint32_t *)nullptr, (unsigned long long *)nullptr,
+                             rib_region, piv_wave, lw, row_cap, M->zbits, M->zwords, M->rseed, spill, err);
+        else if (ks2 == 4)
+          hipLaunchKernelGGL(ribbon_block_kernel<4>, grid2, block2, lds2, stream, (const uint64_t *)leaf_keys,
+                             (const uint8_t *)choice, (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, nd,
+                             (const uint32_t *)defer, 2u, (uint32_t *)nullptr, (unsigned long long *)nullptr,
+                             rib_region, piv_wave, lw, row_cap, M->zbits, M->zwords, M->rseed, spill, err);
+        else
+          hipLaunchKernelGGL(ribbon_block_kernel<kRibWaves>, grid2, block2, lds2, stream, (const uint64_t *)leaf_keys,
+                             (const uint8_t *)choice, (const uint64_t *)bucket_offset, (const uint64_t *)rib_base, nd,
+                             (const uint32_t *)defer, 2u, (uint32_t *)nullptr, (unsigned long long *)nullptr,
+                             rib_region, piv_wave, lw, row_cap, M->zbits, M->zwords, M->rseed, spill, err);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&host[0], err, 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+      }
     }
     const bool walk_some = !walk_all && (host[0] & kErrRibbonSpill) && !(host[0] & (kErrRibbon | kErrRibbonInternal));
     if (walk_all || walk_some) {

@@ -225,7 +225,7 @@ def mphf_footprint(n_keys: int, bucket_size: int = 2000, leaf_target: int = 40, 
     m_est = min(bucket_size + bucket_size // 8 + 256, 16384)
     W = -(-_ribbon_cols(m_est) // 64)
     piv = B * 2 * (-(-16 * 64 * W // 256) * 256)
-    arena = 18 * N + 31 * L + 45 * B + max(slot, piv) + 8192 + (16 * L if bipartite else 0)
+    arena = 18 * N + 31 * L + 49 * B + max(slot, piv) + 8448 + (16 * L if bipartite else 0)
     arena += arena // 8  # the arena grows by an eighth over a reservation
     return 8 * N + arena + (16 + SCRATCH_BYTES_PER_LEAF + (4 if bipartite else 0)) * L + (1 << 20)
 
