@@ -412,3 +412,31 @@ def test_ribbon_large_buckets_block_solver_and_global_walk(shock, oracle_mod):
             assert (pos == lay["positions"]).all()
         finally:
             m.close()
+
+
+@pytest.mark.parametrize("bucket_size,seed", [(3000, 2170), (5000, 2171), (7250, 2172)])
+def test_ribbon_second_launch_widths(shock, oracle_mod, bucket_size, seed):
+    """Twelve buckets whose oracle ribbon seeds reach 2 and more, so the
+    second ribbon launch runs.  Its width (seeds tried at once per bucket)
+    is what the LDS holds for the largest bucket: five waves at buckets of
+    about 3000 keys (two rounds, seed 9 is needed), four at 5000 and two at
+    7250 (three rounds, seed 6).  Every width gives the oracle's seeds, bits
+    and positions."""
+    N = 12 * bucket_size
+    keys = splitmix64(seed, N)
+    print(f"[gpu] ribbon second launch: buckets of {bucket_size}", flush=True)
+    rc, lay = oracle_mod.mphf_build(keys, bucket_size=bucket_size, leaf_target=40, leaf_max=56, bip=True,
+                                    retrieval=RIBBON)
+    assert rc == 0
+    rs = np.asarray(lay["rseed"], dtype=np.int64)
+    assert rs.max() >= 2
+    m, k = _build(shock, keys, bucket_size=bucket_size, leaf_target=40, leaf_max=56, bipartite=True)
+    try:
+        ex, info = m.export(), m.info()
+        assert info["ribbon_walked"] == 0
+        assert info["max_rseed"] == int(rs.max())
+        assert _same_retrieval(ex, lay)
+        pos = _host(m.query(k))
+        assert (pos == lay["positions"]).all()
+    finally:
+        m.close()
