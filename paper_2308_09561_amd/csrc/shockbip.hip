@@ -353,11 +353,12 @@ __global__ __launch_bounds__(64 * kW) void bip_kernel(BipParams P) {
   }
 }
 
-// Per host thread and device: the device counters, two timing events and the
-// CU count, kept between calls (a hipFree per call would wait for the whole
-// device, including other streams' work).
+// Per host thread and device: the device counters and their pinned host
+// copy, two timing events and the CU count, kept between calls (a hipFree
+// per call would wait for the whole device, including other streams' work).
 struct BipCache {
   unsigned long long *ctr = nullptr;
+  unsigned long long *host = nullptr;  // pinned, kCtrWords words
   uint32_t *spill = nullptr;  // the first pass's list of leaves past its pool
   uint64_t spill_cap = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -370,6 +371,8 @@ hipError_t bip_cache(int dev, BipCache *&c) {
   c = &t_bip[dev];
   hipError_t e = hipSuccess;
   if (!c->ctr) e = hipMalloc((void **)&c->ctr, kCtrWords * sizeof(unsigned long long));
+  if (e == hipSuccess && !c->host)
+    e = hipHostMalloc((void **)&c->host, kCtrWords * sizeof(unsigned long long), hipHostMallocDefault);
   if (e == hipSuccess && !c->e0) e = hipEventCreate(&c->e0);
   if (e == hipSuccess && !c->e1) e = hipEventCreate(&c->e1);
   if (e == hipSuccess && !c->cus) {
@@ -386,6 +389,11 @@ hipError_t shock_internal_release_bip_scratch(int dev) {
   BipCache &c = t_bip[dev];
   hipError_t e = hipSuccess;
   if (c.ctr) e = hipFree(c.ctr);
+  if (c.host) {
+    const hipError_t f = hipHostFree(c.host);
+    if (e == hipSuccess) e = f;
+  }
+  c.host = nullptr;
   if (c.spill) {
     const hipError_t f = hipFree(c.spill);
     if (e == hipSuccess) e = f;
@@ -427,7 +435,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
     return e == hipErrorOutOfMemory ? SHOCK_ENOMEM : SHOCK_EHIP;
   }
   unsigned long long *ctr = cache->ctr;
-  unsigned long long host[kCtrWords] = {};  // the batch's counters, then the slices' lines
+  unsigned long long *host = cache->host;  // the batch's counters, then the slices' lines
   uint64_t sums[4] = {0, 0, 0, 0};          // statistics over the slices and passes
   auto add_slices = [&]() {
     for (uint32_t r = 0; r < kRanges; ++r)
@@ -470,14 +478,14 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   P.out_orient = out_orient;
   P.ctr = ctr;
   hipEvent_t e0 = cache->e0, e1 = cache->e1;
-  e = hipMemcpyAsync(ctr, host, sizeof(host), hipMemcpyHostToDevice, stream);
+  e = hipMemsetAsync(ctr, 0, kCtrWords * sizeof(host[0]), stream);
   if (e == hipSuccess) e = hipEventRecord(e0, stream);
   if (e == hipSuccess) {
     hipLaunchKernelGGL((bip_kernel<kPool, kWpw>), dim3(groups), dim3(64 * kWpw), 0, stream, P);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipEventRecord(e1, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(host, ctr, sizeof(host), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(host, ctr, kCtrWords * sizeof(host[0]), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   float ms = 0;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -489,9 +497,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
     P.n_leaves = nsp;
     P.pool = cap;
     P.spill = nullptr;
-    for (uint32_t w = kBipRange; w < kCtrWords; ++w) host[w] = 0;
-    e = hipMemcpyAsync(ctr + kBipRange, &host[kBipRange], (kCtrWords - kBipRange) * sizeof(host[0]), hipMemcpyHostToDevice,
-                       stream);
+    e = hipMemsetAsync(ctr + kBipRange, 0, (kCtrWords - kBipRange) * sizeof(host[0]), stream);
     const uint64_t g2 = nsp < (uint64_t)cus * 2 ? nsp : (uint64_t)cus * 2;
     if (e == hipSuccess) e = hipEventRecord(e0, stream);
     if (e == hipSuccess) {
@@ -499,7 +505,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventRecord(e1, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(host, ctr, sizeof(host), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, ctr, kCtrWords * sizeof(host[0]), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     float ms2 = 0;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms2, e0, e1);
