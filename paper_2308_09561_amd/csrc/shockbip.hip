@@ -225,10 +225,6 @@ __global__ __launch_bounds__(64 * kW) void bip_kernel(BipParams P) {
     uint64_t ra = kNone, rb = kNone;
     uint32_t fh0 = 0, fh1 = 0;
     for (uint64_t base = 0; base < P.max_seed && !found && !overflow; base += 64) {
-      // a leaf that runs long gets the SIMD's issue first: the slowest leaves end the launch
-      if (base == 512) __builtin_amdgcn_s_setprio(1);
-      if (base == 1024) __builtin_amdgcn_s_setprio(2);
-      if (base == 1536) __builtin_amdgcn_s_setprio(3);
       const uint64_t s = base + lane;
       const uint64_t t = seed_mix(s);
       uint32_t ml = 0, mr = 0;
@@ -329,7 +325,6 @@ __global__ __launch_bounds__(64 * kW) void bip_kernel(BipParams P) {
         }
       }
     }
-    __builtin_amdgcn_s_setprio(0);
     uint64_t f = 0;
     if (found && !shockwave::orient_wave(n, fh0, fh1, lds.inc0, lds.inc1, &lds.hit, f)) found = false;
     if (lane == 0) {
