@@ -181,14 +181,15 @@ int shock_rf_leaf_search_async(const uint64_t *keys, const uint64_t *offsets, ui
  * leaf without a pair.  stats (host, may be NULL) receives seeds hashed, candidate pairs
  * formed up to each leaf's answer, the pairs among them that the peeling test
  * ran on (a pair whose graph has a key alone in both of its cells, a one-edge
- * tree, is rejected without it), and the kernel time. */
+ * tree, is rejected without it), the kernel time (both passes), the workers
+ * of the first pass and the leaves the second pass searched again. */
 typedef struct {
   uint64_t seeds_hashed;
   uint64_t pairs_tested;
   uint64_t pairs_peeled;
   double kernel_ms;
   int32_t workers;
-  int32_t reserved;
+  int32_t second_pass_leaves; /* at most INT32_MAX */
 } shock_bip_stats;
 
 int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint64_t n_leaves,

@@ -87,10 +87,10 @@ class ShockStats(ctypes.Structure):
 class BipStats(ctypes.Structure):
     _fields_ = [("seeds_hashed", ctypes.c_uint64), ("pairs_tested", ctypes.c_uint64), ("pairs_peeled", ctypes.c_uint64),
                 ("kernel_ms", ctypes.c_double),
-                ("workers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("workers", ctypes.c_int32), ("second_pass_leaves", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class QueueParams(ctypes.Structure):

@@ -54,9 +54,9 @@ constexpr uint64_t kNone = ~0ull;
 // more is listed and searched again from its first seed by the second, one
 // wave per workgroup with pools of up to kPoolBig (most of 64 KB of LDS).
 // With a smaller limit L per side the first keeps L / 2 (at least 1) and the
-// second L, so both passes run on small inputs too.  Uniform
-// keys rarely need the second: leaves of 64 keys gather about 450 candidates
-// per side, of 48 keys a few dozen.
+// second L, so both passes run on small inputs too.  Uniform keys do not
+// need the second: a leaf of 64 keys gathers about 35 candidates per side
+// before its pair (1233 pairs formed per leaf), one of 48 keys about 13.
 constexpr uint32_t kPool = 512;      // candidates per side and leaf, first pass
 constexpr uint32_t kPoolBig = 7168;  // second pass
 constexpr uint32_t kCache = 16;  // candidates per side whose cells are kept in LDS
@@ -485,9 +485,9 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
   float ms = 0;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
   if (e == hipSuccess) add_slices();
-  if (e == hipSuccess && host[kBipSpilled] > 0) {
+  const uint64_t nsp = e == hipSuccess ? host[kBipSpilled] : 0;
+  if (nsp > 0) {
     // the second pass over the listed leaves, one wave per workgroup
-    const uint64_t nsp = host[kBipSpilled];
     P.list = cache->spill;
     P.n_leaves = nsp;
     P.pool = cap;
@@ -517,6 +517,7 @@ int shock_bip_leaf_search_ex(const uint64_t *keys, const uint64_t *offsets, uint
     stats->pairs_peeled = sums[kSlicePeeled];
     stats->kernel_ms = ms;
     stats->workers = (int32_t)(groups * kWpw);
+    stats->second_pass_leaves = (int32_t)(nsp < 0x7fffffffull ? nsp : 0x7fffffffull);
   }
   if (host[kBipErr] & kErrInvalidLeaf) return SHOCK_EINVAL;
   if (host[kBipErr] & kErrPool) return SHOCK_ENOTFOUND;

@@ -57,6 +57,29 @@ def test_bip_fixed_n_matches_oracle(shock, oracle_mod, n, L):
     assert_same(gpu_bip(shock, keys, offs), oracle_bip(oracle_mod, keys, offs), f"n={n}")
 
 
+def test_bip_64_key_leaves_and_the_second_pass(shock, oracle_mod):
+    """64 leaves of 64 keys (about 35 candidates per side before the pair):
+    with the default pools every leaf equals the oracle and none needs the
+    second pass.  With bip_pool = 100 the first pass keeps 50 per side, so
+    the leaves past that are searched again with pools of 100: each leaf
+    then equals the oracle or, if it needs more than 100 on a side, is
+    reported not found (all ones)."""
+    keys, offs = fixed_leaves(64, 64, 3110)
+    want = oracle_bip(oracle_mod, keys, offs)
+    g = gpu_bip(shock, keys, offs)
+    print(f"[gpu] bip 64 leaves of 64 keys: stats {g[4]}", flush=True)
+    assert_same(g, want, "n=64")
+    assert g[4]["second_pass_leaves"] == 0
+    h = gpu_bip(shock, keys, offs, bip_pool=100)
+    print(f"[gpu] bip 64 leaves of 64 keys, pool 100: stats {h[4]}", flush=True)
+    lost = h[1] == MAX
+    assert h[4]["second_pass_leaves"] > 0 and lost.sum() <= h[4]["second_pass_leaves"]
+    assert (h[2][lost] == MAX).all()
+    ok = ~lost
+    assert (h[1][ok] == want[1][ok]).all() and (h[2][ok] == want[2][ok]).all() and (h[3][ok] == want[3][ok]).all()
+    assert h[0] == (shock.SHOCK_ENOTFOUND if lost.any() else shock.SHOCK_OK)
+
+
 def test_bip_uneven_batch_and_worker_counts(shock, oracle_mod):
     rng = np.random.default_rng(3100)
     sizes = np.repeat(np.arange(0, 50), 3)
@@ -90,6 +113,7 @@ def test_bip_full_batch_statistics(shock, oracle_mod):
     L = len(offs) - 1
     print(f"[gpu] bip fixed48 stats {st}", flush=True)
     assert st["seeds_hashed"] / L < 2000 and st["kernel_ms"] > 0
+    assert st["second_pass_leaves"] == 0  # a 48-key leaf gathers a few dozen candidates per side
     # every leaf peels at least its answer; the lone-key filter rejects most
     # candidate pairs (a one-edge tree is common when both halves are covered)
     assert L <= st["pairs_peeled"] < 0.6 * st["pairs_tested"]
@@ -147,6 +171,8 @@ def test_bip_pool_limit_against_the_oracle(shock, oracle_mod, cap):
                                       int(want[2][j]))) > cap // 2 for j in range(len(offs) - 1)]) & ~over
     print(f"[gpu] bip pool {cap}: {second.sum()} leaves found by the second pass", flush=True)
     assert second.sum() > 0
+    # every leaf past the first pass's pool (cap // 2) was searched again
+    assert g[4]["second_pass_leaves"] == int(second.sum() + over.sum())
     assert g[0] == shock.SHOCK_ENOTFOUND
     assert (g[1][over] == MAX).all() and (g[2][over] == MAX).all()
     ok = ~over
