@@ -91,3 +91,25 @@ def test_leaves_per_bucket_limit(shock, oracle_mod, N, want):
         assert (m.query(k).cpu().numpy().view(np.uint64) == lay["positions"]).all()
     finally:
         m.close()
+
+
+def test_failed_split_after_a_larger_build(shock, oracle_mod):
+    """A build whose buckets cannot all be split (13700 keys, buckets of 2406,
+    leaves of at most 29) right after a larger build on the same thread: the
+    cached scratch then holds the larger build's leaf offsets.  The failing
+    bucket's leaves are still written (empty), so the kernels queued behind
+    the split read none of those offsets, and the build returns the oracle's
+    status."""
+    big = splitmix64(9700, 300000)
+    m = shock.MPHF(torch.from_numpy(big.view(np.int64)).cuda())
+    torch.cuda.synchronize()
+    m.close()
+    keys = splitmix64(9602, 13700)
+    params = dict(bucket_size=2406, leaf_target=24, leaf_max=29)
+    print(f"[gpu] failed split after a larger build: {params}", flush=True)
+    rc_o, _ = oracle_mod.mphf_build(keys, rf=True, retrieval=RIBBON, **params)
+    assert rc_o == shock.SHOCK_ENOTFOUND
+    with pytest.raises(shock.ShockError) as e:
+        shock.MPHF(torch.from_numpy(keys.view(np.int64)).cuda(), rotation_fitting=True, retrieval=RIBBON, **params)
+    assert e.value.status == shock.SHOCK_ENOTFOUND
+    torch.cuda.synchronize()
